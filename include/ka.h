@@ -1,0 +1,182 @@
+/* ka.h -- C ABI of the MI355X matrix-free isogeometric Karhunen-Loeve library.
+ *
+ * The library computes the leading eigenpairs of the generalized eigenvalue
+ * problem  A v = lambda Z v  (paper Sec. 1, eq. matrix_equations) that the
+ * Galerkin (Sec. 3.1) and collocation (Sec. 3.2) discretisations of the
+ * Fredholm problem (Sec. 2, eq. fredholm) produce, without ever forming the
+ * dense matrix A.  The hot path is the on-the-fly covariance-kernel product
+ * Gamma * Y inside the standard-form operator A' (Sec. 3, eq. standard).
+ *
+ * Conventions
+ * -----------
+ * - Tensor index of a degree of freedom: i = i1 + n1 * (i2 + n2 * i3), so the
+ *   Kronecker factors read Z = Z3 (x) Z2 (x) Z1 (Sec. 3.1).
+ * - Blocks of vectors are column-major FP64, N rows, leading dimension ld >= N.
+ * - Pointers named *_dev are device pointers (hipMalloc / torch CUDA tensors);
+ *   *_host are host pointers.  The caller owns every pointer it passes.
+ * - Streams are hipStream_t passed as void* (NULL = the default stream).
+ * - Return value: 0 = KA_OK, < 0 hard error (see ka_last_error()), > 0 soft
+ *   condition (KA_NOT_CONVERGED).
+ * - Apply / solve / gamma calls are asynchronous on the given stream and
+ *   allocate no device memory; ka_setup allocates all workspace.  ka_eigs is
+ *   synchronous on the problem's stream.
+ * - A problem handle must not be used from two host threads at once.
+ */
+#ifndef KA_H
+#define KA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---------------------------------------------------- */
+#define KA_OK 0
+#define KA_ERR_ARG (-1)       /* invalid argument or shape                  */
+#define KA_ERR_OOM (-2)       /* device allocation failed                   */
+#define KA_ERR_HIP (-3)       /* a HIP runtime call or launch failed         */
+#define KA_ERR_SINGULAR (-4)  /* a factorisation met a (near) zero pivot     */
+#define KA_ERR_STATE (-5)     /* call not valid for this problem / server    */
+#define KA_NOT_CONVERGED 1    /* ka_eigs: maxit reached; partial results    */
+
+/* ---- enumerations ------------------------------------------------------ */
+enum ka_method { KA_GALERKIN_IBQ = 0, KA_COLLOCATION = 1 };
+enum ka_domain { KA_BOX = 0, KA_QUARTER_ANNULUS = 1 };
+enum ka_kernel { KA_GAUSSIAN = 0, /* sigma^2 exp(-|x-y|_2^2 / ell^2) */
+                 KA_EXP_L1 = 1    /* sigma^2 exp(-|x-y|_1 / ell)     */ };
+enum ka_precision { KA_FP32 = 0,  /* FP32 kernel tiles, FP32 MFMA contraction        */
+                    KA_BF16X3 = 1 /* FP32 tiles split hi+lo into BF16, 3 BF16 MFMAs,
+                                     FP32 accumulation                               */ };
+enum ka_form { KA_A = 0,          /* the covariance matrix A itself                  */
+               KA_APRIME = 1      /* the standard-form operator A' (Sec. 3, eq. standard):
+                                     Galerkin L^-1 A L^-T, collocation Z^-1 A         */ };
+enum ka_solve_op { KA_ZINV = 0,   /* X <- Z^-1 X                                     */
+                   KA_LINV = 1,   /* X <- L^-1 X   (Galerkin, Z = L L^T)             */
+                   KA_LTINV = 2   /* X <- L^-T X   (Galerkin)                        */ };
+
+/* ---- problem description (paper Sec. 3; Sec. 4 for the spaces) ---------
+ * method       KA_GALERKIN_IBQ (Sec. 3.1) or KA_COLLOCATION (Sec. 3.2).
+ * domain       KA_BOX: [lo, hi] (affine map); KA_QUARTER_ANNULUS: radii r0 < r1,
+ *              quarter circle in the x-y plane extruded to `height` (exact
+ *              rational quadratic NURBS map).
+ * degree/nel   B-spline degree and element count per parametric direction
+ *              (solution space with C^{p-1} continuity, open uniform knots).
+ * interp_cont  Galerkin only: continuity of the interpolation space S~;
+ *              -1 = automatic: C^0 for KA_EXP_L1 (Sec. 4.1), C^{p-1} for
+ *              KA_GAUSSIAN (Sec. 4.2); otherwise 0 .. p-1.
+ * kernel/sigma/ell  covariance kernel and its parameters (ell > 0; ell = +inf
+ *              is allowed for KA_GAUSSIAN and gives the constant kernel).
+ * nq           collocation: Gauss points per element and direction (0 = p+1).
+ * precision    contraction precision of the kernel product.
+ * block        eigensolver block size b (1..64); also the largest nvec that
+ *              one internal pass of ka_apply_A handles (larger nvec loops).
+ * seed         seeds the eigensolver's start block.                          */
+typedef struct ka_desc {
+  int method;
+  int domain;
+  double lo[3], hi[3];
+  double r0, r1, height;
+  int degree[3];
+  int nel[3];
+  int interp_cont;
+  int kernel;
+  double sigma, ell;
+  int nq;
+  int precision;
+  int block;
+  unsigned long long seed;
+} ka_desc;
+
+/* eigensolver report */
+typedef struct ka_info {
+  int iterations;        /* restart cycles                                     */
+  int matvecs;           /* block applications of A'                           */
+  int converged;         /* leading pairs meeting the tolerance                */
+  int nev_computed;      /* M extended to the end of its eigenvalue cluster    */
+  double max_residual;   /* max over the first M of |A'x - theta x| / max(|theta|, 1e-2 |theta_1|) */
+  double max_imag_rel;   /* collocation: max |Im lambda| / |lambda| over the first M */
+  double seconds;        /* wall time of the solve                             */
+  double gamma_seconds;  /* device time inside the kernel-product launches     */
+  double pairs;          /* kernel pair evaluations performed                  */
+} ka_info;
+
+typedef struct ka_problem ka_problem;
+
+/* Build a problem: host FP64 setup of knots, Greville points, Gauss rules,
+ * univariate mass / mixed-mass / collocation matrices and their factors
+ * (Sec. 3.1, Z = Z3 x Z2 x Z1 and its Cholesky factors; Sec. 3.2 pivoted LU of
+ * the Kronecker factors of Z, remark in Sec. 3.3), physical point sets, and
+ * upload.  Allocates all device workspace.  `stream` becomes the problem's
+ * stream for ka_eigs.  On error *out is NULL. */
+int ka_setup(const ka_desc* desc, void* stream, ka_problem** out);
+
+/* Sizes: N degrees of freedom, Ntilde Galerkin interpolation points (0 for
+ * collocation), Nquad collocation quadrature points (0 for Galerkin), and the
+ * device bytes the problem holds.  Any output pointer may be NULL. */
+int ka_size(const ka_problem* p, int64_t* N, int64_t* Ntilde, int64_t* Nquad,
+            size_t* device_bytes);
+
+/* Device bytes ka_setup would allocate for `desc` (admission control); no
+ * device work. */
+int ka_footprint(const ka_desc* desc, size_t* device_bytes);
+
+/* Y = A X or Y = A' X for nvec columns (device, column-major FP64).
+ * Galerkin (Sec. 3.1): A = M^T B~^-1 J Gamma J B~^-T M, and A' = L^-1 A L^-T is
+ * the nine-step product (L^-T, M, B~^-T, J, Gamma, J, B~^-1, M^T, L^-1).
+ * Collocation (Sec. 3.2, Algorithm 1): A = Gamma_c diag(J W) R_q, A' = Z^-1 A.
+ * X and Y must not overlap.  Async on `stream`; no allocation. */
+int ka_apply_A(ka_problem* p, int form, const double* X_dev, int64_t ldx,
+               double* Y_dev, int64_t ldy, int nvec, void* stream);
+
+/* In-place FP64 Kronecker solves on nvec columns (device, column-major):
+ * KA_ZINV X <- Z^-1 X (Galerkin: mass matrix; collocation: Z_ij = R_j(x_i)),
+ * KA_LINV X <- L^-1 X, KA_LTINV X <- L^-T X (Galerkin only; else KA_ERR_STATE).
+ * Async on `stream`; no allocation. */
+int ka_solve_Z(ka_problem* p, int op, double* X_dev, int64_t ld, int nvec, void* stream);
+
+/* Leading M eigenpairs of A v = lambda Z v by a block Krylov method with thick
+ * restarts (FP64 basis, orthogonalisation and Rayleigh-Ritz on the device).
+ * Stops when |A'x - theta x| <= tol * max(|theta|, 1e-2 |theta_1|) for the
+ * first M Ritz pairs (M extended to the end of its cluster), or after maxit
+ * restart cycles (returns KA_NOT_CONVERGED; results are still written).
+ * lambda_host: M doubles (Galerkin), or 2M doubles re/im interleaved
+ *   (collocation), sorted by descending real part.
+ * V_dev: N x M column-major device array or NULL.  Galerkin eigenvectors are
+ *   Z-orthonormal (v = L^-T v'); collocation eigenvectors have unit 2-norm (a
+ *   complex pair is stored as real part, imaginary part in consecutive
+ *   columns).  Each vector's largest-magnitude entry is made positive.
+ * info may be NULL.  Synchronous. */
+int ka_eigs(ka_problem* p, int M, double tol, int maxit, double* lambda_host,
+            double* V_dev, ka_info* info);
+
+/* The raw fused kernel product (hot path, paper Sec. 3.1 step Gamma and
+ * Algorithm 1 step 3): Z[i, :] = sigma^2 sum_c Gamma(xr_i, xc_c) Y[c, :].
+ * xr: nr x 3, xc: nc x 3 FP32 row-major physical coordinates; Y: nc x b and
+ * Z: nr x b FP32 row-major (point-major, b contiguous); b in {16, 32, 64}.
+ * precision KA_FP32 or KA_BF16X3.  Requires nr * b * 4 * nsplit bytes of
+ * split-K scratch from `work_dev` (work_bytes); pass ka_gamma_workspace() bytes.
+ * Async on `stream`. */
+int ka_gamma_apply(int kernel, double sigma, double ell, const float* xr_dev, int64_t nr,
+                   const float* xc_dev, int64_t nc, const float* Y_dev, int b, float* Z_dev,
+                   int precision, void* work_dev, size_t work_bytes, void* stream);
+
+/* Scratch bytes ka_gamma_apply needs for these sizes. */
+size_t ka_gamma_workspace(int64_t nr, int64_t nc, int b, int precision);
+
+/* Timing of kernel-product launches issued through a problem since the last
+ * reset (HIP events on the launch stream; enabled by ka_profile_enable). */
+int ka_profile_enable(ka_problem* p, int on);
+int ka_profile_read(ka_problem* p, int* launches, double* total_ms, double* pairs);
+int ka_profile_reset(ka_problem* p);
+
+void ka_destroy(ka_problem* p);
+
+/* Last error message of the calling host thread. */
+const char* ka_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* KA_H */

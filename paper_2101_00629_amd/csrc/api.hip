@@ -1,0 +1,493 @@
+// C ABI entry points: problem set-up, the matrix-free operators, the Kronecker
+// solves, the raw kernel product and the block eigensolver driver.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "host_setup.hpp"
+#include "ka_internal.hpp"
+
+namespace ka {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+const char* last_error_cstr() { return g_last_error.c_str(); }
+
+int fail(int code, const std::string& msg) {
+  set_error(msg);
+  return code;
+}
+
+#define HIP_TRY(expr)                                                                    \
+  do {                                                                                   \
+    hipError_t e_ = (expr);                                                              \
+    if (e_ != hipSuccess)                                                                \
+      return fail(KA_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_));       \
+  } while (0)
+
+float kernel_coord_scale(int kernel, double ell) {
+  if (std::isinf(ell)) return 0.0f;
+  const double log2e = 1.4426950408889634074;
+  return kernel == KA_GAUSSIAN ? (float)(std::sqrt(log2e) / ell) : (float)(log2e / ell);
+}
+
+static double coord_scale64(int kernel, double ell) {
+  if (std::isinf(ell)) return 0.0;
+  const double log2e = 1.4426950408889634074;
+  return kernel == KA_GAUSSIAN ? std::sqrt(log2e) / ell : log2e / ell;
+}
+
+// ---------------------------------------------------------------------------
+// sizes
+// ---------------------------------------------------------------------------
+struct Sizes {
+  int n[3], nt[3], nq[3];
+  int64_t N, Nt, Nq, n_rows, n_cols;
+  int mult[3];
+};
+
+static int check_desc(const ka_desc* d, Sizes& z) {
+  if (!d) return fail(KA_ERR_ARG, "desc is NULL");
+  if (d->method != KA_GALERKIN_IBQ && d->method != KA_COLLOCATION) return fail(KA_ERR_ARG, "bad method");
+  if (d->domain != KA_BOX && d->domain != KA_QUARTER_ANNULUS) return fail(KA_ERR_ARG, "bad domain");
+  if (d->kernel != KA_GAUSSIAN && d->kernel != KA_EXP_L1) return fail(KA_ERR_ARG, "bad kernel");
+  if (d->precision != KA_FP32 && d->precision != KA_BF16X3) return fail(KA_ERR_ARG, "bad precision");
+  if (!(d->ell > 0)) return fail(KA_ERR_ARG, "ell must be > 0");
+  if (std::isinf(d->ell) && d->kernel != KA_GAUSSIAN) return fail(KA_ERR_ARG, "ell = inf needs the Gaussian kernel");
+  if (!(d->sigma > 0) || std::isinf(d->sigma)) return fail(KA_ERR_ARG, "sigma must be finite and > 0");
+  if (d->block != 16 && d->block != 32 && d->block != 64) return fail(KA_ERR_ARG, "block must be 16, 32 or 64");
+  if (d->domain == KA_BOX) {
+    for (int k = 0; k < 3; ++k)
+      if (!(d->hi[k] > d->lo[k])) return fail(KA_ERR_ARG, "box needs hi > lo");
+  } else {
+    if (!(d->r1 > d->r0 && d->r0 > 0 && d->height > 0)) return fail(KA_ERR_ARG, "annulus needs 0 < r0 < r1, height > 0");
+  }
+  z.N = z.Nt = z.Nq = 1;
+  for (int k = 0; k < 3; ++k) {
+    const int p = d->degree[k], e = d->nel[k];
+    if (p < 1 || p > 8) return fail(KA_ERR_ARG, "degree must be in 1..8");
+    if (e < 1 || e > 4096) return fail(KA_ERR_ARG, "nel must be in 1..4096");
+    z.n[k] = p + e;
+    int mult = 1;
+    if (d->method == KA_GALERKIN_IBQ) {
+      if (d->interp_cont < 0) mult = (d->kernel == KA_EXP_L1) ? p : 1;
+      else if (d->interp_cont <= p - 1) mult = p - d->interp_cont;
+      else return fail(KA_ERR_ARG, "interp_cont must be -1 or 0..p-1");
+    }
+    z.mult[k] = mult;
+    z.nt[k] = p + 1 + mult * (e - 1);
+    const int q = d->nq > 0 ? d->nq : p + 1;
+    if (q > 16) return fail(KA_ERR_ARG, "nq must be <= 16");
+    z.nq[k] = q * e;
+    z.N *= z.n[k];
+    z.Nt *= z.nt[k];
+    z.Nq *= z.nq[k];
+  }
+  if (d->method == KA_GALERKIN_IBQ) {
+    z.Nq = 0;
+    z.n_rows = z.n_cols = z.Nt;
+  } else {
+    z.Nt = 0;
+    z.n_rows = z.N;
+    z.n_cols = z.Nq;
+  }
+  if (z.N > (int64_t)1 << 30) return fail(KA_ERR_ARG, "problem too large");
+  return KA_OK;
+}
+
+static size_t align_up(size_t x) { return (x + 255) / 256 * 256; }
+
+// Largest point count of any intermediate tensor of the Kronecker transfers
+// (forward n -> m direction by direction, and back): sizes the FP32 buffers.
+static int64_t transfer_points(const ka_desc* d, const Sizes& z) {
+  const int* m = d->method == KA_GALERKIN_IBQ ? z.nt : z.nq;
+  const int64_t n0 = z.n[0], n1 = z.n[1], n2 = z.n[2], m0 = m[0], m1 = m[1], m2 = m[2];
+  int64_t big = n0 * n1 * n2;
+  for (int64_t v : {m0 * n1 * n2, m0 * m1 * n2, m0 * m1 * m2, n0 * m1 * m2, n0 * n1 * m2}) big = std::max(big, v);
+  return big;
+}
+
+static size_t setup_bytes(const ka_desc* d, const Sizes& z) {
+  const int b = d->block;
+  size_t s = 0;
+  for (int k = 0; k < 3; ++k) {
+    s += 3 * align_up((size_t)z.n[k] * z.n[k] * 8);          // LinvT, Linv, Zinv
+    const int mk = d->method == KA_GALERKIN_IBQ ? z.nt[k] : z.nq[k];
+    s += 2 * align_up((size_t)mk * z.n[k] * 4);               // T, TT
+  }
+  s += align_up((size_t)z.n_rows * 16) + align_up((size_t)z.n_cols * 16);
+  s += align_up((size_t)z.n_rows * 4) + align_up((size_t)z.n_cols * 4);
+  s += 2 * align_up((size_t)z.N * b * 8);
+  s += 2 * align_up((size_t)transfer_points(d, z) * b * 4);
+  s += align_up(gamma_plan(z.n_rows, z.n_cols, b, d->precision).partial_bytes);
+  return s;
+}
+
+// ---------------------------------------------------------------------------
+// setup
+// ---------------------------------------------------------------------------
+static void* dev_alloc(Problem* P, size_t bytes, bool& ok) {
+  void* p = nullptr;
+  if (bytes == 0) bytes = 256;
+  if (hipMalloc(&p, align_up(bytes)) != hipSuccess) {
+    ok = false;
+    return nullptr;
+  }
+  P->allocs.push_back({p, align_up(bytes)});
+  P->device_bytes += align_up(bytes);
+  return p;
+}
+
+template <typename T>
+static T* upload(Problem* P, const std::vector<T>& v, bool& ok) {
+  T* p = (T*)dev_alloc(P, v.size() * sizeof(T), ok);
+  if (ok && !v.empty()) ok = hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice) == hipSuccess;
+  return p;
+}
+
+static std::vector<double> to_vec(const Mat& m) { return m.a; }
+static std::vector<float> to_vec32(const Mat& m) { return std::vector<float>(m.a.begin(), m.a.end()); }
+
+static void free_problem(Problem* P) {
+  if (!P) return;
+  for (auto& b : P->allocs) (void)hipFree(b.p);
+  for (auto& b : P->eig_allocs) (void)hipFree(b.p);
+  for (auto e : P->ev_start) (void)hipEventDestroy(e);
+  for (auto e : P->ev_stop) (void)hipEventDestroy(e);
+  delete P;
+}
+
+static int setup_impl(const ka_desc* d, hipStream_t stream, Problem** out) {
+  Sizes z;
+  int rc = check_desc(d, z);
+  if (rc) return rc;
+  Problem* P = new Problem();
+  P->d = *d;
+  P->stream = stream;
+  (void)hipGetDevice(&P->device);
+  P->b = d->block;
+  P->N = (int)z.N;
+  P->Nt = (int)z.Nt;
+  P->Nq = z.Nq;
+  for (int k = 0; k < 3; ++k) {
+    P->n[k] = z.n[k];
+    P->nt[k] = z.nt[k];
+    P->nq[k] = z.nq[k];
+  }
+  P->n_rows = z.n_rows;
+  P->n_cols = z.n_cols;
+  P->out_scale = (float)(d->sigma * d->sigma);
+  P->coord_scale = 1.0f;   // coordinates are prescaled in FP64 below
+  Geometry geo;
+  geo.domain = d->domain;
+  for (int k = 0; k < 3; ++k) {
+    geo.lo[k] = d->lo[k];
+    geo.hi[k] = d->hi[k];
+  }
+  geo.r0 = d->r0;
+  geo.r1 = d->r1;
+  geo.height = d->height;
+  const double cs = coord_scale64(d->kernel, d->ell);
+  bool ok = true;
+
+  // univariate factors
+  std::vector<Vec> pts1d(3);      // Galerkin: interpolation Greville points; collocation: Greville points
+  std::vector<Vec> q1d(3), w1d(3);
+  for (int k = 0; k < 3; ++k) {
+    const int p = d->degree[k], e = d->nel[k];
+    const Vec t = open_knots(p, e, 1);
+    if (d->method == KA_GALERKIN_IBQ) {
+      Mat Zk = mass_matrix(t, p, t, p), Lk;
+      if (!cholesky_lower(Zk, Lk)) {
+        free_problem(P);
+        return fail(KA_ERR_SINGULAR, "mass matrix is not SPD");
+      }
+      const Mat Li = lower_inverse(Lk);
+      const Mat LiT = transpose(Li);
+      P->Linv[k] = upload(P, to_vec(Li), ok);
+      P->LinvT[k] = upload(P, to_vec(LiT), ok);
+      P->Zinv[k] = upload(P, to_vec(matmul(LiT, Li)), ok);
+      const Vec ti = open_knots(p, e, z.mult[k]);
+      const Vec g = greville(ti, p);
+      const Mat Mk = mass_matrix(ti, p, t, p);               // nt x n
+      const Mat Bt = bspline_matrix(ti, p, g);               // nt x nt, rows are points
+      Mat Bti;
+      if (!lu_inverse(Bt, Bti)) {
+        free_problem(P);
+        return fail(KA_ERR_SINGULAR, "interpolation collocation matrix is singular");
+      }
+      const Mat Tk = matmul(transpose(Bti), Mk);             // B~^-T M
+      P->T[k] = upload(P, to_vec32(Tk), ok);
+      P->TT[k] = upload(P, to_vec32(transpose(Tk)), ok);
+      pts1d[k] = g;
+    } else {
+      const Vec g = greville(t, p);
+      Vec xq, wq;
+      element_gauss(t, d->nq > 0 ? d->nq : p + 1, xq, wq);
+      // NURBS weights: interpolate the weight function at the Greville points
+      Mat Bg = bspline_matrix(t, p, g), Bgi;
+      if (!lu_inverse(Bg, Bgi)) {
+        free_problem(P);
+        return fail(KA_ERR_SINGULAR, "Greville collocation matrix is singular");
+      }
+      Vec wf(g.size()), w(g.size(), 0.0);
+      for (size_t i = 0; i < g.size(); ++i) wf[i] = geo.weight1d(k, g[i]);
+      for (size_t i = 0; i < g.size(); ++i)
+        for (size_t j = 0; j < g.size(); ++j) w[i] += Bgi(i, j) * wf[j];
+      auto nurbs = [&](const Vec& x) {
+        Mat B = bspline_matrix(t, p, x);
+        for (int a = 0; a < B.rows; ++a) {
+          double den = 0;
+          for (int j = 0; j < B.cols; ++j) den += w[j] * B(a, j);
+          for (int j = 0; j < B.cols; ++j) B(a, j) = w[j] * B(a, j) / den;
+        }
+        return B;
+      };
+      const Mat Rq = nurbs(xq);                               // nq x n
+      const Mat Zc = nurbs(g);                                // n x n
+      Mat Zci;
+      if (!lu_inverse(Zc, Zci)) {
+        free_problem(P);
+        return fail(KA_ERR_SINGULAR, "collocation matrix Z_k is singular");
+      }
+      P->Zinv[k] = upload(P, to_vec(Zci), ok);
+      P->T[k] = upload(P, to_vec32(Rq), ok);
+      P->TT[k] = upload(P, to_vec32(transpose(Rq)), ok);
+      pts1d[k] = g;
+      q1d[k] = xq;
+      w1d[k] = wq;
+    }
+  }
+  // point sets
+  auto tensor_points = [&](const std::vector<Vec>& g, std::vector<float>& xyz, std::vector<double>* detJ) {
+    const int64_t n1 = g[0].size(), n2 = g[1].size(), n3 = g[2].size();
+    xyz.assign((size_t)n1 * n2 * n3 * 4, 0.f);
+    if (detJ) detJ->assign((size_t)n1 * n2 * n3, 0.0);
+    for (int64_t a3 = 0; a3 < n3; ++a3)
+      for (int64_t a2 = 0; a2 < n2; ++a2)
+        for (int64_t a1 = 0; a1 < n1; ++a1) {
+          const int64_t i = a1 + n1 * (a2 + n2 * a3);
+          const double xh[3] = {g[0][a1], g[1][a2], g[2][a3]};
+          double x[3];
+          geo.map(xh, x);
+          for (int c = 0; c < 3; ++c) xyz[i * 4 + c] = (float)(x[c] * cs);
+          if (detJ) (*detJ)[i] = geo.detJ(xh);
+        }
+  };
+  if (d->method == KA_GALERKIN_IBQ) {
+    std::vector<float> xyz;
+    std::vector<double> dj;
+    tensor_points(pts1d, xyz, &dj);
+    std::vector<float> J(dj.size());
+    for (size_t i = 0; i < dj.size(); ++i) J[i] = (float)std::sqrt(dj[i]);
+    P->rows = upload(P, xyz, ok);
+    P->cols = P->rows;
+    P->rscale = upload(P, J, ok);
+    P->cscale = P->rscale;
+  } else {
+    std::vector<float> xr, xq;
+    tensor_points(pts1d, xr, nullptr);
+    std::vector<double> dj;
+    tensor_points(q1d, xq, &dj);
+    std::vector<float> jw(dj.size());
+    const int64_t m1 = q1d[0].size(), m2 = q1d[1].size();
+    for (size_t i = 0; i < dj.size(); ++i) {
+      const int64_t a1 = i % m1, a2 = (i / m1) % m2, a3 = i / (m1 * m2);
+      jw[i] = (float)(dj[i] * w1d[0][a1] * w1d[1][a2] * w1d[2][a3]);
+    }
+    P->rows = upload(P, xr, ok);
+    P->cols = upload(P, xq, ok);
+    P->rscale = nullptr;
+    P->cscale = upload(P, jw, ok);
+  }
+  const int b = P->b;
+  P->w64a = (double*)dev_alloc(P, (size_t)P->N * b * 8, ok);
+  P->w64b = (double*)dev_alloc(P, (size_t)P->N * b * 8, ok);
+  const int64_t big = transfer_points(d, z);
+  P->w32a = (float*)dev_alloc(P, (size_t)big * b * 4, ok);
+  P->w32b = (float*)dev_alloc(P, (size_t)big * b * 4, ok);
+  const GammaPlan gp = gamma_plan(P->n_rows, P->n_cols, b, d->precision);
+  P->gpart_bytes = gp.partial_bytes;
+  P->gpart = (float*)dev_alloc(P, gp.partial_bytes, ok);
+  if (!ok) {
+    free_problem(P);
+    return fail(KA_ERR_OOM, "device allocation failed in ka_setup");
+  }
+  if (fill_zero_f32(P->w32a, big * b, stream) != hipSuccess || fill_zero_f32(P->w32b, big * b, stream) != hipSuccess ||
+      hipStreamSynchronize(stream) != hipSuccess) {
+    free_problem(P);
+    return fail(KA_ERR_HIP, "workspace initialisation failed");
+  }
+  *out = P;
+  return KA_OK;
+}
+
+// ---------------------------------------------------------------------------
+// operator pieces
+// ---------------------------------------------------------------------------
+static ModeArgs mode_args(const void* in, int in_layout, int64_t in_ld, void* out, int out_layout, int64_t out_ld,
+                          const int dims[3], int mode, int m, const void* mat, int nv, const float* scale) {
+  ModeArgs a;
+  a.in = in;
+  a.in_layout = in_layout;
+  a.in_ld = in_ld;
+  a.out = out;
+  a.out_layout = out_layout;
+  a.out_ld = out_ld;
+  for (int k = 0; k < 3; ++k) a.n_in[k] = dims[k];
+  a.mode = mode;
+  a.m = m;
+  a.mat = mat;
+  a.nv = nv;
+  a.out_scale = scale;
+  return a;
+}
+
+static int gamma_step(Problem* P, const float* Y, float* Z, hipStream_t s) {
+  GammaLaunch g;
+  g.xr = P->rows;
+  g.xr_stride = 4;
+  g.rs = P->d.method == KA_GALERKIN_IBQ ? P->rscale : nullptr;
+  g.nr = P->n_rows;
+  g.xc = P->cols;
+  g.xc_stride = 4;
+  g.nc = P->n_cols;
+  g.Y = Y;
+  g.Z = Z;
+  g.partial = P->gpart;
+  g.coord_scale = P->coord_scale;
+  g.out_scale = P->out_scale;
+  g.nsplit = 1;
+  g.cols_per_split = 0;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (P->profile) {
+    if (P->prof_launches < (int)P->ev_start.size()) {
+      e0 = P->ev_start[P->prof_launches];
+      e1 = P->ev_stop[P->prof_launches];
+    } else {
+      HIP_TRY(hipEventCreate(&e0));
+      HIP_TRY(hipEventCreate(&e1));
+      P->ev_start.push_back(e0);
+      P->ev_stop.push_back(e1);
+    }
+    HIP_TRY(hipEventRecord(e0, s));
+  }
+  HIP_TRY(launch_gamma(g, P->d.kernel, P->b, P->d.precision, s));
+  const double pairs = (double)P->n_rows * (double)P->n_cols;
+  P->pairs_total += pairs;
+  if (P->profile) {
+    HIP_TRY(hipEventRecord(e1, s));
+    P->prof_launches++;
+    P->prof_pairs += pairs;
+  }
+  return KA_OK;
+}
+
+// Three FP64 mode products with per-direction matrices mats[k] (n_k x n_k),
+// in-place on a column block through the two FP64 workspaces.
+static int kron64(Problem* P, double* const mats[3], const double* X, int64_t ldx, double* Y, int64_t ldy, int nv,
+                  hipStream_t s) {
+  const int* n = P->n;
+  const int64_t N = P->N;
+  HIP_TRY(launch_mode_f64(mode_args(X, LAYOUT_COL, ldx, P->w64a, LAYOUT_COL, N, n, 0, n[0], mats[0], nv, nullptr), s));
+  HIP_TRY(launch_mode_f64(mode_args(P->w64a, LAYOUT_COL, N, P->w64b, LAYOUT_COL, N, n, 1, n[1], mats[1], nv, nullptr), s));
+  HIP_TRY(launch_mode_f64(mode_args(P->w64b, LAYOUT_COL, N, Y, LAYOUT_COL, ldy, n, 2, n[2], mats[2], nv, nullptr), s));
+  return KA_OK;
+}
+
+// X (FP64, column layout) -> Galerkin: J B~^-T M X ; collocation: JW R_q X.
+// Output: point-major FP32 in w32a with point stride b.
+static int forward_transfer(Problem* P, const double* X, int64_t ldx, int nv, hipStream_t s) {
+  const int b = P->b;
+  const int* n = P->n;
+  const int* m = P->d.method == KA_GALERKIN_IBQ ? P->nt : P->nq;
+  int d0[3] = {n[0], n[1], n[2]};
+  HIP_TRY(launch_mode_f64_to_f32(mode_args(X, LAYOUT_COL, ldx, P->w32b, LAYOUT_PT, b, d0, 0, m[0], P->T[0], nv, nullptr), s));
+  int d1[3] = {m[0], n[1], n[2]};
+  HIP_TRY(launch_mode_f32(mode_args(P->w32b, LAYOUT_PT, b, P->w32a, LAYOUT_PT, b, d1, 1, m[1], P->T[1], nv, nullptr), s));
+  int d2[3] = {m[0], m[1], n[2]};
+  HIP_TRY(launch_mode_f32(mode_args(P->w32a, LAYOUT_PT, b, P->w32b, LAYOUT_PT, b, d2, 2, m[2], P->T[2], nv, P->cscale), s));
+  return KA_OK;   // result in w32b
+}
+
+int apply_block(Problem* P, int form, const double* X, int64_t ldx, double* Y, int64_t ldy, int nv, hipStream_t s) {
+  const int b = P->b;
+  const int* n = P->n;
+  const int64_t N = P->N;
+  int rc;
+  if (P->d.method == KA_GALERKIN_IBQ) {
+    const double* src = X;
+    int64_t lds = ldx;
+    if (form == KA_APRIME) {                       // step 1: L^-T
+      if ((rc = kron64(P, P->LinvT, X, ldx, P->w64a, N, nv, s))) return rc;
+      // kron64 used w64a as scratch for mode 1; its result went to w64a via Y argument
+      src = P->w64a;
+      lds = N;
+    }
+    // steps 2-4: M, B~^-T, J  (fused as B~^-T M per direction, J on the last store)
+    if ((rc = forward_transfer(P, src, lds, nv, s))) return rc;
+    // steps 5-6: Gamma, J
+    if ((rc = gamma_step(P, P->w32b, P->w32a, s))) return rc;
+    // steps 7-8: B~^-1, M^T  (as M^T B~^-1 per direction)
+    const int* m = P->nt;
+    int d0[3] = {m[0], m[1], m[2]};
+    HIP_TRY(launch_mode_f32(mode_args(P->w32a, LAYOUT_PT, b, P->w32b, LAYOUT_PT, b, d0, 0, n[0], P->TT[0], nv, nullptr), s));
+    int d1[3] = {n[0], m[1], m[2]};
+    HIP_TRY(launch_mode_f32(mode_args(P->w32b, LAYOUT_PT, b, P->w32a, LAYOUT_PT, b, d1, 1, n[1], P->TT[1], nv, nullptr), s));
+    int d2[3] = {n[0], n[1], m[2]};
+    if (form == KA_APRIME) {
+      HIP_TRY(launch_mode_f32_to_f64(mode_args(P->w32a, LAYOUT_PT, b, P->w64b, LAYOUT_COL, N, d2, 2, n[2], P->TT[2], nv, nullptr), s));
+      // step 9: L^-1
+      const int nn[3] = {n[0], n[1], n[2]};
+      HIP_TRY(launch_mode_f64(mode_args(P->w64b, LAYOUT_COL, N, P->w64a, LAYOUT_COL, N, nn, 0, n[0], P->Linv[0], nv, nullptr), s));
+      HIP_TRY(launch_mode_f64(mode_args(P->w64a, LAYOUT_COL, N, P->w64b, LAYOUT_COL, N, nn, 1, n[1], P->Linv[1], nv, nullptr), s));
+      HIP_TRY(launch_mode_f64(mode_args(P->w64b, LAYOUT_COL, N, Y, LAYOUT_COL, ldy, nn, 2, n[2], P->Linv[2], nv, nullptr), s));
+    } else {
+      HIP_TRY(launch_mode_f32_to_f64(mode_args(P->w32a, LAYOUT_PT, b, Y, LAYOUT_COL, ldy, d2, 2, n[2], P->TT[2], nv, nullptr), s));
+    }
+    return KA_OK;
+  }
+  // collocation, Algorithm 1: steps 1-2 (R_q, J W), step 3 (Gamma), step 4 (Z^-1)
+  if ((rc = forward_transfer(P, X, ldx, nv, s))) return rc;
+  if ((rc = gamma_step(P, P->w32b, P->w32a, s))) return rc;
+  const int nn[3] = {n[0], n[1], n[2]};
+  if (form == KA_APRIME) {
+    HIP_TRY(launch_mode_f32in_f64(mode_args(P->w32a, LAYOUT_PT, b, P->w64a, LAYOUT_COL, N, nn, 0, n[0], P->Zinv[0], nv, nullptr), s));
+    HIP_TRY(launch_mode_f64(mode_args(P->w64a, LAYOUT_COL, N, P->w64b, LAYOUT_COL, N, nn, 1, n[1], P->Zinv[1], nv, nullptr), s));
+    HIP_TRY(launch_mode_f64(mode_args(P->w64b, LAYOUT_COL, N, Y, LAYOUT_COL, ldy, nn, 2, n[2], P->Zinv[2], nv, nullptr), s));
+  } else {
+    HIP_TRY(cast_pt32_to_col64(P->w32a, b, Y, ldy, N, nv, s));
+  }
+  return KA_OK;
+}
+
+int solve_block(Problem* P, int op, double* X, int64_t ld, int nv, hipStream_t s) {
+  if (op == KA_ZINV) return kron64(P, P->Zinv, X, ld, X, ld, nv, s);
+  if (P->d.method != KA_GALERKIN_IBQ) return fail(KA_ERR_STATE, "L solves exist for the Galerkin method only");
+  if (op == KA_LINV) return kron64(P, P->Linv, X, ld, X, ld, nv, s);
+  if (op == KA_LTINV) return kron64(P, P->LinvT, X, ld, X, ld, nv, s);
+  return fail(KA_ERR_ARG, "bad solve op");
+}
+
+}  // namespace ka
+
+namespace ka {
+int setup_problem(const ka_desc* d, hipStream_t stream, Problem** out) { return setup_impl(d, stream, out); }
+
+int footprint(const ka_desc* d, size_t* bytes) {
+  Sizes z;
+  int rc = check_desc(d, z);
+  if (rc) return rc;
+  *bytes = setup_bytes(d, z);
+  return KA_OK;
+}
+
+void destroy_problem(Problem* P) { free_problem(P); }
+}  // namespace ka

@@ -1,0 +1,516 @@
+// FP64 dense kernels of the block eigensolver: tall-skinny products for the
+// block orthogonalisation and Rayleigh-Ritz projection, Cholesky-QR of a
+// block, the small dense symmetric eigensolve (parallel cyclic Jacobi), column
+// norms, residual assembly, sign normalisation and a counter-based normal
+// generator for start blocks.  All reductions use a fixed partition and a
+// fixed summation order, so results depend only on the shapes.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "ka_internal.hpp"
+
+namespace ka {
+
+// ---------------------------------------------------------------------------
+// tiled FP64 products: 64 x 64 output tile, 256 threads, 4 x 4 per thread
+// ---------------------------------------------------------------------------
+constexpr int TM = 64, TN = 64, TK = 16;
+
+// TRANS_A: C_part(m x n) = A[k0:k1, :]^T B[k0:k1, :], A is K x m (lda).
+// else:    C(M x n) = alpha A B + beta C, A is M x k (lda).
+template <bool TRANS_A>
+__global__ __launch_bounds__(256) void dgemm_tile_kernel(int64_t M, int n, int64_t K, const double* __restrict__ A,
+                                                         int64_t lda, const double* __restrict__ B, int64_t ldb,
+                                                         double* __restrict__ C, int64_t ldc, double alpha,
+                                                         double beta, int64_t k_per_split) {
+  __shared__ double sA[TK][TM + 1];
+  __shared__ double sB[TK][TN + 1];
+  const int tid = threadIdx.x;
+  const int tx = tid % 16, ty = tid / 16;
+  const int64_t i0 = (int64_t)blockIdx.x * TM;
+  const int j0 = blockIdx.y * TN;
+  const int64_t kb = TRANS_A ? (int64_t)blockIdx.z * k_per_split : 0;
+  const int64_t ke = TRANS_A ? ((kb + k_per_split < K) ? kb + k_per_split : K) : K;
+  double acc[4][4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
+
+  for (int64_t k0 = kb; k0 < ke; k0 += TK) {
+    // A tile -> sA[kk][i]
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      if (TRANS_A) {
+        const int kk = tid % 16, ii = tid / 16 + 16 * r;
+        const int64_t k = k0 + kk, i = i0 + ii;
+        sA[kk][ii] = (k < ke && i < M) ? A[k + i * lda] : 0.0;
+      } else {
+        const int ii = tid % 64, kk = tid / 64 + 4 * r;
+        const int64_t k = k0 + kk, i = i0 + ii;
+        sA[kk][ii] = (k < ke && i < M) ? A[i + k * lda] : 0.0;
+      }
+    }
+    // B tile (K x n, column-major) -> sB[kk][j]
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int kk = tid % 16, jj = tid / 16 + 16 * r;
+      const int64_t k = k0 + kk;
+      const int j = j0 + jj;
+      sB[kk][jj] = (k < ke && j < n) ? B[k + (int64_t)j * ldb] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < TK; ++kk) {
+      double av[4], bv[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) av[u] = sA[kk][tx + 16 * u];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) bv[v] = sB[kk][ty + 16 * v];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[u][v] = __builtin_fma(av[u], bv[v], acc[u][v]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int64_t i = i0 + tx + 16 * u;
+    if (i >= M) continue;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int j = j0 + ty + 16 * v;
+      if (j >= n) continue;
+      if (TRANS_A) {
+        C[((size_t)blockIdx.z * n + j) * M + i] = acc[u][v];   // partial[z][j][i]
+      } else {
+        double* c = C + i + (int64_t)j * ldc;
+        *c = (beta == 0.0) ? alpha * acc[u][v] : alpha * acc[u][v] + beta * *c;
+      }
+    }
+  }
+}
+
+__global__ void split_reduce_kernel(const double* __restrict__ part, int nsplit, int m, int n, double alpha,
+                                    double beta, double* __restrict__ C, int64_t ldc) {
+  const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= (int64_t)m * n) return;
+  const int i = (int)(id % m), j = (int)(id / m);
+  double s = 0.0;
+  for (int z = 0; z < nsplit; ++z) s += part[((size_t)z * n + j) * m + i];
+  double* c = C + i + (int64_t)j * ldc;
+  *c = (beta == 0.0) ? alpha * s : alpha * s + beta * *c;
+}
+
+static int tn_splits(int m, int n, int64_t K) {
+  const int64_t tiles = (int64_t)((m + TM - 1) / TM) * ((n + TN - 1) / TN);
+  int64_t ns = (512 + tiles - 1) / tiles;
+  const int64_t by_k = K / 512;
+  if (ns > by_k) ns = by_k;
+  if (ns > 256) ns = 256;
+  if (ns < 1) ns = 1;
+  return (int)ns;
+}
+
+size_t dgemm_tn_work(int m, int n, int64_t K) { return (size_t)tn_splits(m, n, K) * m * n; }
+
+hipError_t dgemm_tn(int m, int n, int64_t K, double alpha, const double* A, int64_t lda, const double* B,
+                    int64_t ldb, double beta, double* C, int64_t ldc, double* work, hipStream_t s) {
+  if (m <= 0 || n <= 0) return hipSuccess;
+  const int ns = tn_splits(m, n, K);
+  int64_t kps = (K + ns - 1) / ns;
+  kps = (kps + TK - 1) / TK * TK;
+  const dim3 grid((m + TM - 1) / TM, (n + TN - 1) / TN, ns);
+  hipLaunchKernelGGL((dgemm_tile_kernel<true>), grid, dim3(256), 0, s, (int64_t)m, n, K, A, lda, B, ldb, work,
+                     (int64_t)m, 1.0, 0.0, kps);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int64_t tot = (int64_t)m * n;
+  hipLaunchKernelGGL(split_reduce_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, work, ns, m, n,
+                     alpha, beta, C, ldc);
+  return hipGetLastError();
+}
+
+hipError_t dgemm_nn(int64_t M, int n, int k, double alpha, const double* A, int64_t lda, const double* B,
+                    int64_t ldb, double beta, double* C, int64_t ldc, hipStream_t s) {
+  if (M <= 0 || n <= 0) return hipSuccess;
+  const dim3 grid((unsigned)((M + TM - 1) / TM), (n + TN - 1) / TN, 1);
+  hipLaunchKernelGGL((dgemm_tile_kernel<false>), grid, dim3(256), 0, s, M, n, (int64_t)k, A, lda, B, ldb, C, ldc,
+                     alpha, beta, (int64_t)0);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Cholesky of a small SPD Gram matrix G = R^T R and R^-1 (upper), n <= 64.
+// status: 0 ok, 1 a pivot was not positive or lost (rank-deficient block).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(64) void chol_upper_inv_kernel(const double* __restrict__ G, int n, int ldg,
+                                                            double* __restrict__ Rinv, int ldr, int* status) {
+  __shared__ double R[64][65];
+  __shared__ double X[64][65];
+  __shared__ int bad;
+  __shared__ double piv;
+  const int t = threadIdx.x;
+  if (t == 0) bad = 0;
+  for (int i = 0; i < n; ++i) R[i][t] = (t < n) ? G[i + t * ldg] : 0.0;   // R holds G (symmetric)
+  __syncthreads();
+  for (int j = 0; j < n; ++j) {
+    // row j of R: R[j][j] = sqrt(G_jj - sum_k R_kj^2), R[j][i] = (G_ji - sum_k R_kj R_ki) / R_jj
+    if (t == 0) {
+      double d = R[j][j];
+      for (int k = 0; k < j; ++k) d -= R[k][j] * R[k][j];
+      const double orig = G[j + j * ldg];
+      if (!(d > 1e-26 * orig) || !(orig > 1e-300)) {
+        bad = 1;
+        d = 1.0;
+      }
+      piv = sqrt(d);
+    }
+    __syncthreads();
+    if (t > j && t < n) {
+      double sv = R[j][t];
+      for (int k = 0; k < j; ++k) sv -= R[k][j] * R[k][t];
+      R[j][t] = sv / piv;
+    }
+    __syncthreads();
+    if (t == 0) R[j][j] = piv;
+    __syncthreads();
+  }
+  // zero strict lower part (it held G)
+  for (int i = 0; i < n; ++i)
+    if (t < i) R[i][t] = 0.0;
+  __syncthreads();
+  // X = R^-1, column t by back substitution: R x = e_t
+  if (t < n) {
+    for (int i = n - 1; i >= 0; --i) {
+      double sv = (i == t) ? 1.0 : 0.0;
+      for (int k = i + 1; k < n; ++k) sv -= R[i][k] * X[k][t];
+      X[i][t] = (i > t) ? 0.0 : sv / R[i][i];
+    }
+  }
+  __syncthreads();
+  for (int i = 0; i < n; ++i)
+    if (t < n) Rinv[i + t * ldr] = X[i][t];
+  if (t == 0) *status = bad;
+}
+
+hipError_t chol_upper_inv(const double* G, int n, int ldg, double* Rinv, int ldr, int* status, hipStream_t s) {
+  if (n > 64) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(chol_upper_inv_kernel, dim3(1), dim3(64), 0, s, G, n, ldg, Rinv, ldr, status);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Symmetric eigensolve by parallel cyclic Jacobi (round-robin pairing), one
+// workgroup.  A (n x n) is copied to `work`; eigenvectors accumulate in S.
+// Output: theta descending, S columns in the same order.
+// ---------------------------------------------------------------------------
+constexpr int kEigThreads = 1024;
+constexpr int kEigMax = 1024;
+
+size_t sym_eig_work(int n) {
+  const int ne = n + (n & 1);
+  return (size_t)ne * ne * 2 + 4 * (size_t)ne;
+}
+
+__global__ __launch_bounds__(kEigThreads) void jacobi_kernel(const double* __restrict__ H, int n, int ldh,
+                                                              double* __restrict__ theta, double* __restrict__ S,
+                                                              int lds, double* __restrict__ work) {
+  const int ne = n + (n & 1);       // even size (a dummy index when n is odd)
+  double* A = work;                 // ne x ne, column-major
+  double* V = work + (size_t)ne * ne;
+  double* tmpv = work + (size_t)2 * ne * ne;
+  __shared__ int top[kEigMax / 2], bot[kEigMax / 2];
+  __shared__ double cs[kEigMax / 2], sn[kEigMax / 2];
+  __shared__ double red[kEigThreads];
+  __shared__ int done;
+  const int t = threadIdx.x, nt = blockDim.x;
+  const int half = ne / 2;
+  for (int64_t e = t; e < (int64_t)ne * ne; e += nt) {
+    const int i = (int)(e % ne), j = (int)(e / ne);
+    A[e] = (i < n && j < n) ? 0.5 * (H[i + (int64_t)j * ldh] + H[j + (int64_t)i * ldh]) : 0.0;
+    V[e] = (i == j) ? 1.0 : 0.0;
+  }
+  for (int k = t; k < half; k += nt) {
+    top[k] = 2 * k;
+    bot[k] = 2 * k + 1;
+  }
+  __syncthreads();
+  for (int sweep = 0; sweep < 40; ++sweep) {
+    // convergence test: off-diagonal vs total Frobenius norm
+    double off = 0.0, tot = 0.0;
+    for (int64_t e = t; e < (int64_t)ne * ne; e += nt) {
+      const int i = (int)(e % ne), j = (int)(e / ne);
+      const double a2 = A[e] * A[e];
+      tot += a2;
+      if (i != j) off += a2;
+    }
+    red[t] = off;
+    __syncthreads();
+    for (int w = nt / 2; w > 0; w >>= 1) {
+      if (t < w) red[t] += red[t + w];
+      __syncthreads();
+    }
+    const double offs = red[0];
+    __syncthreads();
+    red[t] = tot;
+    __syncthreads();
+    for (int w = nt / 2; w > 0; w >>= 1) {
+      if (t < w) red[t] += red[t + w];
+      __syncthreads();
+    }
+    if (t == 0) done = (offs <= 1e-30 * red[0]) || red[0] == 0.0;
+    __syncthreads();
+    if (done) break;
+    for (int round = 0; round < ne - 1; ++round) {
+      for (int k = t; k < half; k += nt) {
+        const int p = min(top[k], bot[k]), q = max(top[k], bot[k]);
+        const double apq = A[p + (int64_t)q * ne];
+        const double app = A[p + (int64_t)p * ne], aqq = A[q + (int64_t)q * ne];
+        double c = 1.0, s = 0.0;
+        if (apq != 0.0 && fabs(apq) > 1e-300) {
+          const double tau = (aqq - app) / (2.0 * apq);
+          const double tt = (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+          c = 1.0 / sqrt(1.0 + tt * tt);
+          s = tt * c;
+        }
+        cs[k] = c;
+        sn[k] = s;
+      }
+      __syncthreads();
+      // rows: A <- J^T A
+      for (int64_t e = t; e < (int64_t)half * ne; e += nt) {
+        const int k = (int)(e % half), l = (int)(e / half);
+        const int p = min(top[k], bot[k]), q = max(top[k], bot[k]);
+        const double c = cs[k], s = sn[k];
+        if (s == 0.0) continue;
+        const double ap = A[p + (int64_t)l * ne], aq = A[q + (int64_t)l * ne];
+        A[p + (int64_t)l * ne] = c * ap - s * aq;
+        A[q + (int64_t)l * ne] = s * ap + c * aq;
+      }
+      __syncthreads();
+      // columns: A <- A J, V <- V J
+      for (int64_t e = t; e < (int64_t)half * ne; e += nt) {
+        const int l = (int)(e % ne), k = (int)(e / ne);
+        const int p = min(top[k], bot[k]), q = max(top[k], bot[k]);
+        const double c = cs[k], s = sn[k];
+        if (s == 0.0) continue;
+        const double ap = A[l + (int64_t)p * ne], aq = A[l + (int64_t)q * ne];
+        A[l + (int64_t)p * ne] = c * ap - s * aq;
+        A[l + (int64_t)q * ne] = s * ap + c * aq;
+        const double vp = V[l + (int64_t)p * ne], vq = V[l + (int64_t)q * ne];
+        V[l + (int64_t)p * ne] = c * vp - s * vq;
+        V[l + (int64_t)q * ne] = s * vp + c * vq;
+      }
+      __syncthreads();
+      // round-robin rotation: top[0] fixed
+      if (t == 0 && half > 1) {
+        const int last_top = top[half - 1];
+        const int first_bot = bot[0];
+        for (int k = half - 1; k > 1; --k) top[k] = top[k - 1];
+        top[1] = first_bot;
+        for (int k = 0; k < half - 1; ++k) bot[k] = bot[k + 1];
+        bot[half - 1] = last_top;
+      }
+      __syncthreads();
+    }
+  }
+  // sort descending (ties by index) over the first n
+  for (int i = t; i < n; i += nt) tmpv[i] = A[i + (int64_t)i * ne];
+  __syncthreads();
+  for (int i = t; i < n; i += nt) {
+    const double di = tmpv[i];
+    int rank = 0;
+    for (int j = 0; j < n; ++j) {
+      const double dj = tmpv[j];
+      if (dj > di || (dj == di && j < i)) ++rank;
+    }
+    theta[rank] = di;
+    for (int l = 0; l < n; ++l) S[l + (int64_t)rank * lds] = V[l + (int64_t)i * ne];
+  }
+}
+
+hipError_t sym_eig(const double* H, int n, int ldh, double* theta, double* S, int lds, double* work,
+                   hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  if (n > kEigMax - 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(jacobi_kernel, dim3(1), dim3(kEigThreads), 0, s, H, n, ldh, theta, S, lds, work);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// column norms (two-stage, fixed order)
+// ---------------------------------------------------------------------------
+constexpr int kNormChunk = 4096;
+
+size_t column_norms_work(int64_t N, int n) { return (size_t)((N + kNormChunk - 1) / kNormChunk) * n; }
+
+__global__ __launch_bounds__(256) void colnorm_partial_kernel(const double* __restrict__ X, int64_t N,
+                                                              int64_t ldx, double* __restrict__ part) {
+  __shared__ double red[256];
+  const int j = blockIdx.y;
+  const int64_t c0 = (int64_t)blockIdx.x * kNormChunk;
+  double s = 0.0;
+  for (int64_t i = c0 + threadIdx.x; i < c0 + kNormChunk && i < N; i += 256) {
+    const double v = X[i + (int64_t)j * ldx];
+    s += v * v;
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[(size_t)j * gridDim.x + blockIdx.x] = red[0];
+}
+
+__global__ void colnorm_final_kernel(const double* __restrict__ part, int nchunk, int n, double* __restrict__ out) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  double s = 0.0;
+  for (int c = 0; c < nchunk; ++c) s += part[(size_t)j * nchunk + c];
+  out[j] = sqrt(s);
+}
+
+hipError_t column_norms(const double* X, int64_t N, int n, int64_t ldx, double* out, double* work, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const int nchunk = (int)((N + kNormChunk - 1) / kNormChunk);
+  hipLaunchKernelGGL(colnorm_partial_kernel, dim3(nchunk, n), dim3(256), 0, s, X, N, ldx, work);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(colnorm_final_kernel, dim3((n + 63) / 64), dim3(64), 0, s, work, nchunk, n, out);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// misc elementwise
+// ---------------------------------------------------------------------------
+// SplitMix64 (Steele, Lea & Flood 2014) as a counter-based hash.
+__device__ __forceinline__ uint64_t splitmix64(uint64_t z) {
+  z += 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+__global__ void fill_normal_kernel(double* X, int64_t N, int n, int64_t ldx, uint64_t seed, uint64_t counter) {
+  const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= N * n) return;
+  const int64_t i = id % N, j = id / N;
+  const uint64_t key = splitmix64(seed ^ splitmix64(counter + 0x632BE59BD9B4E019ull * (uint64_t)j));
+  const uint64_t h1 = splitmix64(key + 2 * (uint64_t)i), h2 = splitmix64(key + 2 * (uint64_t)i + 1);
+  const double u1 = ((h1 >> 11) + 0.5) * (1.0 / 9007199254740992.0);
+  const double u2 = (h2 >> 11) * (1.0 / 9007199254740992.0);
+  X[i + j * ldx] = sqrt(-2.0 * log(u1)) * cos(2.0 * M_PI * u2);   // Box-Muller
+}
+
+hipError_t fill_normal(double* X, int64_t N, int n, int64_t ldx, uint64_t seed, uint64_t counter, hipStream_t s) {
+  const int64_t tot = N * n;
+  if (tot == 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_normal_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, X, N, n, ldx, seed,
+                     counter);
+  return hipGetLastError();
+}
+
+__global__ void copy_cols_kernel(const double* X, int64_t ldx, double* Y, int64_t ldy, int64_t N, int n) {
+  const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= N * n) return;
+  const int64_t i = id % N, j = id / N;
+  Y[i + j * ldy] = X[i + j * ldx];
+}
+
+hipError_t copy_cols(const double* X, int64_t ldx, double* Y, int64_t ldy, int64_t N, int n, hipStream_t s) {
+  const int64_t tot = N * n;
+  if (tot == 0) return hipSuccess;
+  hipLaunchKernelGGL(copy_cols_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, X, ldx, Y, ldy, N, n);
+  return hipGetLastError();
+}
+
+// R = A X s - lambda X s for real and complex-pair Ritz values.
+__global__ void residual_kernel(const double* AXS, const double* XS, int64_t N, int n, int64_t ld, const double* wr,
+                                const double* wi, double* R) {
+  const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= N * n) return;
+  const int64_t i = id % N;
+  const int j = (int)(id / N);
+  const double lr = wr[j], li = wi ? wi[j] : 0.0;
+  double r = AXS[i + j * ld] - lr * XS[i + j * ld];
+  if (li > 0.0 && j + 1 < n) r += li * XS[i + (j + 1) * ld];        // real part of a pair
+  else if (li < 0.0 && j > 0) r += li * XS[i + (j - 1) * ld];       // imaginary part: - |li| x_r
+  R[i + j * ld] = r;
+}
+
+hipError_t residual_combine(const double* AXS, const double* XS, int64_t N, int n, int64_t ld, const double* wr,
+                            const double* wi, double* R, hipStream_t s) {
+  const int64_t tot = N * n;
+  if (tot == 0) return hipSuccess;
+  hipLaunchKernelGGL(residual_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, AXS, XS, N, n, ld, wr,
+                     wi, R);
+  return hipGetLastError();
+}
+
+// sign: make the first largest-magnitude entry of each column positive
+__global__ __launch_bounds__(256) void sign_fix_kernel(double* V, int64_t N, int64_t ld) {
+  __shared__ double bv[256];
+  __shared__ int64_t bi[256];
+  const int j = blockIdx.x;
+  double best = -1.0;
+  int64_t besti = 0;
+  for (int64_t i = threadIdx.x; i < N; i += 256) {
+    const double a = fabs(V[i + j * ld]);
+    if (a > best) { best = a; besti = i; }
+  }
+  bv[threadIdx.x] = best;
+  bi[threadIdx.x] = besti;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) {
+      const double o = bv[threadIdx.x + w];
+      const int64_t oi = bi[threadIdx.x + w];
+      if (o > bv[threadIdx.x] || (o == bv[threadIdx.x] && oi < bi[threadIdx.x])) {
+        bv[threadIdx.x] = o;
+        bi[threadIdx.x] = oi;
+      }
+    }
+    __syncthreads();
+  }
+  const bool neg = V[bi[0] + j * ld] < 0.0;
+  if (neg)
+    for (int64_t i = threadIdx.x; i < N; i += 256) V[i + j * ld] = -V[i + j * ld];
+}
+
+hipError_t sign_fix(double* V, int64_t N, int n, int64_t ld, double* work, hipStream_t s) {
+  (void)work;
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(sign_fix_kernel, dim3(n), dim3(256), 0, s, V, N, ld);
+  return hipGetLastError();
+}
+
+__global__ void scale_cols_kernel(double* V, int64_t N, int n, int64_t ld, const double* scale) {
+  const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= N * n) return;
+  const int64_t i = id % N;
+  const int j = (int)(id / N);
+  V[i + j * ld] *= scale[j];
+}
+
+hipError_t scale_cols(double* V, int64_t N, int n, int64_t ld, const double* scale, hipStream_t s) {
+  const int64_t tot = N * n;
+  if (tot == 0) return hipSuccess;
+  hipLaunchKernelGGL(scale_cols_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, V, N, n, ld, scale);
+  return hipGetLastError();
+}
+
+__global__ void fill_zero_f32_kernel(float* p, int64_t n) {
+  const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id < n) p[id] = 0.f;
+}
+
+hipError_t fill_zero_f32(float* p, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_zero_f32_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n);
+  return hipGetLastError();
+}
+
+}  // namespace ka

@@ -1,0 +1,409 @@
+// Fused covariance-kernel product Z = out_scale * diag(rs) * Gamma * Y with
+// Gamma[r][c] = exp2(-s(xr_r - xc_c)) evaluated on the fly and never stored.
+//
+// This is the quadratic-cost step of both matrix-free operators: the Gamma
+// product of the Galerkin nine-step algorithm (paper Sec. 3.1) and step 3 of
+// Algorithm 1 (paper Sec. 3.2).  Coordinates are prescaled so that the kernel
+// is a bare exp2:
+//   Gaussian     s = |d|_2^2  with coordinates scaled by sqrt(log2 e) / ell,
+//   exponential  s = |d|_1    with coordinates scaled by log2 e / ell.
+//
+// Work decomposition (gfx950, wave64):
+//   * a workgroup of 4 waves owns 4*16*RB consecutive rows; each wave owns RB
+//     16-row sub-blocks whose coordinates live in registers;
+//   * columns stream through LDS in tiles of CT points (coordinates + the
+//     matching rows of Y), double buffered, one barrier per tile;
+//   * per MFMA step every lane evaluates the kernel for its (row, column)
+//     slots straight into the A-operand register(s) of the matrix core; the
+//     B operand is the matching slice of Y; accumulators stay in AGPRs;
+//   * FP32 path: v_mfma_f32_16x16x4_f32, one pair per lane per step, B/16
+//     MFMAs per pair (one per 16 columns of Y);
+//   * BF16x3 path: v_mfma_f32_16x16x32_bf16, eight pairs per lane per step,
+//     Gamma and Y split into hi + lo BF16 parts, products hi*hi + hi*lo +
+//     lo*hi accumulated in FP32;
+//   * the column range is split over gridDim.y (split-K) when there are too
+//     few row blocks to fill the chip; partial results go to a scratch array
+//     and are summed in a fixed split order, so results depend only on the
+//     shape, never on what else runs on the device.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "ka_internal.hpp"
+
+namespace ka {
+
+typedef float f4v __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
+typedef __bf16 bf2v __attribute__((ext_vector_type(2)));
+
+constexpr int kThreads = 256;
+constexpr int kCT = 64;   // columns per LDS tile
+
+template <int KERNEL>
+__device__ __forceinline__ float pair_exponent(float dx, float dy, float dz) {
+  if constexpr (KERNEL == KA_GAUSSIAN) {
+    float s = dx * dx;
+    s = __builtin_fmaf(dy, dy, s);
+    return __builtin_fmaf(dz, dz, s);
+  } else {
+    return (__builtin_fabsf(dx) + __builtin_fabsf(dy)) + __builtin_fabsf(dz);
+  }
+}
+
+__device__ __forceinline__ float load_coord(const float* p, int64_t i, int stride, int k, float scale) {
+  return p[i * stride + k] * scale;
+}
+
+// ---------------------------------------------------------------------------
+// FP32 path
+// ---------------------------------------------------------------------------
+template <int KERNEL, int B, int RB>
+__global__ __launch_bounds__(kThreads) void gamma_f32_kernel(GammaLaunch a) {
+  constexpr int NT = B / 16;
+  constexpr int YS = (B == 16) ? 16 : B + 16;   // LDS row stride of Y (bank spread)
+  constexpr int ROWS = 4 * 16 * RB;
+  __shared__ float4 s_x[2][kCT];
+  __shared__ float s_y[2][kCT * YS];
+
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int64_t row0 = (int64_t)blockIdx.x * ROWS + wave * 16 * RB;
+  const int64_t c_begin = (int64_t)blockIdx.y * a.cols_per_split;
+  const int64_t c_end = (c_begin + a.cols_per_split < a.nc) ? c_begin + a.cols_per_split : a.nc;
+
+  float rx[RB], ry[RB], rz[RB];
+#pragma unroll
+  for (int rb = 0; rb < RB; ++rb) {
+    int64_t r = row0 + 16 * rb + (lane & 15);
+    if (r >= a.nr) r = a.nr - 1;
+    rx[rb] = load_coord(a.xr, r, a.xr_stride, 0, a.coord_scale);
+    ry[rb] = load_coord(a.xr, r, a.xr_stride, 1, a.coord_scale);
+    rz[rb] = load_coord(a.xr, r, a.xr_stride, 2, a.coord_scale);
+  }
+
+  f4v acc[RB][NT];
+#pragma unroll
+  for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[rb][t] = (f4v){0.f, 0.f, 0.f, 0.f};
+
+  // per-thread staging registers for one tile
+  constexpr int YV = kCT * B / 4 / kThreads;   // float4 of Y per thread per tile
+  float4 ybuf[YV];
+  float4 xbuf;
+
+  auto fetch = [&](int64_t ct) {
+#pragma unroll
+    for (int v = 0; v < YV; ++v) {
+      const int e = (threadIdx.x + v * kThreads) * 4;   // element in tile (b fastest)
+      const int64_t c = ct + e / B;
+      ybuf[v] = (c < c_end) ? *reinterpret_cast<const float4*>(a.Y + c * B + (e % B))
+                            : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+    if (threadIdx.x < kCT) {
+      const int64_t c = ct + threadIdx.x;
+      if (c < c_end)
+        xbuf = make_float4(load_coord(a.xc, c, a.xc_stride, 0, a.coord_scale),
+                           load_coord(a.xc, c, a.xc_stride, 1, a.coord_scale),
+                           load_coord(a.xc, c, a.xc_stride, 2, a.coord_scale), 0.f);
+      else
+        xbuf = make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+  };
+  auto stash = [&](int buf) {
+#pragma unroll
+    for (int v = 0; v < YV; ++v) {
+      const int e = (threadIdx.x + v * kThreads) * 4;
+      float* dst = &s_y[buf][(e / B) * YS + (e % B)];
+      dst[0] = ybuf[v].x; dst[1] = ybuf[v].y; dst[2] = ybuf[v].z; dst[3] = ybuf[v].w;
+    }
+    if (threadIdx.x < kCT) s_x[buf][threadIdx.x] = xbuf;
+  };
+
+  int buf = 0;
+  if (c_begin < c_end) {
+    fetch(c_begin);
+    stash(0);
+  }
+  __syncthreads();
+  for (int64_t ct = c_begin; ct < c_end; ct += kCT) {
+    const bool more = ct + kCT < c_end;
+    if (more) fetch(ct + kCT);
+#pragma unroll 2
+    for (int k = 0; k < kCT; k += 4) {
+      const int c = k + (lane >> 4);
+      const float4 p = s_x[buf][c];
+      float yv[NT];
+#pragma unroll
+      for (int t = 0; t < NT; ++t) yv[t] = s_y[buf][c * YS + 16 * t + (lane & 15)];
+#pragma unroll
+      for (int rb = 0; rb < RB; ++rb) {
+        const float g = __builtin_amdgcn_exp2f(-pair_exponent<KERNEL>(rx[rb] - p.x, ry[rb] - p.y, rz[rb] - p.z));
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+          acc[rb][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(g, yv[t], acc[rb][t], 0, 0, 0);
+      }
+    }
+    if (more) stash(buf ^ 1);
+    __syncthreads();
+    buf ^= 1;
+  }
+
+  float* out = a.nsplit > 1 ? a.partial + (size_t)blockIdx.y * a.nr * B : a.Z;
+#pragma unroll
+  for (int rb = 0; rb < RB; ++rb) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int64_t row = row0 + 16 * rb + 4 * (lane >> 4) + r;
+      if (row < a.nr) {
+        const float sc = a.out_scale * (a.rs ? a.rs[row] : 1.0f);
+#pragma unroll
+        for (int t = 0; t < NT; ++t) out[row * B + 16 * t + (lane & 15)] = sc * acc[rb][t][r];
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// split hi/lo BF16 path
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t pack_bf16x2(float lo_elem, float hi_elem) {
+  bf2v h = {(__bf16)lo_elem, (__bf16)hi_elem};
+  return __builtin_bit_cast(uint32_t, h);
+}
+
+// Split two FP32 values into packed BF16 hi and lo words (round to nearest
+// even for both; x - hi is exact in FP32).
+__device__ __forceinline__ void split2(float x0, float x1, uint32_t& hi, uint32_t& lo) {
+  hi = pack_bf16x2(x0, x1);
+  const float h0 = __builtin_bit_cast(float, hi << 16);
+  const float h1 = __builtin_bit_cast(float, hi & 0xffff0000u);
+  lo = pack_bf16x2(x0 - h0, x1 - h1);
+}
+
+template <int KERNEL, int B, int RB>
+__global__ __launch_bounds__(kThreads) void gamma_bf16x3_kernel(GammaLaunch a) {
+  constexpr int NT = B / 16;
+  constexpr int KS = kCT / 32;              // MFMA k-steps per tile
+  constexpr int ROWS = 4 * 16 * RB;
+  __shared__ float4 s_x[2][kCT];
+  // B-operand fragments: [k-step][t][lane] -> 4 dwords (8 bf16)
+  __shared__ uint4 s_yh[2][KS * NT * 64];
+  __shared__ uint4 s_yl[2][KS * NT * 64];
+
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int64_t row0 = (int64_t)blockIdx.x * ROWS + wave * 16 * RB;
+  const int64_t c_begin = (int64_t)blockIdx.y * a.cols_per_split;
+  const int64_t c_end = (c_begin + a.cols_per_split < a.nc) ? c_begin + a.cols_per_split : a.nc;
+
+  float rx[RB], ry[RB], rz[RB];
+#pragma unroll
+  for (int rb = 0; rb < RB; ++rb) {
+    int64_t r = row0 + 16 * rb + (lane & 15);
+    if (r >= a.nr) r = a.nr - 1;
+    rx[rb] = load_coord(a.xr, r, a.xr_stride, 0, a.coord_scale);
+    ry[rb] = load_coord(a.xr, r, a.xr_stride, 1, a.coord_scale);
+    rz[rb] = load_coord(a.xr, r, a.xr_stride, 2, a.coord_scale);
+  }
+
+  f4v acc[RB][NT];
+#pragma unroll
+  for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[rb][t] = (f4v){0.f, 0.f, 0.f, 0.f};
+
+  // staging: item = (g8, j): 8 consecutive columns 8*g8..8*g8+7 of Y column j
+  constexpr int ITEMS = (kCT / 8) * B;
+  constexpr int IPT = ITEMS / kThreads;      // items per thread (B=16: 0.5 -> handled below)
+  constexpr int IPT_R = IPT > 0 ? IPT : 1;
+  uint4 hbuf[IPT_R], lbuf[IPT_R];
+  float4 xbuf;
+
+  auto fetch = [&](int64_t ct) {
+#pragma unroll
+    for (int v = 0; v < IPT_R; ++v) {
+      const int item = threadIdx.x + v * kThreads;
+      if (item < ITEMS) {
+        const int g8 = item / B, j = item % B;
+        float y[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int64_t c = ct + 8 * g8 + u;
+          y[u] = (c < c_end) ? a.Y[c * B + j] : 0.f;
+        }
+        split2(y[0], y[1], hbuf[v].x, lbuf[v].x);
+        split2(y[2], y[3], hbuf[v].y, lbuf[v].y);
+        split2(y[4], y[5], hbuf[v].z, lbuf[v].z);
+        split2(y[6], y[7], hbuf[v].w, lbuf[v].w);
+      }
+    }
+    if (threadIdx.x < kCT) {
+      const int64_t c = ct + threadIdx.x;
+      if (c < c_end)
+        xbuf = make_float4(load_coord(a.xc, c, a.xc_stride, 0, a.coord_scale),
+                           load_coord(a.xc, c, a.xc_stride, 1, a.coord_scale),
+                           load_coord(a.xc, c, a.xc_stride, 2, a.coord_scale), 0.f);
+      else
+        xbuf = make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+  };
+  auto stash = [&](int buf) {
+#pragma unroll
+    for (int v = 0; v < IPT_R; ++v) {
+      const int item = threadIdx.x + v * kThreads;
+      if (item < ITEMS) {
+        const int g8 = item / B, j = item % B;
+        const int ks = g8 / 4, grp = g8 % 4, t = j / 16;
+        const int ln = grp * 16 + (j & 15);
+        s_yh[buf][(ks * NT + t) * 64 + ln] = hbuf[v];
+        s_yl[buf][(ks * NT + t) * 64 + ln] = lbuf[v];
+      }
+    }
+    if (threadIdx.x < kCT) s_x[buf][threadIdx.x] = xbuf;
+  };
+
+  int buf = 0;
+  if (c_begin < c_end) {
+    fetch(c_begin);
+    stash(0);
+  }
+  __syncthreads();
+  for (int64_t ct = c_begin; ct < c_end; ct += kCT) {
+    const bool more = ct + kCT < c_end;
+    if (more) fetch(ct + kCT);
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      float4 p[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) p[u] = s_x[buf][ks * 32 + 8 * (lane >> 4) + u];
+      bf8v yh[NT], yl[NT];
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        yh[t] = __builtin_bit_cast(bf8v, s_yh[buf][(ks * NT + t) * 64 + lane]);
+        yl[t] = __builtin_bit_cast(bf8v, s_yl[buf][(ks * NT + t) * 64 + lane]);
+      }
+#pragma unroll
+      for (int rb = 0; rb < RB; ++rb) {
+        float g[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+          g[u] = __builtin_amdgcn_exp2f(-pair_exponent<KERNEL>(rx[rb] - p[u].x, ry[rb] - p[u].y, rz[rb] - p[u].z));
+        uint4 gh, gl;
+        split2(g[0], g[1], gh.x, gl.x);
+        split2(g[2], g[3], gh.y, gl.y);
+        split2(g[4], g[5], gh.z, gl.z);
+        split2(g[6], g[7], gh.w, gl.w);
+        const bf8v ah = __builtin_bit_cast(bf8v, gh);
+        const bf8v al = __builtin_bit_cast(bf8v, gl);
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+          acc[rb][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, yh[t], acc[rb][t], 0, 0, 0);
+          acc[rb][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, yl[t], acc[rb][t], 0, 0, 0);
+          acc[rb][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, yh[t], acc[rb][t], 0, 0, 0);
+        }
+      }
+    }
+    if (more) stash(buf ^ 1);
+    __syncthreads();
+    buf ^= 1;
+  }
+
+  float* out = a.nsplit > 1 ? a.partial + (size_t)blockIdx.y * a.nr * B : a.Z;
+#pragma unroll
+  for (int rb = 0; rb < RB; ++rb) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int64_t row = row0 + 16 * rb + 4 * (lane >> 4) + r;
+      if (row < a.nr) {
+        const float sc = a.out_scale * (a.rs ? a.rs[row] : 1.0f);
+#pragma unroll
+        for (int t = 0; t < NT; ++t) out[row * B + 16 * t + (lane & 15)] = sc * acc[rb][t][r];
+      }
+    }
+  }
+}
+
+// Sum of split-K partials in fixed order: Z = sum_s partial[s].
+__global__ void gamma_reduce_kernel(const float* __restrict__ partial, int nsplit, int64_t n,
+                                    float* __restrict__ Z) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  float s = 0.f;
+  for (int k = 0; k < nsplit; ++k) s += partial[(size_t)k * n + i];
+  Z[i] = s;
+}
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+static int rows_per_block(int b, int precision) {
+  (void)precision;
+  return 4 * 16 * (b == 64 ? 2 : 4);
+}
+
+GammaPlan gamma_plan(int64_t nr, int64_t nc, int b, int precision) {
+  GammaPlan p;
+  p.rows_per_block = rows_per_block(b, precision);
+  p.row_blocks = (nr + p.rows_per_block - 1) / p.rows_per_block;
+  // Fill the chip: aim for >= 2048 workgroups, but keep >= 2048 columns per
+  // split so the partial-sum traffic stays small next to the pair work.
+  const int64_t target = 2048;
+  int64_t ns = (target + p.row_blocks - 1) / p.row_blocks;
+  const int64_t max_by_cols = nc / 2048;
+  if (ns > max_by_cols) ns = max_by_cols;
+  if (ns > 64) ns = 64;
+  if (ns < 1) ns = 1;
+  int64_t cps = (nc + ns - 1) / ns;
+  cps = (cps + kCT - 1) / kCT * kCT;
+  ns = (nc + cps - 1) / cps;
+  if (ns < 1) ns = 1;
+  p.nsplit = (int)ns;
+  p.cols_per_split = cps;
+  p.partial_bytes = ns > 1 ? (size_t)ns * nr * b * sizeof(float) : 0;
+  return p;
+}
+
+template <int KERNEL>
+static hipError_t launch_kernel_variant(const GammaLaunch& a, int b, int precision, dim3 grid,
+                                        hipStream_t s) {
+  if (precision == KA_FP32) {
+    switch (b) {
+      case 16: hipLaunchKernelGGL((gamma_f32_kernel<KERNEL, 16, 4>), grid, dim3(kThreads), 0, s, a); break;
+      case 32: hipLaunchKernelGGL((gamma_f32_kernel<KERNEL, 32, 4>), grid, dim3(kThreads), 0, s, a); break;
+      case 64: hipLaunchKernelGGL((gamma_f32_kernel<KERNEL, 64, 2>), grid, dim3(kThreads), 0, s, a); break;
+      default: return hipErrorInvalidValue;
+    }
+  } else {
+    switch (b) {
+      case 16: hipLaunchKernelGGL((gamma_bf16x3_kernel<KERNEL, 16, 4>), grid, dim3(kThreads), 0, s, a); break;
+      case 32: hipLaunchKernelGGL((gamma_bf16x3_kernel<KERNEL, 32, 4>), grid, dim3(kThreads), 0, s, a); break;
+      case 64: hipLaunchKernelGGL((gamma_bf16x3_kernel<KERNEL, 64, 2>), grid, dim3(kThreads), 0, s, a); break;
+      default: return hipErrorInvalidValue;
+    }
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_gamma(GammaLaunch a, int kernel, int b, int precision, hipStream_t s) {
+  if (a.nr <= 0) return hipSuccess;
+  const GammaPlan p = gamma_plan(a.nr, a.nc, b, precision);
+  a.nsplit = p.nsplit;
+  a.cols_per_split = p.cols_per_split;
+  if (a.nc <= 0) {
+    return hipMemsetAsync(a.Z, 0, (size_t)a.nr * b * sizeof(float), s);
+  }
+  const dim3 grid((unsigned)p.row_blocks, (unsigned)p.nsplit);
+  hipError_t e = (kernel == KA_GAUSSIAN) ? launch_kernel_variant<KA_GAUSSIAN>(a, b, precision, grid, s)
+                                         : launch_kernel_variant<KA_EXP_L1>(a, b, precision, grid, s);
+  if (e != hipSuccess) return e;
+  if (p.nsplit > 1) {
+    const int64_t n = a.nr * b;
+    hipLaunchKernelGGL(gamma_reduce_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
+                       a.partial, p.nsplit, n, a.Z);
+    e = hipGetLastError();
+  }
+  return e;
+}
+
+}  // namespace ka

@@ -1,0 +1,277 @@
+// Host-side FP64 set-up (see host_setup.hpp).
+#include "host_setup.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <stdexcept>
+
+namespace ka {
+
+Vec open_knots(int p, int nel, int mult) {
+  Vec t;
+  for (int i = 0; i <= p; ++i) t.push_back(0.0);
+  for (int e = 1; e < nel; ++e)
+    for (int m = 0; m < mult; ++m) t.push_back((double)e / nel);
+  for (int i = 0; i <= p; ++i) t.push_back(1.0);
+  return t;
+}
+
+int num_basis(const Vec& t, int p) { return (int)t.size() - p - 1; }
+
+// Knot span s with t[s] <= x < t[s+1]; the right end belongs to the last span.
+static int find_span(const Vec& t, int p, double x) {
+  const int n = num_basis(t, p);
+  if (x >= t[n]) return n - 1;
+  if (x <= t[p]) return p;
+  int lo = p, hi = n;
+  while (hi - lo > 1) {
+    int mid = (lo + hi) / 2;
+    if (x < t[mid]) hi = mid; else lo = mid;
+  }
+  return lo;
+}
+
+// The p+1 non-zero B-splines B_{s-p..s}(x) by the triangular recurrence.
+static void nonzero_basis(const Vec& t, int p, int s, double x, double* N) {
+  double left[32], right[32];
+  N[0] = 1.0;
+  for (int j = 1; j <= p; ++j) {
+    left[j] = x - t[s + 1 - j];
+    right[j] = t[s + j] - x;
+    double saved = 0.0;
+    for (int r = 0; r < j; ++r) {
+      const double tmp = N[r] / (right[r + 1] + left[j - r]);
+      N[r] = saved + right[r + 1] * tmp;
+      saved = left[j - r] * tmp;
+    }
+    N[j] = saved;
+  }
+}
+
+void bspline_row(const Vec& t, int p, double x, double* row) {
+  const int n = num_basis(t, p);
+  std::fill(row, row + n, 0.0);
+  double N[32];
+  const int s = find_span(t, p, x);
+  nonzero_basis(t, p, s, x, N);
+  for (int r = 0; r <= p; ++r) row[s - p + r] = N[r];
+}
+
+Mat bspline_matrix(const Vec& t, int p, const Vec& x) {
+  Mat B((int)x.size(), num_basis(t, p));
+  for (size_t a = 0; a < x.size(); ++a) bspline_row(t, p, x[a], &B.a[a * B.cols]);
+  return B;
+}
+
+Vec greville(const Vec& t, int p) {
+  const int n = num_basis(t, p);
+  Vec g(n);
+  for (int i = 0; i < n; ++i) {
+    double s = 0;
+    for (int k = 1; k <= p; ++k) s += t[i + k];
+    g[i] = s / p;
+  }
+  return g;
+}
+
+void gauss_legendre(int q, double a, double b, Vec& x, Vec& w) {
+  x.assign(q, 0.0);
+  w.assign(q, 0.0);
+  for (int i = 0; i < q; ++i) {
+    double z = std::cos(M_PI * (i + 0.75) / (q + 0.5));
+    double dp = 1.0;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = z;            // Legendre recurrence
+      for (int k = 2; k <= q; ++k) {
+        const double p2 = ((2 * k - 1) * z * p1 - (k - 1) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      if (q == 1) { p1 = z; p0 = 1.0; }
+      dp = q * (z * p1 - p0) / (z * z - 1.0);
+      const double dz = p1 / dp;
+      z -= dz;
+      if (std::fabs(dz) < 1e-16) break;
+    }
+    // recompute derivative at the converged root
+    double p0 = 1.0, p1 = z;
+    for (int k = 2; k <= q; ++k) {
+      const double p2 = ((2 * k - 1) * z * p1 - (k - 1) * p0) / k;
+      p0 = p1;
+      p1 = p2;
+    }
+    if (q == 1) { p1 = z; p0 = 1.0; }
+    dp = q * (z * p1 - p0) / (z * z - 1.0);
+    // ascending order on [a,b]
+    x[q - 1 - i] = a + (b - a) * (z + 1.0) / 2.0;
+    w[q - 1 - i] = (b - a) / ((1.0 - z * z) * dp * dp);
+  }
+}
+
+void element_gauss(const Vec& t, int q, Vec& x, Vec& w) {
+  x.clear();
+  w.clear();
+  Vec xe, we;
+  for (size_t k = 0; k + 1 < t.size(); ++k) {
+    if (t[k + 1] > t[k]) {
+      gauss_legendre(q, t[k], t[k + 1], xe, we);
+      x.insert(x.end(), xe.begin(), xe.end());
+      w.insert(w.end(), we.begin(), we.end());
+    }
+  }
+}
+
+Mat mass_matrix(const Vec& ta, int pa, const Vec& tb, int pb) {
+  Vec x, w;
+  element_gauss(ta, (pa + pb) / 2 + 1, x, w);
+  Mat Ba = bspline_matrix(ta, pa, x), Bb = bspline_matrix(tb, pb, x);
+  Mat Z(Ba.cols, Bb.cols);
+  for (size_t g = 0; g < x.size(); ++g)
+    for (int i = 0; i < Ba.cols; ++i) {
+      const double bi = Ba(g, i) * w[g];
+      if (bi == 0.0) continue;
+      for (int j = 0; j < Bb.cols; ++j) Z(i, j) += bi * Bb(g, j);
+    }
+  return Z;
+}
+
+bool cholesky_lower(const Mat& A, Mat& L) {
+  const int n = A.rows;
+  L = Mat(n, n);
+  for (int j = 0; j < n; ++j) {
+    double d = A(j, j);
+    for (int k = 0; k < j; ++k) d -= L(j, k) * L(j, k);
+    if (!(d > 0)) return false;
+    L(j, j) = std::sqrt(d);
+    for (int i = j + 1; i < n; ++i) {
+      double s = A(i, j);
+      for (int k = 0; k < j; ++k) s -= L(i, k) * L(j, k);
+      L(i, j) = s / L(j, j);
+    }
+  }
+  return true;
+}
+
+Mat lower_inverse(const Mat& L) {
+  const int n = L.rows;
+  Mat X(n, n);
+  for (int c = 0; c < n; ++c) {          // solve L x = e_c
+    for (int i = c; i < n; ++i) {
+      double s = (i == c) ? 1.0 : 0.0;
+      for (int k = c; k < i; ++k) s -= L(i, k) * X(k, c);
+      X(i, c) = s / L(i, i);
+    }
+  }
+  return X;
+}
+
+Mat transpose(const Mat& A) {
+  Mat T(A.cols, A.rows);
+  for (int i = 0; i < A.rows; ++i)
+    for (int j = 0; j < A.cols; ++j) T(j, i) = A(i, j);
+  return T;
+}
+
+Mat matmul(const Mat& A, const Mat& B) {
+  if (A.cols != B.rows) throw std::runtime_error("matmul shape");
+  Mat C(A.rows, B.cols);
+  for (int i = 0; i < A.rows; ++i)
+    for (int k = 0; k < A.cols; ++k) {
+      const double a = A(i, k);
+      if (a == 0.0) continue;
+      for (int j = 0; j < B.cols; ++j) C(i, j) += a * B(k, j);
+    }
+  return C;
+}
+
+bool lu_inverse(const Mat& A0, Mat& Ainv, double tol) {
+  const int n = A0.rows;
+  Mat A = A0;
+  std::vector<int> perm(n);
+  double amax = 0;
+  for (double v : A.a) amax = std::max(amax, std::fabs(v));
+  for (int i = 0; i < n; ++i) perm[i] = i;
+  for (int k = 0; k < n; ++k) {
+    int piv = k;
+    for (int i = k + 1; i < n; ++i)
+      if (std::fabs(A(i, k)) > std::fabs(A(piv, k))) piv = i;
+    if (std::fabs(A(piv, k)) <= tol * amax) return false;
+    if (piv != k) {
+      for (int j = 0; j < n; ++j) std::swap(A(k, j), A(piv, j));
+      std::swap(perm[k], perm[piv]);
+    }
+    for (int i = k + 1; i < n; ++i) {
+      A(i, k) /= A(k, k);
+      const double l = A(i, k);
+      if (l != 0.0)
+        for (int j = k + 1; j < n; ++j) A(i, j) -= l * A(k, j);
+    }
+  }
+  // solve A X = I column by column: P A = L U  ->  x = U^-1 L^-1 P e_c
+  Ainv = Mat(n, n);
+  Vec y(n);
+  for (int c = 0; c < n; ++c) {
+    for (int i = 0; i < n; ++i) {
+      double s = (perm[i] == c) ? 1.0 : 0.0;
+      for (int k = 0; k < i; ++k) s -= A(i, k) * y[k];
+      y[i] = s;
+    }
+    for (int i = n - 1; i >= 0; --i) {
+      double s = y[i];
+      for (int k = i + 1; k < n; ++k) s -= A(i, k) * Ainv(k, c);
+      Ainv(i, c) = s / A(i, i);
+    }
+  }
+  return true;
+}
+
+// ---- geometry ------------------------------------------------------------
+static const double kWmid = 0.70710678118654752440;  // 1/sqrt(2)
+
+// Rational quadratic quarter circle: C = (N0 P0 + w N1 P1 + N2 P2) / D.
+static void quarter_circle(double xi, double* C, double* dC) {
+  const double b0 = (1 - xi) * (1 - xi), b1 = 2 * xi * (1 - xi), b2 = xi * xi;
+  const double d0 = -2 * (1 - xi), d1 = 2 - 4 * xi, d2 = 2 * xi;
+  const double D = b0 + kWmid * b1 + b2, dD = d0 + kWmid * d1 + d2;
+  const double nx = b0 + kWmid * b1, ny = kWmid * b1 + b2;
+  const double dnx = d0 + kWmid * d1, dny = kWmid * d1 + d2;
+  C[0] = nx / D;
+  C[1] = ny / D;
+  dC[0] = (dnx * D - nx * dD) / (D * D);
+  dC[1] = (dny * D - ny * dD) / (D * D);
+}
+
+void Geometry::map(const double* xh, double* x) const {
+  if (domain == 0) {
+    for (int k = 0; k < 3; ++k) x[k] = lo[k] + (hi[k] - lo[k]) * xh[k];
+  } else {
+    double C[2], dC[2];
+    quarter_circle(xh[0], C, dC);
+    const double r = r0 + (r1 - r0) * xh[1];
+    x[0] = r * C[0];
+    x[1] = r * C[1];
+    x[2] = height * xh[2];
+  }
+}
+
+double Geometry::detJ(const double* xh) const {
+  if (domain == 0) return std::fabs((hi[0] - lo[0]) * (hi[1] - lo[1]) * (hi[2] - lo[2]));
+  double C[2], dC[2];
+  quarter_circle(xh[0], C, dC);
+  const double r = r0 + (r1 - r0) * xh[1];
+  // columns dF/dxi = r C', dF/deta = (r1-r0) C, dF/dzeta = height e_z
+  const double cross = C[0] * dC[1] - C[1] * dC[0];
+  return std::fabs(r * (r1 - r0) * height * cross);
+}
+
+double Geometry::volume() const {
+  if (domain == 0) return detJ(lo);
+  return M_PI / 4 * (r1 * r1 - r0 * r0) * height;
+}
+
+double Geometry::weight1d(int k, double t) const {
+  if (domain == 1 && k == 0) return (1 - t) * (1 - t) + kWmid * 2 * t * (1 - t) + t * t;
+  return 1.0;
+}
+
+}  // namespace ka

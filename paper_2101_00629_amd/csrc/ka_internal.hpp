@@ -1,0 +1,168 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/ka.h"
+
+namespace ka {
+
+// ---- kernel product -----------------------------------------------------
+struct GammaLaunch {
+  const float* xr;        // row points, stride xr_stride floats (x, y, z first)
+  int xr_stride;
+  const float* rs;        // optional row scale (nr)
+  int64_t nr;
+  const float* xc;        // column points
+  int xc_stride;
+  int64_t nc;
+  const float* Y;         // nc x b, b contiguous
+  float* Z;               // nr x b, b contiguous
+  float* partial;         // split-K scratch, nsplit * nr * b floats
+  float coord_scale;      // applied to every coordinate on load
+  float out_scale;        // sigma^2
+  int nsplit;             // filled by launch_gamma
+  int64_t cols_per_split; // filled by launch_gamma
+};
+
+struct GammaPlan {
+  int rows_per_block;
+  int64_t row_blocks;
+  int nsplit;
+  int64_t cols_per_split;
+  size_t partial_bytes;
+};
+
+GammaPlan gamma_plan(int64_t nr, int64_t nc, int b, int precision);
+hipError_t launch_gamma(GammaLaunch a, int kernel, int b, int precision, hipStream_t s);
+float kernel_coord_scale(int kernel, double ell);
+
+// ---- Kronecker mode products -------------------------------------------
+// A tensor with dims (n1, n2, n3) per vector and nv vectors.  Layout
+// LAYOUT_COL: element (i, j) at i + j * ld (column-major block, the FP64 API
+// layout); LAYOUT_PT: element (i, j) at i * ld + j (point-major, the kernel
+// product's layout, ld = block size).  i = i1 + n1 (i2 + n2 i3).
+enum { LAYOUT_COL = 0, LAYOUT_PT = 1 };
+
+struct ModeArgs {
+  const void* in;
+  int in_layout;
+  int64_t in_ld;          // column stride (COL) or point stride (PT)
+  void* out;
+  int out_layout;
+  int64_t out_ld;
+  int n_in[3];            // input dims
+  int mode;               // 0, 1, 2
+  int m;                  // output size along `mode`
+  const void* mat;        // m x n_in[mode], row-major
+  int nv;                 // vectors
+  const float* out_scale; // optional per-point scale of the output (output dims)
+};
+
+// TIn/TOut in {float, double}; the matrix and accumulation are TAcc.
+hipError_t launch_mode_f64(const ModeArgs& a, hipStream_t s);                  // in/out/mat double
+hipError_t launch_mode_f64_to_f32(const ModeArgs& a, hipStream_t s);           // in double, mat/out float
+hipError_t launch_mode_f32(const ModeArgs& a, hipStream_t s);                  // all float
+hipError_t launch_mode_f32_to_f64(const ModeArgs& a, hipStream_t s);           // in/mat float, out double
+hipError_t launch_mode_f32in_f64(const ModeArgs& a, hipStream_t s);            // in float, mat/out double
+// point-major FP32 (point stride ld_in) -> column-major FP64
+hipError_t cast_pt32_to_col64(const float* in, int64_t ld_in, double* out, int64_t ld_out, int64_t npts, int nv,
+                              hipStream_t s);
+
+// ---- FP64 dense helpers (eigensolver) ----------------------------------
+// C(m x n) = alpha * A^T B + beta * C, A: K x m (lda), B: K x n (ldb); split-K
+// partials in `work` (>= dgemm_tn_work(m, n, K) doubles), fixed reduction order.
+size_t dgemm_tn_work(int m, int n, int64_t K);
+hipError_t dgemm_tn(int m, int n, int64_t K, double alpha, const double* A, int64_t lda,
+                    const double* B, int64_t ldb, double beta, double* C, int64_t ldc,
+                    double* work, hipStream_t s);
+// C(M x n) = alpha * A B + beta * C, A: M x k (lda), B: k x n (ldb).
+hipError_t dgemm_nn(int64_t M, int n, int k, double alpha, const double* A, int64_t lda,
+                    const double* B, int64_t ldb, double beta, double* C, int64_t ldc, hipStream_t s);
+// Small dense kernels, one workgroup each.
+hipError_t chol_upper_inv(const double* G, int n, int ldg, double* Rinv, int ldr, int* status,
+                          hipStream_t s);
+hipError_t sym_eig(const double* H, int n, int ldh, double* theta, double* S, int lds, double* work,
+                   hipStream_t s);
+size_t sym_eig_work(int n);
+hipError_t nonsym_eig(const double* H, int n, int ldh, double* wr, double* wi, double* S, int lds,
+                      double* work, int* status, hipStream_t s);
+size_t nonsym_eig_work(int n);
+hipError_t column_norms(const double* X, int64_t N, int n, int64_t ldx, double* out, double* work,
+                        hipStream_t s);
+size_t column_norms_work(int64_t N, int n);
+hipError_t fill_normal(double* X, int64_t N, int n, int64_t ldx, uint64_t seed, uint64_t counter,
+                       hipStream_t s);
+hipError_t copy_cols(const double* X, int64_t ldx, double* Y, int64_t ldy, int64_t N, int n,
+                     hipStream_t s);
+hipError_t residual_combine(const double* AXS, const double* XS, int64_t N, int n, int64_t ld,
+                            const double* wr, const double* wi, double* R, hipStream_t s);
+hipError_t sign_fix(double* V, int64_t N, int n, int64_t ld, double* work, hipStream_t s);
+hipError_t scale_cols(double* V, int64_t N, int n, int64_t ld, const double* scale, hipStream_t s);
+hipError_t fill_zero_f32(float* p, int64_t n, hipStream_t s);
+
+// ---- problem ----------------------------------------------------------------
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+struct Problem {
+  ka_desc d;
+  hipStream_t stream = nullptr;
+  int device = 0;
+  int N = 0, n[3] = {0, 0, 0};
+  int Nt = 0, nt[3] = {0, 0, 0};     // Galerkin interpolation space
+  int64_t Nq = 0; int nq[3] = {0, 0, 0};  // collocation quadrature points
+  int b = 16;
+  float coord_scale = 1.f;
+  float out_scale = 1.f;
+  // device factors
+  double* LinvT[3] = {nullptr, nullptr, nullptr};   // (L_k^-T) n x n  (Galerkin)
+  double* Linv[3] = {nullptr, nullptr, nullptr};    // (L_k^-1)
+  double* Zinv[3] = {nullptr, nullptr, nullptr};    // (Z_k^-1) (collocation LU inverse / Galerkin mass inverse)
+  float* T[3] = {nullptr, nullptr, nullptr};        // Galerkin: B~_k^-T M_k (nt x n); collocation: R_q,k (nq x n)
+  float* TT[3] = {nullptr, nullptr, nullptr};       // transposes (n x nt)
+  float* rows = nullptr;     // row points (x, y, z, 0), prescaled
+  float* cols = nullptr;     // column points (Galerkin: == rows)
+  float* rscale = nullptr;   // row scale (Galerkin: J)
+  float* cscale = nullptr;   // column scale folded into Y (Galerkin: J, collocation: |det DF| W)
+  int64_t n_rows = 0, n_cols = 0;
+  // workspace
+  double* w64a = nullptr;    // N x b FP64
+  double* w64b = nullptr;
+  float* w32a = nullptr;     // max(Nt, Nq, N) x b FP32
+  float* w32b = nullptr;
+  float* gpart = nullptr;    // split-K partials
+  size_t gpart_bytes = 0;
+  std::vector<DevBuf> allocs;
+  size_t device_bytes = 0;
+  // profiling
+  bool profile = false;
+  std::vector<hipEvent_t> ev_start, ev_stop;
+  int prof_launches = 0;
+  double prof_ms = 0.0;
+  double prof_pairs = 0.0;
+  double pairs_total = 0.0;
+  // eigensolver workspace (lazily sized per call)
+  std::vector<DevBuf> eig_allocs;
+  size_t eig_bytes = 0;
+};
+
+void set_error(const std::string& msg);
+const char* last_error_cstr();
+int fail(int code, const std::string& msg);
+
+// device-side operator pieces (api.cpp)
+int apply_block(Problem* P, int form, const double* X, int64_t ldx, double* Y, int64_t ldy, int nv,
+                hipStream_t s);
+int solve_block(Problem* P, int op, double* X, int64_t ld, int nv, hipStream_t s);
+int setup_problem(const ka_desc* d, hipStream_t stream, Problem** out);
+int footprint(const ka_desc* d, size_t* bytes);
+void destroy_problem(Problem* P);
+int eigs(Problem* P, int M, double tol, int maxit, double* lambda_host, double* V_dev, ka_info* info);
+
+}  // namespace ka

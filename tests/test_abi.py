@@ -1,0 +1,54 @@
+"""The C-ABI library loads and exports every function include/ka.h declares
+(no GPU: only host-side calls)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "ka.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(ka_[a-zA-Z_0-9]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    import paper_2101_00629_amd as K
+    lib = ctypes.CDLL(K.LIB_PATH)
+    names = _declared()
+    assert len(names) >= 12
+    for n in names:
+        assert hasattr(lib, n), n
+        assert n in K.EXPORTED, n
+
+
+def test_host_side_validation_and_footprint():
+    import paper_2101_00629_amd as K
+    good = K.make_desc("galerkin", "cube", 3, (20, 20, 20), "gaussian", 0.5)
+    assert K.ka_footprint(good) > 12167 * 16 * 8
+    for bad in (dict(ell=-1.0), dict(block=8), dict(sigma=0.0)):
+        kw = dict(method="galerkin", domain="cube", p=2, nel=(4, 4, 4), kernel="gaussian", ell=0.5)
+        kw.update(bad)
+        d = K.make_desc(**kw)
+        with pytest.raises(K.KAError) as e:
+            K.ka_footprint(d)
+        assert e.value.code == K.KA_ERR_ARG
+    d = K.make_desc("galerkin", "cube", 2, (4, 4, 4), "exponential", float("inf"))
+    with pytest.raises(K.KAError):
+        K.ka_footprint(d)
+    # sizes: C^0 interpolation space for the exponential kernel
+    assert K.ka_gamma_workspace(200, 20000, 16, K.KA_FP32) > 0
+    assert K.ka_gamma_workspace(1000000, 10000, 16, K.KA_FP32) == 0
+
+
+def test_product_path_has_no_oracle_dependency():
+    pkg = os.path.join(ROOT, "paper_2101_00629_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".cpp", ".hpp")):
+                txt = open(os.path.join(dirpath, f)).read()
+                assert "import oracle" not in txt and "from oracle" not in txt, f
+                assert "oracle/" not in txt, f
