@@ -451,10 +451,11 @@ hipError_t residual_combine(const double* AXS, const double* XS, int64_t N, int 
 }
 
 // sign: make the first largest-magnitude entry of each column positive
-__global__ __launch_bounds__(256) void sign_fix_kernel(double* V, int64_t N, int64_t ld) {
+__global__ __launch_bounds__(256) void sign_fix_kernel(double* V, int64_t N, int64_t ld, const double* wi) {
   __shared__ double bv[256];
   __shared__ int64_t bi[256];
   const int j = blockIdx.x;
+  if (wi && wi[j] != 0.0) return;   // parts of a complex pair keep their joint phase
   double best = -1.0;
   int64_t besti = 0;
   for (int64_t i = threadIdx.x; i < N; i += 256) {
@@ -480,10 +481,9 @@ __global__ __launch_bounds__(256) void sign_fix_kernel(double* V, int64_t N, int
     for (int64_t i = threadIdx.x; i < N; i += 256) V[i + j * ld] = -V[i + j * ld];
 }
 
-hipError_t sign_fix(double* V, int64_t N, int n, int64_t ld, double* work, hipStream_t s) {
-  (void)work;
+hipError_t sign_fix(double* V, int64_t N, int n, int64_t ld, const double* wi, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(sign_fix_kernel, dim3(n), dim3(256), 0, s, V, N, ld);
+  hipLaunchKernelGGL(sign_fix_kernel, dim3(n), dim3(256), 0, s, V, N, ld, wi);
   return hipGetLastError();
 }
 

@@ -18,6 +18,8 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <string>
 #include <vector>
 
@@ -44,7 +46,7 @@ struct EigWork {
   double *X = nullptr, *AX = nullptr, *P = nullptr, *XS = nullptr, *AXS = nullptr, *R = nullptr, *T = nullptr;
   double *H = nullptr, *Hc = nullptr, *C = nullptr, *G = nullptr, *Rinv = nullptr, *theta = nullptr,
          *thetai = nullptr, *S = nullptr, *norms = nullptr, *ework = nullptr, *tnwork = nullptr,
-         *nwork = nullptr;
+         *nwork = nullptr, *Wm = nullptr, *Gm = nullptr;
   int* status = nullptr;
 };
 
@@ -77,9 +79,17 @@ __global__ void symmetrize_block_kernel(double* H, int ld, int k, int pw) {
   *b = v;
 }
 
+__global__ void inv_sqrt_kernel(const double* g, int n, double* out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = g[i] > 0.0 ? 1.0 / sqrt(g[i]) : 0.0;
+}
+
 class Solver {
  public:
-  Solver(Problem* P) : P_(P), s_(P->stream) {}
+  Solver(Problem* P) : P_(P), s_(P->stream) {
+    const char* v = std::getenv("KA_VERBOSE");
+    verbose_ = v && v[0] && v[0] != '0';
+  }
   ~Solver() {}
   int run(int M, double tol, int maxit, double* lambda_host, double* V_dev, ka_info* info);
 
@@ -90,6 +100,8 @@ class Solver {
   hipStream_t s_;
   EigWork w_;
   std::vector<DevBuf> bufs_;
+  bool verbose_ = false;
+  double noise_ = 0.0;
 };
 
 int Solver::alloc(size_t bytes, double** out) {
@@ -138,8 +150,11 @@ int Solver::run(int M, double tol, int maxit, double* lambda_host, double* V_dev
   const int64_t N = P_->N;
   const int b = P_->b;
   if (M < 1 || M > N) return fail(KA_ERR_ARG, "M must be in 1..N");
-  if (!sym) return fail(KA_ERR_STATE, "collocation eigensolve is not available in this build");
   const double tau = 1e-2;
+  // Residuals of an operator applied in FP32 (or split BF16) cannot fall
+  // below a few units of its rounding times |theta_1|; below that level the
+  // Ritz values no longer move (symmetric case: error ~ r^2 / gap).
+  noise_ = P_->d.precision == KA_FP32 ? 4e-6 : 1e-4;
   if (!(tol > 0)) tol = 1e-6;
   if (maxit <= 0) maxit = 100;
 
@@ -158,10 +173,14 @@ int Solver::run(int M, double tol, int maxit, double* lambda_host, double* V_dev
   KA_TRY(alloc((size_t)N * m_max * 8, &w_.X));
   KA_TRY(alloc((size_t)N * m_max * 8, &w_.AX));
   KA_TRY(alloc((size_t)N * b * 8, &w_.P));
-  KA_TRY(alloc((size_t)N * std::max(nev, b) * 8, &w_.T));
-  KA_TRY(alloc((size_t)N * nev * 8, &w_.XS));
-  KA_TRY(alloc((size_t)N * nev * 8, &w_.AXS));
-  KA_TRY(alloc((size_t)N * nev * 8, &w_.R));
+  const int ncol = nev + 1;   // room for a complex pair that straddles nev
+  KA_TRY(alloc((size_t)N * std::max(ncol, b) * 8, &w_.T));
+  KA_TRY(alloc((size_t)N * ncol * 8, &w_.XS));
+  KA_TRY(alloc((size_t)N * ncol * 8, &w_.AXS));
+  KA_TRY(alloc((size_t)N * ncol * 8, &w_.R));
+  KA_TRY(alloc((size_t)m_max * m_max * 8, &w_.Hc));
+  KA_TRY(alloc((size_t)m_max * m_max * 8, &w_.Wm));
+  KA_TRY(alloc((size_t)m_max * m_max * 8, &w_.Gm));
   KA_TRY(alloc((size_t)m_max * m_max * 8, &w_.H));
   KA_TRY(alloc((size_t)m_max * b * 8, &w_.C));
   KA_TRY(alloc((size_t)b * b * 8, &w_.G));
@@ -170,14 +189,14 @@ int Solver::run(int M, double tol, int maxit, double* lambda_host, double* V_dev
   KA_TRY(alloc((size_t)m_max * 8, &w_.thetai));
   KA_TRY(alloc((size_t)m_max * m_max * 8, &w_.S));
   KA_TRY(alloc((size_t)m_max * 8, &w_.norms));
-  KA_TRY(alloc(sym_eig_work(m_max) * 8, &w_.ework));
-  size_t tnw = 0;
+  KA_TRY(alloc(std::max(sym_eig_work(m_max), nonsym_eig_work(m_max)) * 8, &w_.ework));
+  size_t tnw = (size_t)m_max * m_max;
   for (int m = 1; m <= m_max; ++m) {
     tnw = std::max(tnw, dgemm_tn_work(m, b, N));
     tnw = std::max(tnw, dgemm_tn_work(b, m, N));
   }
   KA_TRY(alloc(tnw * 8, &w_.tnwork));
-  KA_TRY(alloc(column_norms_work(N, nev) * 8, &w_.nwork));
+  KA_TRY(alloc(column_norms_work(N, ncol) * 8, &w_.nwork));
   {
     double* st = nullptr;
     KA_TRY(alloc(256, &st));
@@ -190,9 +209,9 @@ int Solver::run(int M, double tol, int maxit, double* lambda_host, double* V_dev
   int pw = (int)std::min<int64_t>(b, m_max);
   KA_TRY(orth_block(0, pw, rng_counter));
 
-  int k = 0, cycles = 0, matvecs = 0, nconv = 0, Meff = M;
-  double max_res = 0.0;
-  std::vector<double> th(m_max), rn(m_max);
+  int k = 0, cycles = 0, matvecs = 0, nconv = 0, Meff = M, ns_status = 0;
+  double max_res = 0.0, max_imag = 0.0;
+  std::vector<double> th(m_max), rn(m_max), thi(m_max, 0.0);
   int nret = 0;
   bool converged = false;
   while (true) {
@@ -203,10 +222,15 @@ int Solver::run(int M, double tol, int maxit, double* lambda_host, double* V_dev
     // H[0:k+pw, k:k+pw] = X^T AP ; mirror into H[k:k+pw, 0:k]
     HIP_TRY(dgemm_tn(k + pw, pw, N, 1.0, w_.X, N, w_.AX + (size_t)k * N, N, 0.0, w_.H + (size_t)k * m_max, m_max,
                      w_.tnwork, s_));
-    hipLaunchKernelGGL(symmetrize_block_kernel, dim3((pw * pw + 255) / 256), dim3(256), 0, s_, w_.H, m_max, k, pw);
-    if (k > 0)
-      hipLaunchKernelGGL(mirror_kernel, dim3((k * pw + 255) / 256), dim3(256), 0, s_, w_.H, m_max, k, pw);
-    HIP_TRY(hipGetLastError());
+    if (sym) {
+      hipLaunchKernelGGL(symmetrize_block_kernel, dim3((pw * pw + 255) / 256), dim3(256), 0, s_, w_.H, m_max, k, pw);
+      if (k > 0)
+        hipLaunchKernelGGL(mirror_kernel, dim3((k * pw + 255) / 256), dim3(256), 0, s_, w_.H, m_max, k, pw);
+      HIP_TRY(hipGetLastError());
+    } else if (k > 0) {
+      // new rows: H[k:k+pw, 0:k] = P^T A' X
+      HIP_TRY(dgemm_tn(pw, k, N, 1.0, w_.X + (size_t)k * N, N, w_.AX, N, 0.0, w_.H + k, m_max, w_.tnwork, s_));
+    }
     k += pw;
     // next pending block
     const int room = m_max - k;
@@ -222,50 +246,123 @@ int Solver::run(int M, double tol, int maxit, double* lambda_host, double* V_dev
       continue;
     }
     // Rayleigh-Ritz
-    HIP_TRY(sym_eig(w_.H, k, m_max, w_.theta, w_.S, m_max, w_.ework, s_));
-    const int nk = std::min(nev, k);
+    int nk;
+    if (sym) {
+      HIP_TRY(sym_eig(w_.H, k, m_max, w_.theta, w_.S, m_max, w_.ework, s_));
+      nk = std::min(nev, k);
+    } else {
+      HIP_TRY(nonsym_eig(w_.H, k, m_max, w_.theta, w_.thetai, w_.S, m_max, w_.ework, w_.status, s_));
+      nk = std::min(nev + 1, k);
+    }
     HIP_TRY(dgemm_nn(N, nk, k, 1.0, w_.X, N, w_.S, m_max, 0.0, w_.XS, N, s_));
     HIP_TRY(dgemm_nn(N, nk, k, 1.0, w_.AX, N, w_.S, m_max, 0.0, w_.AXS, N, s_));
-    HIP_TRY(residual_combine(w_.AXS, w_.XS, N, nk, N, w_.theta, nullptr, w_.R, s_));
+    HIP_TRY(residual_combine(w_.AXS, w_.XS, N, nk, N, w_.theta, sym ? nullptr : w_.thetai, w_.R, s_));
     HIP_TRY(column_norms(w_.R, N, nk, N, w_.norms, w_.nwork, s_));
     HIP_TRY(hipMemcpyAsync(th.data(), w_.theta, sizeof(double) * nk, hipMemcpyDeviceToHost, s_));
     HIP_TRY(hipMemcpyAsync(rn.data(), w_.norms, sizeof(double) * nk, hipMemcpyDeviceToHost, s_));
+    if (!sym) {
+      HIP_TRY(hipMemcpyAsync(thi.data(), w_.thetai, sizeof(double) * nk, hipMemcpyDeviceToHost, s_));
+      HIP_TRY(hipMemcpyAsync(&ns_status, w_.status, sizeof(int), hipMemcpyDeviceToHost, s_));
+    }
     HIP_TRY(hipStreamSynchronize(s_));
     ++cycles;
-    // extend M to the end of its cluster (relative gap below 1e-6)
-    Meff = std::min(M, nk);
-    while (Meff < nk && std::fabs(th[Meff - 1] - th[Meff]) <= 1e-6 * std::fabs(th[Meff - 1])) ++Meff;
-    const double floor_ = tau * std::fabs(th[0]);
+    if (!sym && ns_status != 0) return fail(KA_ERR_SINGULAR, "Rayleigh-Ritz QR iteration did not converge");
+    if (!sym) {
+      // a complex pair shares one residual (re and im parts of one unit vector)
+      for (int i = 0; i + 1 < nk; ++i)
+        if (thi[i] > 0.0) {
+          rn[i] = rn[i + 1] = std::sqrt(rn[i] * rn[i] + rn[i + 1] * rn[i + 1]);
+          ++i;
+        }
+    }
+    auto modulus = [&](int i) { return sym ? std::fabs(th[i]) : std::hypot(th[i], thi[i]); };
+    // extend M to the end of its cluster (relative gap below 1e-6) or pair
+    const int nlim = sym ? nk : std::min(nev, k);
+    Meff = std::min(M, nlim);
+    while (Meff < nlim && std::fabs(th[Meff - 1] - th[Meff]) <= 1e-6 * std::fabs(th[Meff - 1])) ++Meff;
+    if (!sym && Meff < nk && thi[Meff - 1] > 0.0) ++Meff;
+    const double floor_ = std::max(tol * tau, noise_) * modulus(0);
     nconv = 0;
     max_res = 0.0;
+    max_imag = 0.0;
     for (int i = 0; i < Meff; ++i) {
-      const double rel = rn[i] / std::max(std::fabs(th[i]), floor_);
-      if (i < M) max_res = std::max(max_res, rel);
-      if (rel <= tol && nconv == i) ++nconv;
+      const double crit = std::max(tol * modulus(i), floor_);
+      const double rel = rn[i] / std::max(modulus(i), tau * modulus(0));
+      if (i < M) {
+        max_res = std::max(max_res, rel);
+        if (!sym) max_imag = std::max(max_imag, std::fabs(thi[i]) / modulus(i));
+      }
+      if (rn[i] <= crit && nconv == i) ++nconv;
     }
-    nret = nk;
+    nret = sym ? nk : std::min(nk, Meff + 1);
     converged = nconv >= Meff;
+    if (verbose_) {
+      double rmax = 0.0;
+      for (int i = 0; i < Meff; ++i) rmax = std::max(rmax, rn[i] / modulus(0));
+      std::fprintf(stderr, "[ka_eigs] cycle %d k %d matvecs %d nconv %d/%d max_rel %.3e max_abs/theta1 %.3e theta1 %.6e\n",
+                   cycles, k, matvecs, nconv, Meff, max_res, rmax, th[0]);
+    }
     if (converged || cycles >= maxit || full) break;
-    // thick restart
-    HIP_TRY(copy_cols(w_.XS, N, w_.X, N, N, nk, s_));
-    HIP_TRY(copy_cols(w_.AXS, N, w_.AX, N, N, nk, s_));
-    hipLaunchKernelGGL(set_diag_kernel, dim3((nk * nk + 255) / 256), dim3(256), 0, s_, w_.H, m_max, nk, w_.theta);
-    HIP_TRY(hipGetLastError());
-    k = nk;
+    // thick restart onto the leading Ritz vectors
+    if (sym) {
+      HIP_TRY(copy_cols(w_.XS, N, w_.X, N, N, nk, s_));
+      HIP_TRY(copy_cols(w_.AXS, N, w_.AX, N, N, nk, s_));
+      hipLaunchKernelGGL(set_diag_kernel, dim3((nk * nk + 255) / 256), dim3(256), 0, s_, w_.H, m_max, nk, w_.theta);
+      HIP_TRY(hipGetLastError());
+      k = nk;
+    } else {
+      int nkeep = std::min(nev, k);
+      if (nkeep < nk && thi[nkeep - 1] > 0.0) ++nkeep;
+      // orthonormal basis of the kept Ritz vectors: W = V Lambda^-1/2 from S^T S = V Lambda V^T
+      HIP_TRY(dgemm_tn(nkeep, nkeep, k, 1.0, w_.S, m_max, w_.S, m_max, 0.0, w_.Gm, m_max, w_.tnwork, s_));
+      HIP_TRY(sym_eig(w_.Gm, nkeep, m_max, w_.norms, w_.Wm, m_max, w_.ework, s_));
+      std::vector<double> gl(nkeep);
+      HIP_TRY(hipMemcpyAsync(gl.data(), w_.norms, sizeof(double) * nkeep, hipMemcpyDeviceToHost, s_));
+      HIP_TRY(hipStreamSynchronize(s_));
+      int good = 0;
+      while (good < nkeep && gl[good] > 1e-12 * gl[0]) ++good;
+      hipLaunchKernelGGL(inv_sqrt_kernel, dim3((good + 63) / 64), dim3(64), 0, s_, w_.norms, good, w_.norms);
+      HIP_TRY(hipGetLastError());
+      HIP_TRY(scale_cols(w_.Wm, nkeep, good, m_max, w_.norms, s_));
+      // X <- XS W, AX <- AXS W
+      HIP_TRY(dgemm_nn(N, good, nkeep, 1.0, w_.XS, N, w_.Wm, m_max, 0.0, w_.T, N, s_));
+      HIP_TRY(copy_cols(w_.T, N, w_.X, N, N, good, s_));
+      HIP_TRY(dgemm_nn(N, good, nkeep, 1.0, w_.AXS, N, w_.Wm, m_max, 0.0, w_.T, N, s_));
+      HIP_TRY(copy_cols(w_.T, N, w_.AX, N, N, good, s_));
+      // H <- W^T S^T H S W
+      HIP_TRY(dgemm_nn(k, nkeep, k, 1.0, w_.H, m_max, w_.S, m_max, 0.0, w_.Hc, m_max, s_));
+      HIP_TRY(dgemm_tn(nkeep, nkeep, k, 1.0, w_.S, m_max, w_.Hc, m_max, 0.0, w_.Gm, m_max, w_.tnwork, s_));
+      HIP_TRY(dgemm_nn(nkeep, good, nkeep, 1.0, w_.Gm, m_max, w_.Wm, m_max, 0.0, w_.Hc, m_max, s_));
+      HIP_TRY(dgemm_tn(good, good, nkeep, 1.0, w_.Wm, m_max, w_.Hc, m_max, 0.0, w_.H, m_max, w_.tnwork, s_));
+      k = good;
+    }
     pw = b;
   }
   if (full) converged = true, nconv = std::max(nconv, Meff);
 
-  // outputs: eigenvalues, eigenvectors v = L^-T y (Z-orthonormal)
+  // outputs.  Galerkin: v = L^-T y (Z-orthonormal).  Collocation: v = y
+  // (unit 2-norm; complex pairs as re, im columns).
   const int Mo = std::min(M, nret);
-  for (int i = 0; i < Mo; ++i) lambda_host[i] = th[i];
-  for (int i = Mo; i < M; ++i) lambda_host[i] = 0.0;
-  if (V_dev) {
-    for (int c0 = 0; c0 < Mo; c0 += b) {
-      const int nv = std::min(b, Mo - c0);
-      KA_TRY(solve_block(P_, KA_LTINV, w_.XS + (size_t)c0 * N, N, nv, s_));
+  for (int i = 0; i < Mo; ++i) {
+    if (sym) {
+      lambda_host[i] = th[i];
+    } else {
+      lambda_host[2 * i] = th[i];
+      lambda_host[2 * i + 1] = thi[i];
     }
-    HIP_TRY(sign_fix(w_.XS, N, Mo, N, nullptr, s_));
+  }
+  for (int i = Mo; i < M; ++i) {
+    if (sym) lambda_host[i] = 0.0;
+    else lambda_host[2 * i] = lambda_host[2 * i + 1] = 0.0;
+  }
+  if (V_dev && Mo > 0) {
+    if (sym) {
+      for (int c0 = 0; c0 < Mo; c0 += b) {
+        const int nv = std::min(b, Mo - c0);
+        KA_TRY(solve_block(P_, KA_LTINV, w_.XS + (size_t)c0 * N, N, nv, s_));
+      }
+    }
+    HIP_TRY(sign_fix(w_.XS, N, Mo, N, sym ? nullptr : w_.thetai, s_));
     HIP_TRY(copy_cols(w_.XS, N, V_dev, N, N, Mo, s_));
   }
   HIP_TRY(hipStreamSynchronize(s_));
@@ -276,7 +373,7 @@ int Solver::run(int M, double tol, int maxit, double* lambda_host, double* V_dev
     info->converged = std::min(nconv, M);
     info->nev_computed = Meff;
     info->max_residual = max_res;
-    info->max_imag_rel = 0.0;
+    info->max_imag_rel = max_imag;
     info->seconds = secs;
     info->gamma_seconds = 0.0;
     info->pairs = P_->pairs_total - pairs0;

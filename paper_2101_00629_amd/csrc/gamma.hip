@@ -346,6 +346,12 @@ GammaPlan gamma_plan(int64_t nr, int64_t nc, int b, int precision) {
   GammaPlan p;
   p.rows_per_block = rows_per_block(b, precision);
   p.row_blocks = (nr + p.rows_per_block - 1) / p.rows_per_block;
+  if (nr <= 0 || nc <= 0) {   // nothing to split
+    p.nsplit = 1;
+    p.cols_per_split = nc > 0 ? nc : 0;
+    p.partial_bytes = 0;
+    return p;
+  }
   // Fill the chip: aim for >= 2048 workgroups, but keep >= 2048 columns per
   // split so the partial-sum traffic stays small next to the pair work.
   const int64_t target = 2048;
@@ -391,7 +397,7 @@ hipError_t launch_gamma(GammaLaunch a, int kernel, int b, int precision, hipStre
   a.nsplit = p.nsplit;
   a.cols_per_split = p.cols_per_split;
   if (a.nc <= 0) {
-    return hipMemsetAsync(a.Z, 0, (size_t)a.nr * b * sizeof(float), s);
+    return fill_zero_f32(a.Z, a.nr * b, s);
   }
   const dim3 grid((unsigned)p.row_blocks, (unsigned)p.nsplit);
   hipError_t e = (kernel == KA_GAUSSIAN) ? launch_kernel_variant<KA_GAUSSIAN>(a, b, precision, grid, s)

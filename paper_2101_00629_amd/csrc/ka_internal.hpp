@@ -100,7 +100,7 @@ hipError_t copy_cols(const double* X, int64_t ldx, double* Y, int64_t ldy, int64
                      hipStream_t s);
 hipError_t residual_combine(const double* AXS, const double* XS, int64_t N, int n, int64_t ld,
                             const double* wr, const double* wi, double* R, hipStream_t s);
-hipError_t sign_fix(double* V, int64_t N, int n, int64_t ld, double* work, hipStream_t s);
+hipError_t sign_fix(double* V, int64_t N, int n, int64_t ld, const double* wi, hipStream_t s);
 hipError_t scale_cols(double* V, int64_t N, int n, int64_t ld, const double* scale, hipStream_t s);
 hipError_t fill_zero_f32(float* p, int64_t n, hipStream_t s);
 

@@ -80,3 +80,41 @@ def test_eigs_argument_errors():
     with pytest.raises(K.KAError):
         K.ka_eigs(prob.h, prob.N + 1)
     prob.close()
+
+
+def test_small_cube_collocation_gaussian():
+    from oracle import collocation
+    desc = K.make_desc("collocation", "cube", 2, (8, 8, 8), "gaussian", 0.5, seed=2)
+    rc, lam, V, info = _solve_c(desc, 10)
+    ref = product1d.collocation_box_spectrum(2, (8, 8, 8), "gaussian", 0.5, M=10)
+    lr = lam[0::2]
+    print("small cube collocation", info, errors.floored_rel_errors(ref.real, lr).max())
+    assert rc == 0
+    assert np.abs(lam[1::2]).max() <= 1e-7 * lr[0]      # FP32 noise in a real spectrum
+    assert errors.floored_rel_errors(ref.real, lr).max() < 1e-6
+    # eigenvectors: A v = lambda Z v against the assembled oracle, unit norm
+    o = collocation.Collocation("cube", 2, (8, 8, 8), "gaussian", 0.5)
+    R = o.apply_A(V) - (o.Z_dense() @ V) * lr[None, :]
+    assert (np.linalg.norm(R, axis=0) / lr).max() < 1e-4
+    assert np.allclose(np.linalg.norm(V, axis=0), 1.0, atol=1e-10)
+
+
+def test_annulus_collocation_small_dense():
+    from oracle import collocation
+    o = collocation.Collocation(geometry.QuarterAnnulus(), 3, (4, 4, 3), "exponential", 0.5)
+    ref, _ = o.eig_dense(12)
+    desc = K.make_desc("collocation", "quarter_annulus", 3, (4, 4, 3), "exponential", 0.5, seed=4)
+    rc, lam, V, info = _solve_c(desc, 12)
+    print("annulus collocation", info, errors.floored_rel_errors(ref.real, lam[0::2]).max())
+    assert rc == 0
+    assert errors.floored_rel_errors(ref.real, lam[0::2]).max() < 1e-6
+    assert np.abs(lam[1::2] - ref.imag).max() < 1e-6 * abs(ref[0])
+
+
+def _solve_c(desc, M, tol=1e-6, maxit=60):
+    prob = K.Problem(desc)
+    V = torch.zeros((M, prob.N), dtype=torch.float64, device="cuda")
+    rc, lam, info = K.ka_eigs(prob.h, M, tol=tol, maxit=maxit, V=V, complex_values=True)
+    Vn = V.cpu().numpy().T
+    prob.close()
+    return rc, lam, Vn, info

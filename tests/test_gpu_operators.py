@@ -65,7 +65,17 @@ def test_apply_matches_oracle(c):
         Y = _gpu_apply(prob, form, X)
         ref = o.apply_A(X) if form == K.KA_A else o.apply_Aprime(X)
         err = _colerr(Y, ref)
-        assert np.isfinite(Y).all() and err < 2e-5, (form, err)
+        tol = 2e-5
+        if form == K.KA_APRIME and c["method"] == "collocation":
+            # A' = Z^-1 A: the FP64 solve is exact, but it amplifies the FP32
+            # error of A X by up to cond(Z) = prod_k cond(Z_k).  Check the
+            # backward error Z Y - A X at the FP32 bar and the forward error
+            # against the condition number.
+            AX = o.apply_A(X)
+            back = _colerr(o.Z_dense() @ Y, AX)
+            assert back < 2e-5, back
+            tol *= np.prod([np.linalg.cond(Zk) for Zk in o.Zk])
+        assert np.isfinite(Y).all() and err < tol, (form, err, tol)
     prob.close()
 
 
