@@ -1,0 +1,198 @@
+"""Benchmark: matrix-free isogeometric K-L solves on one MI355X.
+
+One step = the full hot path on the unit-cube workload (p = 3, 20^3
+elements, N = 12167, M = 50 eigenpairs, block b = 16, FP32 tiles + FP32
+MFMA contraction): four complete K-L solves, Galerkin-IBQ and collocation,
+each with the Gaussian kernel (ell = 0.5) and the L1-exponential kernel
+(ell = 1, C^0 interpolation space for Galerkin, N~ = 226981).  Every solve
+runs the block Krylov eigensolver on the device around the matrix-free
+operator (Kronecker transfers, fused on-the-fly kernel product, FP64 solves).
+
+Printed: one JSON line.  value = kernel-pair evaluations per second over the
+whole timed region (all steps), with K-L solves/s, per-solve latency
+percentiles, the eigenvalue error against the FP64 product-of-1D oracle,
+the roofline of the fused kernel product (device time from HIP events on its
+launch stream) and the FP64 CPU oracle timed on a bounded sample.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Γ-pair evals/s vs roofline; K-L solves/s + p99 latency @1e-6 eig err"
+
+# MI355X unit counts: 256 CUs x 4 SIMDs x 16 lanes at 2.4 GHz issue 39.32e12
+# lane-instructions/s of non-packed FP32 VALU work; v_exp_f32 issues at half
+# rate (two issue slots).  Gaussian pair: 3 sub + mul + 2 fma + exp = 8 slots;
+# exponential pair: 3 sub + 2 add (abs as operand modifiers) + exp = 7 slots.
+VALU_SLOTS_PER_S = 256 * 4 * 16 * 2.4e9
+SLOTS = {"gaussian": 8, "exponential": 7}
+
+
+def peak_pairs(kernel):
+    return VALU_SLOTS_PER_S / SLOTS[kernel]
+
+
+def workload(M=50, b=16, precision="fp32"):
+    from workloads import cube_p3_20
+    probs = []
+    for method in ("galerkin", "collocation"):
+        for kernel in ("gaussian", "exponential"):
+            p = cube_p3_20(method, kernel, precision=precision)
+            p["M"], p["block"] = M, b
+            probs.append(p)
+    return probs
+
+
+def reference_spectrum(p):
+    from oracle import product1d
+    if p["method"] == "galerkin":
+        return product1d.galerkin_box_spectrum(p["p"], p["nel"], p["kernel"], p["ell"], M=p["M"])
+    return product1d.collocation_box_spectrum(p["p"], p["nel"], p["kernel"], p["ell"], M=p["M"]).real
+
+
+def cpu_baseline(probs, seconds_target=20.0):
+    """FP64 C/OpenMP oracle kernel product on row samples of each problem."""
+    from oracle import cmatvec, collocation, galerkin
+    total_pairs, total_time = 0.0, 0.0
+    rng = np.random.default_rng(5)
+    per = seconds_target / len(probs)
+    parts = []
+    # calibrate the rate on a small slice first
+    for p in probs:
+        if p["method"] == "galerkin":
+            o = galerkin.GalerkinIBQ("cube", p["p"], p["nel"], p["kernel"], p["ell"])
+            Xr, Xc = o.X, o.X
+        else:
+            o = collocation.Collocation("cube", p["p"], p["nel"], p["kernel"], p["ell"])
+            Xr, Xc = o.Xc, o.Xq
+        Y = rng.standard_normal((len(Xc), p["block"]))
+        nprobe = 512
+        t0 = time.perf_counter()
+        cmatvec.gamma_apply(p["kernel"], 1.0, p["ell"], Xr[:nprobe], Xc, Y)
+        rate = nprobe * len(Xc) / max(time.perf_counter() - t0, 1e-6)
+        rows = int(min(len(Xr), max(64, per * rate / len(Xc))))
+        t0 = time.perf_counter()
+        cmatvec.gamma_apply(p["kernel"], 1.0, p["ell"], Xr[:rows], Xc, Y)
+        dt = time.perf_counter() - t0
+        total_pairs += rows * len(Xc)
+        total_time += dt
+        parts.append(f"{p['method']}-{p['kernel']}: {rows} rows x {len(Xc)} cols")
+    return {"value": total_pairs / total_time, "unit": "pairs/s", "cores": cmatvec.max_threads(), "kind": "oracle",
+            "sample": "FP64 C/OpenMP kernel product (oracle/cmatvec.c), b=16, " + "; ".join(parts)
+            + f"; {total_pairs:.3g} pairs in {total_time:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16x3"])
+    ap.add_argument("--tol", type=float, default=1e-5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: the kernel product of one GPU's share; "
+              "multi-GPU runs are not part of this build (see DESIGN.md, sharding)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2101_00629_amd as K
+
+    torch.cuda.set_device(0)
+    probs = workload(precision=args.precision)
+    handles = []
+    for i, p in enumerate(probs):
+        h = K.Problem(K.desc_from_problem(p, seed=1000 + i))
+        handles.append(h)
+
+    def one_step(record):
+        out = []
+        for p, h in zip(probs, handles):
+            t0 = time.perf_counter()
+            rc, lam, info = K.ka_eigs(h.h, p["M"], tol=args.tol, maxit=60,
+                                      complex_values=(p["method"] == "collocation"))
+            dt = time.perf_counter() - t0
+            if rc != 0:
+                raise RuntimeError(f"ka_eigs returned {rc} for {p['name']}: {info}")
+            out.append((lam, info, dt))
+        return out
+
+    for _ in range(args.warmup):
+        one_step(False)
+    for h in handles:
+        K.ka_profile_reset(h.h)
+        K.ka_profile_enable(h.h, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    results = []
+    for _ in range(args.steps):
+        results.append(one_step(True))
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    prof = [K.ka_profile_read(h.h) for h in handles]
+    for h in handles:
+        K.ka_profile_enable(h.h, False)
+
+    pairs = sum(info["pairs"] for step in results for (_, info, _) in step)
+    lat = np.array([dt for step in results for (_, _, dt) in step]) * 1e3
+    nsolves = len(lat)
+    # eigenvalue accuracy of the last step against the FP64 oracle
+    from oracle import errors
+    eig = {}
+    worst = 0.0
+    for p, (lam, info, _) in zip(probs, results[-1]):
+        ref = reference_spectrum(p)
+        lr = lam[0::2] if p["method"] == "collocation" else lam
+        e = errors.floored_rel_errors(ref, lr)
+        worst = max(worst, float(e.max()))
+        eig[f"{p['method']}-{p['kernel']}"] = {"max_floored_rel_err": float(e.max()),
+                                               "max_raw_rel_err": float(errors.rel_errors(ref, lr).max()),
+                                               "matvecs": info["matvecs"], "cycles": info["iterations"]}
+    # roofline of the fused kernel product
+    gl_pairs = sum(pp for (_, _, pp) in prof)
+    gl_ms = sum(ms for (_, ms, _) in prof)
+    launches = sum(n for (n, _, _) in prof)
+    achieved = gl_pairs / (gl_ms / 1e3)
+    peak = gl_pairs / sum(pp / peak_pairs(p["kernel"]) for p, (_, _, pp) in zip(probs, prof))
+    line = {
+        "metric": METRIC,
+        "value": pairs / elapsed,
+        "unit": "pairs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if args.precision == "fp32" else "bf16x3",
+        "data": "synthetic",
+        "config": {"workload": "unit cube p=3 20^3 (N=12167), M=50, b=16: Galerkin-IBQ + collocation x "
+                               "Gaussian(l=0.5) + exponential-L1(l=1), one full K-L solve each",
+                   "solves_per_step": len(probs), "tol": args.tol, "precision": args.precision},
+        "solves_per_s": nsolves / elapsed,
+        "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                       "max": float(lat.max())},
+        "eig_err": {"max_floored_rel_err": worst, "per_problem": eig},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "pairs/s",
+                     "frac": achieved / peak, "traffic": None,
+                     "kernel": "gamma_f32_kernel" if args.precision == "fp32" else "gamma_bf16x3_kernel",
+                     "launches": launches, "kernel_ms": gl_ms, "kernel_share_of_step": gl_ms / 1e3 / elapsed},
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(probs)
+    print(json.dumps(line), flush=True)
+    for h in handles:
+        h.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -350,7 +350,7 @@ static ModeArgs mode_args(const void* in, int in_layout, int64_t in_ld, void* ou
   return a;
 }
 
-static int gamma_step(Problem* P, const float* Y, float* Z, hipStream_t s) {
+int gamma_step(Problem* P, const float* Y, float* Z, hipStream_t s) {
   GammaLaunch g;
   g.xr = P->rows;
   g.xr_stride = 4;
@@ -417,25 +417,33 @@ static int forward_transfer(Problem* P, const double* X, int64_t ldx, int nv, hi
   return KA_OK;   // result in w32b
 }
 
-int apply_block(Problem* P, int form, const double* X, int64_t ldx, double* Y, int64_t ldy, int nv, hipStream_t s) {
+// Operator steps before the kernel product: X (FP64, column layout) ->
+// kernel-product input in w32b (point-major FP32, stride b).
+//   Galerkin: [L^-T if A'], then B~^-T M per direction with J on the last store
+//   (nine-step algorithm, steps 1-4).  Collocation: R_q per direction with
+//   J W on the last store (Algorithm 1, steps 1-2).
+int apply_pre(Problem* P, int form, const double* X, int64_t ldx, int nv, hipStream_t s) {
+  const int64_t N = P->N;
+  int rc;
+  const double* src = X;
+  int64_t lds = ldx;
+  if (P->d.method == KA_GALERKIN_IBQ && form == KA_APRIME) {
+    if ((rc = kron64(P, P->LinvT, X, ldx, P->w64a, N, nv, s))) return rc;
+    src = P->w64a;
+    lds = N;
+  }
+  return forward_transfer(P, src, lds, nv, s);
+}
+
+// Operator steps after the kernel product: w32a (point-major FP32) -> Y.
+//   Galerkin: M^T B~^-1 per direction, [L^-1 if A'] (steps 7-9; step 6 is
+//   folded into the product's store).  Collocation: [Z^-1 if A'] (step 4).
+int apply_post(Problem* P, int form, double* Y, int64_t ldy, int nv, hipStream_t s) {
   const int b = P->b;
   const int* n = P->n;
   const int64_t N = P->N;
-  int rc;
+  const int nn[3] = {n[0], n[1], n[2]};
   if (P->d.method == KA_GALERKIN_IBQ) {
-    const double* src = X;
-    int64_t lds = ldx;
-    if (form == KA_APRIME) {                       // step 1: L^-T
-      if ((rc = kron64(P, P->LinvT, X, ldx, P->w64a, N, nv, s))) return rc;
-      // kron64 used w64a as scratch for mode 1; its result went to w64a via Y argument
-      src = P->w64a;
-      lds = N;
-    }
-    // steps 2-4: M, B~^-T, J  (fused as B~^-T M per direction, J on the last store)
-    if ((rc = forward_transfer(P, src, lds, nv, s))) return rc;
-    // steps 5-6: Gamma, J
-    if ((rc = gamma_step(P, P->w32b, P->w32a, s))) return rc;
-    // steps 7-8: B~^-1, M^T  (as M^T B~^-1 per direction)
     const int* m = P->nt;
     int d0[3] = {m[0], m[1], m[2]};
     HIP_TRY(launch_mode_f32(mode_args(P->w32a, LAYOUT_PT, b, P->w32b, LAYOUT_PT, b, d0, 0, n[0], P->TT[0], nv, nullptr), s));
@@ -444,8 +452,6 @@ int apply_block(Problem* P, int form, const double* X, int64_t ldx, double* Y, i
     int d2[3] = {n[0], n[1], m[2]};
     if (form == KA_APRIME) {
       HIP_TRY(launch_mode_f32_to_f64(mode_args(P->w32a, LAYOUT_PT, b, P->w64b, LAYOUT_COL, N, d2, 2, n[2], P->TT[2], nv, nullptr), s));
-      // step 9: L^-1
-      const int nn[3] = {n[0], n[1], n[2]};
       HIP_TRY(launch_mode_f64(mode_args(P->w64b, LAYOUT_COL, N, P->w64a, LAYOUT_COL, N, nn, 0, n[0], P->Linv[0], nv, nullptr), s));
       HIP_TRY(launch_mode_f64(mode_args(P->w64a, LAYOUT_COL, N, P->w64b, LAYOUT_COL, N, nn, 1, n[1], P->Linv[1], nv, nullptr), s));
       HIP_TRY(launch_mode_f64(mode_args(P->w64b, LAYOUT_COL, N, Y, LAYOUT_COL, ldy, nn, 2, n[2], P->Linv[2], nv, nullptr), s));
@@ -454,10 +460,6 @@ int apply_block(Problem* P, int form, const double* X, int64_t ldx, double* Y, i
     }
     return KA_OK;
   }
-  // collocation, Algorithm 1: steps 1-2 (R_q, J W), step 3 (Gamma), step 4 (Z^-1)
-  if ((rc = forward_transfer(P, X, ldx, nv, s))) return rc;
-  if ((rc = gamma_step(P, P->w32b, P->w32a, s))) return rc;
-  const int nn[3] = {n[0], n[1], n[2]};
   if (form == KA_APRIME) {
     HIP_TRY(launch_mode_f32in_f64(mode_args(P->w32a, LAYOUT_PT, b, P->w64a, LAYOUT_COL, N, nn, 0, n[0], P->Zinv[0], nv, nullptr), s));
     HIP_TRY(launch_mode_f64(mode_args(P->w64a, LAYOUT_COL, N, P->w64b, LAYOUT_COL, N, nn, 1, n[1], P->Zinv[1], nv, nullptr), s));
@@ -466,6 +468,35 @@ int apply_block(Problem* P, int form, const double* X, int64_t ldx, double* Y, i
     HIP_TRY(cast_pt32_to_col64(P->w32a, b, Y, ldy, N, nv, s));
   }
   return KA_OK;
+}
+
+// The kernel-product job of one block application (input w32b, output
+// w32a), for single or batched launches.
+GammaLaunch gamma_job(Problem* P) {
+  GammaLaunch g;
+  g.xr = P->rows;
+  g.xr_stride = 4;
+  g.rs = P->d.method == KA_GALERKIN_IBQ ? P->rscale : nullptr;
+  g.nr = P->n_rows;
+  g.xc = P->cols;
+  g.xc_stride = 4;
+  g.nc = P->n_cols;
+  g.Y = P->w32b;
+  g.Z = P->w32a;
+  g.partial = P->gpart;
+  g.coord_scale = P->coord_scale;
+  g.out_scale = P->out_scale;
+  const GammaPlan gp = gamma_plan(g.nr, g.nc, P->b, P->d.precision);
+  g.nsplit = gp.nsplit;
+  g.cols_per_split = gp.cols_per_split;
+  return g;
+}
+
+int apply_block(Problem* P, int form, const double* X, int64_t ldx, double* Y, int64_t ldy, int nv, hipStream_t s) {
+  int rc;
+  if ((rc = apply_pre(P, form, X, ldx, nv, s))) return rc;
+  if ((rc = gamma_step(P, P->w32b, P->w32a, s))) return rc;
+  return apply_post(P, form, Y, ldy, nv, s);
 }
 
 int solve_block(Problem* P, int op, double* X, int64_t ld, int nv, hipStream_t s) {

@@ -202,39 +202,55 @@ hipError_t chol_upper_inv(const double* G, int n, int ldg, double* Rinv, int ldr
 }
 
 // ---------------------------------------------------------------------------
-// Symmetric eigensolve by parallel cyclic Jacobi (round-robin pairing), one
-// workgroup.  A (n x n) is copied to `work`; eigenvectors accumulate in S.
-// Output: theta descending, S columns in the same order.
+// Symmetric eigensolve by parallel cyclic Jacobi, one workgroup.  Each sweep
+// runs ne-1 rounds of ne/2 disjoint rotations in round-robin order (circle
+// method: index ne-1 meets r, and (r+i) meets (r-i) mod ne-1).  A round
+// updates A <- J^T A J one 2x2 block (pair k1, pair k2) per work item, so a
+// round costs two barriers.  A lives in LDS for ne <= 128, else in `work`;
+// eigenvectors accumulate in `work`.  Output: theta descending, S columns in
+// the same order.
 // ---------------------------------------------------------------------------
 constexpr int kEigThreads = 1024;
 constexpr int kEigMax = 1024;
+constexpr int kEigLds = 128;
 
 size_t sym_eig_work(int n) {
   const int ne = n + (n & 1);
   return (size_t)ne * ne * 2 + 4 * (size_t)ne;
 }
 
+__device__ __forceinline__ void rr_pair(int r, int k, int ne, int& p, int& q) {
+  const int m = ne - 1;
+  int a, b;
+  if (k == 0) {
+    a = m;
+    b = r;
+  } else {
+    a = (r + k) % m;
+    b = (r - k + m) % m;
+  }
+  p = a < b ? a : b;
+  q = a < b ? b : a;
+}
+
+template <bool LDS>
 __global__ __launch_bounds__(kEigThreads) void jacobi_kernel(const double* __restrict__ H, int n, int ldh,
                                                               double* __restrict__ theta, double* __restrict__ S,
                                                               int lds, double* __restrict__ work) {
   const int ne = n + (n & 1);       // even size (a dummy index when n is odd)
-  double* A = work;                 // ne x ne, column-major
+  __shared__ double A_lds[LDS ? kEigLds * kEigLds : 1];
+  double* A = LDS ? A_lds : work;   // ne x ne, column-major
   double* V = work + (size_t)ne * ne;
   double* tmpv = work + (size_t)2 * ne * ne;
-  __shared__ int top[kEigMax / 2], bot[kEigMax / 2];
+  __shared__ int pp[kEigMax / 2], qq[kEigMax / 2];
   __shared__ double cs[kEigMax / 2], sn[kEigMax / 2];
-  __shared__ double red[kEigThreads];
-  __shared__ int done;
+  __shared__ double red[2][kEigThreads / 64];
   const int t = threadIdx.x, nt = blockDim.x;
   const int half = ne / 2;
   for (int64_t e = t; e < (int64_t)ne * ne; e += nt) {
     const int i = (int)(e % ne), j = (int)(e / ne);
     A[e] = (i < n && j < n) ? 0.5 * (H[i + (int64_t)j * ldh] + H[j + (int64_t)i * ldh]) : 0.0;
     V[e] = (i == j) ? 1.0 : 0.0;
-  }
-  for (int k = t; k < half; k += nt) {
-    top[k] = 2 * k;
-    bot[k] = 2 * k + 1;
   }
   __syncthreads();
   for (int sweep = 0; sweep < 40; ++sweep) {
@@ -246,30 +262,32 @@ __global__ __launch_bounds__(kEigThreads) void jacobi_kernel(const double* __res
       tot += a2;
       if (i != j) off += a2;
     }
-    red[t] = off;
-    __syncthreads();
-    for (int w = nt / 2; w > 0; w >>= 1) {
-      if (t < w) red[t] += red[t + w];
-      __syncthreads();
+    for (int o = 32; o > 0; o >>= 1) {
+      off += __shfl_xor(off, o);
+      tot += __shfl_xor(tot, o);
     }
-    const double offs = red[0];
-    __syncthreads();
-    red[t] = tot;
-    __syncthreads();
-    for (int w = nt / 2; w > 0; w >>= 1) {
-      if (t < w) red[t] += red[t + w];
-      __syncthreads();
+    if ((t & 63) == 0) {
+      red[0][t >> 6] = off;
+      red[1][t >> 6] = tot;
     }
-    if (t == 0) done = (offs <= 1e-30 * red[0]) || red[0] == 0.0;
     __syncthreads();
-    if (done) break;
+    double offs = 0.0, tots = 0.0;
+    for (int w = 0; w < nt / 64; ++w) {
+      offs += red[0][w];
+      tots += red[1][w];
+    }
+    __syncthreads();
+    if (offs <= 1e-30 * tots || tots == 0.0) break;
     for (int round = 0; round < ne - 1; ++round) {
       for (int k = t; k < half; k += nt) {
-        const int p = min(top[k], bot[k]), q = max(top[k], bot[k]);
+        int p, q;
+        rr_pair(round, k, ne, p, q);
+        pp[k] = p;
+        qq[k] = q;
         const double apq = A[p + (int64_t)q * ne];
         const double app = A[p + (int64_t)p * ne], aqq = A[q + (int64_t)q * ne];
         double c = 1.0, s = 0.0;
-        if (apq != 0.0 && fabs(apq) > 1e-300) {
+        if (fabs(apq) > 1e-300) {
           const double tau = (aqq - app) / (2.0 * apq);
           const double tt = (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
           c = 1.0 / sqrt(1.0 + tt * tt);
@@ -279,39 +297,33 @@ __global__ __launch_bounds__(kEigThreads) void jacobi_kernel(const double* __res
         sn[k] = s;
       }
       __syncthreads();
-      // rows: A <- J^T A
-      for (int64_t e = t; e < (int64_t)half * ne; e += nt) {
-        const int k = (int)(e % half), l = (int)(e / half);
-        const int p = min(top[k], bot[k]), q = max(top[k], bot[k]);
-        const double c = cs[k], s = sn[k];
-        if (s == 0.0) continue;
-        const double ap = A[p + (int64_t)l * ne], aq = A[q + (int64_t)l * ne];
-        A[p + (int64_t)l * ne] = c * ap - s * aq;
-        A[q + (int64_t)l * ne] = s * ap + c * aq;
+      // A <- J^T A J, one 2 x 2 block per item (rows of pair k1, columns of pair k2)
+      for (int64_t e = t; e < (int64_t)half * half; e += nt) {
+        const int k1 = (int)(e % half), k2 = (int)(e / half);
+        const double c1 = cs[k1], s1 = sn[k1], c2 = cs[k2], s2 = sn[k2];
+        if (s1 == 0.0 && s2 == 0.0) continue;
+        const int p1 = pp[k1], q1 = qq[k1], p2 = pp[k2], q2 = qq[k2];
+        double* a00 = A + p1 + (int64_t)p2 * ne;
+        double* a01 = A + p1 + (int64_t)q2 * ne;
+        double* a10 = A + q1 + (int64_t)p2 * ne;
+        double* a11 = A + q1 + (int64_t)q2 * ne;
+        const double b00 = *a00, b01 = *a01, b10 = *a10, b11 = *a11;
+        const double rpp = c1 * b00 - s1 * b10, rpq = c1 * b01 - s1 * b11;
+        const double rqp = s1 * b00 + c1 * b10, rqq = s1 * b01 + c1 * b11;
+        *a00 = c2 * rpp - s2 * rpq;
+        *a01 = s2 * rpp + c2 * rpq;
+        *a10 = c2 * rqp - s2 * rqq;
+        *a11 = s2 * rqp + c2 * rqq;
       }
-      __syncthreads();
-      // columns: A <- A J, V <- V J
+      // V <- V J
       for (int64_t e = t; e < (int64_t)half * ne; e += nt) {
         const int l = (int)(e % ne), k = (int)(e / ne);
-        const int p = min(top[k], bot[k]), q = max(top[k], bot[k]);
         const double c = cs[k], s = sn[k];
         if (s == 0.0) continue;
-        const double ap = A[l + (int64_t)p * ne], aq = A[l + (int64_t)q * ne];
-        A[l + (int64_t)p * ne] = c * ap - s * aq;
-        A[l + (int64_t)q * ne] = s * ap + c * aq;
+        const int p = pp[k], q = qq[k];
         const double vp = V[l + (int64_t)p * ne], vq = V[l + (int64_t)q * ne];
         V[l + (int64_t)p * ne] = c * vp - s * vq;
         V[l + (int64_t)q * ne] = s * vp + c * vq;
-      }
-      __syncthreads();
-      // round-robin rotation: top[0] fixed
-      if (t == 0 && half > 1) {
-        const int last_top = top[half - 1];
-        const int first_bot = bot[0];
-        for (int k = half - 1; k > 1; --k) top[k] = top[k - 1];
-        top[1] = first_bot;
-        for (int k = 0; k < half - 1; ++k) bot[k] = bot[k + 1];
-        bot[half - 1] = last_top;
       }
       __syncthreads();
     }
@@ -335,7 +347,11 @@ hipError_t sym_eig(const double* H, int n, int ldh, double* theta, double* S, in
                    hipStream_t s) {
   if (n <= 0) return hipSuccess;
   if (n > kEigMax - 1) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(jacobi_kernel, dim3(1), dim3(kEigThreads), 0, s, H, n, ldh, theta, S, lds, work);
+  const int ne = n + (n & 1);
+  if (ne <= kEigLds)
+    hipLaunchKernelGGL(jacobi_kernel<true>, dim3(1), dim3(kEigThreads), 0, s, H, n, ldh, theta, S, lds, work);
+  else
+    hipLaunchKernelGGL(jacobi_kernel<false>, dim3(1), dim3(kEigThreads), 0, s, H, n, ldh, theta, S, lds, work);
   return hipGetLastError();
 }
 

@@ -9,10 +9,14 @@
 //   Cholesky-QR twice; a rank-deficient block is replaced by fresh random
 //   vectors), and when X is full: Rayleigh-Ritz (small dense eigensolve of H),
 //   residuals |A'y - theta y|, convergence test, thick restart keeping the
-//   leading nev Ritz vectors (X <- X S, AX <- AX S, H <- diag(theta)).
-// Galerkin (symmetric A'): parallel Jacobi on H.  Collocation (A' = Z^-1 A,
-// non-symmetric): Hessenberg QR on H, restart onto an orthonormal basis of
-// the wanted Ritz vectors.
+//   leading nev Ritz vectors.
+// Galerkin (symmetric A'): parallel Jacobi on H, X <- X S, H <- diag(theta).
+// Collocation (A' = Z^-1 A, non-symmetric): Hessenberg QR on H, restart onto
+// an orthonormal basis of the wanted Ritz vectors, H <- W^T S^T H S W.
+//
+// The solve is a resumable state machine (EigRun): pre_apply() issues the
+// operator steps up to the kernel product, the caller runs the product
+// (alone, or batched with other problems), post_apply() finishes the step.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -23,7 +27,7 @@
 #include <string>
 #include <vector>
 
-#include "ka_internal.hpp"
+#include "eigrun.hpp"
 
 namespace ka {
 
@@ -42,15 +46,6 @@ namespace ka {
 
 namespace {
 
-struct EigWork {
-  double *X = nullptr, *AX = nullptr, *P = nullptr, *XS = nullptr, *AXS = nullptr, *R = nullptr, *T = nullptr;
-  double *H = nullptr, *Hc = nullptr, *C = nullptr, *G = nullptr, *Rinv = nullptr, *theta = nullptr,
-         *thetai = nullptr, *S = nullptr, *norms = nullptr, *ework = nullptr, *tnwork = nullptr,
-         *nwork = nullptr, *Wm = nullptr, *Gm = nullptr;
-  int* status = nullptr;
-};
-
-// small device kernels local to the solver
 __global__ void mirror_kernel(double* H, int ld, int k, int pw) {
   // H[k + j][i] = H[i][k + j] for i < k, j < pw  (column-major: (r, c) at r + c ld)
   const int id = blockIdx.x * blockDim.x + threadIdx.x;
@@ -84,40 +79,73 @@ __global__ void inv_sqrt_kernel(const double* g, int n, double* out) {
   if (i < n) out[i] = g[i] > 0.0 ? 1.0 / sqrt(g[i]) : 0.0;
 }
 
-class Solver {
- public:
-  Solver(Problem* P) : P_(P), s_(P->stream) {
-    const char* v = std::getenv("KA_VERBOSE");
-    verbose_ = v && v[0] && v[0] != '0';
+}  // namespace
+
+// ---- sizes ----------------------------------------------------------------
+static void basis_sizes(int64_t N, int M, int b, int& nev, int& m_max, bool& full) {
+  nev = (int)std::min<int64_t>(N, (int64_t)M + b);
+  const int nb = std::max(2, (nev + 2 * b - 1) / (2 * b));
+  m_max = nev + nb * b;
+  full = false;
+  if ((int64_t)m_max >= N) {   // small problem: the Krylov space becomes the whole space
+    m_max = (int)N;
+    full = true;
   }
-  ~Solver() {}
-  int run(int M, double tol, int maxit, double* lambda_host, double* V_dev, ka_info* info);
+}
 
- private:
-  int alloc(size_t bytes, double** out);
-  int orth_block(int k, int pw, uint64_t& rng_counter);
-  Problem* P_;
-  hipStream_t s_;
-  EigWork w_;
-  std::vector<DevBuf> bufs_;
-  bool verbose_ = false;
-  double noise_ = 0.0;
-};
+static size_t tn_work_doubles(int m_max, int b, int64_t N) {
+  size_t tnw = (size_t)m_max * m_max;
+  for (int m = 1; m <= m_max; ++m) {
+    tnw = std::max(tnw, dgemm_tn_work(m, b, N));
+    tnw = std::max(tnw, dgemm_tn_work(b, m, N));
+  }
+  return tnw;
+}
 
-int Solver::alloc(size_t bytes, double** out) {
+size_t eig_workspace_bytes(int64_t N, int M, int b) {
+  int nev, m_max;
+  bool full;
+  basis_sizes(N, M, b, nev, m_max, full);
+  const int ncol = nev + 1;
+  auto al = [](size_t x) { return (x + 255) / 256 * 256 + 256; };
+  size_t s = 0;
+  s += 2 * al((size_t)N * m_max * 8);
+  s += al((size_t)N * b * 8);
+  s += al((size_t)N * std::max(ncol, b) * 8);
+  s += 3 * al((size_t)N * ncol * 8);
+  s += 5 * al((size_t)m_max * m_max * 8);
+  s += al((size_t)m_max * b * 8) + 2 * al((size_t)b * b * 8) + 3 * al((size_t)m_max * 8);
+  s += al(std::max(sym_eig_work(m_max), nonsym_eig_work(m_max)) * 8);
+  s += al(tn_work_doubles(m_max, b, N) * 8);
+  s += al(column_norms_work(N, ncol) * 8) + al(256);
+  return s;
+}
+
+// ---- EigRun -----------------------------------------------------------------
+EigRun::EigRun(Problem* P, int M, double tol, int maxit) : P_(P), s_(P->stream), M_(M), tol_(tol), maxit_(maxit) {
+  const char* v = std::getenv("KA_VERBOSE");
+  verbose_ = v && v[0] && v[0] != '0';
+}
+
+EigRun::~EigRun() {
+  if (!bufs_.empty()) (void)hipStreamSynchronize(s_);
+  for (auto& b : bufs_) (void)hipFree(b.p);
+}
+
+int EigRun::alloc(size_t bytes, double** out) {
   bytes = (bytes + 255) / 256 * 256;
   if (bytes == 0) bytes = 256;
   void* p = nullptr;
   if (hipMalloc(&p, bytes) != hipSuccess) return fail(KA_ERR_OOM, "eigensolver workspace allocation failed");
-  P_->eig_allocs.push_back({p, bytes});
-  P_->eig_bytes += bytes;
+  bufs_.push_back({p, bytes});
+  bytes_ += bytes;
   *out = (double*)p;
   return KA_OK;
 }
 
 // Orthonormalise P (N x pw) against X[:, :k] (block CGS twice) and within
 // itself (Cholesky-QR twice).  Rank-deficient blocks are redrawn at random.
-int Solver::orth_block(int k, int pw, uint64_t& rng_counter) {
+int EigRun::orth_block(int k, int pw) {
   const int64_t N = P_->N;
   for (int attempt = 0; attempt < 4; ++attempt) {
     if (k > 0) {
@@ -139,262 +167,307 @@ int Solver::orth_block(int k, int pw, uint64_t& rng_counter) {
     }
     if (!bad) return KA_OK;
     // Krylov space exhausted along some direction: continue with random ones
-    HIP_TRY(fill_normal(w_.P, N, pw, N, P_->d.seed, ++rng_counter, s_));
+    HIP_TRY(fill_normal(w_.P, N, pw, N, P_->d.seed, ++rng_counter_, s_));
   }
   return fail(KA_ERR_SINGULAR, "could not extend the Krylov basis");
 }
 
-int Solver::run(int M, double tol, int maxit, double* lambda_host, double* V_dev, ka_info* info) {
-  const auto t_start = std::chrono::steady_clock::now();
-  const bool sym = P_->d.method == KA_GALERKIN_IBQ;
+int EigRun::start() {
+  t_start_ = std::chrono::steady_clock::now();
+  sym_ = P_->d.method == KA_GALERKIN_IBQ;
   const int64_t N = P_->N;
   const int b = P_->b;
-  if (M < 1 || M > N) return fail(KA_ERR_ARG, "M must be in 1..N");
-  const double tau = 1e-2;
+  if (M_ < 1 || M_ > N) return fail(KA_ERR_ARG, "M must be in 1..N");
+  if (!(tol_ > 0)) tol_ = 1e-6;
+  if (maxit_ <= 0) maxit_ = 100;
   // Residuals of an operator applied in FP32 (or split BF16) cannot fall
   // below a few units of its rounding times |theta_1|; below that level the
-  // Ritz values no longer move (symmetric case: error ~ r^2 / gap).
-  noise_ = P_->d.precision == KA_FP32 ? 4e-6 : 1e-4;
-  if (!(tol > 0)) tol = 1e-6;
-  if (maxit <= 0) maxit = 100;
-
-  // basis sizes
-  int nev = (int)std::min<int64_t>(N, (int64_t)M + b);
-  const int nb = std::max(2, (nev + 2 * b - 1) / (2 * b));
-  int m_max = nev + nb * b;
-  bool full = false;
-  if ((int64_t)m_max >= N) {   // small problem: the Krylov space becomes the whole space
-    m_max = (int)N;
-    full = true;
-  }
-  if (m_max > 1000) return fail(KA_ERR_ARG, "M too large for the dense Rayleigh-Ritz (M + block <= ~600)");
-
-  // workspace
-  KA_TRY(alloc((size_t)N * m_max * 8, &w_.X));
-  KA_TRY(alloc((size_t)N * m_max * 8, &w_.AX));
+  // Ritz values no longer move.  Symmetric problems tolerate this (eigenvalue
+  // error ~ r^2 / gap); for the non-symmetric collocation operator the error
+  // is first order in r, so its floor is set 20x lower, close to what the
+  // FP32 operator can resolve.
+  if (sym_) noise_ = P_->d.precision == KA_FP32 ? 4e-6 : 1e-4;
+  else noise_ = P_->d.precision == KA_FP32 ? 2e-7 : 5e-6;
+  basis_sizes(N, M_, b, nev_, m_max_, full_);
+  if (m_max_ > 1000) return fail(KA_ERR_ARG, "M too large for the dense Rayleigh-Ritz (M + block <= ~600)");
+  const int ncol = nev_ + 1;   // room for a complex pair that straddles nev
+  const int m = m_max_;
+  KA_TRY(alloc((size_t)N * m * 8, &w_.X));
+  KA_TRY(alloc((size_t)N * m * 8, &w_.AX));
   KA_TRY(alloc((size_t)N * b * 8, &w_.P));
-  const int ncol = nev + 1;   // room for a complex pair that straddles nev
   KA_TRY(alloc((size_t)N * std::max(ncol, b) * 8, &w_.T));
   KA_TRY(alloc((size_t)N * ncol * 8, &w_.XS));
   KA_TRY(alloc((size_t)N * ncol * 8, &w_.AXS));
   KA_TRY(alloc((size_t)N * ncol * 8, &w_.R));
-  KA_TRY(alloc((size_t)m_max * m_max * 8, &w_.Hc));
-  KA_TRY(alloc((size_t)m_max * m_max * 8, &w_.Wm));
-  KA_TRY(alloc((size_t)m_max * m_max * 8, &w_.Gm));
-  KA_TRY(alloc((size_t)m_max * m_max * 8, &w_.H));
-  KA_TRY(alloc((size_t)m_max * b * 8, &w_.C));
+  KA_TRY(alloc((size_t)m * m * 8, &w_.H));
+  KA_TRY(alloc((size_t)m * m * 8, &w_.Hc));
+  KA_TRY(alloc((size_t)m * m * 8, &w_.Wm));
+  KA_TRY(alloc((size_t)m * m * 8, &w_.Gm));
+  KA_TRY(alloc((size_t)m * m * 8, &w_.S));
+  KA_TRY(alloc((size_t)m * b * 8, &w_.C));
   KA_TRY(alloc((size_t)b * b * 8, &w_.G));
   KA_TRY(alloc((size_t)b * b * 8, &w_.Rinv));
-  KA_TRY(alloc((size_t)m_max * 8, &w_.theta));
-  KA_TRY(alloc((size_t)m_max * 8, &w_.thetai));
-  KA_TRY(alloc((size_t)m_max * m_max * 8, &w_.S));
-  KA_TRY(alloc((size_t)m_max * 8, &w_.norms));
-  KA_TRY(alloc(std::max(sym_eig_work(m_max), nonsym_eig_work(m_max)) * 8, &w_.ework));
-  size_t tnw = (size_t)m_max * m_max;
-  for (int m = 1; m <= m_max; ++m) {
-    tnw = std::max(tnw, dgemm_tn_work(m, b, N));
-    tnw = std::max(tnw, dgemm_tn_work(b, m, N));
-  }
-  KA_TRY(alloc(tnw * 8, &w_.tnwork));
+  KA_TRY(alloc((size_t)m * 8, &w_.theta));
+  KA_TRY(alloc((size_t)m * 8, &w_.thetai));
+  KA_TRY(alloc((size_t)m * 8, &w_.norms));
+  KA_TRY(alloc(std::max(sym_eig_work(m), nonsym_eig_work(m)) * 8, &w_.ework));
+  KA_TRY(alloc(tn_work_doubles(m, b, N) * 8, &w_.tnwork));
   KA_TRY(alloc(column_norms_work(N, ncol) * 8, &w_.nwork));
   {
     double* st = nullptr;
     KA_TRY(alloc(256, &st));
     w_.status = (int*)st;
   }
-  const double pairs0 = P_->pairs_total;
+  th_.assign(m, 0.0);
+  thi_.assign(m, 0.0);
+  rn_.assign(m, 0.0);
+  pairs0_ = P_->pairs_total;
+  HIP_TRY(fill_normal(w_.P, N, b, N, P_->d.seed, rng_counter_, s_));
+  pw_ = (int)std::min<int64_t>(b, m);
+  KA_TRY(orth_block(0, pw_));
+  k_ = 0;
+  return KA_OK;
+}
 
-  uint64_t rng_counter = 0;
-  HIP_TRY(fill_normal(w_.P, N, b, N, P_->d.seed, rng_counter, s_));
-  int pw = (int)std::min<int64_t>(b, m_max);
-  KA_TRY(orth_block(0, pw, rng_counter));
+int EigRun::pre_apply() {
+  const int64_t N = P_->N;
+  HIP_TRY(copy_cols(w_.P, N, w_.X + (size_t)k_ * N, N, N, pw_, s_));
+  return apply_pre(P_, KA_APRIME, w_.X + (size_t)k_ * N, N, pw_, s_);
+}
 
-  int k = 0, cycles = 0, matvecs = 0, nconv = 0, Meff = M, ns_status = 0;
-  double max_res = 0.0, max_imag = 0.0;
-  std::vector<double> th(m_max), rn(m_max), thi(m_max, 0.0);
-  int nret = 0;
-  bool converged = false;
-  while (true) {
-    // append the pending block and apply A'
-    HIP_TRY(copy_cols(w_.P, N, w_.X + (size_t)k * N, N, N, pw, s_));
-    KA_TRY(apply_block(P_, KA_APRIME, w_.X + (size_t)k * N, N, w_.AX + (size_t)k * N, N, pw, s_));
-    ++matvecs;
-    // H[0:k+pw, k:k+pw] = X^T AP ; mirror into H[k:k+pw, 0:k]
-    HIP_TRY(dgemm_tn(k + pw, pw, N, 1.0, w_.X, N, w_.AX + (size_t)k * N, N, 0.0, w_.H + (size_t)k * m_max, m_max,
-                     w_.tnwork, s_));
-    if (sym) {
-      hipLaunchKernelGGL(symmetrize_block_kernel, dim3((pw * pw + 255) / 256), dim3(256), 0, s_, w_.H, m_max, k, pw);
-      if (k > 0)
-        hipLaunchKernelGGL(mirror_kernel, dim3((k * pw + 255) / 256), dim3(256), 0, s_, w_.H, m_max, k, pw);
-      HIP_TRY(hipGetLastError());
-    } else if (k > 0) {
-      // new rows: H[k:k+pw, 0:k] = P^T A' X
-      HIP_TRY(dgemm_tn(pw, k, N, 1.0, w_.X + (size_t)k * N, N, w_.AX, N, 0.0, w_.H + k, m_max, w_.tnwork, s_));
-    }
-    k += pw;
-    // next pending block
-    const int room = m_max - k;
-    const bool need_rr = full ? (k >= m_max) : (room < b);
-    int next_pw = full ? std::min(b, m_max - k) : b;
-    if (next_pw > 0) {
-      HIP_TRY(copy_cols(w_.AX + (size_t)(k - pw) * N, N, w_.P, N, N, std::min(pw, next_pw), s_));
-      if (next_pw > pw) HIP_TRY(fill_normal(w_.P + (size_t)pw * N, N, next_pw - pw, N, P_->d.seed, ++rng_counter, s_));
-      KA_TRY(orth_block(k, next_pw, rng_counter));
-    }
-    if (!need_rr) {
-      pw = next_pw;
-      continue;
-    }
-    // Rayleigh-Ritz
-    int nk;
-    if (sym) {
-      HIP_TRY(sym_eig(w_.H, k, m_max, w_.theta, w_.S, m_max, w_.ework, s_));
-      nk = std::min(nev, k);
-    } else {
-      HIP_TRY(nonsym_eig(w_.H, k, m_max, w_.theta, w_.thetai, w_.S, m_max, w_.ework, w_.status, s_));
-      nk = std::min(nev + 1, k);
-    }
-    HIP_TRY(dgemm_nn(N, nk, k, 1.0, w_.X, N, w_.S, m_max, 0.0, w_.XS, N, s_));
-    HIP_TRY(dgemm_nn(N, nk, k, 1.0, w_.AX, N, w_.S, m_max, 0.0, w_.AXS, N, s_));
-    HIP_TRY(residual_combine(w_.AXS, w_.XS, N, nk, N, w_.theta, sym ? nullptr : w_.thetai, w_.R, s_));
-    HIP_TRY(column_norms(w_.R, N, nk, N, w_.norms, w_.nwork, s_));
-    HIP_TRY(hipMemcpyAsync(th.data(), w_.theta, sizeof(double) * nk, hipMemcpyDeviceToHost, s_));
-    HIP_TRY(hipMemcpyAsync(rn.data(), w_.norms, sizeof(double) * nk, hipMemcpyDeviceToHost, s_));
-    if (!sym) {
-      HIP_TRY(hipMemcpyAsync(thi.data(), w_.thetai, sizeof(double) * nk, hipMemcpyDeviceToHost, s_));
-      HIP_TRY(hipMemcpyAsync(&ns_status, w_.status, sizeof(int), hipMemcpyDeviceToHost, s_));
-    }
-    HIP_TRY(hipStreamSynchronize(s_));
-    ++cycles;
-    if (!sym && ns_status != 0) return fail(KA_ERR_SINGULAR, "Rayleigh-Ritz QR iteration did not converge");
-    if (!sym) {
-      // a complex pair shares one residual (re and im parts of one unit vector)
-      for (int i = 0; i + 1 < nk; ++i)
-        if (thi[i] > 0.0) {
-          rn[i] = rn[i + 1] = std::sqrt(rn[i] * rn[i] + rn[i + 1] * rn[i + 1]);
-          ++i;
-        }
-    }
-    auto modulus = [&](int i) { return sym ? std::fabs(th[i]) : std::hypot(th[i], thi[i]); };
-    // extend M to the end of its cluster (relative gap below 1e-6) or pair
-    const int nlim = sym ? nk : std::min(nev, k);
-    Meff = std::min(M, nlim);
-    while (Meff < nlim && std::fabs(th[Meff - 1] - th[Meff]) <= 1e-6 * std::fabs(th[Meff - 1])) ++Meff;
-    if (!sym && Meff < nk && thi[Meff - 1] > 0.0) ++Meff;
-    const double floor_ = std::max(tol * tau, noise_) * modulus(0);
-    nconv = 0;
-    max_res = 0.0;
-    max_imag = 0.0;
-    for (int i = 0; i < Meff; ++i) {
-      const double crit = std::max(tol * modulus(i), floor_);
-      const double rel = rn[i] / std::max(modulus(i), tau * modulus(0));
-      if (i < M) {
-        max_res = std::max(max_res, rel);
-        if (!sym) max_imag = std::max(max_imag, std::fabs(thi[i]) / modulus(i));
+int EigRun::rayleigh_ritz(bool& stop) {
+  const int64_t N = P_->N;
+  const int m = m_max_;
+  const int k = k_;
+  int nk;
+  int ns_status = 0;
+  if (sym_) {
+    HIP_TRY(sym_eig(w_.H, k, m, w_.theta, w_.S, m, w_.ework, s_));
+    nk = std::min(nev_, k);
+  } else {
+    HIP_TRY(nonsym_eig(w_.H, k, m, w_.theta, w_.thetai, w_.S, m, w_.ework, w_.status, s_));
+    nk = std::min(nev_ + 1, k);
+  }
+  HIP_TRY(dgemm_nn(N, nk, k, 1.0, w_.X, N, w_.S, m, 0.0, w_.XS, N, s_));
+  HIP_TRY(dgemm_nn(N, nk, k, 1.0, w_.AX, N, w_.S, m, 0.0, w_.AXS, N, s_));
+  HIP_TRY(residual_combine(w_.AXS, w_.XS, N, nk, N, w_.theta, sym_ ? nullptr : w_.thetai, w_.R, s_));
+  HIP_TRY(column_norms(w_.R, N, nk, N, w_.norms, w_.nwork, s_));
+  HIP_TRY(hipMemcpyAsync(th_.data(), w_.theta, sizeof(double) * nk, hipMemcpyDeviceToHost, s_));
+  HIP_TRY(hipMemcpyAsync(rn_.data(), w_.norms, sizeof(double) * nk, hipMemcpyDeviceToHost, s_));
+  if (!sym_) {
+    HIP_TRY(hipMemcpyAsync(thi_.data(), w_.thetai, sizeof(double) * nk, hipMemcpyDeviceToHost, s_));
+    HIP_TRY(hipMemcpyAsync(&ns_status, w_.status, sizeof(int), hipMemcpyDeviceToHost, s_));
+  }
+  HIP_TRY(hipStreamSynchronize(s_));
+  ++cycles_;
+  if (!sym_ && ns_status != 0) return fail(KA_ERR_SINGULAR, "Rayleigh-Ritz QR iteration did not converge");
+  if (!sym_) {
+    // a complex pair shares one residual (re and im parts of one unit vector)
+    for (int i = 0; i + 1 < nk; ++i)
+      if (thi_[i] > 0.0) {
+        rn_[i] = rn_[i + 1] = std::sqrt(rn_[i] * rn_[i] + rn_[i + 1] * rn_[i + 1]);
+        ++i;
       }
-      if (rn[i] <= crit && nconv == i) ++nconv;
-    }
-    nret = sym ? nk : std::min(nk, Meff + 1);
-    converged = nconv >= Meff;
-    if (verbose_) {
-      double rmax = 0.0;
-      for (int i = 0; i < Meff; ++i) rmax = std::max(rmax, rn[i] / modulus(0));
-      std::fprintf(stderr, "[ka_eigs] cycle %d k %d matvecs %d nconv %d/%d max_rel %.3e max_abs/theta1 %.3e theta1 %.6e\n",
-                   cycles, k, matvecs, nconv, Meff, max_res, rmax, th[0]);
-    }
-    if (converged || cycles >= maxit || full) break;
-    // thick restart onto the leading Ritz vectors
-    if (sym) {
-      HIP_TRY(copy_cols(w_.XS, N, w_.X, N, N, nk, s_));
-      HIP_TRY(copy_cols(w_.AXS, N, w_.AX, N, N, nk, s_));
-      hipLaunchKernelGGL(set_diag_kernel, dim3((nk * nk + 255) / 256), dim3(256), 0, s_, w_.H, m_max, nk, w_.theta);
-      HIP_TRY(hipGetLastError());
-      k = nk;
-    } else {
-      int nkeep = std::min(nev, k);
-      if (nkeep < nk && thi[nkeep - 1] > 0.0) ++nkeep;
-      // orthonormal basis of the kept Ritz vectors: W = V Lambda^-1/2 from S^T S = V Lambda V^T
-      HIP_TRY(dgemm_tn(nkeep, nkeep, k, 1.0, w_.S, m_max, w_.S, m_max, 0.0, w_.Gm, m_max, w_.tnwork, s_));
-      HIP_TRY(sym_eig(w_.Gm, nkeep, m_max, w_.norms, w_.Wm, m_max, w_.ework, s_));
-      std::vector<double> gl(nkeep);
-      HIP_TRY(hipMemcpyAsync(gl.data(), w_.norms, sizeof(double) * nkeep, hipMemcpyDeviceToHost, s_));
-      HIP_TRY(hipStreamSynchronize(s_));
-      int good = 0;
-      while (good < nkeep && gl[good] > 1e-12 * gl[0]) ++good;
-      hipLaunchKernelGGL(inv_sqrt_kernel, dim3((good + 63) / 64), dim3(64), 0, s_, w_.norms, good, w_.norms);
-      HIP_TRY(hipGetLastError());
-      HIP_TRY(scale_cols(w_.Wm, nkeep, good, m_max, w_.norms, s_));
-      // X <- XS W, AX <- AXS W
-      HIP_TRY(dgemm_nn(N, good, nkeep, 1.0, w_.XS, N, w_.Wm, m_max, 0.0, w_.T, N, s_));
-      HIP_TRY(copy_cols(w_.T, N, w_.X, N, N, good, s_));
-      HIP_TRY(dgemm_nn(N, good, nkeep, 1.0, w_.AXS, N, w_.Wm, m_max, 0.0, w_.T, N, s_));
-      HIP_TRY(copy_cols(w_.T, N, w_.AX, N, N, good, s_));
-      // H <- W^T S^T H S W
-      HIP_TRY(dgemm_nn(k, nkeep, k, 1.0, w_.H, m_max, w_.S, m_max, 0.0, w_.Hc, m_max, s_));
-      HIP_TRY(dgemm_tn(nkeep, nkeep, k, 1.0, w_.S, m_max, w_.Hc, m_max, 0.0, w_.Gm, m_max, w_.tnwork, s_));
-      HIP_TRY(dgemm_nn(nkeep, good, nkeep, 1.0, w_.Gm, m_max, w_.Wm, m_max, 0.0, w_.Hc, m_max, s_));
-      HIP_TRY(dgemm_tn(good, good, nkeep, 1.0, w_.Wm, m_max, w_.Hc, m_max, 0.0, w_.H, m_max, w_.tnwork, s_));
-      k = good;
-    }
-    pw = b;
   }
-  if (full) converged = true, nconv = std::max(nconv, Meff);
+  const double tau = 1e-2;
+  // extend M to the end of its cluster (relative gap below 1e-6) or pair
+  const int nlim = sym_ ? nk : std::min(nev_, k);
+  Meff_ = std::min(M_, nlim);
+  while (Meff_ < nlim && std::fabs(th_[Meff_ - 1] - th_[Meff_]) <= 1e-6 * std::fabs(th_[Meff_ - 1])) ++Meff_;
+  if (!sym_ && Meff_ < nk && thi_[Meff_ - 1] > 0.0) ++Meff_;
+  const double floor_ = std::max(tol_ * tau, noise_) * modulus(0);
+  nconv_ = 0;
+  max_res_ = 0.0;
+  max_imag_ = 0.0;
+  for (int i = 0; i < Meff_; ++i) {
+    const double crit = std::max(tol_ * modulus(i), floor_);
+    const double rel = rn_[i] / std::max(modulus(i), tau * modulus(0));
+    if (i < M_) {
+      max_res_ = std::max(max_res_, rel);
+      if (!sym_) max_imag_ = std::max(max_imag_, std::fabs(thi_[i]) / modulus(i));
+    }
+    if (rn_[i] <= crit && nconv_ == i) ++nconv_;
+  }
+  nret_ = sym_ ? nk : std::min(nk, Meff_ + 1);
+  converged_ = nconv_ >= Meff_;
+  // stagnation: three restart cycles without a 10% drop of the largest
+  // scaled residual end the iteration (KA_NOT_CONVERGED, results valid)
+  if (max_res_ < 0.9 * best_res_) {
+    best_res_ = max_res_;
+    stall_ = 0;
+  } else {
+    ++stall_;
+  }
+  if (verbose_) {
+    double rmax = 0.0;
+    for (int i = 0; i < Meff_; ++i) rmax = std::max(rmax, rn_[i] / modulus(0));
+    std::fprintf(stderr, "[ka_eigs] cycle %d k %d matvecs %d nconv %d/%d max_rel %.3e max_abs/theta1 %.3e theta1 %.6e\n",
+                 cycles_, k, matvecs_, nconv_, Meff_, max_res_, rmax, th_[0]);
+  }
+  if (converged_ || cycles_ >= maxit_ || full_ || stall_ >= 3) {
+    stop = true;
+    return KA_OK;
+  }
+  stop = false;
+  // thick restart onto the leading Ritz vectors
+  if (sym_) {
+    HIP_TRY(copy_cols(w_.XS, N, w_.X, N, N, nk, s_));
+    HIP_TRY(copy_cols(w_.AXS, N, w_.AX, N, N, nk, s_));
+    hipLaunchKernelGGL(set_diag_kernel, dim3((nk * nk + 255) / 256), dim3(256), 0, s_, w_.H, m, nk, w_.theta);
+    HIP_TRY(hipGetLastError());
+    k_ = nk;
+  } else {
+    int nkeep = std::min(nev_, k);
+    if (nkeep < nk && thi_[nkeep - 1] > 0.0) ++nkeep;
+    // orthonormal basis of the kept Ritz vectors: W = V Lambda^-1/2 from S^T S = V Lambda V^T
+    HIP_TRY(dgemm_tn(nkeep, nkeep, k, 1.0, w_.S, m, w_.S, m, 0.0, w_.Gm, m, w_.tnwork, s_));
+    HIP_TRY(sym_eig(w_.Gm, nkeep, m, w_.norms, w_.Wm, m, w_.ework, s_));
+    std::vector<double> gl(nkeep);
+    HIP_TRY(hipMemcpyAsync(gl.data(), w_.norms, sizeof(double) * nkeep, hipMemcpyDeviceToHost, s_));
+    HIP_TRY(hipStreamSynchronize(s_));
+    int good = 0;
+    while (good < nkeep && gl[good] > 1e-12 * gl[0]) ++good;
+    hipLaunchKernelGGL(inv_sqrt_kernel, dim3((good + 63) / 64), dim3(64), 0, s_, w_.norms, good, w_.norms);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(scale_cols(w_.Wm, nkeep, good, m, w_.norms, s_));
+    // X <- XS W, AX <- AXS W
+    HIP_TRY(dgemm_nn(N, good, nkeep, 1.0, w_.XS, N, w_.Wm, m, 0.0, w_.T, N, s_));
+    HIP_TRY(copy_cols(w_.T, N, w_.X, N, N, good, s_));
+    HIP_TRY(dgemm_nn(N, good, nkeep, 1.0, w_.AXS, N, w_.Wm, m, 0.0, w_.T, N, s_));
+    HIP_TRY(copy_cols(w_.T, N, w_.AX, N, N, good, s_));
+    // H <- W^T S^T H S W
+    HIP_TRY(dgemm_nn(k, nkeep, k, 1.0, w_.H, m, w_.S, m, 0.0, w_.Hc, m, s_));
+    HIP_TRY(dgemm_tn(nkeep, nkeep, k, 1.0, w_.S, m, w_.Hc, m, 0.0, w_.Gm, m, w_.tnwork, s_));
+    HIP_TRY(dgemm_nn(nkeep, good, nkeep, 1.0, w_.Gm, m, w_.Wm, m, 0.0, w_.Hc, m, s_));
+    HIP_TRY(dgemm_tn(good, good, nkeep, 1.0, w_.Wm, m, w_.Hc, m, 0.0, w_.H, m, w_.tnwork, s_));
+    k_ = good;
+  }
+  pw_ = P_->b;
+  return KA_OK;
+}
 
-  // outputs.  Galerkin: v = L^-T y (Z-orthonormal).  Collocation: v = y
-  // (unit 2-norm; complex pairs as re, im columns).
-  const int Mo = std::min(M, nret);
-  for (int i = 0; i < Mo; ++i) {
-    if (sym) {
-      lambda_host[i] = th[i];
-    } else {
-      lambda_host[2 * i] = th[i];
-      lambda_host[2 * i + 1] = thi[i];
+int EigRun::post_apply(bool& done) {
+  const int64_t N = P_->N;
+  const int b = P_->b;
+  const int m = m_max_;
+  done = false;
+  KA_TRY(apply_post(P_, KA_APRIME, w_.AX + (size_t)k_ * N, N, pw_, s_));
+  ++matvecs_;
+  // H[0:k+pw, k:k+pw] = X^T AP
+  HIP_TRY(dgemm_tn(k_ + pw_, pw_, N, 1.0, w_.X, N, w_.AX + (size_t)k_ * N, N, 0.0, w_.H + (size_t)k_ * m, m,
+                   w_.tnwork, s_));
+  if (sym_) {
+    hipLaunchKernelGGL(symmetrize_block_kernel, dim3((pw_ * pw_ + 255) / 256), dim3(256), 0, s_, w_.H, m, k_, pw_);
+    if (k_ > 0)
+      hipLaunchKernelGGL(mirror_kernel, dim3((k_ * pw_ + 255) / 256), dim3(256), 0, s_, w_.H, m, k_, pw_);
+    HIP_TRY(hipGetLastError());
+  } else if (k_ > 0) {
+    // new rows: H[k:k+pw, 0:k] = P^T A' X
+    HIP_TRY(dgemm_tn(pw_, k_, N, 1.0, w_.X + (size_t)k_ * N, N, w_.AX, N, 0.0, w_.H + k_, m, w_.tnwork, s_));
+  }
+  k_ += pw_;
+  // next pending block
+  const int room = m - k_;
+  const bool need_rr = full_ ? (k_ >= m) : (room < b);
+  const int next_pw = full_ ? std::min(b, m - k_) : b;
+  if (next_pw > 0) {
+    HIP_TRY(copy_cols(w_.AX + (size_t)(k_ - pw_) * N, N, w_.P, N, N, std::min(pw_, next_pw), s_));
+    if (next_pw > pw_)
+      HIP_TRY(fill_normal(w_.P + (size_t)pw_ * N, N, next_pw - pw_, N, P_->d.seed, ++rng_counter_, s_));
+    KA_TRY(orth_block(k_, next_pw));
+  }
+  if (!need_rr) {
+    pw_ = next_pw;
+    return KA_OK;
+  }
+  return rayleigh_ritz(done);
+}
+
+int EigRun::finish(double* lambda_host, double* V_dev, ka_info* info) {
+  const int64_t N = P_->N;
+  const int b = P_->b;
+  if (full_) {
+    converged_ = true;
+    nconv_ = std::max(nconv_, Meff_);
+  }
+  // Galerkin: v = L^-T y (Z-orthonormal).  Collocation: v = y (unit 2-norm;
+  // a genuine complex pair as re, im columns).  Imaginary parts at the
+  // arithmetic noise level (a cluster split into a complex pair by rounding)
+  // are reported as zero and both columns as real vectors.
+  const int Mo = std::min(M_, nret_);
+  std::vector<double> wi_out(std::max(Mo, 1), 0.0);
+  if (!sym_) {
+    const double real_tol = 10.0 * noise_;
+    for (int i = 0; i < Mo; ++i) {
+      const bool pair_start = thi_[i] > 0.0 && i + 1 < nret_;
+      if (pair_start && std::fabs(thi_[i]) > real_tol * modulus(i)) {
+        wi_out[i] = thi_[i];
+        if (i + 1 < Mo) wi_out[i + 1] = thi_[i + 1];
+        ++i;
+      } else if (pair_start) {
+        ++i;
+      }
     }
   }
-  for (int i = Mo; i < M; ++i) {
-    if (sym) lambda_host[i] = 0.0;
+  for (int i = 0; i < Mo; ++i) {
+    if (sym_) {
+      lambda_host[i] = th_[i];
+    } else {
+      lambda_host[2 * i] = th_[i];
+      lambda_host[2 * i + 1] = wi_out[i];
+    }
+  }
+  for (int i = Mo; i < M_; ++i) {
+    if (sym_) lambda_host[i] = 0.0;
     else lambda_host[2 * i] = lambda_host[2 * i + 1] = 0.0;
   }
   if (V_dev && Mo > 0) {
-    if (sym) {
+    if (sym_) {
       for (int c0 = 0; c0 < Mo; c0 += b) {
         const int nv = std::min(b, Mo - c0);
         KA_TRY(solve_block(P_, KA_LTINV, w_.XS + (size_t)c0 * N, N, nv, s_));
       }
+      HIP_TRY(sign_fix(w_.XS, N, Mo, N, nullptr, s_));
+    } else {
+      // columns reported as real get unit norm each
+      std::vector<double> nrm(Mo), sc(Mo);
+      HIP_TRY(column_norms(w_.XS, N, Mo, N, w_.norms, w_.nwork, s_));
+      HIP_TRY(hipMemcpyAsync(nrm.data(), w_.norms, sizeof(double) * Mo, hipMemcpyDeviceToHost, s_));
+      HIP_TRY(hipStreamSynchronize(s_));
+      for (int i = 0; i < Mo; ++i) sc[i] = (wi_out[i] == 0.0 && nrm[i] > 0.0) ? 1.0 / nrm[i] : 1.0;
+      HIP_TRY(hipMemcpyAsync(w_.norms, sc.data(), sizeof(double) * Mo, hipMemcpyHostToDevice, s_));
+      HIP_TRY(scale_cols(w_.XS, N, Mo, N, w_.norms, s_));
+      HIP_TRY(hipMemcpyAsync(w_.thetai, wi_out.data(), sizeof(double) * Mo, hipMemcpyHostToDevice, s_));
+      HIP_TRY(sign_fix(w_.XS, N, Mo, N, w_.thetai, s_));
     }
-    HIP_TRY(sign_fix(w_.XS, N, Mo, N, sym ? nullptr : w_.thetai, s_));
     HIP_TRY(copy_cols(w_.XS, N, V_dev, N, N, Mo, s_));
   }
   HIP_TRY(hipStreamSynchronize(s_));
-  const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+  const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start_).count();
   if (info) {
-    info->iterations = cycles;
-    info->matvecs = matvecs;
-    info->converged = std::min(nconv, M);
-    info->nev_computed = Meff;
-    info->max_residual = max_res;
-    info->max_imag_rel = max_imag;
+    info->iterations = cycles_;
+    info->matvecs = matvecs_;
+    info->converged = std::min(nconv_, M_);
+    info->nev_computed = Meff_;
+    info->max_residual = max_res_;
+    info->max_imag_rel = max_imag_;
     info->seconds = secs;
     info->gamma_seconds = 0.0;
-    info->pairs = P_->pairs_total - pairs0;
+    info->pairs = P_->pairs_total - pairs0_;
   }
-  return converged ? KA_OK : KA_NOT_CONVERGED;
+  return converged_ ? KA_OK : KA_NOT_CONVERGED;
 }
 
-}  // namespace
-
 int eigs(Problem* P, int M, double tol, int maxit, double* lambda_host, double* V_dev, ka_info* info) {
-  int rc;
-  {
-    Solver S(P);
-    rc = S.run(M, tol, maxit, lambda_host, V_dev, info);
+  EigRun run(P, M, tol, maxit);
+  KA_TRY(run.start());
+  bool done = false;
+  while (!done) {
+    KA_TRY(run.pre_apply());
+    KA_TRY(gamma_step(P, P->w32b, P->w32a, P->stream));
+    KA_TRY(run.post_apply(done));
   }
-  // release the solver workspace
-  (void)hipStreamSynchronize(P->stream);
-  for (auto& b : P->eig_allocs) (void)hipFree(b.p);
-  P->eig_allocs.clear();
-  P->eig_bytes = 0;
-  return rc;
+  return run.finish(lambda_host, V_dev, info);
 }
 
 }  // namespace ka

@@ -37,7 +37,8 @@ typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
 typedef __bf16 bf2v __attribute__((ext_vector_type(2)));
 
 constexpr int kThreads = 256;
-constexpr int kCT = 64;   // columns per LDS tile
+constexpr int kCT = 64;         // columns per LDS tile
+constexpr int kFlushTiles = 8;  // MFMA accumulators are flushed into running totals every 8 tiles (512 columns)
 
 template <int KERNEL>
 __device__ __forceinline__ float pair_exponent(float dx, float dy, float dz) {
@@ -57,18 +58,23 @@ __device__ __forceinline__ float load_coord(const float* p, int64_t i, int strid
 // ---------------------------------------------------------------------------
 // FP32 path
 // ---------------------------------------------------------------------------
+// LDS row stride of Y in the FP32 path (spreads the 16-lane groups over banks)
+template <int B>
+constexpr int y_stride() { return (B == 16) ? 16 : B + 16; }
+
+// One work item: rows [rblk * ROWS, +ROWS) against the column range of split
+// `split` of one kernel product.  LDS buffers are provided by the caller.
 template <int KERNEL, int B, int RB>
-__global__ __launch_bounds__(kThreads) void gamma_f32_kernel(GammaLaunch a) {
+__device__ __forceinline__ void gamma_f32_tile(const GammaLaunch& a, int64_t rblk, int split,
+                                               float4 (*s_x)[kCT], float (*s_y)[kCT * y_stride<B>()]) {
   constexpr int NT = B / 16;
-  constexpr int YS = (B == 16) ? 16 : B + 16;   // LDS row stride of Y (bank spread)
+  constexpr int YS = y_stride<B>();
   constexpr int ROWS = 4 * 16 * RB;
-  __shared__ float4 s_x[2][kCT];
-  __shared__ float s_y[2][kCT * YS];
 
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
-  const int64_t row0 = (int64_t)blockIdx.x * ROWS + wave * 16 * RB;
-  const int64_t c_begin = (int64_t)blockIdx.y * a.cols_per_split;
+  const int64_t row0 = rblk * ROWS + wave * 16 * RB;
+  const int64_t c_begin = (int64_t)split * a.cols_per_split;
   const int64_t c_end = (c_begin + a.cols_per_split < a.nc) ? c_begin + a.cols_per_split : a.nc;
 
   float rx[RB], ry[RB], rz[RB];
@@ -86,6 +92,24 @@ __global__ __launch_bounds__(kThreads) void gamma_f32_kernel(GammaLaunch a) {
   for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
     for (int t = 0; t < NT; ++t) acc[rb][t] = (f4v){0.f, 0.f, 0.f, 0.f};
+  // Two-level summation: MFMA chains of at most kFlushTiles tiles are added
+  // into running totals, so the rounding error grows with the square roots of
+  // the chain length and of the number of chains, not of the column count.
+  f4v tot[RB][NT];
+#pragma unroll
+  for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+    for (int t = 0; t < NT; ++t) tot[rb][t] = (f4v){0.f, 0.f, 0.f, 0.f};
+  auto flush = [&]() {
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        tot[rb][t] += acc[rb][t];
+        acc[rb][t] = (f4v){0.f, 0.f, 0.f, 0.f};
+      }
+  };
+  int tiles_since_flush = 0;
 
   // per-thread staging registers for one tile
   constexpr int YV = kCT * B / 4 / kThreads;   // float4 of Y per thread per tile
@@ -145,11 +169,16 @@ __global__ __launch_bounds__(kThreads) void gamma_f32_kernel(GammaLaunch a) {
       }
     }
     if (more) stash(buf ^ 1);
+    if (++tiles_since_flush == kFlushTiles) {
+      flush();
+      tiles_since_flush = 0;
+    }
     __syncthreads();
     buf ^= 1;
   }
+  flush();
 
-  float* out = a.nsplit > 1 ? a.partial + (size_t)blockIdx.y * a.nr * B : a.Z;
+  float* out = a.nsplit > 1 ? a.partial + (size_t)split * a.nr * B : a.Z;
 #pragma unroll
   for (int rb = 0; rb < RB; ++rb) {
 #pragma unroll
@@ -158,10 +187,17 @@ __global__ __launch_bounds__(kThreads) void gamma_f32_kernel(GammaLaunch a) {
       if (row < a.nr) {
         const float sc = a.out_scale * (a.rs ? a.rs[row] : 1.0f);
 #pragma unroll
-        for (int t = 0; t < NT; ++t) out[row * B + 16 * t + (lane & 15)] = sc * acc[rb][t][r];
+        for (int t = 0; t < NT; ++t) out[row * B + 16 * t + (lane & 15)] = sc * tot[rb][t][r];
       }
     }
   }
+}
+
+template <int KERNEL, int B, int RB>
+__global__ __launch_bounds__(kThreads) void gamma_f32_kernel(GammaLaunch a) {
+  __shared__ float4 s_x[2][kCT];
+  __shared__ float s_y[2][kCT * y_stride<B>()];
+  gamma_f32_tile<KERNEL, B, RB>(a, blockIdx.x, blockIdx.y, s_x, s_y);
 }
 
 // ---------------------------------------------------------------------------
@@ -181,20 +217,21 @@ __device__ __forceinline__ void split2(float x0, float x1, uint32_t& hi, uint32_
   lo = pack_bf16x2(x0 - h0, x1 - h1);
 }
 
+constexpr int kKS = kCT / 32;   // BF16 MFMA k-steps per tile
+
+// B-operand fragments in LDS: [k-step][t][lane] -> 4 dwords (8 bf16)
 template <int KERNEL, int B, int RB>
-__global__ __launch_bounds__(kThreads) void gamma_bf16x3_kernel(GammaLaunch a) {
+__device__ __forceinline__ void gamma_bf16x3_tile(const GammaLaunch& a, int64_t rblk, int split,
+                                                  float4 (*s_x)[kCT], uint4 (*s_yh)[kKS * (B / 16) * 64],
+                                                  uint4 (*s_yl)[kKS * (B / 16) * 64]) {
   constexpr int NT = B / 16;
-  constexpr int KS = kCT / 32;              // MFMA k-steps per tile
+  constexpr int KS = kKS;
   constexpr int ROWS = 4 * 16 * RB;
-  __shared__ float4 s_x[2][kCT];
-  // B-operand fragments: [k-step][t][lane] -> 4 dwords (8 bf16)
-  __shared__ uint4 s_yh[2][KS * NT * 64];
-  __shared__ uint4 s_yl[2][KS * NT * 64];
 
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
-  const int64_t row0 = (int64_t)blockIdx.x * ROWS + wave * 16 * RB;
-  const int64_t c_begin = (int64_t)blockIdx.y * a.cols_per_split;
+  const int64_t row0 = rblk * ROWS + wave * 16 * RB;
+  const int64_t c_begin = (int64_t)split * a.cols_per_split;
   const int64_t c_end = (c_begin + a.cols_per_split < a.nc) ? c_begin + a.cols_per_split : a.nc;
 
   float rx[RB], ry[RB], rz[RB];
@@ -212,6 +249,24 @@ __global__ __launch_bounds__(kThreads) void gamma_bf16x3_kernel(GammaLaunch a) {
   for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
     for (int t = 0; t < NT; ++t) acc[rb][t] = (f4v){0.f, 0.f, 0.f, 0.f};
+  // Two-level summation: MFMA chains of at most kFlushTiles tiles are added
+  // into running totals, so the rounding error grows with the square roots of
+  // the chain length and of the number of chains, not of the column count.
+  f4v tot[RB][NT];
+#pragma unroll
+  for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+    for (int t = 0; t < NT; ++t) tot[rb][t] = (f4v){0.f, 0.f, 0.f, 0.f};
+  auto flush = [&]() {
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        tot[rb][t] += acc[rb][t];
+        acc[rb][t] = (f4v){0.f, 0.f, 0.f, 0.f};
+      }
+  };
+  int tiles_since_flush = 0;
 
   // staging: item = (g8, j): 8 consecutive columns 8*g8..8*g8+7 of Y column j
   constexpr int ITEMS = (kCT / 8) * B;
@@ -305,11 +360,16 @@ __global__ __launch_bounds__(kThreads) void gamma_bf16x3_kernel(GammaLaunch a) {
       }
     }
     if (more) stash(buf ^ 1);
+    if (++tiles_since_flush == kFlushTiles) {
+      flush();
+      tiles_since_flush = 0;
+    }
     __syncthreads();
     buf ^= 1;
   }
+  flush();
 
-  float* out = a.nsplit > 1 ? a.partial + (size_t)blockIdx.y * a.nr * B : a.Z;
+  float* out = a.nsplit > 1 ? a.partial + (size_t)split * a.nr * B : a.Z;
 #pragma unroll
   for (int rb = 0; rb < RB; ++rb) {
 #pragma unroll
@@ -318,9 +378,46 @@ __global__ __launch_bounds__(kThreads) void gamma_bf16x3_kernel(GammaLaunch a) {
       if (row < a.nr) {
         const float sc = a.out_scale * (a.rs ? a.rs[row] : 1.0f);
 #pragma unroll
-        for (int t = 0; t < NT; ++t) out[row * B + 16 * t + (lane & 15)] = sc * acc[rb][t][r];
+        for (int t = 0; t < NT; ++t) out[row * B + 16 * t + (lane & 15)] = sc * tot[rb][t][r];
       }
     }
+  }
+}
+
+template <int KERNEL, int B, int RB>
+__global__ __launch_bounds__(kThreads) void gamma_bf16x3_kernel(GammaLaunch a) {
+  __shared__ float4 s_x[2][kCT];
+  __shared__ uint4 s_yh[2][kKS * (B / 16) * 64];
+  __shared__ uint4 s_yl[2][kKS * (B / 16) * 64];
+  gamma_bf16x3_tile<KERNEL, B, RB>(a, blockIdx.x, blockIdx.y, s_x, s_yh, s_yl);
+}
+
+// Several kernel products in one persistent launch: work items (product,
+// row block, column split) are taken round-robin by the workgroups.  Each
+// product keeps its own split-K partition, so its result does not depend on
+// what else is in the batch.
+template <int B, int RB, int PREC>
+__global__ __launch_bounds__(kThreads) void gamma_batch_kernel(const GammaJob* __restrict__ jobs,
+                                                               const GammaItem* __restrict__ items, int n_items) {
+  __shared__ float4 s_x[2][kCT];
+  __shared__ float s_y[PREC == KA_FP32 ? 2 : 1][PREC == KA_FP32 ? kCT * y_stride<B>() : 1];
+  __shared__ uint4 s_yh[PREC == KA_FP32 ? 1 : 2][PREC == KA_FP32 ? 1 : kKS * (B / 16) * 64];
+  __shared__ uint4 s_yl[PREC == KA_FP32 ? 1 : 2][PREC == KA_FP32 ? 1 : kKS * (B / 16) * 64];
+  for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+    const GammaItem item = items[it];
+    const GammaLaunch a = jobs[item.job].a;
+    const int kernel = jobs[item.job].kernel;
+    if constexpr (PREC == KA_FP32) {
+      auto sy = reinterpret_cast<float(*)[kCT * y_stride<B>()]>(&s_y[0][0]);
+      if (kernel == KA_GAUSSIAN) gamma_f32_tile<KA_GAUSSIAN, B, RB>(a, item.rblk, item.split, s_x, sy);
+      else gamma_f32_tile<KA_EXP_L1, B, RB>(a, item.rblk, item.split, s_x, sy);
+    } else {
+      auto yh = reinterpret_cast<uint4(*)[kKS * (B / 16) * 64]>(&s_yh[0][0]);
+      auto yl = reinterpret_cast<uint4(*)[kKS * (B / 16) * 64]>(&s_yl[0][0]);
+      if (kernel == KA_GAUSSIAN) gamma_bf16x3_tile<KA_GAUSSIAN, B, RB>(a, item.rblk, item.split, s_x, yh, yl);
+      else gamma_bf16x3_tile<KA_EXP_L1, B, RB>(a, item.rblk, item.split, s_x, yh, yl);
+    }
+    __syncthreads();
   }
 }
 
@@ -410,6 +507,36 @@ hipError_t launch_gamma(GammaLaunch a, int kernel, int b, int precision, hipStre
     e = hipGetLastError();
   }
   return e;
+}
+
+int gamma_rows_per_block(int b) { return rows_per_block(b, KA_FP32); }
+
+hipError_t launch_gamma_batch(const GammaJob* jobs_dev, const GammaItem* items_dev, int n_items, int b,
+                              int precision, hipStream_t s) {
+  if (n_items <= 0) return hipSuccess;
+  const int grid = n_items < 4096 ? n_items : 4096;
+  if (precision == KA_FP32) {
+    switch (b) {
+      case 16: hipLaunchKernelGGL((gamma_batch_kernel<16, 4, KA_FP32>), dim3(grid), dim3(kThreads), 0, s, jobs_dev, items_dev, n_items); break;
+      case 32: hipLaunchKernelGGL((gamma_batch_kernel<32, 4, KA_FP32>), dim3(grid), dim3(kThreads), 0, s, jobs_dev, items_dev, n_items); break;
+      case 64: hipLaunchKernelGGL((gamma_batch_kernel<64, 2, KA_FP32>), dim3(grid), dim3(kThreads), 0, s, jobs_dev, items_dev, n_items); break;
+      default: return hipErrorInvalidValue;
+    }
+  } else {
+    switch (b) {
+      case 16: hipLaunchKernelGGL((gamma_batch_kernel<16, 4, KA_BF16X3>), dim3(grid), dim3(kThreads), 0, s, jobs_dev, items_dev, n_items); break;
+      case 32: hipLaunchKernelGGL((gamma_batch_kernel<32, 4, KA_BF16X3>), dim3(grid), dim3(kThreads), 0, s, jobs_dev, items_dev, n_items); break;
+      case 64: hipLaunchKernelGGL((gamma_batch_kernel<64, 2, KA_BF16X3>), dim3(grid), dim3(kThreads), 0, s, jobs_dev, items_dev, n_items); break;
+      default: return hipErrorInvalidValue;
+    }
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_gamma_reduce(const float* partial, int nsplit, int64_t n, float* Z, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(gamma_reduce_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, partial, nsplit, n, Z);
+  return hipGetLastError();
 }
 
 }  // namespace ka

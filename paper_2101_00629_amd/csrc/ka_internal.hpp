@@ -37,6 +37,21 @@ struct GammaPlan {
 };
 
 GammaPlan gamma_plan(int64_t nr, int64_t nc, int b, int precision);
+
+// One kernel product of a batched launch, and one work item of it.
+struct GammaJob {
+  GammaLaunch a;    // nsplit / cols_per_split filled from gamma_plan
+  int kernel;
+};
+struct GammaItem {
+  int job;
+  int rblk;
+  int split;
+};
+int gamma_rows_per_block(int b);
+hipError_t launch_gamma_batch(const GammaJob* jobs_dev, const GammaItem* items_dev, int n_items, int b,
+                              int precision, hipStream_t s);
+hipError_t launch_gamma_reduce(const float* partial, int nsplit, int64_t n, float* Z, hipStream_t s);
 hipError_t launch_gamma(GammaLaunch a, int kernel, int b, int precision, hipStream_t s);
 float kernel_coord_scale(int kernel, double ell);
 
@@ -160,6 +175,10 @@ int fail(int code, const std::string& msg);
 int apply_block(Problem* P, int form, const double* X, int64_t ldx, double* Y, int64_t ldy, int nv,
                 hipStream_t s);
 int solve_block(Problem* P, int op, double* X, int64_t ld, int nv, hipStream_t s);
+int apply_pre(Problem* P, int form, const double* X, int64_t ldx, int nv, hipStream_t s);
+int apply_post(Problem* P, int form, double* Y, int64_t ldy, int nv, hipStream_t s);
+GammaLaunch gamma_job(Problem* P);
+int gamma_step(Problem* P, const float* Y, float* Z, hipStream_t s);
 int setup_problem(const ka_desc* d, hipStream_t stream, Problem** out);
 int footprint(const ka_desc* d, size_t* bytes);
 void destroy_problem(Problem* P);

@@ -24,20 +24,29 @@ struct WaveTeam {
   }
 };
 
+constexpr int kNsLds = 120;   // working matrix in LDS up to this order (112.5 KB)
+
+template <bool LDS>
 __global__ __launch_bounds__(kNsThreads) void nonsym_eig_kernel(const double* __restrict__ H, int n, int ldh,
                                                                 double* __restrict__ wr, double* __restrict__ wi,
                                                                 double* __restrict__ S, int lds,
                                                                 double* __restrict__ work, int* status) {
   __shared__ double v[kNsMax];
+  __shared__ double A_lds[LDS ? kNsLds * kNsLds : 1];
   WaveTeam tm{v};
-  nonsym_core(tm, H, n, ldh, wr, wi, S, lds, work, status);
+  nonsym_core(tm, H, n, ldh, wr, wi, S, lds, work, status, LDS ? A_lds : nullptr);
 }
 
 hipError_t nonsym_eig(const double* H, int n, int ldh, double* wr, double* wi, double* S, int lds, double* work,
                       int* status, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   if (n > kNsMax) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(nonsym_eig_kernel, dim3(1), dim3(kNsThreads), 0, s, H, n, ldh, wr, wi, S, lds, work, status);
+  if (n <= kNsLds)
+    hipLaunchKernelGGL(nonsym_eig_kernel<true>, dim3(1), dim3(kNsThreads), 0, s, H, n, ldh, wr, wi, S, lds, work,
+                       status);
+  else
+    hipLaunchKernelGGL(nonsym_eig_kernel<false>, dim3(1), dim3(kNsThreads), 0, s, H, n, ldh, wr, wi, S, lds, work,
+                       status);
   return hipGetLastError();
 }
 

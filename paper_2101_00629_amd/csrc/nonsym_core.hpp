@@ -13,7 +13,8 @@
 // status: 0 ok, 1 the QR iteration did not converge.
 //
 // Team interface: tid(), size(), sync(), sum(x) (over all lanes), scratch
-// (>= n doubles shared by the team).  work: nonsym_work_doubles(n) doubles.
+// (>= n doubles shared by the team).  work: nonsym_work_doubles(n) doubles;
+// Abuf: optional n x n buffer in faster memory for the working matrix.
 #pragma once
 #include <math.h>
 #include <stdint.h>
@@ -36,8 +37,8 @@ KA_HD inline double ns_sgn(double a, double b) { return b >= 0.0 ? fabs(a) : -fa
 
 template <class Team>
 KA_HD void nonsym_core(Team& tm, const double* H, int n, int ldh, double* wr_out, double* wi_out, double* S,
-                       int lds, double* work, int* status) {
-  double* A = work;                          // n x n: Hessenberg, then Schur form T
+                       int lds, double* work, int* status, double* Abuf = nullptr) {
+  double* A = Abuf ? Abuf : work;            // n x n: Hessenberg, then Schur form T (fast memory if given)
   double* Zm = work + (size_t)n * n;         // accumulated orthogonal transformations
   double* Yv = work + (size_t)2 * n * n;     // eigenvectors of T (columns)
   double* Vv = work + (size_t)3 * n * n;     // Zm * Yv

@@ -1,0 +1,87 @@
+"""Parity at the workloads' full sizes, in the launch configurations the
+benchmark times: the fused kernel product on sampled output rows (each row
+computed by the FP64 oracle over all columns), and complete K-L solves
+against the exact product-of-1D spectra on the cube.
+
+Kernel-product bar as in test_gpu_gamma (|err| <= tol * |Gamma| |Y|), with the
+FP32 tolerance derived for the longest accumulation here (75k columns per
+split, two-level summation): 1e-5.
+"""
+import numpy as np
+import pytest
+import torch
+
+import paper_2101_00629_amd as K
+from oracle import cmatvec, collocation, errors, galerkin, kernels, product1d
+from workloads import cube_p2_64, cube_p3_20, normal_block
+
+pytestmark = pytest.mark.gpu
+
+TOL = {K.KA_FP32: 1e-5, K.KA_BF16X3: 6e-5}
+
+
+def _points(p):
+    if p["method"] == "galerkin":
+        o = galerkin.GalerkinIBQ("cube", p["p"], p["nel"], p["kernel"], p["ell"])
+        return o.X, o.X
+    o = collocation.Collocation("cube", p["p"], p["nel"], p["kernel"], p["ell"])
+    return o.Xc, o.Xq
+
+
+def _sampled_check(p, precision, nsample=48, seed=0):
+    Xr, Xc = _points(p)
+    b = p["block"]
+    Y = normal_block(seed + 1, len(Xc), b, dtype=np.float32)
+    kid = K.KERNELS[p["kernel"]]
+    xr = torch.tensor(Xr, dtype=torch.float32, device="cuda")
+    xc = torch.tensor(Xc, dtype=torch.float32, device="cuda")
+    y = torch.tensor(Y, device="cuda")
+    z = torch.empty((len(Xr), b), dtype=torch.float32, device="cuda")
+    nbytes = K.ka_gamma_workspace(len(Xr), len(Xc), b, precision)
+    work = torch.empty(max(nbytes // 4, 1), dtype=torch.float32, device="cuda")
+    K.ka_gamma_apply(kid, 1.0, p["ell"], xr, xc, y, z, precision, work)
+    torch.cuda.synchronize()
+    rows = np.random.default_rng(seed).choice(len(Xr), nsample, replace=False)
+    rows[0], rows[-1] = 0, len(Xr) - 1
+    Z = z.cpu().numpy()[rows].astype(np.float64)
+    Xr32 = Xr[rows].astype(np.float32).astype(np.float64)
+    Xc32 = Xc.astype(np.float32).astype(np.float64)
+    ref = cmatvec.gamma_apply(p["kernel"], 1.0, p["ell"], Xr32, Xc32, Y.astype(np.float64))
+    scale = cmatvec.gamma_apply(p["kernel"], 1.0, p["ell"], Xr32, Xc32, np.abs(Y.astype(np.float64)))
+    err = (np.abs(Z - ref) / scale).max()
+    print(p["name"], precision, "max scaled err", err)
+    assert np.isfinite(Z).all() and err < TOL[precision]
+
+
+@pytest.mark.parametrize("precision", [K.KA_FP32, K.KA_BF16X3])
+def test_gamma_cube_p3_20_galerkin_exponential_c0(precision):
+    _sampled_check(cube_p3_20("galerkin", "exponential"), precision)     # 226981 x 226981
+
+
+@pytest.mark.parametrize("precision", [K.KA_FP32, K.KA_BF16X3])
+def test_gamma_cube_p3_20_collocation_gaussian(precision):
+    _sampled_check(cube_p3_20("collocation", "gaussian"), precision)     # 12167 x 512000
+
+
+@pytest.mark.parametrize("precision", [K.KA_FP32, K.KA_BF16X3])
+def test_gamma_cube_p2_64_galerkin_gaussian(precision):
+    _sampled_check(cube_p2_64("galerkin"), precision, nsample=24)        # 287496 x 287496, b = 64
+
+
+@pytest.mark.parametrize("method,kernel", [("galerkin", "gaussian"), ("galerkin", "exponential"),
+                                           ("collocation", "gaussian"), ("collocation", "exponential")])
+def test_cube_p3_20_solves(method, kernel):
+    p = cube_p3_20(method, kernel)
+    prob = K.Problem(K.desc_from_problem(p, seed=1000))
+    rc, lam, info = K.ka_eigs(prob.h, p["M"], tol=1e-5, maxit=60, complex_values=(method == "collocation"))
+    prob.close()
+    if method == "galerkin":
+        ref = product1d.galerkin_box_spectrum(p["p"], p["nel"], kernel, p["ell"], M=p["M"])
+        lr = lam
+    else:
+        ref = product1d.collocation_box_spectrum(p["p"], p["nel"], kernel, p["ell"], M=p["M"]).real
+        lr = lam[0::2]
+        assert np.abs(lam[1::2]).max() <= 1e-6 * lr[0]
+    err = errors.floored_rel_errors(ref, lr)
+    print(p["name"], info, "floored", err.max(), "raw", errors.rel_errors(ref, lr).max())
+    assert rc == 0 and err.max() < 1e-6
