@@ -173,6 +173,43 @@ int ka_profile_reset(ka_problem* p);
 
 void ka_destroy(ka_problem* p);
 
+/* ---- serving (continuous batching of K-L solve requests on one GPU) ----
+ * Not in the paper: a request loop around the solver.  Requests queue in
+ * arrival order; one is admitted once it has arrived (arrival_s, seconds
+ * after the first ka_server_run), a slot is free and its device footprint
+ * (ka_footprint plus the eigensolver workspace) fits hbm_budget.  Admitted
+ * solves keep their Krylov state on the device, each on its own stream; all
+ * their kernel products run together as shared persistent launches, one
+ * block application per request per loop iteration; finished requests free
+ * their memory at once so waiting ones join the running batch.  A request's
+ * eigenvalues are bitwise the same alone or in any mix (each product keeps
+ * its own split-K partition and every reduction a fixed order). */
+typedef struct ka_server ka_server;
+
+typedef struct ka_result {
+  int64_t id;            /* from ka_server_submit                              */
+  uint64_t tag;          /* caller's tag                                       */
+  int status;            /* ka_eigs return code, or KA_ERR_OOM if it can never fit */
+  ka_info info;
+  double arrival_s, admit_s, done_s;   /* seconds on the server clock           */
+} ka_result;
+
+int ka_server_create(size_t hbm_budget, int max_slots, ka_server** out);
+/* Device bytes a request holds while admitted: ka_footprint plus the
+ * eigensolver workspace for M eigenpairs at the descriptor's block size. */
+int ka_request_bytes(const ka_desc* desc, int M, size_t* bytes);
+/* lambda_host: caller-owned, M doubles (Galerkin) or 2M (collocation), written
+ * when the request completes.  tol/maxit as for ka_eigs. */
+int ka_server_submit(ka_server* s, const ka_desc* desc, int M, double tol, int maxit, double arrival_s,
+                     uint64_t tag, double* lambda_host, int64_t* req_id);
+/* Serve until every submitted request has completed (or timeout_s elapses:
+ * KA_NOT_CONVERGED).  Synchronous; may be called again after new submits. */
+int ka_server_run(ka_server* s, double timeout_s);
+/* Move up to max completed results into out; *n = number moved. */
+int ka_server_poll(ka_server* s, ka_result* out, int max, int* n);
+int ka_server_stats(ka_server* s, int* batches, double* mean_items, int* max_active, size_t* bytes_in_use);
+void ka_server_destroy(ka_server* s);
+
 /* Last error message of the calling host thread. */
 const char* ka_last_error(void);
 

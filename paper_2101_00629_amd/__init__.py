@@ -56,6 +56,11 @@ class ka_info(ctypes.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
+class ka_result(ctypes.Structure):
+    _fields_ = [("id", ctypes.c_int64), ("tag", ctypes.c_uint64), ("status", ctypes.c_int), ("info", ka_info),
+                ("arrival_s", ctypes.c_double), ("admit_s", ctypes.c_double), ("done_s", ctypes.c_double)]
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"HIP library not built: {LIB_PATH} is missing (run __graft_entry__.build())")
@@ -77,6 +82,15 @@ def _load():
         "ka_profile_read": ([vp, ctypes.POINTER(ctypes.c_int), dp, dp], ctypes.c_int),
         "ka_profile_reset": ([vp], ctypes.c_int),
         "ka_destroy": ([vp], None),
+        "ka_server_create": ([ctypes.c_size_t, ctypes.c_int, ctypes.POINTER(vp)], ctypes.c_int),
+        "ka_server_submit": ([vp, ctypes.POINTER(ka_desc), ctypes.c_int, ctypes.c_double, ctypes.c_int,
+                              ctypes.c_double, ctypes.c_uint64, dp, ctypes.POINTER(i64)], ctypes.c_int),
+        "ka_server_run": ([vp, ctypes.c_double], ctypes.c_int),
+        "ka_server_poll": ([vp, ctypes.POINTER(ka_result), ctypes.c_int, ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
+        "ka_server_stats": ([vp, ctypes.POINTER(ctypes.c_int), dp, ctypes.POINTER(ctypes.c_int),
+                             ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+        "ka_server_destroy": ([vp], None),
+        "ka_request_bytes": ([ctypes.POINTER(ka_desc), ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
         "ka_last_error": ([], ctypes.c_char_p),
     }
     for name, (args, res) in sig.items():
@@ -89,7 +103,8 @@ def _load():
 _lib = _load()
 EXPORTED = ("ka_setup", "ka_size", "ka_footprint", "ka_apply_A", "ka_solve_Z", "ka_eigs", "ka_gamma_apply",
             "ka_gamma_workspace", "ka_profile_enable", "ka_profile_read", "ka_profile_reset", "ka_destroy",
-            "ka_last_error")
+            "ka_last_error", "ka_server_create", "ka_server_submit", "ka_server_run", "ka_server_poll",
+            "ka_server_stats", "ka_server_destroy", "ka_request_bytes")
 
 
 class KAError(RuntimeError):
@@ -222,6 +237,56 @@ def ka_destroy(h):
 def ka_last_error():
     m = _lib.ka_last_error()
     return m.decode() if m else ""
+
+
+def ka_request_bytes(desc, M):
+    nb = ctypes.c_size_t()
+    _check(_lib.ka_request_bytes(ctypes.byref(desc), M, ctypes.byref(nb)), "ka_request_bytes")
+    return nb.value
+
+
+def ka_server_create(hbm_budget, max_slots):
+    h = ctypes.c_void_p()
+    _check(_lib.ka_server_create(int(hbm_budget), int(max_slots), ctypes.byref(h)), "ka_server_create")
+    return h
+
+
+def ka_server_submit(srv, desc, M, lam, tol=1e-5, maxit=60, arrival_s=0.0, tag=0):
+    """lam: caller-owned float64 numpy array of M (Galerkin) or 2M
+    (collocation) entries; it must stay alive until the request completes."""
+    rid = ctypes.c_int64()
+    _check(_lib.ka_server_submit(srv, ctypes.byref(desc), M, tol, maxit, arrival_s, tag,
+                                 lam.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ctypes.byref(rid)),
+           "ka_server_submit")
+    return rid.value
+
+
+def ka_server_run(srv, timeout_s=0.0):
+    return _check(_lib.ka_server_run(srv, timeout_s), "ka_server_run")
+
+
+def ka_server_poll(srv, max_results=4096):
+    buf = (ka_result * max_results)()
+    n = ctypes.c_int()
+    _check(_lib.ka_server_poll(srv, buf, max_results, ctypes.byref(n)), "ka_server_poll")
+    out = []
+    for i in range(n.value):
+        r = buf[i]
+        out.append(dict(id=r.id, tag=r.tag, status=r.status, info=r.info.as_dict(), arrival_s=r.arrival_s,
+                        admit_s=r.admit_s, done_s=r.done_s))
+    return out
+
+
+def ka_server_stats(srv):
+    b, mi, ma, used = ctypes.c_int(), ctypes.c_double(), ctypes.c_int(), ctypes.c_size_t()
+    _check(_lib.ka_server_stats(srv, ctypes.byref(b), ctypes.byref(mi), ctypes.byref(ma), ctypes.byref(used)),
+           "ka_server_stats")
+    return dict(batches=b.value, mean_items=mi.value, max_active=ma.value, bytes_in_use=used.value)
+
+
+def ka_server_destroy(srv):
+    if srv:
+        _lib.ka_server_destroy(srv)
 
 
 class Problem:

@@ -31,7 +31,8 @@ __global__ __launch_bounds__(kNsThreads) void nonsym_eig_kernel(const double* __
                                                                 double* __restrict__ wr, double* __restrict__ wi,
                                                                 double* __restrict__ S, int lds,
                                                                 double* __restrict__ work, int* status) {
-  __shared__ double v[kNsMax];
+  // team scratch: Householder vector (n) and the per-sweep log (6n)
+  __shared__ double v[LDS ? 6 * kNsLds : 6 * kNsMax];
   __shared__ double A_lds[LDS ? kNsLds * kNsLds : 1];
   WaveTeam tm{v};
   nonsym_core(tm, H, n, ldh, wr, wi, S, lds, work, status, LDS ? A_lds : nullptr);

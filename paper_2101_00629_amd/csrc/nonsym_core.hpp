@@ -13,7 +13,7 @@
 // status: 0 ok, 1 the QR iteration did not converge.
 //
 // Team interface: tid(), size(), sync(), sum(x) (over all lanes), scratch
-// (>= n doubles shared by the team).  work: nonsym_work_doubles(n) doubles;
+// (>= 6n doubles shared by the team).  work: nonsym_work_doubles(n) doubles;
 // Abuf: optional n x n buffer in faster memory for the working matrix.
 #pragma once
 #include <math.h>
@@ -238,7 +238,11 @@ KA_HD void nonsym_core(Team& tm, const double* H, int n, int ldh, double* wr_out
         if (i != m + 2) AT(A, i, i - 3) = 0.0;
       }
       tm.sync();
-      // double QR step
+      // double QR step.  The transformations of the accumulated Schur vectors
+      // Zm are logged per bulge position and applied after the sweep, one
+      // row per lane with a sliding window of three columns, so the sweep
+      // does not wait on a memory round trip of Zm per position.
+      double* zlog = v;   // 6 doubles per position: x1, y1, z1, q1, r1, flag
       for (int k = m; k <= nn - 1; ++k) {
         const bool notlast = (k != nn - 1);
         double xx = 0.0;
@@ -254,18 +258,29 @@ KA_HD void nonsym_core(Team& tm, const double* H, int n, int ldh, double* wr_out
           }
         }
         const double s = ns_sgn(sqrt(p * p + q * q + r * r), p);
-        if (s == 0.0) continue;
+        double* e = zlog + 6 * (k - m);
+        if (s == 0.0) {
+          tm.sync();
+          if (t == 0) e[5] = 0.0;   // no transformation at this position
+          continue;
+        }
         tm.sync();
+        const double pp = p + s;
+        const double x1 = pp / s, y1 = q / s, z1 = r / s;
+        const double q1 = q / pp, r1 = r / pp;
         if (t == 0) {
           if (k == m) {
             if (l != m) AT(A, k, k - 1) = -AT(A, k, k - 1);
           } else {
             AT(A, k, k - 1) = -s * xx;
           }
+          e[0] = x1;
+          e[1] = y1;
+          e[2] = z1;
+          e[3] = q1;
+          e[4] = r1;
+          e[5] = 1.0;
         }
-        const double pp = p + s;
-        const double x1 = pp / s, y1 = q / s, z1 = r / s;
-        const double q1 = q / pp, r1 = r / pp;
         tm.sync();
         // rows k, k+1, (k+2) over columns k..n-1
         for (int j = k + t; j < n; j += NT) {
@@ -288,17 +303,31 @@ KA_HD void nonsym_core(Team& tm, const double* H, int n, int ldh, double* wr_out
           AT(A, i, k + 1) -= pv * q1;
           AT(A, i, k) -= pv;
         }
-        for (int i = t; i < n; i += NT) {
-          double pv = x1 * AT(Zm, i, k) + y1 * AT(Zm, i, k + 1);
-          if (notlast) {
-            pv += z1 * AT(Zm, i, k + 2);
-            AT(Zm, i, k + 2) -= pv * r1;
-          }
-          AT(Zm, i, k + 1) -= pv * q1;
-          AT(Zm, i, k) -= pv;
-        }
         tm.sync();
       }
+      // apply the sweep's logged transformations to the rows of Zm
+      tm.sync();
+      for (int i = t; i < n; i += NT) {
+        double c0 = AT(Zm, i, m), c1 = AT(Zm, i, m + 1), c2 = AT(Zm, i, m + 2);
+        for (int k = m; k <= nn - 1; ++k) {
+          const double* e = zlog + 6 * (k - m);
+          if (e[5] != 0.0) {
+            double pv = e[0] * c0 + e[1] * c1;
+            if (k != nn - 1) {
+              pv += e[2] * c2;
+              c2 -= pv * e[4];
+            }
+            c1 -= pv * e[3];
+            c0 -= pv;
+          }
+          AT(Zm, i, k) = c0;
+          c0 = c1;
+          c1 = c2;
+          c2 = (k + 3 <= nn) ? AT(Zm, i, k + 3) : 0.0;
+        }
+        AT(Zm, i, nn) = c0;
+      }
+      tm.sync();
     }
   }
   tm.sync();

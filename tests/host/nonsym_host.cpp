@@ -15,7 +15,7 @@ struct HostTeam {
 }  // namespace
 
 extern "C" int ka_host_nonsym_eig(const double* H, int n, double* wr, double* wi, double* S) {
-  std::vector<double> work(ka::nonsym_work_doubles(n)), scratch(n + 1);
+  std::vector<double> work(ka::nonsym_work_doubles(n)), scratch(6 * n + 6);
   HostTeam tm{scratch.data()};
   int status = -1;
   ka::nonsym_core(tm, H, n, n, wr, wi, S, n, work.data(), &status);
