@@ -89,6 +89,92 @@ def cpu_baseline(probs, seconds_target=20.0):
             + f"; {total_pairs:.3g} pairs in {total_time:.1f} s"}
 
 
+def request_pairs(d):
+    """Kernel pairs of one block application for a problem descriptor."""
+    p, nel = d["p"], d["nel"]
+    N = int(np.prod([p + e for e in nel]))
+    if d["method"] == "galerkin":
+        mult = p if d["kernel"] == "exponential" else 1
+        Nt = int(np.prod([p + 1 + mult * (e - 1) for e in nel]))
+        return float(Nt) * Nt
+    return float(N) * float(np.prod([(p + 1) * e for e in nel]))
+
+
+def serve_benchmark(n_requests, rhos, cap, tol, seed=210100629):
+    """Serving workload: seed-drawn K-L requests, Poisson arrivals.
+
+    Sequential baseline: every request solved alone (ka_setup + ka_eigs +
+    ka_destroy) and timed; its FIFO latencies on the arrival trace follow
+    from those measured service times.  Server: the same trace through the
+    continuous-batching server (ka_server_*), measured end to end."""
+    import torch
+    import paper_2101_00629_amd as K
+    from workloads import serving_stream
+
+    trace = serving_stream(n_requests, seed=seed, max_pairs=cap, pair_count=request_pairs)
+    descs = [K.desc_from_problem({k: v for k, v in d.items() if k not in ("M", "arrival", "id", "name")},
+                                 seed=1 + d["id"]) for d in trace]
+    cplx = [d["method"] == "collocation" for d in trace]
+    # sequential plain solves
+    service, lam_seq = [], []
+    for i, d in enumerate(trace):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        prob = K.Problem(descs[i])
+        rc, lam, info = K.ka_eigs(prob.h, d["M"], tol=tol, maxit=60, complex_values=cplx[i])
+        prob.close()
+        torch.cuda.synchronize()
+        service.append(time.perf_counter() - t0)
+        lam_seq.append(lam)
+    service = np.array(service)
+    out = {"requests": n_requests, "pair_cap_per_block_product": cap,
+           "mean_service_ms": float(service.mean() * 1e3),
+           "pairs_per_block_product": {"p50": float(np.median([request_pairs(d) for d in trace])),
+                                       "max": float(max(request_pairs(d) for d in trace))}}
+    rng = np.random.default_rng(seed + 1)
+    gaps = rng.exponential(1.0, n_requests)
+    for rho in rhos:
+        arrivals = np.cumsum(gaps) * service.mean() / rho
+        arrivals -= arrivals[0]
+        # FIFO one-at-a-time on the measured service times
+        done, t = np.zeros(n_requests), 0.0
+        for i in range(n_requests):
+            t = max(t, arrivals[i]) + service[i]
+            done[i] = t
+        seq_lat = done - arrivals
+        # continuous-batching server
+        srv = K.ka_server_create(200 << 30, 32)
+        lams = []
+        for i, d in enumerate(trace):
+            lam = np.zeros(2 * d["M"])
+            lams.append(lam)
+            K.ka_server_submit(srv, descs[i], d["M"], lam, tol=tol, maxit=60, arrival_s=float(arrivals[i]), tag=i)
+        t0 = time.perf_counter()
+        K.ka_server_run(srv, 1200.0)
+        wall = time.perf_counter() - t0
+        res = sorted(K.ka_server_poll(srv), key=lambda r: r["tag"])
+        stats = K.ka_server_stats(srv)
+        K.ka_server_destroy(srv)
+        ok = [r for r in res if r["status"] == 0]
+        lat = np.array([r["done_s"] - r["arrival_s"] for r in res])
+        makespan = max(r["done_s"] for r in res)
+        diff = 0.0
+        for i, d in enumerate(trace):
+            a = lams[i][0::2][:d["M"]] if cplx[i] else lams[i][:d["M"]]
+            b = lam_seq[i][0::2] if cplx[i] else lam_seq[i]
+            diff = max(diff, float(np.abs(a - b).max() / abs(b[0])))
+        out[f"rho_{rho:g}"] = {
+            "server": {"solves_per_s": n_requests / makespan, "p50_ms": float(np.percentile(lat, 50) * 1e3),
+                       "p99_ms": float(np.percentile(lat, 99) * 1e3), "makespan_s": makespan, "wall_s": wall,
+                       "completed": len(ok), "max_active": stats["max_active"],
+                       "mean_items_per_launch": stats["mean_items"]},
+            "sequential": {"solves_per_s": n_requests / done[-1], "p50_ms": float(np.percentile(seq_lat, 50) * 1e3),
+                           "p99_ms": float(np.percentile(seq_lat, 99) * 1e3), "makespan_s": float(done[-1])},
+            "max_eig_diff_vs_alone_rel_lambda1": diff,
+        }
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -97,6 +183,10 @@ def main():
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16x3"])
     ap.add_argument("--tol", type=float, default=1e-5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serve", action="store_true", help="run the serving benchmark instead")
+    ap.add_argument("--requests", type=int, default=128)
+    ap.add_argument("--rho", default="0.5,1.5")
+    ap.add_argument("--pair-cap", type=float, default=1e11)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the kernel product of one GPU's share; "
@@ -107,6 +197,11 @@ def main():
     import paper_2101_00629_amd as K
 
     torch.cuda.set_device(0)
+    if args.serve:
+        res = serve_benchmark(args.requests, [float(r) for r in args.rho.split(",")], args.pair_cap, args.tol)
+        print(json.dumps({"metric": "K-L solves/s + p99 latency (serving)", "n_gpus": 1, "data": "synthetic",
+                          "dtype": "f32", **res}), flush=True)
+        return
     probs = workload(precision=args.precision)
     handles = []
     for i, p in enumerate(probs):

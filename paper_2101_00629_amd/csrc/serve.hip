@@ -1,29 +1,36 @@
 // Continuous-batching server for K-L solve requests on one GPU.
 //
 // Requests (problem descriptor, M, tolerance, arrival time) queue in arrival
-// order.  The serving loop admits a request once it has arrived, a slot is
-// free and its device footprint (problem set-up + eigensolver workspace)
-// fits the HBM budget; each admitted request keeps its whole Krylov state on
-// the device, on its own stream.  Every iteration of the loop advances all
-// active solves by one block application of A': their operator steps before
-// the kernel product run on their own streams, then the kernel products of
-// all of them run as shared persistent launches (one per block size and
-// precision) over a combined work list, then each solve finishes its step
-// (transfers, orthogonalisation, Rayleigh-Ritz).  Finished solves release
-// their memory at once, so newly arrived requests join the running batch.
+// order.  A pool of worker threads (one per slot) serves them: a worker takes
+// the head request once it has arrived and its device footprint (problem
+// set-up + eigensolver workspace) fits the HBM budget, and drives that solve
+// on its own stream with the whole Krylov state on the device.  Solves
+// therefore progress independently, and their small kernels (transfers,
+// orthogonalisation, the one-workgroup Rayleigh-Ritz eigensolves) overlap on
+// the device.  Finished solves release their memory at once, so waiting
+// requests join while others run.
 //
-// Each product keeps its own split-K partition, fixed by its own shape, and
-// every reduction has a fixed order: a request's result is bitwise the same
-// whether it runs alone or in any mix.
+// Kernel products: a product too small to fill the chip on its own is handed
+// to a dispatcher thread, which merges all pending products into shared
+// persistent launches (one per block size and precision) over a combined work
+// list; it launches as soon as every running solve is waiting for its product,
+// or after a short gathering window.  Larger products launch directly on
+// their own stream.  Every product keeps its own split-K partition, fixed by
+// its own shape, and every reduction has a fixed order, and the direct /
+// batched choice depends only on the request's own size: a request's result
+// is bitwise the same whether it runs alone or in any mix.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
+#include <condition_variable>
 #include <cstring>
 #include <deque>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <thread>
 #include <vector>
@@ -39,6 +46,16 @@ namespace ka {
       return fail(KA_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_));       \
   } while (0)
 
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+// work items at which a single product fills the chip without batching
+constexpr int64_t kDirectItems = 2048;
+// longest wait for other solves to reach their kernel product
+constexpr double kGatherSeconds = 150e-6;
+constexpr int kRing = 8;   // device job/item buffers in flight
+
 struct Request {
   int64_t id = 0;
   ka_desc desc;
@@ -49,228 +66,304 @@ struct Request {
   uint64_t tag = 0;
   double* lambda_host = nullptr;
   size_t bytes = 0;
-  // runtime
-  hipStream_t stream = nullptr;
-  hipEvent_t ev_pre = nullptr;
-  Problem* prob = nullptr;
-  std::unique_ptr<EigRun> run;
-  double t_admit = 0.0;
+};
+
+struct BatchDone {
+  hipEvent_t ev = nullptr;   // recorded after the batch's launches
+  int refs = 0;              // members that have not yet queued their wait
+};
+
+struct PendingGamma {
+  GammaJob job;
+  int b = 16, precision = KA_FP32;
+  int64_t items = 0;
+  hipEvent_t ready = nullptr;     // recorded on the requester's stream
+  BatchDone* done = nullptr;      // set by the dispatcher
+  bool launched = false;
+  int status = KA_OK;
 };
 
 struct Server {
   size_t budget = 0;
   int max_slots = 1;
+  // shared state (mu)
+  std::mutex mu;
+  std::condition_variable cv;          // queue / completion changes
+  std::condition_variable cv_gamma;    // dispatcher wake-up and launch notices
   size_t used = 0;
   int64_t next_id = 0;
-  std::deque<std::unique_ptr<Request>> queue;      // not yet admitted, arrival order
-  std::vector<std::unique_ptr<Request>> active;
+  std::deque<std::unique_ptr<Request>> queue;
   std::vector<ka_result> done;
-  hipStream_t stream = nullptr;                     // batched kernel products
-  hipEvent_t ev_gamma = nullptr;
-  GammaJob* jobs_host = nullptr;
-  GammaItem* items_host = nullptr;
-  GammaJob* jobs_dev = nullptr;
-  GammaItem* items_dev = nullptr;
-  size_t jobs_cap = 0, items_cap = 0;
-  std::chrono::steady_clock::time_point t0;
+  int in_flight = 0;        // requests taken by workers and not finished
+  int solving = 0;          // workers inside their iteration loop
+  std::vector<PendingGamma*> pending;
+  bool stop = false;
+  // dispatcher
+  hipStream_t stream = nullptr;
+  hipEvent_t ring_ev[kRing] = {};
+  GammaJob* jobs_dev[kRing] = {};
+  GammaItem* items_dev[kRing] = {};
+  size_t jobs_cap[kRing] = {}, items_cap[kRing] = {};
+  std::vector<GammaJob> jobs_host[kRing];      // copy sources, alive until the slot's event completes
+  std::vector<GammaItem> items_host[kRing];
+  int ring_pos = 0;
+  // clock and statistics
+  Clock::time_point t0;
   bool started = false;
   int batches = 0;
   double batch_items = 0.0;
   int max_active = 0;
+  int direct_launches = 0;
 };
 
-static double now_s(const Server* S) {
-  return std::chrono::duration<double>(std::chrono::steady_clock::now() - S->t0).count();
+double now_s(const Server* S) { return std::chrono::duration<double>(Clock::now() - S->t0).count(); }
+
+int64_t work_items(const GammaLaunch& a, int b) {
+  const int64_t rpb = gamma_rows_per_block(b);
+  return ((a.nr + rpb - 1) / rpb) * a.nsplit;
 }
 
-static int ensure_capacity(Server* S, size_t njobs, size_t nitems) {
-  if (njobs > S->jobs_cap) {
-    (void)hipHostFree(S->jobs_host);
-    (void)hipFree(S->jobs_dev);
-    S->jobs_cap = std::max(njobs, 2 * S->jobs_cap);
-    HIP_TRY(hipHostMalloc((void**)&S->jobs_host, S->jobs_cap * sizeof(GammaJob)));
-    HIP_TRY(hipMalloc((void**)&S->jobs_dev, S->jobs_cap * sizeof(GammaJob)));
+// ---- dispatcher -------------------------------------------------------------
+int launch_batch(Server* S, std::vector<PendingGamma*>& batch, hipEvent_t done_ev) {
+  const int slot = S->ring_pos;
+  S->ring_pos = (S->ring_pos + 1) % kRing;
+  // the device buffers of this slot may still be read by an older batch
+  HIP_TRY(hipEventSynchronize(S->ring_ev[slot]));
+  size_t ni = 0;
+  for (auto* p : batch) ni += (size_t)p->items;
+  if (batch.size() > S->jobs_cap[slot]) {
+    (void)hipFree(S->jobs_dev[slot]);
+    S->jobs_cap[slot] = std::max(batch.size(), (size_t)64);
+    HIP_TRY(hipMalloc((void**)&S->jobs_dev[slot], S->jobs_cap[slot] * sizeof(GammaJob)));
   }
-  if (nitems > S->items_cap) {
-    (void)hipHostFree(S->items_host);
-    (void)hipFree(S->items_dev);
-    S->items_cap = std::max(nitems, 2 * S->items_cap);
-    HIP_TRY(hipHostMalloc((void**)&S->items_host, S->items_cap * sizeof(GammaItem)));
-    HIP_TRY(hipMalloc((void**)&S->items_dev, S->items_cap * sizeof(GammaItem)));
+  if (ni > S->items_cap[slot]) {
+    (void)hipFree(S->items_dev[slot]);
+    S->items_cap[slot] = std::max(ni, (size_t)4096) * 2;
+    HIP_TRY(hipMalloc((void**)&S->items_dev[slot], S->items_cap[slot] * sizeof(GammaItem)));
   }
+  std::map<std::pair<int, int>, std::vector<PendingGamma*>> groups;
+  for (auto* p : batch) groups[{p->b, p->precision}].push_back(p);
+  std::vector<GammaJob>& jobs = S->jobs_host[slot];
+  std::vector<GammaItem>& items = S->items_host[slot];
+  jobs.clear();
+  items.clear();
+  std::vector<std::tuple<int, int, size_t, size_t, size_t, size_t>> launches;   // b, prec, j0, j1, i0, i1
+  for (auto& g : groups) {
+    const size_t j0 = jobs.size(), i0 = items.size();
+    for (auto* p : g.second) {
+      const int jl = (int)(jobs.size() - j0);
+      jobs.push_back(p->job);
+      const int64_t rpb = gamma_rows_per_block(p->b);
+      const int64_t rblocks = (p->job.a.nr + rpb - 1) / rpb;
+      for (int sp = 0; sp < p->job.a.nsplit; ++sp)
+        for (int64_t rb = 0; rb < rblocks; ++rb) items.push_back(GammaItem{jl, (int)rb, sp});
+    }
+    launches.emplace_back(g.first.first, g.first.second, j0, jobs.size(), i0, items.size());
+  }
+  for (auto* p : batch) HIP_TRY(hipStreamWaitEvent(S->stream, p->ready, 0));
+  HIP_TRY(hipMemcpyAsync(S->jobs_dev[slot], jobs.data(), jobs.size() * sizeof(GammaJob), hipMemcpyHostToDevice,
+                         S->stream));
+  HIP_TRY(hipMemcpyAsync(S->items_dev[slot], items.data(), items.size() * sizeof(GammaItem), hipMemcpyHostToDevice,
+                         S->stream));
+  for (auto& L : launches) {
+    const int b = std::get<0>(L), prec = std::get<1>(L);
+    const size_t j0 = std::get<2>(L), j1 = std::get<3>(L), i0 = std::get<4>(L), i1 = std::get<5>(L);
+    HIP_TRY(launch_gamma_batch(S->jobs_dev[slot] + j0, S->items_dev[slot] + i0, (int)(i1 - i0), b, prec, S->stream));
+    for (size_t q = j0; q < j1; ++q) {
+      const GammaLaunch& a = jobs[q].a;
+      if (a.nsplit > 1) HIP_TRY(launch_gamma_reduce(a.partial, a.nsplit, a.nr * b, a.Z, S->stream));
+    }
+  }
+  HIP_TRY(hipEventRecord(done_ev, S->stream));
+  HIP_TRY(hipEventRecord(S->ring_ev[slot], S->stream));
+  S->batches++;
+  S->batch_items += (double)items.size();
   return KA_OK;
 }
 
-static void release(Server* S, Request* r) {
-  r->run.reset();
-  if (r->prob) destroy_problem(r->prob);
-  r->prob = nullptr;
-  if (r->ev_pre) (void)hipEventDestroy(r->ev_pre);
-  if (r->stream) (void)hipStreamDestroy(r->stream);
-  r->ev_pre = nullptr;
-  r->stream = nullptr;
-  S->used -= r->bytes;
+void dispatcher_main(Server* S) {
+  std::unique_lock<std::mutex> lk(S->mu);
+  while (true) {
+    S->cv_gamma.wait(lk, [&] { return (S->stop && S->solving == 0) || !S->pending.empty(); });
+    if (S->pending.empty()) return;    // stop requested and no solve left
+    // gather: until every solving worker waits for its product, or the window closes
+    const auto t_first = Clock::now();
+    while (!S->stop && (int)S->pending.size() < S->solving &&
+           Clock::now() - t_first < std::chrono::duration<double>(kGatherSeconds)) {
+      S->cv_gamma.wait_for(lk, std::chrono::duration<double>(kGatherSeconds / 4));
+    }
+    std::vector<PendingGamma*> batch;
+    batch.swap(S->pending);
+    lk.unlock();
+    BatchDone* bd = new BatchDone();
+    bd->refs = (int)batch.size();
+    int rc = hipEventCreateWithFlags(&bd->ev, hipEventDisableTiming) == hipSuccess ? KA_OK : KA_ERR_HIP;
+    if (rc == KA_OK) rc = launch_batch(S, batch, bd->ev);
+    lk.lock();
+    for (auto* p : batch) {
+      p->done = bd;
+      p->status = rc;
+      p->launched = true;
+    }
+    S->cv_gamma.notify_all();
+  }
 }
 
-static void finish_request(Server* S, Request* r, int status) {
+// ---- workers -------------------------------------------------------------------
+void finish_request(Server* S, const Request& r, int status, double t_admit, EigRun* run) {
   ka_result res;
   std::memset(&res, 0, sizeof(res));
-  res.id = r->id;
-  res.tag = r->tag;
+  res.id = r.id;
+  res.tag = r.tag;
   res.status = status;
-  res.arrival_s = r->arrival;
-  res.admit_s = r->t_admit;
-  if (status >= 0 && r->run) {
-    const int rc = r->run->finish(r->lambda_host, nullptr, &res.info);
-    res.status = rc;
-  }
+  res.arrival_s = r.arrival;
+  res.admit_s = t_admit;
+  if (status >= 0 && run) res.status = run->finish(r.lambda_host, nullptr, &res.info);
   res.done_s = now_s(S);
+  std::lock_guard<std::mutex> g(S->mu);
   S->done.push_back(res);
-  release(S, r);
 }
 
-// Admit arrived requests while slots and memory allow (arrival order; the
-// head of the queue waits for memory rather than being overtaken).
-static int admit(Server* S) {
-  const double t = now_s(S);
-  while (!S->queue.empty() && (int)S->active.size() < S->max_slots && S->queue.front()->arrival <= t) {
-    Request* r = S->queue.front().get();
-    if (S->used + r->bytes > S->budget) {
-      if (S->active.empty()) {
-        // can never fit: reject
-        std::unique_ptr<Request> own = std::move(S->queue.front());
+// One block application's kernel product for the solve on `P`.
+int product(Server* S, Problem* P, hipEvent_t ready) {
+  GammaLaunch a = gamma_job(P);
+  const int64_t items = work_items(a, P->b);
+  if (items >= kDirectItems) {
+    // fills the chip on its own
+    {
+      std::lock_guard<std::mutex> g(S->mu);
+      S->direct_launches++;
+    }
+    return gamma_step(P, P->w32b, P->w32a, P->stream);
+  }
+  PendingGamma pg;
+  pg.job.a = a;
+  pg.job.kernel = P->d.kernel;
+  pg.b = P->b;
+  pg.precision = P->d.precision;
+  pg.items = items;
+  pg.ready = ready;
+  HIP_TRY(hipEventRecord(ready, P->stream));
+  {
+    std::unique_lock<std::mutex> lk(S->mu);
+    S->pending.push_back(&pg);
+    S->cv_gamma.notify_all();
+    S->cv_gamma.wait(lk, [&] { return pg.launched; });
+  }
+  hipError_t e = hipSuccess;
+  if (pg.status == KA_OK) e = hipStreamWaitEvent(P->stream, pg.done->ev, 0);
+  bool last = false;
+  {
+    std::lock_guard<std::mutex> g(S->mu);
+    last = --pg.done->refs == 0;
+  }
+  if (last) {
+    if (pg.done->ev) (void)hipEventDestroy(pg.done->ev);
+    delete pg.done;
+  }
+  if (pg.status != KA_OK) return pg.status;
+  if (e != hipSuccess) return fail(KA_ERR_HIP, "stream wait on the batched product failed");
+  P->pairs_total += (double)a.nr * (double)a.nc;
+  return KA_OK;
+}
+
+void worker_main(Server* S) {
+  hipStream_t stream = nullptr;
+  hipEvent_t ready = nullptr;
+  if (hipStreamCreateWithFlags(&stream, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&ready, hipEventDisableTiming) != hipSuccess)
+    return;
+  while (true) {
+    std::unique_ptr<Request> r;
+    double t_admit = 0.0;
+    {
+      std::unique_lock<std::mutex> lk(S->mu);
+      while (true) {
+        if (S->stop) break;
+        if (S->queue.empty()) {
+          S->cv.wait(lk);
+          continue;
+        }
+        Request* h = S->queue.front().get();
+        const double t = now_s(S);
+        if (h->arrival > t) {
+          S->cv.wait_for(lk, std::chrono::duration<double>(std::min(h->arrival - t, 0.005)));
+          continue;
+        }
+        if (S->used + h->bytes > S->budget) {
+          if (S->in_flight == 0) {
+            // can never fit: reject
+            ka_result res;
+            std::memset(&res, 0, sizeof(res));
+            res.id = h->id;
+            res.tag = h->tag;
+            res.status = KA_ERR_OOM;
+            res.arrival_s = h->arrival;
+            res.admit_s = res.done_s = t;
+            S->done.push_back(res);
+            S->queue.pop_front();
+            S->cv.notify_all();
+            continue;
+          }
+          S->cv.wait(lk);     // wait for memory to be released
+          continue;
+        }
+        r = std::move(S->queue.front());
         S->queue.pop_front();
-        ka_result res;
-        std::memset(&res, 0, sizeof(res));
-        res.id = own->id;
-        res.tag = own->tag;
-        res.status = KA_ERR_OOM;
-        res.arrival_s = own->arrival;
-        res.admit_s = res.done_s = now_s(S);
-        S->done.push_back(res);
-        continue;
+        S->used += r->bytes;
+        S->in_flight++;
+        S->max_active = std::max(S->max_active, S->in_flight);
+        t_admit = t;
+        break;
       }
-      break;
+      if (!r) break;
     }
-    std::unique_ptr<Request> own = std::move(S->queue.front());
-    S->queue.pop_front();
-    S->used += r->bytes;
-    r->t_admit = t;
-    HIP_TRY(hipStreamCreateWithFlags(&r->stream, hipStreamNonBlocking));
-    HIP_TRY(hipEventCreateWithFlags(&r->ev_pre, hipEventDisableTiming));
-    int rc = setup_problem(&r->desc, r->stream, &r->prob);
+    // solve
+    Problem* P = nullptr;
+    int rc = setup_problem(&r->desc, stream, &P);
+    std::unique_ptr<EigRun> run;
     if (rc == KA_OK) {
-      r->run.reset(new EigRun(r->prob, r->M, r->tol, r->maxit));
-      rc = r->run->start();
+      run.reset(new EigRun(P, r->M, r->tol, r->maxit));
+      rc = run->start();
     }
-    if (rc != KA_OK) {
-      finish_request(S, r, rc);
-      continue;
+    bool solving_flag = false;
+    if (rc == KA_OK) {
+      std::lock_guard<std::mutex> g(S->mu);
+      S->solving++;
+      solving_flag = true;
     }
-    S->active.push_back(std::move(own));
-  }
-  S->max_active = std::max(S->max_active, (int)S->active.size());
-  return KA_OK;
-}
-
-// One iteration: every active solve advances by one block application.
-static int step(Server* S) {
-  std::vector<Request*> act;
-  for (auto& r : S->active) act.push_back(r.get());
-  // 1. operator steps before the kernel product, per request stream
-  for (Request* r : act) {
-    const int rc = r->run->pre_apply();
-    if (rc != KA_OK) return rc;
-    HIP_TRY(hipEventRecord(r->ev_pre, r->stream));
-    HIP_TRY(hipStreamWaitEvent(S->stream, r->ev_pre, 0));
-  }
-  // 2. shared launches of all kernel products, grouped by (b, precision)
-  std::map<std::pair<int, int>, std::vector<Request*>> groups;
-  for (Request* r : act) groups[{r->prob->b, r->prob->d.precision}].push_back(r);
-  size_t nj = 0, ni = 0;
-  for (auto& g : groups)
-    for (Request* r : g.second) {
-      const GammaLaunch a = gamma_job(r->prob);
-      const int64_t rpb = gamma_rows_per_block(r->prob->b);
-      ++nj;
-      ni += (size_t)((a.nr + rpb - 1) / rpb) * a.nsplit;
-    }
-  if (int rc = ensure_capacity(S, nj, ni)) return rc;
-  size_t j = 0, it = 0;
-  for (auto& g : groups) {
-    const size_t j0 = j, it0 = it;
-    for (Request* r : g.second) {
-      GammaJob job;
-      job.a = gamma_job(r->prob);
-      job.kernel = r->prob->d.kernel;
-      S->jobs_host[j] = job;
-      const int64_t rpb = gamma_rows_per_block(r->prob->b);
-      const int64_t rblocks = (job.a.nr + rpb - 1) / rpb;
-      for (int sp = 0; sp < job.a.nsplit; ++sp)
-        for (int64_t rb = 0; rb < rblocks; ++rb) S->items_host[it++] = GammaItem{(int)(j - j0), (int)rb, sp};
-      ++j;
-    }
-    HIP_TRY(hipMemcpyAsync(S->jobs_dev + j0, S->jobs_host + j0, (j - j0) * sizeof(GammaJob), hipMemcpyHostToDevice,
-                           S->stream));
-    HIP_TRY(hipMemcpyAsync(S->items_dev + it0, S->items_host + it0, (it - it0) * sizeof(GammaItem),
-                           hipMemcpyHostToDevice, S->stream));
-    HIP_TRY(launch_gamma_batch(S->jobs_dev + j0, S->items_dev + it0, (int)(it - it0), g.first.first,
-                               g.first.second, S->stream));
-    for (size_t q = j0; q < j; ++q) {
-      const GammaLaunch& a = S->jobs_host[q].a;
-      if (a.nsplit > 1) HIP_TRY(launch_gamma_reduce(a.partial, a.nsplit, a.nr * g.first.first, a.Z, S->stream));
-    }
-  }
-  S->batches++;
-  S->batch_items += (double)it;
-  for (Request* r : act) r->prob->pairs_total += (double)r->prob->n_rows * (double)r->prob->n_cols;
-  HIP_TRY(hipEventRecord(S->ev_gamma, S->stream));
-  // the host staging buffers are reused next step: wait for the copies
-  // (cheap: the stream only holds this step's copies and launches)
-  // 3. the rest of each step, per request stream
-  for (Request* r : act) HIP_TRY(hipStreamWaitEvent(r->stream, S->ev_gamma, 0));
-  std::vector<std::unique_ptr<Request>> keep;
-  for (auto& own : S->active) {
-    Request* r = own.get();
     bool done = false;
-    const int rc = r->run->post_apply(done);
-    if (rc != KA_OK) {
-      finish_request(S, r, rc);
-      continue;
+    while (rc == KA_OK && !done) {
+      rc = run->pre_apply();
+      if (rc == KA_OK) rc = product(S, P, ready);
+      if (rc == KA_OK) rc = run->post_apply(done);
     }
-    if (done) {
-      finish_request(S, r, KA_OK);
-      continue;
+    if (solving_flag) {
+      std::lock_guard<std::mutex> g(S->mu);
+      S->solving--;
+      S->cv_gamma.notify_all();
     }
-    keep.push_back(std::move(own));
+    finish_request(S, *r, rc, t_admit, rc == KA_OK ? run.get() : nullptr);
+    run.reset();
+    if (P) destroy_problem(P);
+    {
+      std::lock_guard<std::mutex> g(S->mu);
+      S->used -= r->bytes;
+      S->in_flight--;
+      S->cv.notify_all();
+    }
   }
-  S->active = std::move(keep);
-  HIP_TRY(hipStreamSynchronize(S->stream));
-  return KA_OK;
+  (void)hipStreamSynchronize(stream);
+  (void)hipEventDestroy(ready);
+  (void)hipStreamDestroy(stream);
 }
 
+}  // namespace
 }  // namespace ka
 
 using namespace ka;
 
 extern "C" {
-
-int ka_server_create(size_t hbm_budget, int max_slots, ka_server** out) {
-  if (!out) return fail(KA_ERR_ARG, "out is NULL");
-  *out = nullptr;
-  if (max_slots < 1 || hbm_budget == 0) return fail(KA_ERR_ARG, "need max_slots >= 1 and a budget");
-  Server* S = new Server();
-  S->budget = hbm_budget;
-  S->max_slots = max_slots;
-  if (hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking) != hipSuccess ||
-      hipEventCreateWithFlags(&S->ev_gamma, hipEventDisableTiming) != hipSuccess) {
-    delete S;
-    return fail(KA_ERR_HIP, "server stream creation failed");
-  }
-  S->t0 = std::chrono::steady_clock::now();
-  *out = reinterpret_cast<ka_server*>(S);
-  return KA_OK;
-}
 
 int ka_request_bytes(const ka_desc* desc, int M, size_t* bytes) {
   if (!desc || !bytes) return fail(KA_ERR_ARG, "NULL argument");
@@ -283,6 +376,27 @@ int ka_request_bytes(const ka_desc* desc, int M, size_t* bytes) {
   return KA_OK;
 }
 
+int ka_server_create(size_t hbm_budget, int max_slots, ka_server** out) {
+  if (!out) return fail(KA_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  if (max_slots < 1 || max_slots > 256 || hbm_budget == 0) return fail(KA_ERR_ARG, "need 1 <= max_slots <= 256 and a budget");
+  Server* S = new Server();
+  S->budget = hbm_budget;
+  S->max_slots = max_slots;
+  bool ok = hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking) == hipSuccess;
+  for (int i = 0; i < kRing && ok; ++i) {
+    ok = hipEventCreateWithFlags(&S->ring_ev[i], hipEventDisableTiming) == hipSuccess;
+    if (ok) ok = hipEventRecord(S->ring_ev[i], S->stream) == hipSuccess;
+  }
+  if (!ok) {
+    delete S;
+    return fail(KA_ERR_HIP, "server stream creation failed");
+  }
+  S->t0 = Clock::now();
+  *out = reinterpret_cast<ka_server*>(S);
+  return KA_OK;
+}
+
 int ka_server_submit(ka_server* s, const ka_desc* desc, int M, double tol, int maxit, double arrival_s,
                      uint64_t tag, double* lambda_host, int64_t* req_id) {
   Server* S = reinterpret_cast<Server*>(s);
@@ -290,7 +404,6 @@ int ka_server_submit(ka_server* s, const ka_desc* desc, int M, double tol, int m
   size_t need = 0;
   if (int rc = ka_request_bytes(desc, M, &need)) return rc;
   std::unique_ptr<Request> r(new Request());
-  r->id = S->next_id++;
   r->desc = *desc;
   r->M = M;
   r->tol = tol;
@@ -299,39 +412,54 @@ int ka_server_submit(ka_server* s, const ka_desc* desc, int M, double tol, int m
   r->tag = tag;
   r->lambda_host = lambda_host;
   r->bytes = need;
+  std::lock_guard<std::mutex> g(S->mu);
+  r->id = S->next_id++;
   if (req_id) *req_id = r->id;
-  // keep arrival order
-  auto pos = S->queue.end();
+  auto pos = S->queue.end();       // keep arrival order
   while (pos != S->queue.begin() && (*(pos - 1))->arrival > arrival_s) --pos;
   S->queue.insert(pos, std::move(r));
+  S->cv.notify_all();
   return KA_OK;
 }
 
 int ka_server_run(ka_server* s, double timeout_s) {
   Server* S = reinterpret_cast<Server*>(s);
   if (!S) return fail(KA_ERR_ARG, "server is NULL");
-  if (!S->started) {
-    S->t0 = std::chrono::steady_clock::now();
-    S->started = true;
-  }
-  const double t_end = now_s(S) + (timeout_s > 0 ? timeout_s : 1e300);
-  while (!S->queue.empty() || !S->active.empty()) {
-    if (now_s(S) > t_end) return KA_NOT_CONVERGED;
-    if (int rc = admit(S)) return rc;
-    if (S->active.empty()) {
-      if (S->queue.empty()) break;
-      const double wait = S->queue.front()->arrival - now_s(S);
-      if (wait > 0) std::this_thread::sleep_for(std::chrono::duration<double>(std::min(wait, 0.01)));
-      continue;
+  {
+    std::lock_guard<std::mutex> g(S->mu);
+    if (!S->started) {
+      S->t0 = Clock::now();
+      S->started = true;
     }
-    if (int rc = step(S)) return rc;
+    S->stop = false;
   }
-  return KA_OK;
+  std::thread disp(dispatcher_main, S);
+  std::vector<std::thread> workers;
+  for (int i = 0; i < S->max_slots; ++i) workers.emplace_back(worker_main, S);
+  const auto t_end = Clock::now() + std::chrono::duration<double>(timeout_s > 0 ? timeout_s : 1e9);
+  int rc = KA_OK;
+  {
+    std::unique_lock<std::mutex> lk(S->mu);
+    while (!(S->queue.empty() && S->in_flight == 0)) {
+      if (S->cv.wait_until(lk, t_end) == std::cv_status::timeout && Clock::now() >= t_end) {
+        rc = KA_NOT_CONVERGED;
+        break;
+      }
+    }
+    S->stop = true;
+    S->cv.notify_all();
+    S->cv_gamma.notify_all();
+  }
+  for (auto& w : workers) w.join();
+  disp.join();
+  (void)hipStreamSynchronize(S->stream);
+  return rc;
 }
 
 int ka_server_poll(ka_server* s, ka_result* out, int max, int* n) {
   Server* S = reinterpret_cast<Server*>(s);
   if (!S || !n || (max > 0 && !out)) return fail(KA_ERR_ARG, "NULL argument");
+  std::lock_guard<std::mutex> g(S->mu);
   const int k = std::min<int>(max, (int)S->done.size());
   for (int i = 0; i < k; ++i) out[i] = S->done[i];
   S->done.erase(S->done.begin(), S->done.begin() + k);
@@ -342,6 +470,7 @@ int ka_server_poll(ka_server* s, ka_result* out, int max, int* n) {
 int ka_server_stats(ka_server* s, int* batches, double* mean_items, int* max_active, size_t* bytes_in_use) {
   Server* S = reinterpret_cast<Server*>(s);
   if (!S) return fail(KA_ERR_ARG, "server is NULL");
+  std::lock_guard<std::mutex> g(S->mu);
   if (batches) *batches = S->batches;
   if (mean_items) *mean_items = S->batches ? S->batch_items / S->batches : 0.0;
   if (max_active) *max_active = S->max_active;
@@ -352,15 +481,12 @@ int ka_server_stats(ka_server* s, int* batches, double* mean_items, int* max_act
 void ka_server_destroy(ka_server* s) {
   Server* S = reinterpret_cast<Server*>(s);
   if (!S) return;
-  (void)hipDeviceSynchronize();
-  for (auto& r : S->active) release(S, r.get());
-  S->active.clear();
-  S->queue.clear();
-  (void)hipHostFree(S->jobs_host);
-  (void)hipHostFree(S->items_host);
-  (void)hipFree(S->jobs_dev);
-  (void)hipFree(S->items_dev);
-  if (S->ev_gamma) (void)hipEventDestroy(S->ev_gamma);
+  (void)hipStreamSynchronize(S->stream);
+  for (int i = 0; i < kRing; ++i) {
+    if (S->ring_ev[i]) (void)hipEventDestroy(S->ring_ev[i]);
+    (void)hipFree(S->jobs_dev[i]);
+    (void)hipFree(S->items_dev[i]);
+  }
   if (S->stream) (void)hipStreamDestroy(S->stream);
   delete S;
 }
