@@ -64,6 +64,12 @@ class ka_result(ctypes.Structure):
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"HIP library not built: {LIB_PATH} is missing (run __graft_entry__.build())")
+    # One HIP runtime per process: torch ships its own libamdhip64 (same soname
+    # as the system one the library links).  Loading torch first makes the
+    # library bind to that copy; loading the library first would map a second
+    # runtime beside torch's, and streams or pointers from one are invalid in
+    # the other.
+    import torch  # noqa: F401
     lib = ctypes.CDLL(LIB_PATH)
     vp, i64, dp, fp = ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(ctypes.c_double), ctypes.c_void_p
     sig = {

@@ -115,7 +115,7 @@ size_t eig_workspace_bytes(int64_t N, int M, int b) {
   s += 3 * al((size_t)N * ncol * 8);
   s += 5 * al((size_t)m_max * m_max * 8);
   s += al((size_t)m_max * b * 8) + 2 * al((size_t)b * b * 8) + 3 * al((size_t)m_max * 8);
-  s += al(std::max(sym_eig_work(m_max), nonsym_eig_work(m_max)) * 8);
+  s += al(std::max({sym_eig_work(m_max), sym_tri_work(m_max), nonsym_eig_work(m_max)}) * 8);
   s += al(tn_work_doubles(m_max, b, N) * 8);
   s += al(column_norms_work(N, ncol) * 8) + al(256);
   return s;
@@ -210,7 +210,7 @@ int EigRun::start() {
   KA_TRY(alloc((size_t)m * 8, &w_.theta));
   KA_TRY(alloc((size_t)m * 8, &w_.thetai));
   KA_TRY(alloc((size_t)m * 8, &w_.norms));
-  KA_TRY(alloc(std::max(sym_eig_work(m), nonsym_eig_work(m)) * 8, &w_.ework));
+  KA_TRY(alloc(std::max({sym_eig_work(m), sym_tri_work(m), nonsym_eig_work(m)}) * 8, &w_.ework));
   KA_TRY(alloc(tn_work_doubles(m, b, N) * 8, &w_.tnwork));
   KA_TRY(alloc(column_norms_work(N, ncol) * 8, &w_.nwork));
   {
@@ -242,7 +242,7 @@ int EigRun::rayleigh_ritz(bool& stop) {
   int nk;
   int ns_status = 0;
   if (sym_) {
-    HIP_TRY(sym_eig(w_.H, k, m, w_.theta, w_.S, m, w_.ework, s_));
+    HIP_TRY(sym_eig_tri(w_.H, k, m, w_.theta, w_.S, m, w_.ework, s_));
     nk = std::min(nev_, k);
   } else {
     HIP_TRY(nonsym_eig(w_.H, k, m, w_.theta, w_.thetai, w_.S, m, w_.ework, w_.status, s_));
@@ -252,7 +252,7 @@ int EigRun::rayleigh_ritz(bool& stop) {
   HIP_TRY(dgemm_nn(N, nk, k, 1.0, w_.AX, N, w_.S, m, 0.0, w_.AXS, N, s_));
   HIP_TRY(residual_combine(w_.AXS, w_.XS, N, nk, N, w_.theta, sym_ ? nullptr : w_.thetai, w_.R, s_));
   HIP_TRY(column_norms(w_.R, N, nk, N, w_.norms, w_.nwork, s_));
-  HIP_TRY(hipMemcpyAsync(th_.data(), w_.theta, sizeof(double) * nk, hipMemcpyDeviceToHost, s_));
+  HIP_TRY(hipMemcpyAsync(th_.data(), w_.theta, sizeof(double) * (sym_ ? k : nk), hipMemcpyDeviceToHost, s_));
   HIP_TRY(hipMemcpyAsync(rn_.data(), w_.norms, sizeof(double) * nk, hipMemcpyDeviceToHost, s_));
   if (!sym_) {
     HIP_TRY(hipMemcpyAsync(thi_.data(), w_.thetai, sizeof(double) * nk, hipMemcpyDeviceToHost, s_));
@@ -286,7 +286,17 @@ int EigRun::rayleigh_ritz(bool& stop) {
       max_res_ = std::max(max_res_, rel);
       if (!sym_) max_imag_ = std::max(max_imag_, std::fabs(thi_[i]) / modulus(i));
     }
-    if (rn_[i] <= crit && nconv_ == i) ++nconv_;
+    bool ok = rn_[i] <= crit;
+    if (sym_ && ok && rn_[i] > tol_ * modulus(i)) {
+      // accepted through the noise floor only: also require the Ritz value to be
+      // accurate, |theta - lambda| <= r^2 / gap (gap to the nearest Ritz value
+      // outside its cluster, among all k), to a tenth of tol on the floored scale
+      double gap = 1e300;
+      for (int j = 0; j < k; ++j)
+        if (std::fabs(th_[j] - th_[i]) > 1e-6 * std::fabs(th_[i])) gap = std::min(gap, std::fabs(th_[j] - th_[i]));
+      ok = rn_[i] * rn_[i] <= 0.1 * tol_ * std::max(modulus(i), tau * modulus(0)) * gap;
+    }
+    if (ok && nconv_ == i) ++nconv_;
   }
   nret_ = sym_ ? nk : std::min(nk, Meff_ + 1);
   converged_ = nconv_ >= Meff_;

@@ -103,6 +103,11 @@ hipError_t chol_upper_inv(const double* G, int n, int ldg, double* Rinv, int ldr
 hipError_t sym_eig(const double* H, int n, int ldh, double* theta, double* S, int lds, double* work,
                    hipStream_t s);
 size_t sym_eig_work(int n);
+// Tridiagonal route (Householder, multisection, inverse iteration): the Galerkin
+// Rayleigh-Ritz step.  The Jacobi solver above stays for near-identity Gram matrices.
+hipError_t sym_eig_tri(const double* H, int n, int ldh, double* theta, double* S, int lds, double* work,
+                       hipStream_t s);
+size_t sym_tri_work(int n);
 hipError_t nonsym_eig(const double* H, int n, int ldh, double* wr, double* wi, double* S, int lds,
                       double* work, int* status, hipStream_t s);
 size_t nonsym_eig_work(int n);

@@ -1,0 +1,296 @@
+// Small dense symmetric eigensolve for the Rayleigh-Ritz step of the Galerkin
+// method (the projected matrix of the symmetric standard form A' = L^-1 A L^-T,
+// paper Sec. 3.1).  Split into stages that parallelise differently:
+//   1. Householder tridiagonalisation  H = Q T Q^T  by a team of threads
+//      (reflectors kept in the strictly lower part of the working copy A);
+//   2. eigenvalue k of T by multisection on Sturm counts (one wave per value);
+//   3. eigenvectors of T by inverse iteration with the pivoted tridiagonal
+//      LU; eigenvalues closer than a gap form a cluster, handled by one thread
+//      that orthogonalises each member against the earlier ones after every
+//      solve, so clustered vectors come out orthonormal  (one per cluster);
+//   4. back-transformation x <- Q x by the reflectors          (one per vector).
+// Every function here is plain C++ usable on the host (unit tests) and on the
+// device (sym.hip runs stage 1 as one workgroup, stages 2-4 as wide grids).
+//
+// Work layout (doubles), n = order:
+//   A    n*n    column-major working copy, reflectors below the sub-diagonal
+//   V    n*n    vectors interleaved: element i of vector k at V[i*n + k]
+//   F    5*n*n  per-eigenvalue LU factors, interleaved the same way per field
+//   d, e, beta, lam   4*n  (diagonal, off-diagonal, reflector coefficients,
+//                           eigenvalues ascending)
+//   bnd  4      Gershgorin lower / upper bound, norm estimate
+#pragma once
+#include <math.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#ifndef KA_HD
+#ifdef __HIPCC__
+#define KA_HD __host__ __device__
+#else
+#define KA_HD
+#endif
+#endif
+
+namespace ka {
+
+struct SymWork {
+  double *A, *V, *F, *d, *e, *beta, *lam, *bnd;
+};
+
+KA_HD inline size_t sym_tri_work_doubles(int n) { return (size_t)7 * n * n + (size_t)4 * n + 4; }
+
+KA_HD inline SymWork sym_work_split(double* w, int n) {
+  const size_t nn = (size_t)n * n;
+  SymWork s;
+  s.A = w;
+  s.V = w + nn;
+  s.F = w + 2 * nn;
+  s.d = w + 7 * nn;
+  s.e = s.d + n;
+  s.beta = s.e + n;
+  s.lam = s.beta + n;
+  s.bnd = s.lam + n;
+  return s;
+}
+
+constexpr double kSymEps = 2.220446049250313e-16;
+// eigenvalues closer than this (relative to the norm estimate) form a cluster
+constexpr double kSymClusterGap = 1e-6;
+
+KA_HD inline double sym_copysign(double a, double b) { return b >= 0.0 ? fabs(a) : -fabs(a); }
+
+// ---- stage 1: tridiagonalisation by a team ---------------------------------------
+// Team interface: tid(), size(), sync(), sum(x) (total over the team, returned to
+// every thread).  v: team-shared scratch of >= n doubles.  A: n x n column-major
+// (may live in fast memory); w: a free column of >= n doubles for the product.
+template <class Team>
+KA_HD void sym_tridiagonalize(Team& tm, double* A, int n, double* d, double* e, double* beta, double* v,
+                              double* w) {
+  const int t = tm.tid(), NT = tm.size();
+  for (int j = 0; j + 2 < n; ++j) {
+    const int m = n - j - 1;
+    double* col = A + (j + 1) + (size_t)j * n;      // column j below the diagonal
+    double ss = 0.0;
+    for (int i = t; i < m; i += NT) ss += col[i] * col[i];
+    ss = tm.sum(ss);
+    const double x0 = col[0];
+    const double alpha = -sym_copysign(sqrt(ss), x0);
+    const double v0 = x0 - alpha;
+    const bool skip = !(ss > 1e-300);
+    const double vtv = ss - x0 * x0 + v0 * v0;     // >= ss whenever ss > 0
+    const double b = skip ? 0.0 : 2.0 / vtv;
+    for (int i = t; i < m; i += NT) v[i] = (i == 0) ? v0 : col[i];
+    if (t == 0) {
+      d[j] = A[j + (size_t)j * n];
+      e[j] = skip ? x0 : alpha;
+      beta[j] = b;
+    }
+    tm.sync();
+    if (!skip) {
+      double* A22 = A + (j + 1) + (size_t)(j + 1) * n;
+      // w = b A22 v
+      for (int r = t; r < m; r += NT) {
+        double acc = 0.0;
+        for (int c = 0; c < m; ++c) acc += A22[r + (size_t)c * n] * v[c];
+        w[r] = b * acc;
+      }
+      tm.sync();
+      double wv = 0.0;
+      for (int r = t; r < m; r += NT) wv += w[r] * v[r];
+      wv = tm.sum(wv);
+      const double K = 0.5 * b * wv;
+      for (int r = t; r < m; r += NT) w[r] -= K * v[r];
+      tm.sync();
+      // A22 <- A22 - v w^T - w v^T  (= H A22 H)
+      for (int64_t q = t; q < (int64_t)m * m; q += NT) {
+        const int r = (int)(q % m), c = (int)(q / m);
+        A22[r + (size_t)c * n] -= v[r] * w[c] + w[r] * v[c];
+      }
+    }
+    tm.sync();
+    for (int i = t; i < m; i += NT) col[i] = v[i];  // reflector for the back-transformation
+    tm.sync();
+  }
+  if (t == 0) {
+    if (n >= 2) {
+      d[n - 2] = A[(n - 2) + (size_t)(n - 2) * n];
+      e[n - 2] = A[(n - 1) + (size_t)(n - 2) * n];
+    }
+    d[n - 1] = A[(n - 1) + (size_t)(n - 1) * n];
+  }
+  tm.sync();
+}
+
+// Gershgorin interval and norm estimate of T (d, e)
+KA_HD inline void sym_bounds(const double* d, const double* e, int n, double* bnd) {
+  double lo = 1e300, hi = -1e300, tn = 0.0;
+  for (int i = 0; i < n; ++i) {
+    const double r = (i > 0 ? fabs(e[i - 1]) : 0.0) + (i + 1 < n ? fabs(e[i]) : 0.0);
+    lo = fmin(lo, d[i] - r);
+    hi = fmax(hi, d[i] + r);
+    tn = fmax(tn, fabs(d[i]) + r);
+  }
+  if (!(tn > 0.0)) tn = 1.0;
+  bnd[0] = lo - 4.0 * kSymEps * tn;
+  bnd[1] = hi + 4.0 * kSymEps * tn;
+  bnd[2] = tn;
+  bnd[3] = 0.0;
+}
+
+// number of eigenvalues of T smaller than x (Sturm sequence of the LDL^T pivots)
+KA_HD inline int sym_sturm_count(const double* d, const double* e, int n, double x, double pivmin) {
+  int c = 0;
+  double q = d[0] - x;
+  if (fabs(q) < pivmin) q = -pivmin;
+  if (q < 0.0) ++c;
+  for (int i = 1; i < n; ++i) {
+    q = d[i] - x - e[i - 1] * e[i - 1] / q;
+    if (fabs(q) < pivmin) q = -pivmin;
+    if (q < 0.0) ++c;
+  }
+  return c;
+}
+
+// ---- stage 2: the k-th smallest eigenvalue (k = 0 .. n-1) by multisection ----------
+// Each round evaluates the Sturm count at P interior points of [lo, hi] (one per
+// lane on the GPU) and keeps the sub-interval where the count passes k, so the
+// interval shrinks by P + 1 per round.
+KA_HD inline double sym_pivmin(const double* bnd) { return 1e-280 * fmax(1.0, bnd[2] * bnd[2]); }
+
+KA_HD inline bool sym_section_done(double lo, double hi, const double* bnd) {
+  return hi - lo <= 2.0 * kSymEps * fmax(fabs(lo), fabs(hi)) + 1e-3 * kSymEps * bnd[2];
+}
+
+KA_HD inline double sym_section_point(double lo, double hi, int t, int P) {
+  return lo + (hi - lo) * ((double)(t + 1) / (double)(P + 1));
+}
+
+// mask bit t set when count(point t) > k
+KA_HD inline void sym_section_narrow(double& lo, double& hi, uint64_t mask, int P) {
+  const double lo0 = lo, hi0 = hi;
+  if (mask == 0) {
+    lo = sym_section_point(lo0, hi0, P - 1, P);
+  } else {
+    const int f = __builtin_ctzll(mask);
+    hi = sym_section_point(lo0, hi0, f, P);
+    if (f > 0) lo = sym_section_point(lo0, hi0, f - 1, P);
+  }
+}
+
+constexpr int kSymSectionRounds = 32;
+
+KA_HD inline double sym_hash_unit(uint64_t a, uint64_t b) {
+  uint64_t z = a * 0x9E3779B97F4A7C15ull + b + 0x632BE59BD9B4E019ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  z ^= z >> 31;
+  return ((double)(z >> 11) + 0.5) * (1.0 / 9007199254740992.0) - 0.5;
+}
+
+// does the cluster containing eigenvalue k start at k?  (lam ascending)
+KA_HD inline bool sym_cluster_start(const double* lam, int k, const double* bnd) {
+  return k == 0 || lam[k] - lam[k - 1] >= kSymClusterGap * bnd[2];
+}
+
+// ---- stage 3: inverse iteration for the cluster starting at c0 -------------------------
+KA_HD inline void sym_inverse_iteration(const double* d, const double* e, int n, const double* lam, int c0,
+                                        const double* bnd, double* V, double* F) {
+  const double tn = bnd[2];
+  const double gap = kSymClusterGap * tn;
+  const double tiny = kSymEps * tn;
+  const size_t nn = (size_t)n * n;
+  int c1 = c0 + 1;
+  while (c1 < n && lam[c1] - lam[c1 - 1] < gap) ++c1;
+  double sig_prev = -1e300;
+  for (int k = c0; k < c1; ++k) {
+#define XK(i) V[(size_t)(i) * n + k]
+#define FK(f, i) F[(f) * nn + (size_t)(i) * n + k]
+    // distinct shifts inside a cluster
+    double sig = lam[k];
+    if (k > c0 && sig < sig_prev + 10.0 * tiny) sig = sig_prev + 10.0 * tiny;
+    sig_prev = sig;
+    // LU of T - sig I with partial pivoting; fields: 0 U diagonal, 1 and 2 the
+    // two super-diagonals of U, 3 multiplier, 4 row interchange flag
+    double a = d[0] - sig, bs = n > 1 ? e[0] : 0.0, cs = 0.0;
+    for (int i = 0; i + 1 < n; ++i) {
+      const double sub = e[i], dn = d[i + 1] - sig, en = (i + 2 < n) ? e[i + 1] : 0.0;
+      if (fabs(a) >= fabs(sub)) {
+        const double l = (a != 0.0) ? sub / a : 0.0;
+        FK(0, i) = a;
+        FK(1, i) = bs;
+        FK(2, i) = cs;
+        FK(3, i) = l;
+        FK(4, i) = 0.0;
+        a = dn - l * bs;
+        bs = en - l * cs;
+      } else {
+        const double l = a / sub;
+        FK(0, i) = sub;
+        FK(1, i) = dn;
+        FK(2, i) = en;
+        FK(3, i) = l;
+        FK(4, i) = 1.0;
+        a = bs - l * dn;
+        bs = cs - l * en;
+      }
+      cs = 0.0;
+    }
+    FK(0, n - 1) = a;
+    FK(1, n - 1) = 0.0;
+    FK(2, n - 1) = 0.0;
+    for (int i = 0; i < n; ++i)
+      if (fabs(FK(0, i)) < tiny) FK(0, i) = sym_copysign(tiny, FK(0, i));
+    for (int i = 0; i < n; ++i) XK(i) = sym_hash_unit((uint64_t)k + 1, (uint64_t)i);
+    for (int iter = 0; iter < 3; ++iter) {
+      for (int i = 0; i + 1 < n; ++i) {
+        if (FK(4, i) != 0.0) {
+          const double tmp = XK(i);
+          XK(i) = XK(i + 1);
+          XK(i + 1) = tmp;
+        }
+        XK(i + 1) -= FK(3, i) * XK(i);
+      }
+      for (int i = n - 1; i >= 0; --i) {
+        double s = XK(i);
+        if (i + 1 < n) s -= FK(1, i) * XK(i + 1);
+        if (i + 2 < n) s -= FK(2, i) * XK(i + 2);
+        s /= FK(0, i);
+        if (fabs(s) > 1e150) {                      // keep the growth representable
+          for (int r = 0; r < n; ++r) XK(r) *= 1e-150;
+          s *= 1e-150;
+        }
+        XK(i) = s;
+      }
+      // orthogonalise against the cluster's earlier vectors (two passes)
+      for (int pass = 0; pass < (k > c0 ? 2 : 0); ++pass)
+        for (int j = c0; j < k; ++j) {
+          double dot = 0.0;
+          for (int i = 0; i < n; ++i) dot += XK(i) * V[(size_t)i * n + j];
+          for (int i = 0; i < n; ++i) XK(i) -= dot * V[(size_t)i * n + j];
+        }
+      double nr = 0.0;
+      for (int i = 0; i < n; ++i) nr += XK(i) * XK(i);
+      nr = nr > 0.0 ? 1.0 / sqrt(nr) : 0.0;
+      for (int i = 0; i < n; ++i) XK(i) *= nr;
+    }
+#undef XK
+#undef FK
+  }
+}
+
+// ---- stage 4: x_k <- Q x_k = H_0 H_1 ... H_{n-3} x_k ---------------------------------
+KA_HD inline void sym_back_transform(const double* A, const double* beta, int n, double* V, int k) {
+  for (int j = n - 3; j >= 0; --j) {
+    const double b = beta[j];
+    if (b == 0.0) continue;
+    const double* vj = A + (j + 1) + (size_t)j * n;
+    const int m = n - j - 1;
+    double s = 0.0;
+    for (int i = 0; i < m; ++i) s += vj[i] * V[(size_t)(j + 1 + i) * n + k];
+    s *= b;
+    for (int i = 0; i < m; ++i) V[(size_t)(j + 1 + i) * n + k] -= s * vj[i];
+  }
+}
+
+}  // namespace ka

@@ -1,0 +1,52 @@
+// Host build of the library's small symmetric eigensolve stages (the same
+// source the GPU kernels run), for CPU unit tests of their logic.
+#include <vector>
+
+#include "../../paper_2101_00629_amd/csrc/sym_core.hpp"
+
+namespace {
+struct HostTeam {
+  int tid() const { return 0; }
+  int size() const { return 1; }
+  void sync() const {}
+  double sum(double x) const { return x; }
+};
+}  // namespace
+
+// theta descending, S (n x n column-major) the matching unit eigenvectors;
+// returns the number of clusters found
+extern "C" int ka_host_sym_eig(const double* H, int n, double* theta, double* S) {
+  std::vector<double> work(ka::sym_tri_work_doubles(n)), v(n), w(n);
+  ka::SymWork sw = ka::sym_work_split(work.data(), n);
+  for (int j = 0; j < n; ++j)
+    for (int i = 0; i < n; ++i) sw.A[i + (size_t)j * n] = 0.5 * (H[i + (size_t)j * n] + H[j + (size_t)i * n]);
+  HostTeam tm;
+  ka::sym_tridiagonalize(tm, sw.A, n, sw.d, sw.e, sw.beta, v.data(), w.data());
+  ka::sym_bounds(sw.d, sw.e, n, sw.bnd);
+  const double pivmin = ka::sym_pivmin(sw.bnd);
+  for (int k = 0; k < n; ++k) {
+    // one wave of 64 lanes, emulated
+    double lo = sw.bnd[0], hi = sw.bnd[1];
+    for (int r = 0; r < ka::kSymSectionRounds && !ka::sym_section_done(lo, hi, sw.bnd); ++r) {
+      uint64_t mask = 0;
+      for (int t = 0; t < 64; ++t)
+        if (ka::sym_sturm_count(sw.d, sw.e, n, ka::sym_section_point(lo, hi, t, 64), pivmin) > k)
+          mask |= 1ull << t;
+      ka::sym_section_narrow(lo, hi, mask, 64);
+    }
+    sw.lam[k] = 0.5 * (lo + hi);
+  }
+  int clusters = 0;
+  for (int k = 0; k < n; ++k)
+    if (ka::sym_cluster_start(sw.lam, k, sw.bnd)) {
+      ++clusters;
+      ka::sym_inverse_iteration(sw.d, sw.e, n, sw.lam, k, sw.bnd, sw.V, sw.F);
+    }
+  for (int k = 0; k < n; ++k) ka::sym_back_transform(sw.A, sw.beta, n, sw.V, k);
+  for (int k = 0; k < n; ++k) {
+    const int src = n - 1 - k;
+    theta[k] = sw.lam[src];
+    for (int i = 0; i < n; ++i) S[i + (size_t)k * n] = sw.V[(size_t)i * n + src];
+  }
+  return clusters;
+}

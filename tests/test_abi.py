@@ -52,3 +52,17 @@ def test_product_path_has_no_oracle_dependency():
                 txt = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in txt and "from oracle" not in txt, f
                 assert "oracle/" not in txt, f
+
+
+def test_single_hip_runtime_whatever_the_import_order():
+    """The package binds the library to the HIP runtime torch ships, even when
+    it is imported before torch: two runtimes in one process would not share
+    streams or device pointers."""
+    import subprocess
+    import sys
+    code = ("import os, paper_2101_00629_amd, torch\n"
+            "m = open(f'/proc/{os.getpid()}/maps').read()\n"
+            "print(len(set(l.split()[-1] for l in m.splitlines() if 'libamdhip64' in l)))\n")
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, cwd=ROOT, timeout=300)
+    assert out.returncode == 0, out.stderr
+    assert out.stdout.strip().splitlines()[-1] == "1"

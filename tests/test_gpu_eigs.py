@@ -118,3 +118,30 @@ def _solve_c(desc, M, tol=1e-6, maxit=60):
     Vn = V.cpu().numpy().T
     prob.close()
     return rc, lam, Vn, info
+
+
+# p = 4 annulus with the curved-domain workload's kernels (Gaussian l = 0.5,
+# exponential l = 0.25) on a reduced mesh, both methods, both precisions,
+# against the dense FP64 oracle.
+@pytest.mark.parametrize("precision,bar", [("fp32", 1e-6), ("bf16x3", 1e-5)])
+@pytest.mark.parametrize("method,kernel,ell", [("galerkin", "gaussian", 0.5), ("galerkin", "exponential", 0.25),
+                                               ("collocation", "gaussian", 0.5),
+                                               ("collocation", "exponential", 0.25)])
+def test_annulus_p4_reduced_mesh(method, kernel, ell, precision, bar):
+    from oracle import collocation
+    dom = geometry.QuarterAnnulus()
+    if method == "galerkin":
+        o = galerkin.GalerkinIBQ(dom, 4, (6, 6, 3), kernel, ell)
+    else:
+        o = collocation.Collocation(dom, 4, (6, 6, 3), kernel, ell)
+    ref, _ = o.eig_dense(20)
+    desc = K.make_desc(method, "quarter_annulus", 4, (6, 6, 3), kernel, ell, precision=precision, seed=9)
+    prob = K.Problem(desc)
+    rc, lam, info = K.ka_eigs(prob.h, 20, tol=1e-6, maxit=60, complex_values=(method == "collocation"))
+    prob.close()
+    if method == "collocation":
+        assert np.abs(lam[1::2] - ref.imag).max() < 10 * bar * abs(ref[0])
+        lam, ref = lam[0::2], ref.real
+    err = errors.floored_rel_errors(ref, lam)
+    print(method, kernel, precision, info, err.max())
+    assert rc == 0 and err.max() < bar
