@@ -195,6 +195,10 @@ static int setup_impl(const ka_desc* d, hipStream_t stream, Problem** out) {
   geo.r1 = d->r1;
   geo.height = d->height;
   const double cs = coord_scale64(d->kernel, d->ell);
+  // The kernel depends on differences only: coordinates are centred on the
+  // domain before rounding to FP32, which halves their absolute rounding error.
+  double ctr[3];
+  geo.center(ctr);
   bool ok = true;
 
   // univariate factors
@@ -277,7 +281,7 @@ static int setup_impl(const ka_desc* d, hipStream_t stream, Problem** out) {
           const double xh[3] = {g[0][a1], g[1][a2], g[2][a3]};
           double x[3];
           geo.map(xh, x);
-          for (int c = 0; c < 3; ++c) xyz[i * 4 + c] = (float)(x[c] * cs);
+          for (int c = 0; c < 3; ++c) xyz[i * 4 + c] = (float)((x[c] - ctr[c]) * cs);
           if (detJ) (*detJ)[i] = geo.detJ(xh);
         }
   };

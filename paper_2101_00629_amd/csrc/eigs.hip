@@ -115,7 +115,7 @@ size_t eig_workspace_bytes(int64_t N, int M, int b) {
   s += 3 * al((size_t)N * ncol * 8);
   s += 5 * al((size_t)m_max * m_max * 8);
   s += al((size_t)m_max * b * 8) + 2 * al((size_t)b * b * 8) + 3 * al((size_t)m_max * 8);
-  s += al(std::max({sym_eig_work(m_max), sym_tri_work(m_max), nonsym_eig_work(m_max)}) * 8);
+  s += al(std::max({sym_eig_work(m_max), sym_tri_work(m_max), nonsym_eig_work(m_max, std::min(nev + 1, m_max))}) * 8);
   s += al(tn_work_doubles(m_max, b, N) * 8);
   s += al(column_norms_work(N, ncol) * 8) + al(256);
   return s;
@@ -210,7 +210,7 @@ int EigRun::start() {
   KA_TRY(alloc((size_t)m * 8, &w_.theta));
   KA_TRY(alloc((size_t)m * 8, &w_.thetai));
   KA_TRY(alloc((size_t)m * 8, &w_.norms));
-  KA_TRY(alloc(std::max({sym_eig_work(m), sym_tri_work(m), nonsym_eig_work(m)}) * 8, &w_.ework));
+  KA_TRY(alloc(std::max({sym_eig_work(m), sym_tri_work(m), nonsym_eig_work(m, std::min(nev_ + 1, m))}) * 8, &w_.ework));
   KA_TRY(alloc(tn_work_doubles(m, b, N) * 8, &w_.tnwork));
   KA_TRY(alloc(column_norms_work(N, ncol) * 8, &w_.nwork));
   {
@@ -242,11 +242,11 @@ int EigRun::rayleigh_ritz(bool& stop) {
   int nk;
   int ns_status = 0;
   if (sym_) {
-    HIP_TRY(sym_eig_tri(w_.H, k, m, w_.theta, w_.S, m, w_.ework, s_));
     nk = std::min(nev_, k);
+    HIP_TRY(sym_eig_tri(w_.H, k, m, nk, w_.theta, w_.S, m, w_.ework, s_));
   } else {
-    HIP_TRY(nonsym_eig(w_.H, k, m, w_.theta, w_.thetai, w_.S, m, w_.ework, w_.status, s_));
     nk = std::min(nev_ + 1, k);
+    HIP_TRY(nonsym_eig(w_.H, k, m, nk, w_.theta, w_.thetai, w_.S, m, w_.ework, w_.status, s_));
   }
   HIP_TRY(dgemm_nn(N, nk, k, 1.0, w_.X, N, w_.S, m, 0.0, w_.XS, N, s_));
   HIP_TRY(dgemm_nn(N, nk, k, 1.0, w_.AX, N, w_.S, m, 0.0, w_.AXS, N, s_));
@@ -289,11 +289,14 @@ int EigRun::rayleigh_ritz(bool& stop) {
     bool ok = rn_[i] <= crit;
     if (sym_ && ok && rn_[i] > tol_ * modulus(i)) {
       // accepted through the noise floor only: also require the Ritz value to be
-      // accurate, |theta - lambda| <= r^2 / gap (gap to the nearest Ritz value
-      // outside its cluster, among all k), to a tenth of tol on the floored scale
+      // accurate, |theta - lambda| <= r^2 / gap, to a tenth of tol on the floored
+      // scale.  gap: distance to the nearest Ritz value (among all k) outside the
+      // cluster of values that neither r nor the arithmetic noise can separate
+      // from theta_i.
+      const double sep = std::max({1e-6 * std::fabs(th_[i]), rn_[i], noise_ * modulus(0)});
       double gap = 1e300;
       for (int j = 0; j < k; ++j)
-        if (std::fabs(th_[j] - th_[i]) > 1e-6 * std::fabs(th_[i])) gap = std::min(gap, std::fabs(th_[j] - th_[i]));
+        if (std::fabs(th_[j] - th_[i]) > sep) gap = std::min(gap, std::fabs(th_[j] - th_[i]));
       ok = rn_[i] * rn_[i] <= 0.1 * tol_ * std::max(modulus(i), tau * modulus(0)) * gap;
     }
     if (ok && nconv_ == i) ++nconv_;

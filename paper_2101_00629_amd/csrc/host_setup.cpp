@@ -254,6 +254,16 @@ void Geometry::map(const double* xh, double* x) const {
   }
 }
 
+void Geometry::center(double* c) const {
+  if (domain == 0) {
+    for (int k = 0; k < 3; ++k) c[k] = 0.5 * (lo[k] + hi[k]);
+  } else {
+    // the quarter annulus lies in [0, r1] x [0, r1] x [0, height]
+    c[0] = c[1] = 0.5 * r1;
+    c[2] = 0.5 * height;
+  }
+}
+
 double Geometry::detJ(const double* xh) const {
   if (domain == 0) return std::fabs((hi[0] - lo[0]) * (hi[1] - lo[1]) * (hi[2] - lo[2]));
   double C[2], dC[2];

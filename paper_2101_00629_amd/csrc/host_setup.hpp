@@ -60,6 +60,8 @@ struct Geometry {
   void map(const double* xh, double* x) const;
   double detJ(const double* xh) const;
   double volume() const;
+  // midpoint of the axis-aligned bounding box of the mapped domain
+  void center(double* c) const;
   // NURBS weight function of parametric direction k (1 for B-spline directions).
   double weight1d(int k, double t) const;
 };

@@ -105,12 +105,19 @@ hipError_t sym_eig(const double* H, int n, int ldh, double* theta, double* S, in
 size_t sym_eig_work(int n);
 // Tridiagonal route (Householder, multisection, inverse iteration): the Galerkin
 // Rayleigh-Ritz step.  The Jacobi solver above stays for near-identity Gram matrices.
-hipError_t sym_eig_tri(const double* H, int n, int ldh, double* theta, double* S, int lds, double* work,
+// All n eigenvalues (theta, descending) and the eigenvectors of the nvec largest
+// (S columns 0 .. nvec-1).
+hipError_t sym_eig_tri(const double* H, int n, int ldh, int nvec, double* theta, double* S, int lds, double* work,
                        hipStream_t s);
 size_t sym_tri_work(int n);
-hipError_t nonsym_eig(const double* H, int n, int ldh, double* wr, double* wi, double* S, int lds,
+// All n eigenvalues (wr, wi; descending real part, a pair as consecutive entries
+// with the positive imaginary part first) and the eigenvectors of the nvec
+// leading ones (S columns; a pair as real and imaginary parts, extended by one
+// column when a pair straddles nvec).  status: 0, or 1 if the QR iteration
+// did not converge.
+hipError_t nonsym_eig(const double* H, int n, int ldh, int nvec, double* wr, double* wi, double* S, int lds,
                       double* work, int* status, hipStream_t s);
-size_t nonsym_eig_work(int n);
+size_t nonsym_eig_work(int n, int nvec_max);
 hipError_t column_norms(const double* X, int64_t N, int n, int64_t ldx, double* out, double* work,
                         hipStream_t s);
 size_t column_norms_work(int64_t N, int n);

@@ -1,115 +1,177 @@
-// Small dense non-symmetric eigensolve (real Schur form and eigenvectors),
-// written once for a "team" of cooperating lanes so that the same code runs
-// as one GPU wave (nonsym.hip) and as a single host thread (unit tests).
-//
-//   1. Householder reduction of H to upper Hessenberg form, H = Q0 Hh Q0^T.
-//   2. Francis double-shift QR iteration on Hh (Golub & Van Loan, Sec. 7.5),
-//      accumulating the orthogonal transformations: Hh = Q1 T Q1^T with T
-//      quasi upper triangular (real Schur form).
-//   3. Eigenvectors of T by back substitution, one eigenvalue per lane,
-//      complex pairs in real arithmetic; then V = Q0 Q1 Y.
-//   4. Sort by descending real part; normalise (unit 2-norm per real vector,
-//      |re|^2 + |im|^2 = 1 per complex pair; re and im in consecutive columns).
-// status: 0 ok, 1 the QR iteration did not converge.
-//
-// Team interface: tid(), size(), sync(), sum(x) (over all lanes), scratch
-// (>= 6n doubles shared by the team).  work: nonsym_work_doubles(n) doubles;
-// Abuf: optional n x n buffer in faster memory for the working matrix.
+// Small dense non-symmetric eigensolve for the Rayleigh-Ritz step of the
+// collocation method (the projected matrix of Z^-1 A, paper Sec. 3.2, is not
+// symmetric).  Stages, each written once as plain C++ for the host (unit
+// tests) and the device (nonsym.hip):
+//   1. Householder reduction to upper Hessenberg form H = Q Hh Q^T by a team
+//      of threads; reflector j is kept below the sub-diagonal of column j.
+//   2. All eigenvalues of Hh by the Francis double-shift QR iteration
+//      (Golub & Van Loan, Sec. 7.5) restricted to the active window, without
+//      forming the Schur vectors; one wave, on a banded copy of Hh.
+//   3. Ranking by descending real part; a complex pair stays together with
+//      the positive imaginary part first.
+//   4. Eigenvectors of Hh for the wanted (leading) eigenvalues only, by
+//      inverse iteration with the pivoted Hessenberg LU of Hh - lambda I in
+//      complex arithmetic, one team per cluster (each row operation split
+//      over the team); eigenvalues closer than a gap form a cluster whose
+//      vectors are orthogonalised against each other after every solve.
+//   5. Back-transformation x <- Q x (the reflectors of stage 1).
+//   6. Output: column c real (unit 2-norm) or, for a pair, columns c, c+1 the
+//      real and imaginary parts of one eigenvector with |re|^2 + |im|^2 = 1.
 #pragma once
 #include <math.h>
+#include <stddef.h>
 #include <stdint.h>
 
-#ifndef KA_HD
-#ifdef __HIPCC__
-#define KA_HD __host__ __device__
-#else
-#define KA_HD
-#endif
-#endif
+#include "sym_core.hpp"
 
 namespace ka {
 
-KA_HD inline size_t nonsym_work_doubles(int n) { return (size_t)4 * n * n + 8 * (size_t)n; }
+constexpr double kNsEps = 2.220446049250313e-16;
+// eigenvalues closer than this, relative to the largest modulus, form a cluster
+constexpr double kNsClusterGap = 1e-8;
+
+// ---- work layout -------------------------------------------------------------------------
+// A    n*n      Hessenberg reduction, reflectors below the sub-diagonal
+// hsub n        sub-diagonal of Hh;  beta n   reflector coefficients
+// wr0, wi0 2n   eigenvalues in QR order;  rank n (as doubles), wr, wi 2n sorted
+// misc 8        [0] norm of Hh, [1] QR status
+// V    n*nv     wanted vectors, element i of output column c at V[i*nv + c]
+// F    nv*(n*n + 4n)  per-entry LU planes and multipliers (contiguous per entry)
+// HT   n*n      row-major copy of Hh (rows of B = Hh - lambda I for the LU)
+// (nv: column capacity, at least the wanted count plus one for a pair that
+// straddles it)
+// HB   n*(n+7)/2 + 8  banded copy of Hh for the QR iteration
+struct NsWork {
+  double *A, *hsub, *beta, *wr0, *wi0, *rank, *wr, *wi, *misc, *V, *F, *HB, *HT;
+  int nv;
+};
+
+KA_HD inline size_t ns_band_doubles(int n) { return (size_t)n * (n + 7) / 2 + 8; }
+KA_HD inline size_t ns_lu_doubles(int n) { return (size_t)n * n + 4 * (size_t)n; }
+
+KA_HD inline size_t nonsym_work_doubles(int n, int nv) {
+  return (size_t)2 * n * n + 8 * (size_t)n + 8 + (size_t)n * nv + (size_t)nv * ns_lu_doubles(n) + ns_band_doubles(n);
+}
+
+KA_HD inline NsWork ns_work_split(double* w, int n, int nv) {
+  NsWork s;
+  s.nv = nv;
+  s.A = w;
+  s.hsub = w + (size_t)n * n;
+  s.beta = s.hsub + n;
+  s.wr0 = s.beta + n;
+  s.wi0 = s.wr0 + n;
+  s.rank = s.wi0 + n;
+  s.wr = s.rank + n;
+  s.wi = s.wr + n;
+  s.misc = s.wi + n;
+  s.V = s.misc + 8;
+  s.F = s.V + (size_t)n * nv;
+  s.HB = s.F + (size_t)nv * ns_lu_doubles(n);
+  s.HT = s.HB + ns_band_doubles(n);
+  return s;
+}
 
 KA_HD inline double ns_sgn(double a, double b) { return b >= 0.0 ? fabs(a) : -fabs(a); }
+KA_HD inline double ns_cabs(double a, double b) { return sqrt(a * a + b * b); }
 
-#define AT(M, i, j) M[(i) + (int64_t)(j) * n]
-
+// ---- stage 1: Hessenberg reduction by a team ---------------------------------------------
+// A: n x n with leading dimension ld (fast memory if available).  v, w: team
+// scratch of >= n doubles each.  Team interface as in sym_core.hpp.
 template <class Team>
-KA_HD void nonsym_core(Team& tm, const double* H, int n, int ldh, double* wr_out, double* wi_out, double* S,
-                       int lds, double* work, int* status, double* Abuf = nullptr) {
-  double* A = Abuf ? Abuf : work;            // n x n: Hessenberg, then Schur form T (fast memory if given)
-  double* Zm = work + (size_t)n * n;         // accumulated orthogonal transformations
-  double* Yv = work + (size_t)2 * n * n;     // eigenvectors of T (columns)
-  double* Vv = work + (size_t)3 * n * n;     // Zm * Yv
-  double* wr = work + (size_t)4 * n * n;
-  double* wi = wr + n;
-  double* nrm = wi + n;
-  double* key = nrm + n;
-  double* v = tm.scratch;
-  const int t = tm.tid();
-  const int NT = tm.size();
-  const double eps = 2.220446049250313e-16;
-
-  for (int64_t e = t; e < (int64_t)n * n; e += NT) {
-    const int i = (int)(e % n), j = (int)(e / n);
-    A[e] = H[i + (int64_t)j * ldh];
-    Zm[e] = (i == j) ? 1.0 : 0.0;
-  }
-  tm.sync();
-
-  // ---- 1. Hessenberg reduction ------------------------------------------
+KA_HD void ns_hessenberg(Team& tm, double* A, int ld, int n, double* hsub, double* beta, double* v, double* w) {
+  const int t = tm.tid(), NT = tm.size();
+#define AH(i, j) A[(i) + (size_t)(j) * ld]
   for (int j = 0; j + 2 < n; ++j) {
-    const int m = n - j - 1;                 // length of x = A[j+1:n, j]
+    const int m = n - j - 1;
     double ss = 0.0;
-    for (int i = t; i < m; i += NT) ss += AT(A, j + 1 + i, j) * AT(A, j + 1 + i, j);
+    for (int i = t; i < m; i += NT) ss += AH(j + 1 + i, j) * AH(j + 1 + i, j);
     ss = tm.sum(ss);
-    const double x0 = AT(A, j + 1, j);
+    const double x0 = AH(j + 1, j);
     const double alpha = -ns_sgn(sqrt(ss), x0);
-    const double vtv = ss - x0 * x0 + (x0 - alpha) * (x0 - alpha);
-    if (ss == 0.0 || vtv <= 1e-300) continue;
-    for (int i = t; i < m; i += NT) v[i] = (i == 0) ? x0 - alpha : AT(A, j + 1 + i, j);
-    tm.sync();
-    const double beta = 2.0 / vtv;
-    // left: A[j+1:, c] -= beta v (v^T A[j+1:, c]) for c >= j
-    for (int c = j + t; c < n; c += NT) {
-      double w = 0.0;
-      for (int i = 0; i < m; ++i) w += v[i] * AT(A, j + 1 + i, c);
-      w *= beta;
-      for (int i = 0; i < m; ++i) AT(A, j + 1 + i, c) -= w * v[i];
+    const double v0 = x0 - alpha;
+    const bool skip = !(ss > 1e-300);
+    const double b = skip ? 0.0 : 2.0 / (ss - x0 * x0 + v0 * v0);
+    for (int i = t; i < m; i += NT) v[i] = (i == 0) ? v0 : AH(j + 1 + i, j);
+    if (t == 0) {
+      hsub[j] = skip ? x0 : alpha;
+      beta[j] = b;
     }
     tm.sync();
-    // right: A[r, j+1:] -= beta (A[r, j+1:] v) v^T for all rows; same for Zm
-    for (int r = t; r < n; r += NT) {
-      double w = 0.0, wz = 0.0;
-      for (int i = 0; i < m; ++i) {
-        w += AT(A, r, j + 1 + i) * v[i];
-        wz += AT(Zm, r, j + 1 + i) * v[i];
+    if (!skip) {
+      // left: A[j+1:, c] -= b v (v^T A[j+1:, c]) for c > j
+      for (int c = j + 1 + t; c < n; c += NT) {
+        double s0 = 0.0, s1 = 0.0;
+        int i = 0;
+        for (; i + 1 < m; i += 2) {
+          s0 += v[i] * AH(j + 1 + i, c);
+          s1 += v[i + 1] * AH(j + 2 + i, c);
+        }
+        if (i < m) s0 += v[i] * AH(j + 1 + i, c);
+        w[c] = b * (s0 + s1);
       }
-      w *= beta;
-      wz *= beta;
-      for (int i = 0; i < m; ++i) {
-        AT(A, r, j + 1 + i) -= w * v[i];
-        AT(Zm, r, j + 1 + i) -= wz * v[i];
+      tm.sync();
+      for (int i = t; i < m; i += NT) {
+        const double vi = v[i];
+        for (int c = j + 1; c < n; ++c) AH(j + 1 + i, c) -= w[c] * vi;
+      }
+      tm.sync();
+      // right: A[r, j+1:] -= b (A[r, j+1:] v) v^T for every row
+      for (int r = t; r < n; r += NT) {
+        double s0 = 0.0, s1 = 0.0;
+        int i = 0;
+        for (; i + 1 < m; i += 2) {
+          s0 += AH(r, j + 1 + i) * v[i];
+          s1 += AH(r, j + 2 + i) * v[i + 1];
+        }
+        if (i < m) s0 += AH(r, j + 1 + i) * v[i];
+        const double u = b * (s0 + s1);
+        for (i = 0; i < m; ++i) AH(r, j + 1 + i) -= u * v[i];
       }
     }
     tm.sync();
-    for (int i = t; i < m; i += NT)
-      if (i > 0) AT(A, j + 1 + i, j) = 0.0;
+    for (int i = t; i < m; i += NT) AH(j + 1 + i, j) = v[i];   // reflector
     tm.sync();
   }
+  if (t == 0 && n >= 2) hsub[n - 2] = AH(n - 1, n - 2);
+  tm.sync();
+#undef AH
+}
 
-  // norm of the Hessenberg matrix (for tolerances)
+// ---- stage 2: eigenvalues of Hh (double-shift QR, no Schur vectors) -----------------------
+// hb: banded column storage, element (i, j) for i <= j + 3 at hb[j (j + 7) / 2 + i]
+// (the sub-diagonal, the two bulge diagonals and the upper triangle).
+KA_HD inline size_t ns_band_index(int i, int j) { return (size_t)j * (j + 7) / 2 + i; }
+
+// Fill the banded copy (and, if given, the row-major copy HT) from stage 1's
+// output (team, then sync by the caller).
+template <class Team>
+KA_HD void ns_band_fill(Team& tm, const double* A, int ld, const double* hsub, int n, double* hb, double* HT) {
+  const int t = tm.tid(), NT = tm.size();
+  for (int j = 0; j < n; ++j)
+    for (int i = t; i <= j + 3; i += NT) {
+      double x = 0.0;
+      if (i <= j) x = A[i + (size_t)j * ld];
+      else if (i == j + 1 && i < n) x = hsub[j];
+      hb[ns_band_index(i, j)] = x;
+    }
+  if (HT)
+    for (int i = 0; i < n; ++i)
+      for (int j = t; j < n; j += NT) HT[(size_t)i * n + j] = (j >= i) ? A[i + (size_t)j * ld] : (j == i - 1 ? hsub[j] : 0.0);
+}
+
+// Scalar control flow is identical in every thread (all read the same values
+// after a barrier); row and column updates are split over the team.
+// Returns 0, or 1 when an eigenvalue needed more than 60 iterations.
+template <class Team>
+KA_HD int ns_qr_values(Team& tm, double* hb, int n, double* wr, double* wi, double* anorm_out) {
+  const int t = tm.tid(), NT = tm.size();
+#define HB(i, j) hb[ns_band_index((i), (j))]
   double anorm = 0.0;
-  for (int64_t e = t; e < (int64_t)n * n; e += NT) {
-    const int i = (int)(e % n), j = (int)(e / n);
-    if (i <= j + 1) anorm += fabs(A[e]);
-  }
+  for (int j = t; j < n; j += NT)
+    for (int i = 0; i <= j + 1 && i < n; ++i) anorm += fabs(HB(i, j));
   anorm = tm.sum(anorm);
-
-  // ---- 2. Francis double-shift QR ------------------------------------------
-  // Scalar control flow is identical in every lane (all lanes read the same
-  // global values after a barrier); row / column updates are split over lanes.
+  if (anorm_out && t == 0) *anorm_out = anorm;
   int nn = n - 1;
   double shift = 0.0;
   int fail = 0;
@@ -119,78 +181,33 @@ KA_HD void nonsym_core(Team& tm, const double* H, int n, int ldh, double* wr_out
       tm.sync();
       int l;
       for (l = nn; l >= 1; --l) {
-        double s = fabs(AT(A, l - 1, l - 1)) + fabs(AT(A, l, l));
+        double s = fabs(HB(l - 1, l - 1)) + fabs(HB(l, l));
         if (s == 0.0) s = anorm;
-        if (fabs(AT(A, l, l - 1)) <= eps * s) break;
+        if (fabs(HB(l, l - 1)) <= kNsEps * s) break;
       }
-      if (l >= 1) {
-        tm.sync();
-        if (t == 0) AT(A, l, l - 1) = 0.0;
-        tm.sync();
-      }
-      double x = AT(A, nn, nn);
-      if (l == nn) {                               // one real root
-        tm.sync();
+      double x = HB(nn, nn);
+      if (l == nn) {                                   // one real eigenvalue
         if (t == 0) {
-          AT(A, nn, nn) = x + shift;
           wr[nn] = x + shift;
           wi[nn] = 0.0;
         }
         --nn;
         break;
       }
-      double y = AT(A, nn - 1, nn - 1);
-      double w = AT(A, nn, nn - 1) * AT(A, nn - 1, nn);
-      if (l == nn - 1) {                           // a 2 x 2 block
+      double y = HB(nn - 1, nn - 1);
+      double w = HB(nn, nn - 1) * HB(nn - 1, nn);
+      if (l == nn - 1) {                               // a 2 x 2 block
         const double p = 0.5 * (y - x);
         const double q = p * p + w;
         double z = sqrt(fabs(q));
         x += shift;
-        tm.sync();
         if (t == 0) {
-          AT(A, nn, nn) = x;
-          AT(A, nn - 1, nn - 1) = y + shift;
-        }
-        tm.sync();
-        if (q >= 0.0) {                            // real pair: rotate to triangular
-          z = p + ns_sgn(z, p);
-          const double r1 = x + z;
-          const double r2 = (z != 0.0) ? x - w / z : x + z;
-          const double xs = AT(A, nn, nn - 1);
-          const double s = fabs(xs) + fabs(z);
-          double pp = xs / s, qq = z / s;
-          const double r = sqrt(pp * pp + qq * qq);
-          pp /= r;
-          qq /= r;
-          tm.sync();
-          for (int j = nn - 1 + t; j < n; j += NT) {
-            const double zz = AT(A, nn - 1, j);
-            AT(A, nn - 1, j) = qq * zz + pp * AT(A, nn, j);
-            AT(A, nn, j) = qq * AT(A, nn, j) - pp * zz;
-          }
-          tm.sync();
-          for (int i = t; i <= nn; i += NT) {
-            const double zz = AT(A, i, nn - 1);
-            AT(A, i, nn - 1) = qq * zz + pp * AT(A, i, nn);
-            AT(A, i, nn) = qq * AT(A, i, nn) - pp * zz;
-          }
-          for (int i = t; i < n; i += NT) {
-            const double zz = AT(Zm, i, nn - 1);
-            AT(Zm, i, nn - 1) = qq * zz + pp * AT(Zm, i, nn);
-            AT(Zm, i, nn) = qq * AT(Zm, i, nn) - pp * zz;
-          }
-          tm.sync();
-          if (t == 0) {
-            AT(A, nn, nn - 1) = 0.0;
-            // eigenvalues are the diagonal of the now triangular block
-            wr[nn - 1] = AT(A, nn - 1, nn - 1);
-            wr[nn] = AT(A, nn, nn);
+          if (q >= 0.0) {
+            z = p + ns_sgn(z, p);
+            wr[nn - 1] = wr[nn] = x + z;
+            if (z != 0.0) wr[nn] = x - w / z;
             wi[nn - 1] = wi[nn] = 0.0;
-            (void)r1;
-            (void)r2;
-          }
-        } else {                                   // complex pair
-          if (t == 0) {
+          } else {
             wr[nn - 1] = wr[nn] = x + p;
             wi[nn - 1] = z;
             wi[nn] = -z;
@@ -203,53 +220,49 @@ KA_HD void nonsym_core(Team& tm, const double* H, int n, int ldh, double* wr_out
         fail = 1;
         break;
       }
-      if (its == 10 || its == 20 || its == 40) {   // exceptional shift
+      if (its == 10 || its == 20 || its == 40) {       // exceptional shift
         shift += x;
         tm.sync();
-        for (int i = t; i <= nn; i += NT) AT(A, i, i) -= x;
+        for (int i = t; i <= nn; i += NT) HB(i, i) -= x;
         tm.sync();
-        const double s = fabs(AT(A, nn, nn - 1)) + fabs(AT(A, nn - 1, nn - 2));
+        const double s = fabs(HB(nn, nn - 1)) + fabs(HB(nn - 1, nn - 2));
         x = y = 0.75 * s;
         w = -0.4375 * s * s;
       }
       ++its;
-      // two consecutive small sub-diagonal elements
+      // start of the double step: two consecutive small sub-diagonal elements
       int m;
       double p = 0.0, q = 0.0, r = 0.0, z = 0.0;
       for (m = nn - 2; m >= l; --m) {
-        z = AT(A, m, m);
+        z = HB(m, m);
         r = x - z;
         const double s0 = y - z;
-        p = (r * s0 - w) / AT(A, m + 1, m) + AT(A, m, m + 1);
-        q = AT(A, m + 1, m + 1) - z - r - s0;
-        r = AT(A, m + 2, m + 1);
+        p = (r * s0 - w) / HB(m + 1, m) + HB(m, m + 1);
+        q = HB(m + 1, m + 1) - z - r - s0;
+        r = HB(m + 2, m + 1);
         const double s = fabs(p) + fabs(q) + fabs(r);
         p /= s;
         q /= s;
         r /= s;
         if (m == l) break;
-        const double u = fabs(AT(A, m, m - 1)) * (fabs(q) + fabs(r));
-        const double vv = fabs(p) * (fabs(AT(A, m - 1, m - 1)) + fabs(z) + fabs(AT(A, m + 1, m + 1)));
-        if (u <= eps * vv) break;
+        const double u = fabs(HB(m, m - 1)) * (fabs(q) + fabs(r));
+        const double vv = fabs(p) * (fabs(HB(m - 1, m - 1)) + fabs(z) + fabs(HB(m + 1, m + 1)));
+        if (u <= kNsEps * vv) break;
       }
       tm.sync();
       for (int i = m + 2 + t; i <= nn; i += NT) {
-        AT(A, i, i - 2) = 0.0;
-        if (i != m + 2) AT(A, i, i - 3) = 0.0;
+        HB(i, i - 2) = 0.0;
+        if (i != m + 2) HB(i, i - 3) = 0.0;
       }
       tm.sync();
-      // double QR step.  The transformations of the accumulated Schur vectors
-      // Zm are logged per bulge position and applied after the sweep, one
-      // row per lane with a sliding window of three columns, so the sweep
-      // does not wait on a memory round trip of Zm per position.
-      double* zlog = v;   // 6 doubles per position: x1, y1, z1, q1, r1, flag
+      // bulge chase over the active window [l, nn]
       for (int k = m; k <= nn - 1; ++k) {
         const bool notlast = (k != nn - 1);
         double xx = 0.0;
         if (k != m) {
-          p = AT(A, k, k - 1);
-          q = AT(A, k + 1, k - 1);
-          r = notlast ? AT(A, k + 2, k - 1) : 0.0;
+          p = HB(k, k - 1);
+          q = HB(k + 1, k - 1);
+          r = notlast ? HB(k + 2, k - 1) : 0.0;
           xx = fabs(p) + fabs(q) + fabs(r);
           if (xx != 0.0) {
             p /= xx;
@@ -258,222 +271,268 @@ KA_HD void nonsym_core(Team& tm, const double* H, int n, int ldh, double* wr_out
           }
         }
         const double s = ns_sgn(sqrt(p * p + q * q + r * r), p);
-        double* e = zlog + 6 * (k - m);
-        if (s == 0.0) {
-          tm.sync();
-          if (t == 0) e[5] = 0.0;   // no transformation at this position
-          continue;
-        }
         tm.sync();
+        if (s == 0.0) continue;
+        if (t == 0) {
+          if (k == m) {
+            if (l != m) HB(k, k - 1) = -HB(k, k - 1);
+          } else {
+            HB(k, k - 1) = -s * xx;
+          }
+        }
         const double pp = p + s;
         const double x1 = pp / s, y1 = q / s, z1 = r / s;
         const double q1 = q / pp, r1 = r / pp;
-        if (t == 0) {
-          if (k == m) {
-            if (l != m) AT(A, k, k - 1) = -AT(A, k, k - 1);
-          } else {
-            AT(A, k, k - 1) = -s * xx;
-          }
-          e[0] = x1;
-          e[1] = y1;
-          e[2] = z1;
-          e[3] = q1;
-          e[4] = r1;
-          e[5] = 1.0;
-        }
-        tm.sync();
-        // rows k, k+1, (k+2) over columns k..n-1
-        for (int j = k + t; j < n; j += NT) {
-          double pv = AT(A, k, j) + q1 * AT(A, k + 1, j);
+        for (int j = k + t; j <= nn; j += NT) {
+          double pv = HB(k, j) + q1 * HB(k + 1, j);
           if (notlast) {
-            pv += r1 * AT(A, k + 2, j);
-            AT(A, k + 2, j) -= pv * z1;
+            pv += r1 * HB(k + 2, j);
+            HB(k + 2, j) -= pv * z1;
           }
-          AT(A, k + 1, j) -= pv * y1;
-          AT(A, k, j) -= pv * x1;
+          HB(k + 1, j) -= pv * y1;
+          HB(k, j) -= pv * x1;
         }
         tm.sync();
         const int imax = (nn < k + 3) ? nn : k + 3;
-        for (int i = t; i <= imax; i += NT) {
-          double pv = x1 * AT(A, i, k) + y1 * AT(A, i, k + 1);
+        for (int i = l + t; i <= imax; i += NT) {
+          double pv = x1 * HB(i, k) + y1 * HB(i, k + 1);
           if (notlast) {
-            pv += z1 * AT(A, i, k + 2);
-            AT(A, i, k + 2) -= pv * r1;
+            pv += z1 * HB(i, k + 2);
+            HB(i, k + 2) -= pv * r1;
           }
-          AT(A, i, k + 1) -= pv * q1;
-          AT(A, i, k) -= pv;
+          HB(i, k + 1) -= pv * q1;
+          HB(i, k) -= pv;
         }
         tm.sync();
       }
-      // apply the sweep's logged transformations to the rows of Zm
-      tm.sync();
-      for (int i = t; i < n; i += NT) {
-        double c0 = AT(Zm, i, m), c1 = AT(Zm, i, m + 1), c2 = AT(Zm, i, m + 2);
-        for (int k = m; k <= nn - 1; ++k) {
-          const double* e = zlog + 6 * (k - m);
-          if (e[5] != 0.0) {
-            double pv = e[0] * c0 + e[1] * c1;
-            if (k != nn - 1) {
-              pv += e[2] * c2;
-              c2 -= pv * e[4];
-            }
-            c1 -= pv * e[3];
-            c0 -= pv;
-          }
-          AT(Zm, i, k) = c0;
-          c0 = c1;
-          c1 = c2;
-          c2 = (k + 3 <= nn) ? AT(Zm, i, k + 3) : 0.0;
-        }
-        AT(Zm, i, nn) = c0;
-      }
-      tm.sync();
     }
   }
   tm.sync();
-  if (fail) {
-    if (t == 0) *status = 1;
-    return;
-  }
-
-  // ---- 3. eigenvectors of T by back substitution (one eigenvalue per lane) --
-  double tnorm = 0.0;
-  for (int64_t e = t; e < (int64_t)n * n; e += NT) {
-    const int i = (int)(e % n), j = (int)(e / n);
-    if (i <= j + 1) tnorm += fabs(A[e]);
-    Yv[e] = 0.0;
-  }
-  tnorm = tm.sum(tnorm);
-  tm.sync();
-  const double small = eps * (tnorm > 0.0 ? tnorm : 1.0);
-  for (int c = t; c < n; c += NT) {
-    const double p = wr[c], q = wi[c];
-    if (q == 0.0) {
-      // real eigenvalue p: solve (T - p I) y = 0 with y[c] = 1, y[i > c] = 0
-      AT(Yv, c, c) = 1.0;
-      for (int i = c - 1; i >= 0; --i) {
-        const bool second_of_pair = (i > 0) && (wi[i] < 0.0);
-        if (second_of_pair) {
-          // 2x2 diagonal block (i-1, i): solve the coupled pair
-          const int i0 = i - 1;
-          double r0 = 0.0, r1 = 0.0;
-          for (int j = i + 1; j <= c; ++j) {
-            r0 += AT(A, i0, j) * AT(Yv, j, c);
-            r1 += AT(A, i, j) * AT(Yv, j, c);
-          }
-          const double a = AT(A, i0, i0) - p, b = AT(A, i0, i), cc = AT(A, i, i0), d = AT(A, i, i) - p;
-          double det = a * d - b * cc;
-          if (det == 0.0) det = small;
-          AT(Yv, i0, c) = (-r0 * d + r1 * b) / det;
-          AT(Yv, i, c) = (-r1 * a + r0 * cc) / det;
-          --i;
-        } else {
-          double r = 0.0;
-          for (int j = i + 1; j <= c; ++j) r += AT(A, i, j) * AT(Yv, j, c);
-          double den = AT(A, i, i) - p;
-          if (den == 0.0) den = small;
-          AT(Yv, i, c) = -r / den;
-        }
-      }
-    } else if (q < 0.0) {
-      // complex pair (c-1, c): eigenvalue lambda = p + i|q| belongs to the
-      // 2x2 block; eigenvector u + i v with components for indices <= c.
-      const int c0 = c - 1;
-      const double lr = p, li = -q;   // li > 0
-      // choose the block component: solve (B - lambda I) [a; b] = 0 with b = 1
-      const double b00 = AT(A, c0, c0), b01 = AT(A, c0, c), b10 = AT(A, c, c0);
-      (void)b10;
-      // row 0: (b00 - lambda) a + b01 * 1 = 0  ->  a = -b01 / (b00 - lambda)
-      const double dr = b00 - lr, di = -li;
-      const double den = dr * dr + di * di;
-      double ar = -b01 * dr / (den > 0 ? den : small), ai = b01 * di / (den > 0 ? den : small);
-      AT(Yv, c0, c0) = ar;
-      AT(Yv, c0, c) = ai;
-      AT(Yv, c, c0) = 1.0;
-      AT(Yv, c, c) = 0.0;
-      for (int i = c0 - 1; i >= 0; --i) {
-        const bool second_of_pair = (i > 0) && (wi[i] < 0.0);
-        if (second_of_pair) {
-          const int i0 = i - 1;
-          double r0r = 0.0, r0i = 0.0, r1r = 0.0, r1i = 0.0;
-          for (int j = i + 1; j <= c; ++j) {
-            r0r += AT(A, i0, j) * AT(Yv, j, c0);
-            r0i += AT(A, i0, j) * AT(Yv, j, c);
-            r1r += AT(A, i, j) * AT(Yv, j, c0);
-            r1i += AT(A, i, j) * AT(Yv, j, c);
-          }
-          // [a - lam, b; cc, d - lam] [y0; y1] = -[r0; r1]  (complex)
-          const double ar_ = AT(A, i0, i0) - lr, ai_ = -li, b = AT(A, i0, i), cc = AT(A, i, i0);
-          const double dr_ = AT(A, i, i) - lr, di_ = -li;
-          // det = (a-lam)(d-lam) - b cc
-          double detr = ar_ * dr_ - ai_ * di_ - b * cc, deti = ar_ * di_ + ai_ * dr_;
-          double dd = detr * detr + deti * deti;
-          if (dd == 0.0) {
-            detr = small;
-            dd = small * small;
-          }
-          // y0 = (-r0 (d-lam) + b r1) / det ; y1 = (-r1 (a-lam) + cc r0) / det
-          const double n0r = -(r0r * dr_ - r0i * di_) + b * r1r, n0i = -(r0r * di_ + r0i * dr_) + b * r1i;
-          const double n1r = -(r1r * ar_ - r1i * ai_) + cc * r0r, n1i = -(r1r * ai_ + r1i * ar_) + cc * r0i;
-          AT(Yv, i0, c0) = (n0r * detr + n0i * deti) / dd;
-          AT(Yv, i0, c) = (n0i * detr - n0r * deti) / dd;
-          AT(Yv, i, c0) = (n1r * detr + n1i * deti) / dd;
-          AT(Yv, i, c) = (n1i * detr - n1r * deti) / dd;
-          --i;
-        } else {
-          double rr = 0.0, ri = 0.0;
-          for (int j = i + 1; j <= c; ++j) {
-            rr += AT(A, i, j) * AT(Yv, j, c0);
-            ri += AT(A, i, j) * AT(Yv, j, c);
-          }
-          // (T_ii - lambda) y = -r
-          const double er = AT(A, i, i) - lr, ei = -li;
-          double dd = er * er + ei * ei;
-          if (dd == 0.0) dd = small * small;
-          AT(Yv, i, c0) = (-rr * er - ri * ei) / dd;
-          AT(Yv, i, c) = (-ri * er + rr * ei) / dd;
-        }
-      }
-    }
-  }
-  tm.sync();
-  // V = Zm * Yv
-  for (int64_t e = t; e < (int64_t)n * n; e += NT) {
-    const int i = (int)(e % n), j = (int)(e / n);
-    double s = 0.0;
-    for (int k2 = 0; k2 < n; ++k2) s += AT(Zm, i, k2) * AT(Yv, k2, j);
-    Vv[e] = s;
-  }
-  tm.sync();
-  // norms: real vectors individually, complex pairs jointly
-  for (int c = t; c < n; c += NT) {
-    double s = 0.0;
-    for (int i = 0; i < n; ++i) s += AT(Vv, i, c) * AT(Vv, i, c);
-    nrm[c] = s;
-  }
-  tm.sync();
-  for (int c = t; c < n; c += NT) {
-    if (wi[c] > 0.0 && c + 1 < n) nrm[c] = nrm[c + 1] = nrm[c] + nrm[c + 1];
-  }
-  tm.sync();
-  // sort by descending real part; a complex pair stays together (re first)
-  for (int c = t; c < n; c += NT) key[c] = wr[c];
-  tm.sync();
-  for (int c = t; c < n; c += NT) {
-    const double kc = key[c];
-    int rank = 0;
-    for (int j = 0; j < n; ++j) {
-      const double kj = key[j];
-      if (kj > kc || (kj == kc && j < c)) ++rank;
-    }
-    wr_out[rank] = wr[c];
-    wi_out[rank] = wi[c];
-    const double sc = nrm[c] > 0.0 ? 1.0 / sqrt(nrm[c]) : 0.0;
-    for (int i = 0; i < n; ++i) S[i + (int64_t)rank * lds] = AT(Vv, i, c) * sc;
-  }
-  if (t == 0) *status = 0;
+#undef HB
+  return fail;
 }
 
-#undef AT
+// ---- stage 3: rank of eigenvalue c by descending real part (ties by index) ---------------
+// A conjugate pair has equal real parts and consecutive indices (positive
+// imaginary part first), so it keeps its order.
+KA_HD inline int ns_rank(const double* wr0, int n, int c) {
+  const double kc = wr0[c];
+  int rank = 0;
+  for (int j = 0; j < n; ++j)
+    if (wr0[j] > kc || (wr0[j] == kc && j < c)) ++rank;
+  return rank;
+}
+
+// largest eigenvalue modulus: the scale of the cluster gap and pivot floor
+KA_HD inline double ns_scale(const double* wr, const double* wi, int n) {
+  double m = 0.0;
+  for (int c = 0; c < n; ++c) m = fmax(m, ns_cabs(wr[c], wi[c]));
+  return m;
+}
+
+// wanted columns: nvec, plus one when column nvec - 1 is the first of a pair
+KA_HD inline int ns_wanted(const double* wi_sorted, int n, int nvec) {
+  return (nvec >= 1 && nvec < n && wi_sorted[nvec - 1] > 0.0) ? nvec + 1 : nvec;
+}
+
+// ---- stage 4: inverse iteration on Hh, one team per cluster ---------------------------------
+// Entries are the sorted output columns c < nv with wi[c] >= 0 (a pair is one
+// entry).  B = Hh - lambda I with Hh read row-wise from HT (row-major copy of
+// the upper Hessenberg matrix, sub-diagonal included).  LU with row
+// interchanges between neighbours only, row-oriented so that the team splits
+// each row over its threads: U row j holds columns j .. n-1 at offset
+// j n - j (j - 1) / 2 of the planes Ur, Ui.  ml: multipliers (re, im) and
+// interchange flags, 3n.  xs: team-shared vector (re, im), 2n.
+KA_HD inline size_t ns_urow(int n, int j) { return (size_t)j * n - (size_t)j * (j - 1) / 2; }
+KA_HD inline size_t ns_lu_plane(int n) { return (size_t)n * (n + 1) / 2; }
+
+KA_HD inline bool ns_is_entry(const double* wi, int c) { return c == 0 || wi[c] >= 0.0 || wi[c - 1] <= 0.0; }
+
+// is the entry at column c the first of its cluster?  (entries in sorted order)
+KA_HD inline bool ns_cluster_first(const double* wr, const double* wi, int c, double gap) {
+  if (c == 0) return true;
+  int p = c - 1;
+  if (p > 0 && wi[p] < 0.0) --p;                    // previous entry: the pair's first column
+  return ns_cabs(wr[c] - wr[p], wi[c] - wi[p]) >= gap;
+}
+
+// column of the next entry after c, or nv
+KA_HD inline int ns_next_entry(const double* wi, int c, int nv) {
+  const int nx = c + ((wi[c] > 0.0) ? 2 : 1);
+  return nx < nv ? nx : nv;
+}
+
+// The cluster that starts at entry c_first; V: output columns, element i of
+// column c at V[i * stride + c].  scale: the largest eigenvalue modulus.
+template <class Team>
+KA_HD void ns_invit_team(Team& tm, const double* HT, const double* hsub, int n, const double* wr, const double* wi,
+                         int c_first, int nv, int stride, double scale, double* V, double* Ur, double* Ui,
+                         double* ml, double* xs) {
+  const int t = tm.tid(), NT = tm.size();
+  const double gap = kNsClusterGap * scale;
+  const double tiny = kNsEps * (scale > 0.0 ? scale : 1.0);
+  const size_t S = (size_t)stride;
+  double* mr = ml;
+  double* mi = ml + n;
+  double* fl = ml + 2 * n;
+  double* xr = xs;
+  double* xi = xs + n;
+#define UR(j, cc) Ur[ns_urow(n, j) + (size_t)((cc) - (j))]
+#define UI(j, cc) Ui[ns_urow(n, j) + (size_t)((cc) - (j))]
+  for (int c = c_first; c < nv; c = ns_next_entry(wi, c, nv)) {
+    if (c != c_first && ns_cluster_first(wr, wi, c, gap)) break;
+    const double lr = wr[c], li = wi[c];
+    const bool cplx = li > 0.0;
+    // ---- LU of B = Hh - lambda I --------------------------------------------------------
+    for (int cc = t; cc < n; cc += NT) {
+      UR(0, cc) = HT[cc] - (cc == 0 ? lr : 0.0);
+      if (cplx) UI(0, cc) = (cc == 0 ? -li : 0.0);
+    }
+    tm.sync();
+    for (int j = 0; j + 1 < n; ++j) {
+      double ar = UR(j, j), ai = cplx ? UI(j, j) : 0.0;
+      if (ns_cabs(ar, ai) < tiny) {                // keep the factorisation finite
+        ar = tiny;
+        ai = 0.0;
+      }
+      const double sub = hsub[j];                   // B[j+1][j], real
+      const double* brow = HT + (size_t)(j + 1) * n;
+      const bool swap = fabs(sub) > ns_cabs(ar, ai);
+      double l_r, l_i;
+      if (swap) {
+        l_r = ar / sub;
+        l_i = ai / sub;
+      } else {
+        const double den = ar * ar + ai * ai;
+        l_r = den > 0.0 ? sub * ar / den : 0.0;
+        l_i = den > 0.0 ? -sub * ai / den : 0.0;
+      }
+      tm.sync();                                    // every thread has read the pivot
+      for (int cc = j + 1 + t; cc < n; cc += NT) {
+        const double br = brow[cc] - (cc == j + 1 ? lr : 0.0), bi = (cc == j + 1 ? -li : 0.0);
+        const double ur = UR(j, cc), ui = cplx ? UI(j, cc) : 0.0;
+        if (swap) {
+          // U row j <- B row j+1; new current row = old row - l B row j+1
+          UR(j, cc) = br;
+          UR(j + 1, cc) = ur - (l_r * br - l_i * bi);
+          if (cplx) {
+            UI(j, cc) = bi;
+            UI(j + 1, cc) = ui - (l_r * bi + l_i * br);
+          }
+        } else {
+          // new current row = B row j+1 - l U row j
+          UR(j + 1, cc) = br - (l_r * ur - l_i * ui);
+          if (cplx) UI(j + 1, cc) = bi - (l_r * ui + l_i * ur);
+        }
+      }
+      if (t == 0) {
+        mr[j] = l_r;
+        mi[j] = l_i;
+        fl[j] = swap ? 1.0 : 0.0;
+        UR(j, j) = swap ? sub : ar;
+        if (cplx) UI(j, j) = swap ? 0.0 : ai;
+      }
+      tm.sync();
+    }
+    if (t == 0 && ns_cabs(UR(n - 1, n - 1), cplx ? UI(n - 1, n - 1) : 0.0) < tiny) {
+      UR(n - 1, n - 1) = tiny;
+      if (cplx) UI(n - 1, n - 1) = 0.0;
+    }
+    for (int i = t; i < n; i += NT) {
+      xr[i] = sym_hash_unit((uint64_t)c + 1, (uint64_t)i);
+      xi[i] = cplx ? sym_hash_unit((uint64_t)c + 7919, (uint64_t)i) : 0.0;
+    }
+    tm.sync();
+    for (int iter = 0; iter < 3; ++iter) {
+      // forward: interchanges and multipliers (a short serial chain)
+      if (t == 0) {
+        double ar = xr[0], ai = xi[0];
+        for (int j = 0; j + 1 < n; ++j) {
+          double br = xr[j + 1], bi = xi[j + 1];
+          if (fl[j] != 0.0) {
+            const double tr = ar, ti = ai;
+            ar = br;
+            ai = bi;
+            br = tr;
+            bi = ti;
+          }
+          br -= mr[j] * ar - mi[j] * ai;
+          bi -= mr[j] * ai + mi[j] * ar;
+          xr[j] = ar;
+          xi[j] = ai;
+          ar = br;
+          ai = bi;
+        }
+        xr[n - 1] = ar;
+        xi[n - 1] = ai;
+      }
+      tm.sync();
+      // back substitution, one row at a time, the row product split over the team
+      for (int i = n - 1; i >= 0; --i) {
+        double pr = 0.0, pi = 0.0;
+        for (int cc = i + 1 + t; cc < n; cc += NT) {
+          const double ur = UR(i, cc), ui = cplx ? UI(i, cc) : 0.0;
+          pr += ur * xr[cc] - ui * xi[cc];
+          pi += ur * xi[cc] + ui * xr[cc];
+        }
+        pr = tm.sum(pr);
+        if (cplx) pi = tm.sum(pi);
+        const double sr = xr[i] - pr, si = xi[i] - pi;
+        const double dr = UR(i, i), di = cplx ? UI(i, i) : 0.0;
+        const double den = dr * dr + di * di;
+        const double qr = (sr * dr + si * di) / den, qi = (si * dr - sr * di) / den;
+        tm.sync();
+        if (t == 0) {
+          xr[i] = qr;
+          xi[i] = qi;
+        }
+        if (fabs(qr) + fabs(qi) > 1e150) {          // keep the growth representable
+          tm.sync();
+          for (int r = t; r < n; r += NT) {
+            xr[r] *= 1e-150;
+            xi[r] *= 1e-150;
+          }
+        }
+        tm.sync();
+      }
+      // orthogonalise against the cluster's earlier entries of the same kind
+      for (int pass = 0; pass < 2; ++pass)
+        for (int e = c_first; e < c; e = ns_next_entry(wi, e, nv)) {
+          const bool ecplx = wi[e] > 0.0;
+          if (ecplx != cplx) continue;
+          double dr = 0.0, di = 0.0;
+          for (int i = t; i < n; i += NT) {
+            const double er = V[(size_t)i * S + e], ei = ecplx ? V[(size_t)i * S + e + 1] : 0.0;
+            dr += er * xr[i] + ei * xi[i];
+            di += er * xi[i] - ei * xr[i];
+          }
+          dr = tm.sum(dr);
+          di = tm.sum(di);
+          for (int i = t; i < n; i += NT) {
+            const double er = V[(size_t)i * S + e], ei = ecplx ? V[(size_t)i * S + e + 1] : 0.0;
+            xr[i] -= dr * er - di * ei;
+            xi[i] -= dr * ei + di * er;
+          }
+          tm.sync();
+        }
+      double nrm = 0.0;
+      for (int i = t; i < n; i += NT) nrm += xr[i] * xr[i] + xi[i] * xi[i];
+      nrm = tm.sum(nrm);
+      nrm = nrm > 0.0 ? 1.0 / sqrt(nrm) : 0.0;
+      for (int i = t; i < n; i += NT) {
+        xr[i] *= nrm;
+        xi[i] *= nrm;
+      }
+      tm.sync();
+    }
+    for (int i = t; i < n; i += NT) {
+      V[(size_t)i * S + c] = xr[i];
+      if (cplx) V[(size_t)i * S + c + 1] = xi[i];
+    }
+    tm.sync();
+  }
+#undef UR
+#undef UI
+}
 
 }  // namespace ka

@@ -1,8 +1,11 @@
 // Device driver of the small symmetric eigensolve (sym_core.hpp) used by the
 // Galerkin Rayleigh-Ritz step: the tridiagonalisation runs as one workgroup
 // (working matrix in LDS up to order 128), the other stages as grids with one
-// wave per eigenvalue, one thread per cluster and one thread per vector.
+// wave per eigenvalue, one thread per cluster and one thread per vector; only
+// the leading nvec eigenvectors are formed.
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
 
 #include "ka_internal.hpp"
 #include "sym_core.hpp"
@@ -12,6 +15,7 @@ namespace ka {
 constexpr int kTriThreads = 512;
 constexpr int kTriLds = 128;
 constexpr int kSymTriMax = 1024;
+constexpr int kBackLds = 240;
 
 size_t sym_tri_work(int n) { return sym_tri_work_doubles(n); }
 
@@ -40,10 +44,9 @@ __global__ __launch_bounds__(kTriThreads) void sym_tridiag_kernel(const double* 
   __shared__ double red[kTriThreads / 64];
   const SymWork sw = sym_work_split(work, n);
   double* A = LDS ? A_lds : sw.A;
-  for (int64_t q = threadIdx.x; q < (int64_t)n * n; q += kTriThreads) {
-    const int i = (int)(q % n), j = (int)(q / n);
-    A[q] = 0.5 * (H[i + (int64_t)j * ldh] + H[j + (int64_t)i * ldh]);
-  }
+  for (int j = 0; j < n; ++j)
+    for (int i = threadIdx.x; i < n; i += kTriThreads)
+      A[i + (int64_t)j * n] = 0.5 * (H[i + (int64_t)j * ldh] + H[j + (int64_t)i * ldh]);
   __syncthreads();
   BlockTeam tm{red};
   sym_tridiagonalize(tm, A, n, sw.d, sw.e, sw.beta, v, w);
@@ -73,52 +76,89 @@ __global__ __launch_bounds__(64) void sym_section_kernel(double* __restrict__ wo
   if (t == 0) sw.lam[k] = 0.5 * (lo + hi);
 }
 
-// one thread per cluster of eigenvalues
-__global__ __launch_bounds__(64) void sym_invit_kernel(double* __restrict__ work, int n) {
+// one thread per cluster that meets the wanted range [n - nvec, n); the
+// iterated vector lives in LDS up to order kBackLds, else in V
+template <bool LDS>
+__global__ __launch_bounds__(64) void sym_invit_kernel(double* __restrict__ work, int n, int nvec) {
   __shared__ double sd[kSymTriMax], se[kSymTriMax];
+  __shared__ double xs[LDS ? kBackLds * 64 : 1];
   const SymWork sw = sym_work_split(work, n);
   for (int i = threadIdx.x; i < n; i += 64) {
     sd[i] = sw.d[i];
     se[i] = (i + 1 < n) ? sw.e[i] : 0.0;
   }
   __syncthreads();
-  const int k = blockIdx.x * 64 + threadIdx.x;
-  if (k < n && sym_cluster_start(sw.lam, k, sw.bnd)) sym_inverse_iteration(sd, se, n, sw.lam, k, sw.bnd, sw.V, sw.F);
+  const int k = n - nvec + blockIdx.x * 64 + threadIdx.x;
+  if (k < n && sym_cluster_top(sw.lam, n, k, sw.bnd)) {
+    // the iterated vector: this thread's LDS slot, or its interleaved column of Xw
+    double* xw = LDS ? xs + threadIdx.x : sw.Xw + k;
+    const int xstride = LDS ? 64 : n;
+    sym_inverse_iteration(sd, se, n, sw.lam, k, n - nvec, sw.bnd, sw.V, sw.F, xw, xstride);
+  }
 }
 
-// one thread per vector
-__global__ __launch_bounds__(64) void sym_back_kernel(double* __restrict__ work, int n) {
+// one thread per wanted vector; the workgroup's 64 vectors are staged in LDS
+// (element i of vector t at xs[i * 64 + t]) up to order kBackLds
+
+template <bool LDS>
+__global__ __launch_bounds__(64) void sym_back_kernel(double* __restrict__ work, int n, int nvec) {
+  __shared__ double xs[LDS ? kBackLds * 64 : 1];
+  __shared__ double vs[kSymTriMax];
   const SymWork sw = sym_work_split(work, n);
-  const int k = blockIdx.x * 64 + threadIdx.x;
-  if (k < n) sym_back_transform(sw.A, sw.beta, n, sw.V, k);
+  const int t = threadIdx.x;
+  const int k = n - nvec + blockIdx.x * 64 + t;
+  const bool act = k < n;
+  double* x = LDS ? xs + t : sw.V + (act ? k : 0);
+  const int stride = LDS ? 64 : n;
+  if (LDS)
+    for (int i = 0; i < n; ++i) xs[i * 64 + t] = act ? sw.V[(int64_t)i * n + k] : 0.0;
+  for (int j = n - 3; j >= 0; --j) {
+    const double b = sw.beta[j];
+    if (b == 0.0) continue;                      // uniform over the workgroup
+    const int m = n - j - 1;
+    __syncthreads();
+    for (int i = t; i < m; i += 64) vs[i] = sw.A[(j + 1 + i) + (int64_t)j * n];
+    __syncthreads();
+    if (LDS || act) sym_reflect(vs, m, b, x + (size_t)(j + 1) * stride, stride);
+  }
+  if (LDS && act)
+    for (int i = 0; i < n; ++i) sw.V[(int64_t)i * n + k] = xs[i * 64 + t];
 }
 
-// theta descending, S column k = vector n-1-k
-__global__ __launch_bounds__(256) void sym_out_kernel(const double* __restrict__ work, int n,
+// theta descending (all n); S column k (k < nvec) = vector n-1-k
+__global__ __launch_bounds__(256) void sym_out_kernel(const double* __restrict__ work, int n, int nvec,
                                                       double* __restrict__ theta, double* __restrict__ S, int lds) {
   const SymWork sw = sym_work_split(const_cast<double*>(work), n);
   const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (q >= (int64_t)n * n) return;
+  if (q < n) theta[q] = sw.lam[n - 1 - q];
+  if (q >= (int64_t)n * nvec) return;
   const int i = (int)(q % n), k = (int)(q / n);
-  const int src = n - 1 - k;
-  S[i + (int64_t)k * lds] = sw.V[(int64_t)i * n + src];
-  if (i == 0) theta[k] = sw.lam[src];
+  S[i + (int64_t)k * lds] = sw.V[(int64_t)i * n + (n - 1 - k)];
 }
 
-hipError_t sym_eig_tri(const double* H, int n, int ldh, double* theta, double* S, int lds, double* work,
+hipError_t sym_eig_tri(const double* H, int n, int ldh, int nvec, double* theta, double* S, int lds, double* work,
                        hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  if (n > kSymTriMax || ldh < n || lds < n) return hipErrorInvalidValue;
+  if (n > kSymTriMax || ldh < n || lds < n || nvec < 0 || nvec > n) return hipErrorInvalidValue;
   if (n <= kTriLds)
     hipLaunchKernelGGL(sym_tridiag_kernel<true>, dim3(1), dim3(kTriThreads), 0, s, H, n, ldh, work);
   else
     hipLaunchKernelGGL(sym_tridiag_kernel<false>, dim3(1), dim3(kTriThreads), 0, s, H, n, ldh, work);
-  const int g64 = (n + 63) / 64;
   hipLaunchKernelGGL(sym_section_kernel, dim3(n), dim3(64), 0, s, work, n);
-  hipLaunchKernelGGL(sym_invit_kernel, dim3(g64), dim3(64), 0, s, work, n);
-  hipLaunchKernelGGL(sym_back_kernel, dim3(g64), dim3(64), 0, s, work, n);
-  const int64_t nn = (int64_t)n * n;
-  hipLaunchKernelGGL(sym_out_kernel, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, s, work, n, theta, S, lds);
+  if (nvec > 0) {
+    const int g64 = (nvec + 63) / 64;
+    if (n <= kBackLds)
+      hipLaunchKernelGGL(sym_invit_kernel<true>, dim3(g64), dim3(64), 0, s, work, n, nvec);
+    else
+      hipLaunchKernelGGL(sym_invit_kernel<false>, dim3(g64), dim3(64), 0, s, work, n, nvec);
+    if (n <= kBackLds)
+      hipLaunchKernelGGL(sym_back_kernel<true>, dim3(g64), dim3(64), 0, s, work, n, nvec);
+    else
+      hipLaunchKernelGGL(sym_back_kernel<false>, dim3(g64), dim3(64), 0, s, work, n, nvec);
+  }
+  const int64_t nq = std::max<int64_t>((int64_t)n * nvec, n);
+  hipLaunchKernelGGL(sym_out_kernel, dim3((unsigned)((nq + 255) / 256)), dim3(256), 0, s, work, n, nvec, theta, S,
+                     lds);
   return hipGetLastError();
 }
 

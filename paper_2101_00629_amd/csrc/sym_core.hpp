@@ -5,9 +5,10 @@
 //      (reflectors kept in the strictly lower part of the working copy A);
 //   2. eigenvalue k of T by multisection on Sturm counts (one wave per value);
 //   3. eigenvectors of T by inverse iteration with the pivoted tridiagonal
-//      LU; eigenvalues closer than a gap form a cluster, handled by one thread
-//      that orthogonalises each member against the earlier ones after every
-//      solve, so clustered vectors come out orthonormal  (one per cluster);
+//      LU, for the wanted (largest) eigenvalues only; eigenvalues closer than
+//      a gap form a cluster, handled by one thread that orthogonalises each
+//      member against the ones before it after every solve, so clustered
+//      vectors come out orthonormal                           (one per cluster);
 //   4. back-transformation x <- Q x by the reflectors          (one per vector).
 // Every function here is plain C++ usable on the host (unit tests) and on the
 // device (sym.hip runs stage 1 as one workgroup, stages 2-4 as wide grids).
@@ -19,6 +20,7 @@
 //   d, e, beta, lam   4*n  (diagonal, off-diagonal, reflector coefficients,
 //                           eigenvalues ascending)
 //   bnd  4      Gershgorin lower / upper bound, norm estimate
+//   Xw   n*n    per-thread iteration vectors when they do not fit in fast memory
 #pragma once
 #include <math.h>
 #include <stddef.h>
@@ -35,10 +37,10 @@
 namespace ka {
 
 struct SymWork {
-  double *A, *V, *F, *d, *e, *beta, *lam, *bnd;
+  double *A, *V, *F, *d, *e, *beta, *lam, *bnd, *Xw;
 };
 
-KA_HD inline size_t sym_tri_work_doubles(int n) { return (size_t)7 * n * n + (size_t)4 * n + 4; }
+KA_HD inline size_t sym_tri_work_doubles(int n) { return (size_t)8 * n * n + (size_t)4 * n + 4; }
 
 KA_HD inline SymWork sym_work_split(double* w, int n) {
   const size_t nn = (size_t)n * n;
@@ -51,12 +53,13 @@ KA_HD inline SymWork sym_work_split(double* w, int n) {
   s.beta = s.e + n;
   s.lam = s.beta + n;
   s.bnd = s.lam + n;
+  s.Xw = s.bnd + 4;
   return s;
 }
 
 constexpr double kSymEps = 2.220446049250313e-16;
 // eigenvalues closer than this (relative to the norm estimate) form a cluster
-constexpr double kSymClusterGap = 1e-6;
+constexpr double kSymClusterGap = 1e-8;
 
 KA_HD inline double sym_copysign(double a, double b) { return b >= 0.0 ? fabs(a) : -fabs(a); }
 
@@ -89,11 +92,16 @@ KA_HD void sym_tridiagonalize(Team& tm, double* A, int n, double* d, double* e, 
     tm.sync();
     if (!skip) {
       double* A22 = A + (j + 1) + (size_t)(j + 1) * n;
-      // w = b A22 v
+      // w = b A22 v  (two partial sums shorten the dependent FMA chain)
       for (int r = t; r < m; r += NT) {
-        double acc = 0.0;
-        for (int c = 0; c < m; ++c) acc += A22[r + (size_t)c * n] * v[c];
-        w[r] = b * acc;
+        double acc0 = 0.0, acc1 = 0.0;
+        int c = 0;
+        for (; c + 1 < m; c += 2) {
+          acc0 += A22[r + (size_t)c * n] * v[c];
+          acc1 += A22[r + (size_t)(c + 1) * n] * v[c + 1];
+        }
+        if (c < m) acc0 += A22[r + (size_t)c * n] * v[c];
+        w[r] = b * (acc0 + acc1);
       }
       tm.sync();
       double wv = 0.0;
@@ -102,10 +110,10 @@ KA_HD void sym_tridiagonalize(Team& tm, double* A, int n, double* d, double* e, 
       const double K = 0.5 * b * wv;
       for (int r = t; r < m; r += NT) w[r] -= K * v[r];
       tm.sync();
-      // A22 <- A22 - v w^T - w v^T  (= H A22 H)
-      for (int64_t q = t; q < (int64_t)m * m; q += NT) {
-        const int r = (int)(q % m), c = (int)(q / m);
-        A22[r + (size_t)c * n] -= v[r] * w[c] + w[r] * v[c];
+      // A22 <- A22 - v w^T - w v^T  (= H A22 H), one row per thread
+      for (int r = t; r < m; r += NT) {
+        const double vr = v[r], wr = w[r];
+        for (int c = 0; c < m; ++c) A22[r + (size_t)c * n] -= vr * w[c] + wr * v[c];
       }
     }
     tm.sync();
@@ -188,27 +196,35 @@ KA_HD inline double sym_hash_unit(uint64_t a, uint64_t b) {
   return ((double)(z >> 11) + 0.5) * (1.0 / 9007199254740992.0) - 0.5;
 }
 
-// does the cluster containing eigenvalue k start at k?  (lam ascending)
-KA_HD inline bool sym_cluster_start(const double* lam, int k, const double* bnd) {
-  return k == 0 || lam[k] - lam[k - 1] >= kSymClusterGap * bnd[2];
+// Only the leading nvec eigenvectors (the largest eigenvalues, indices
+// n - nvec .. n - 1 of the ascending order) are computed.  A cluster is
+// walked from its largest member down, so it can stop at the first index that
+// is not wanted.
+
+// is eigenvalue k the largest of its cluster?  (lam ascending)
+KA_HD inline bool sym_cluster_top(const double* lam, int n, int k, const double* bnd) {
+  return k == n - 1 || lam[k + 1] - lam[k] >= kSymClusterGap * bnd[2];
 }
 
-// ---- stage 3: inverse iteration for the cluster starting at c0 -------------------------
-KA_HD inline void sym_inverse_iteration(const double* d, const double* e, int n, const double* lam, int c0,
-                                        const double* bnd, double* V, double* F) {
+// ---- stage 3: inverse iteration, cluster with largest member ktop, down to kstop ----
+// The vector being iterated lives at xw[i * xstride] (fast memory on the GPU);
+// finished vectors are stored in V.
+KA_HD inline void sym_inverse_iteration(const double* d, const double* e, int n, const double* lam, int ktop,
+                                        int kstop, const double* bnd, double* V, double* F, double* xw,
+                                        int xstride) {
   const double tn = bnd[2];
   const double gap = kSymClusterGap * tn;
   const double tiny = kSymEps * tn;
   const size_t nn = (size_t)n * n;
-  int c1 = c0 + 1;
-  while (c1 < n && lam[c1] - lam[c1 - 1] < gap) ++c1;
-  double sig_prev = -1e300;
-  for (int k = c0; k < c1; ++k) {
-#define XK(i) V[(size_t)(i) * n + k]
+  int c0 = ktop;
+  while (c0 > kstop && lam[c0] - lam[c0 - 1] < gap) --c0;
+  double sig_prev = 1e300;
+  for (int k = ktop; k >= c0; --k) {
+#define XK(i) xw[(size_t)(i) * xstride]
 #define FK(f, i) F[(f) * nn + (size_t)(i) * n + k]
     // distinct shifts inside a cluster
     double sig = lam[k];
-    if (k > c0 && sig < sig_prev + 10.0 * tiny) sig = sig_prev + 10.0 * tiny;
+    if (k < ktop && sig > sig_prev - 10.0 * tiny) sig = sig_prev - 10.0 * tiny;
     sig_prev = sig;
     // LU of T - sig I with partial pivoting; fields: 0 U diagonal, 1 and 2 the
     // two super-diagonals of U, 3 multiplier, 4 row interchange flag
@@ -243,28 +259,38 @@ KA_HD inline void sym_inverse_iteration(const double* d, const double* e, int n,
       if (fabs(FK(0, i)) < tiny) FK(0, i) = sym_copysign(tiny, FK(0, i));
     for (int i = 0; i < n; ++i) XK(i) = sym_hash_unit((uint64_t)k + 1, (uint64_t)i);
     for (int iter = 0; iter < 3; ++iter) {
+      // forward: row interchanges and multipliers (running value in a register)
+      double xi = XK(0);
       for (int i = 0; i + 1 < n; ++i) {
+        double xn = XK(i + 1);
         if (FK(4, i) != 0.0) {
-          const double tmp = XK(i);
-          XK(i) = XK(i + 1);
-          XK(i + 1) = tmp;
+          const double tmp = xi;
+          xi = xn;
+          xn = tmp;
         }
-        XK(i + 1) -= FK(3, i) * XK(i);
+        xn -= FK(3, i) * xi;
+        XK(i) = xi;
+        xi = xn;
       }
+      XK(n - 1) = xi;
+      // back substitution with the three bands of U
+      double x1 = 0.0, x2 = 0.0;   // x[i+1], x[i+2]
       for (int i = n - 1; i >= 0; --i) {
-        double s = XK(i);
-        if (i + 1 < n) s -= FK(1, i) * XK(i + 1);
-        if (i + 2 < n) s -= FK(2, i) * XK(i + 2);
-        s /= FK(0, i);
+        double s = (XK(i) - FK(1, i) * x1 - FK(2, i) * x2) / FK(0, i);
         if (fabs(s) > 1e150) {                      // keep the growth representable
-          for (int r = 0; r < n; ++r) XK(r) *= 1e-150;
+          for (int r = i + 1; r < n; ++r) XK(r) *= 1e-150;
+          for (int r = 0; r < i; ++r) XK(r) *= 1e-150;
           s *= 1e-150;
+          x1 *= 1e-150;
+          x2 *= 1e-150;
         }
         XK(i) = s;
+        x2 = x1;
+        x1 = s;
       }
-      // orthogonalise against the cluster's earlier vectors (two passes)
-      for (int pass = 0; pass < (k > c0 ? 2 : 0); ++pass)
-        for (int j = c0; j < k; ++j) {
+      // orthogonalise against the cluster's members computed before (two passes)
+      for (int pass = 0; pass < (k < ktop ? 2 : 0); ++pass)
+        for (int j = k + 1; j <= ktop; ++j) {
           double dot = 0.0;
           for (int i = 0; i < n; ++i) dot += XK(i) * V[(size_t)i * n + j];
           for (int i = 0; i < n; ++i) XK(i) -= dot * V[(size_t)i * n + j];
@@ -274,23 +300,29 @@ KA_HD inline void sym_inverse_iteration(const double* d, const double* e, int n,
       nr = nr > 0.0 ? 1.0 / sqrt(nr) : 0.0;
       for (int i = 0; i < n; ++i) XK(i) *= nr;
     }
+    for (int i = 0; i < n; ++i) V[(size_t)i * n + k] = XK(i);
 #undef XK
 #undef FK
   }
 }
 
-// ---- stage 4: x_k <- Q x_k = H_0 H_1 ... H_{n-3} x_k ---------------------------------
-KA_HD inline void sym_back_transform(const double* A, const double* beta, int n, double* V, int k) {
-  for (int j = n - 3; j >= 0; --j) {
-    const double b = beta[j];
-    if (b == 0.0) continue;
-    const double* vj = A + (j + 1) + (size_t)j * n;
-    const int m = n - j - 1;
-    double s = 0.0;
-    for (int i = 0; i < m; ++i) s += vj[i] * V[(size_t)(j + 1 + i) * n + k];
-    s *= b;
-    for (int i = 0; i < m; ++i) V[(size_t)(j + 1 + i) * n + k] -= s * vj[i];
+// ---- stage 4: x <- Q x = H_0 H_1 ... H_{n-3} x, element i of x at x[i * stride] ----
+// one reflector: y <- (I - b v v^T) y, y and v of length m
+KA_HD inline void sym_reflect(const double* v, int m, double b, double* y, int stride) {
+  double s0 = 0.0, s1 = 0.0;
+  int i = 0;
+  for (; i + 1 < m; i += 2) {
+    s0 += v[i] * y[(size_t)i * stride];
+    s1 += v[i + 1] * y[(size_t)(i + 1) * stride];
   }
+  if (i < m) s0 += v[i] * y[(size_t)i * stride];
+  const double s = b * (s0 + s1);
+  for (i = 0; i < m; ++i) y[(size_t)i * stride] -= s * v[i];
+}
+
+KA_HD inline void sym_back_transform(const double* A, const double* beta, int n, double* x, int stride) {
+  for (int j = n - 3; j >= 0; --j)
+    if (beta[j] != 0.0) sym_reflect(A + (j + 1) + (size_t)j * n, n - j - 1, beta[j], x + (size_t)(j + 1) * stride, stride);
 }
 
 }  // namespace ka

@@ -13,9 +13,9 @@ struct HostTeam {
 };
 }  // namespace
 
-// theta descending, S (n x n column-major) the matching unit eigenvectors;
-// returns the number of clusters found
-extern "C" int ka_host_sym_eig(const double* H, int n, double* theta, double* S) {
+// theta descending (all n), S (n x nvec column-major) the unit eigenvectors of
+// the nvec largest; returns the number of clusters met among them
+extern "C" int ka_host_sym_eig(const double* H, int n, int nvec, double* theta, double* S) {
   std::vector<double> work(ka::sym_tri_work_doubles(n)), v(n), w(n);
   ka::SymWork sw = ka::sym_work_split(work.data(), n);
   for (int j = 0; j < n; ++j)
@@ -37,15 +37,16 @@ extern "C" int ka_host_sym_eig(const double* H, int n, double* theta, double* S)
     sw.lam[k] = 0.5 * (lo + hi);
   }
   int clusters = 0;
-  for (int k = 0; k < n; ++k)
-    if (ka::sym_cluster_start(sw.lam, k, sw.bnd)) {
+  std::vector<double> xw(n);
+  for (int k = n - 1; k >= n - nvec; --k)
+    if (ka::sym_cluster_top(sw.lam, n, k, sw.bnd)) {
       ++clusters;
-      ka::sym_inverse_iteration(sw.d, sw.e, n, sw.lam, k, sw.bnd, sw.V, sw.F);
+      ka::sym_inverse_iteration(sw.d, sw.e, n, sw.lam, k, n - nvec, sw.bnd, sw.V, sw.F, xw.data(), 1);
     }
-  for (int k = 0; k < n; ++k) ka::sym_back_transform(sw.A, sw.beta, n, sw.V, k);
-  for (int k = 0; k < n; ++k) {
+  for (int k = n - nvec; k < n; ++k) ka::sym_back_transform(sw.A, sw.beta, n, sw.V + k, n);
+  for (int k = 0; k < n; ++k) theta[k] = sw.lam[n - 1 - k];
+  for (int k = 0; k < nvec; ++k) {
     const int src = n - 1 - k;
-    theta[k] = sw.lam[src];
     for (int i = 0; i < n; ++i) S[i + (size_t)k * n] = sw.V[(size_t)i * n + src];
   }
   return clusters;

@@ -20,30 +20,32 @@ def lib(tmp_path_factory):
     subprocess.check_call(["g++", "-O2", "-std=c++17", "-shared", "-fPIC", SRC, "-o", so])
     L = ctypes.CDLL(so)
     dp = ctypes.POINTER(ctypes.c_double)
-    L.ka_host_sym_eig.argtypes = [dp, ctypes.c_int, dp, dp]
+    L.ka_host_sym_eig.argtypes = [dp, ctypes.c_int, ctypes.c_int, dp, dp]
     L.ka_host_sym_eig.restype = ctypes.c_int
     return L
 
 
-def _eig(lib, H):
+def _eig(lib, H, nvec=None):
     n = H.shape[0]
+    nvec = n if nvec is None else nvec
     Hc = np.asfortranarray(H, dtype=np.float64)
-    th, S = np.zeros(n), np.zeros((n, n), order="F")
+    th, S = np.zeros(n), np.zeros((n, nvec), order="F")
     p = lambda a: a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
-    nc = lib.ka_host_sym_eig(p(Hc), n, p(th), p(S))
+    nc = lib.ka_host_sym_eig(p(Hc), n, nvec, p(th), p(S))
     return nc, th, S
 
 
 def _check(H, th, S, tol=1e-12):
     n = H.shape[0]
+    nvec = S.shape[1]
     scale = max(np.abs(np.linalg.eigvalsh(H)).max(), 1e-300)
     ref = np.sort(np.linalg.eigvalsh(H))[::-1]
     assert np.all(np.diff(th) <= 0)
     assert np.abs(th - ref).max() <= tol * scale * max(1, n / 10)
-    # residuals and orthonormality of the whole basis
-    R = H @ S - S * th[None, :]
+    # residuals and orthonormality of the computed vectors
+    R = H @ S - S * th[None, :nvec]
     assert np.linalg.norm(R, axis=0).max() <= 100 * tol * scale * np.sqrt(n)
-    assert np.abs(S.T @ S - np.eye(n)).max() <= 1e-10
+    assert np.abs(S.T @ S - np.eye(nvec)).max() <= 1e-10
 
 
 @pytest.mark.parametrize("n", [1, 2, 3, 8, 37, 114, 228])
@@ -77,6 +79,10 @@ def test_exact_multiplicities(lib):
     nc, th, S = _eig(lib, H)
     _check(H, th, S)
     assert nc == 6       # clusters {1}, {.5 x3}, {.25 x6}, {.1}, {0 x2}, {-.3}
+    # leading vectors only; the cut falls inside the six-fold cluster
+    nc, th, S = _eig(lib, H, nvec=7)
+    _check(H, th, S)
+    assert nc == 3
 
 
 def test_near_degenerate_and_tiny(lib):
@@ -101,3 +107,16 @@ def test_already_tridiagonal_and_diagonal(lib):
     Z = np.zeros((5, 5))
     nc, th, S = _eig(lib, Z)
     assert np.abs(th).max() < 1e-15 and np.abs(S.T @ S - np.eye(5)).max() < 1e-12
+
+
+@pytest.mark.parametrize("nvec", [1, 10, 66])
+def test_leading_vectors_only(lib, nvec):
+    # Rayleigh-Ritz use: all eigenvalues, the leading nvec vectors, a tail of
+    # numerically zero eigenvalues that is never touched
+    rng = np.random.default_rng(11)
+    n = 114
+    Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    lam = np.concatenate([0.9 ** np.arange(70), 1e-17 * rng.random(n - 70)])
+    H = (Q * lam) @ Q.T
+    nc, th, S = _eig(lib, H, nvec=nvec)
+    _check(H, th, S)
