@@ -33,10 +33,38 @@ METRIC = "Γ-pair evals/s vs roofline; K-L solves/s + p99 latency @1e-6 eig err"
 # exponential pair: 3 sub + 2 add (abs as operand modifiers) + exp = 7 slots.
 VALU_SLOTS_PER_S = 256 * 4 * 16 * 2.4e9
 SLOTS = {"gaussian": 8, "exponential": 7}
+# The contraction: b/16 v_mfma_f32_16x16x4_f32 (2048 flops each) per 64 pairs,
+# published dense FP32 matrix peak 157.3 TFLOP/s.  On gfx950 FP32 MFMA and VALU
+# work do not overlap (measured: mixed waves take the sum of the two times), so
+# the attainable rate of the FP32 path is the serial combination of both.
+MFMA_F32_FLOPS = 157.3e12
+
+
+def serial_peak_pairs(kernel, b):
+    mfma_pairs = MFMA_F32_FLOPS / 2048.0 * 64.0 * 16.0 / b
+    return 1.0 / (1.0 / peak_pairs(kernel) + 1.0 / mfma_pairs)
 
 
 def peak_pairs(kernel):
     return VALU_SLOTS_PER_S / SLOTS[kernel]
+
+
+# HBM traffic of the FP32 kernel product per launch, averaged over the 46
+# launches of one step of this workload: rocprofv3 --pmc FETCH_SIZE, then
+# WRITE_SIZE (profiles/gamma_f32_cube_p3_20_traffic.md), scaled by what the
+# same counters read for a plain 256 MiB device copy (FETCH x 2.0, WRITE x 1.0).
+# Valid only for the kernel source it was measured on.
+TRAFFIC = {"gamma_src_sha256_16": "addd8ad29788c146", "fetch_bytes": 191.6e6, "write_bytes": 31.9e6,
+           "algorithmic_bytes": 33.2e6}
+
+
+def measured_traffic():
+    import hashlib
+    src = os.path.join(ROOT, "paper_2101_00629_amd", "csrc", "gamma.hip")
+    with open(src, "rb") as f:
+        if hashlib.sha256(f.read()).hexdigest()[:16] != TRAFFIC["gamma_src_sha256_16"]:
+            return None
+    return TRAFFIC["fetch_bytes"] + TRAFFIC["write_bytes"]
 
 
 def workload(M=50, b=16, precision="fp32"):
@@ -187,6 +215,8 @@ def main():
     ap.add_argument("--requests", type=int, default=128)
     ap.add_argument("--rho", default="0.5,1.5")
     ap.add_argument("--pair-cap", type=float, default=1e11)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="first run one plain device copy of MIB MiB (reference for HBM traffic counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the kernel product of one GPU's share; "
@@ -197,6 +227,12 @@ def main():
     import paper_2101_00629_amd as K
 
     torch.cuda.set_device(0)
+    if args.copy_calibration > 0:
+        src = torch.ones(args.copy_calibration << 18, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     if args.serve:
         res = serve_benchmark(args.requests, [float(r) for r in args.rho.split(",")], args.pair_cap, args.tol)
         print(json.dumps({"metric": "K-L solves/s + p99 latency (serving)", "n_gpus": 1, "data": "synthetic",
@@ -257,6 +293,7 @@ def main():
     launches = sum(n for (n, _, _) in prof)
     achieved = gl_pairs / (gl_ms / 1e3)
     peak = gl_pairs / sum(pp / peak_pairs(p["kernel"]) for p, (_, _, pp) in zip(probs, prof))
+    speak = gl_pairs / sum(pp / serial_peak_pairs(p["kernel"], p["block"]) for p, (_, _, pp) in zip(probs, prof))
     line = {
         "metric": METRIC,
         "value": pairs / elapsed,
@@ -278,7 +315,12 @@ def main():
                        "max": float(lat.max())},
         "eig_err": {"max_floored_rel_err": worst, "per_problem": eig},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "pairs/s",
-                     "frac": achieved / peak, "traffic": None,
+                     "frac": achieved / peak,
+                     "traffic": measured_traffic() if args.precision == "fp32" else None,
+                     "traffic_unit": "HBM bytes per launch",
+                     "algorithmic_bytes_per_launch": TRAFFIC["algorithmic_bytes"],
+                     "serial_valu_mfma_peak": speak if args.precision == "fp32" else None,
+                     "frac_of_serial_peak": achieved / speak if args.precision == "fp32" else None,
                      "kernel": "gamma_f32_kernel" if args.precision == "fp32" else "gamma_bf16x3_kernel",
                      "launches": launches, "kernel_ms": gl_ms, "kernel_share_of_step": gl_ms / 1e3 / elapsed},
     }

@@ -38,6 +38,7 @@ typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
 typedef __bf16 bf2v __attribute__((ext_vector_type(2)));
 
 constexpr int kThreads = 256;
+constexpr int kXcds = 8;        // MI355X: workgroups are dealt to the 8 XCDs round-robin by id
 constexpr int kCT = 64;         // columns per LDS tile
 // MFMA accumulators are flushed into FP64 running totals every 2 tiles (128
 // columns, 32 chained MFMAs per FP32 accumulator).  The FP32 chain length is
@@ -46,6 +47,26 @@ constexpr int kCT = 64;         // columns per LDS tile
 // of 200 eigenvalues (1.4% of the largest), 2-tile chains 3.8e-7, at the same
 // speed within 1%.
 constexpr int kFlushTiles = 2;
+
+
+// (row block, split) of this workgroup.  Grouped grid (xcd_splits > 0): a 1-D
+// grid of row_blocks * xcd_splits workgroups; workgroup id L runs on XCD
+// L % 8, and the XCD's own sequence L / 8 walks split by split (all row
+// blocks of a split back to back), splits x, x + 8, ... on XCD x.  Returns
+// false for padding workgroups (split beyond the real split count).
+__device__ __forceinline__ bool gamma_item(const GammaLaunch& a, int64_t& rblk, int& split) {
+  if (a.xcd_splits == 0) {
+    rblk = blockIdx.x;
+    split = blockIdx.y;
+    return true;
+  }
+  const int64_t L = blockIdx.x;
+  const int x = (int)(L % kXcds);
+  const int64_t j = L / kXcds;
+  rblk = j % a.row_blocks;
+  split = x + kXcds * (int)(j / a.row_blocks);
+  return split < a.nsplit;
+}
 
 template <int KERNEL>
 __device__ __forceinline__ float pair_exponent(float dx, float dy, float dz) {
@@ -204,7 +225,10 @@ template <int KERNEL, int B, int RB>
 __global__ __launch_bounds__(kThreads) void gamma_f32_kernel(GammaLaunch a) {
   __shared__ float4 s_x[2][kCT];
   __shared__ float s_y[2][kCT * y_stride<B>()];
-  gamma_f32_tile<KERNEL, B, RB>(a, blockIdx.x, blockIdx.y, s_x, s_y);
+  int64_t rblk;
+  int split;
+  if (!gamma_item(a, rblk, split)) return;
+  gamma_f32_tile<KERNEL, B, RB>(a, rblk, split, s_x, s_y);
 }
 
 // ---------------------------------------------------------------------------
@@ -396,7 +420,10 @@ __global__ __launch_bounds__(kThreads) void gamma_bf16x3_kernel(GammaLaunch a) {
   __shared__ float4 s_x[2][kCT];
   __shared__ uint4 s_yh[2][kKS * (B / 16) * 64];
   __shared__ uint4 s_yl[2][kKS * (B / 16) * 64];
-  gamma_bf16x3_tile<KERNEL, B, RB>(a, blockIdx.x, blockIdx.y, s_x, s_yh, s_yl);
+  int64_t rblk;
+  int split;
+  if (!gamma_item(a, rblk, split)) return;
+  gamma_bf16x3_tile<KERNEL, B, RB>(a, rblk, split, s_x, s_yh, s_yl);
 }
 
 // Several kernel products in one persistent launch: work items (product,
@@ -450,6 +477,7 @@ GammaPlan gamma_plan(int64_t nr, int64_t nc, int b, int precision) {
   GammaPlan p;
   p.rows_per_block = rows_per_block(b, precision);
   p.row_blocks = (nr + p.rows_per_block - 1) / p.rows_per_block;
+  p.xcd_splits = 0;
   if (nr <= 0 || nc <= 0) {   // nothing to split
     p.nsplit = 1;
     p.cols_per_split = nc > 0 ? nc : 0;
@@ -464,13 +492,19 @@ GammaPlan gamma_plan(int64_t nr, int64_t nc, int b, int precision) {
   if (ns > max_by_cols) ns = max_by_cols;
   if (ns > 64) ns = 64;
   if (ns < 1) ns = 1;
+  // With at least one split per XCD, round the split count up to a multiple
+  // of the XCD count: the grouped grid then keeps every split on one XCD, so
+  // its column range is fetched from HBM into that XCD's L2 once.
+  if (ns >= kXcds) ns = (ns + kXcds - 1) / kXcds * kXcds;
   int64_t cps = (nc + ns - 1) / ns;
   cps = (cps + kCT - 1) / kCT * kCT;
+  const int64_t ns_grid = ns;
   ns = (nc + cps - 1) / cps;
   if (ns < 1) ns = 1;
   p.nsplit = (int)ns;
   p.cols_per_split = cps;
   p.partial_bytes = ns > 1 ? (size_t)ns * nr * b * sizeof(float) : 0;
+  p.xcd_splits = ns_grid >= kXcds ? (int)ns_grid : 0;
   return p;
 }
 
@@ -500,10 +534,13 @@ hipError_t launch_gamma(GammaLaunch a, int kernel, int b, int precision, hipStre
   const GammaPlan p = gamma_plan(a.nr, a.nc, b, precision);
   a.nsplit = p.nsplit;
   a.cols_per_split = p.cols_per_split;
+  a.row_blocks = p.row_blocks;
+  a.xcd_splits = p.xcd_splits;
   if (a.nc <= 0) {
     return fill_zero_f32(a.Z, a.nr * b, s);
   }
-  const dim3 grid((unsigned)p.row_blocks, (unsigned)p.nsplit);
+  const dim3 grid = p.xcd_splits > 0 ? dim3((unsigned)(p.row_blocks * p.xcd_splits), 1u)
+                                     : dim3((unsigned)p.row_blocks, (unsigned)p.nsplit);
   hipError_t e = (kernel == KA_GAUSSIAN) ? launch_kernel_variant<KA_GAUSSIAN>(a, b, precision, grid, s)
                                          : launch_kernel_variant<KA_EXP_L1>(a, b, precision, grid, s);
   if (e != hipSuccess) return e;

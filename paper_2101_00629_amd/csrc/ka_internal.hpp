@@ -26,6 +26,8 @@ struct GammaLaunch {
   float out_scale;        // sigma^2
   int nsplit;             // filled by launch_gamma
   int64_t cols_per_split; // filled by launch_gamma
+  int64_t row_blocks;     // filled by launch_gamma
+  int xcd_splits;         // filled by launch_gamma: > 0 selects the XCD-grouped 1-D grid
 };
 
 struct GammaPlan {
@@ -34,6 +36,7 @@ struct GammaPlan {
   int nsplit;
   int64_t cols_per_split;
   size_t partial_bytes;
+  int xcd_splits;         // 0, or the split count rounded up to the XCD count (grouped grid)
 };
 
 GammaPlan gamma_plan(int64_t nr, int64_t nc, int b, int precision);

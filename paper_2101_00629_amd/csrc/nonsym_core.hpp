@@ -265,9 +265,10 @@ KA_HD int ns_qr_values(Team& tm, double* hb, int n, double* wr, double* wi, doub
           r = notlast ? HB(k + 2, k - 1) : 0.0;
           xx = fabs(p) + fabs(q) + fabs(r);
           if (xx != 0.0) {
-            p /= xx;
-            q /= xx;
-            r /= xx;
+            const double ixx = 1.0 / xx;
+            p *= ixx;
+            q *= ixx;
+            r *= ixx;
           }
         }
         const double s = ns_sgn(sqrt(p * p + q * q + r * r), p);
@@ -281,8 +282,9 @@ KA_HD int ns_qr_values(Team& tm, double* hb, int n, double* wr, double* wi, doub
           }
         }
         const double pp = p + s;
-        const double x1 = pp / s, y1 = q / s, z1 = r / s;
-        const double q1 = q / pp, r1 = r / pp;
+        const double is = 1.0 / s, ipp = 1.0 / pp;
+        const double x1 = pp * is, y1 = q * is, z1 = r * is;
+        const double q1 = q * ipp, r1 = r * ipp;
         for (int j = k + t; j <= nn; j += NT) {
           double pv = HB(k, j) + q1 * HB(k + 1, j);
           if (notlast) {

@@ -76,24 +76,33 @@ __global__ __launch_bounds__(64) void sym_section_kernel(double* __restrict__ wo
   if (t == 0) sw.lam[k] = 0.5 * (lo + hi);
 }
 
-// one thread per cluster that meets the wanted range [n - nvec, n); the
-// iterated vector lives in LDS up to order kBackLds, else in V
+// one thread per cluster that meets the wanted range [n - nvec, n).  Up to
+// order kInvLds a workgroup of kInvThreads threads keeps each thread's LU
+// fields and iterated vector in LDS ([field][i][thread]); above it they live
+// in the interleaved global arrays F and Xw.
+constexpr int kInvThreads = 16;
+constexpr int kInvLds = 200;
+
 template <bool LDS>
-__global__ __launch_bounds__(64) void sym_invit_kernel(double* __restrict__ work, int n, int nvec) {
-  __shared__ double sd[kSymTriMax], se[kSymTriMax];
-  __shared__ double xs[LDS ? kBackLds * 64 : 1];
+__global__ __launch_bounds__(LDS ? kInvThreads : 64) void sym_invit_kernel(double* __restrict__ work, int n,
+                                                                           int nvec) {
+  constexpr int NT = LDS ? kInvThreads : 64;
+  __shared__ double sd[LDS ? kInvLds : kSymTriMax], se[LDS ? kInvLds : kSymTriMax];
+  __shared__ double fx[LDS ? 6 * kInvLds * kInvThreads : 1];
   const SymWork sw = sym_work_split(work, n);
-  for (int i = threadIdx.x; i < n; i += 64) {
+  for (int i = threadIdx.x; i < n; i += NT) {
     sd[i] = sw.d[i];
     se[i] = (i + 1 < n) ? sw.e[i] : 0.0;
   }
   __syncthreads();
-  const int k = n - nvec + blockIdx.x * 64 + threadIdx.x;
+  const int t = threadIdx.x;
+  const int k = n - nvec + blockIdx.x * NT + t;
   if (k < n && sym_cluster_top(sw.lam, n, k, sw.bnd)) {
-    // the iterated vector: this thread's LDS slot, or its interleaved column of Xw
-    double* xw = LDS ? xs + threadIdx.x : sw.Xw + k;
-    const int xstride = LDS ? 64 : n;
-    sym_inverse_iteration(sd, se, n, sw.lam, k, n - nvec, sw.bnd, sw.V, sw.F, xw, xstride);
+    if (LDS)
+      sym_inverse_iteration(sd, se, n, sw.lam, k, n - nvec, sw.bnd, sw.V, fx + t, (size_t)n * NT, NT,
+                            fx + 5 * (size_t)n * NT + t, NT);
+    else
+      sym_inverse_iteration(sd, se, n, sw.lam, k, n - nvec, sw.bnd, sw.V, sw.F + k, (size_t)n * n, n, sw.Xw + k, n);
   }
 }
 
@@ -147,8 +156,9 @@ hipError_t sym_eig_tri(const double* H, int n, int ldh, int nvec, double* theta,
   hipLaunchKernelGGL(sym_section_kernel, dim3(n), dim3(64), 0, s, work, n);
   if (nvec > 0) {
     const int g64 = (nvec + 63) / 64;
-    if (n <= kBackLds)
-      hipLaunchKernelGGL(sym_invit_kernel<true>, dim3(g64), dim3(64), 0, s, work, n, nvec);
+    if (n <= kInvLds)
+      hipLaunchKernelGGL(sym_invit_kernel<true>, dim3((nvec + kInvThreads - 1) / kInvThreads), dim3(kInvThreads), 0,
+                         s, work, n, nvec);
     else
       hipLaunchKernelGGL(sym_invit_kernel<false>, dim3(g64), dim3(64), 0, s, work, n, nvec);
     if (n <= kBackLds)

@@ -16,7 +16,8 @@
 // Work layout (doubles), n = order:
 //   A    n*n    column-major working copy, reflectors below the sub-diagonal
 //   V    n*n    vectors interleaved: element i of vector k at V[i*n + k]
-//   F    5*n*n  per-eigenvalue LU factors, interleaved the same way per field
+//   F    5*n*n  per-thread LU factors (when not in fast memory), interleaved
+//               like V per field
 //   d, e, beta, lam   4*n  (diagonal, off-diagonal, reflector coefficients,
 //                           eigenvalues ascending)
 //   bnd  4      Gershgorin lower / upper bound, norm estimate
@@ -207,21 +208,21 @@ KA_HD inline bool sym_cluster_top(const double* lam, int n, int k, const double*
 }
 
 // ---- stage 3: inverse iteration, cluster with largest member ktop, down to kstop ----
-// The vector being iterated lives at xw[i * xstride] (fast memory on the GPU);
-// finished vectors are stored in V.
+// Working storage of the calling thread: the iterated vector at xw[i * xs],
+// the five LU fields at fw[f * fs + i * is] (fast memory on the GPU when they
+// fit); finished vectors are stored in V.
 KA_HD inline void sym_inverse_iteration(const double* d, const double* e, int n, const double* lam, int ktop,
-                                        int kstop, const double* bnd, double* V, double* F, double* xw,
-                                        int xstride) {
+                                        int kstop, const double* bnd, double* V, double* fw, size_t fs, int is,
+                                        double* xw, int xs) {
   const double tn = bnd[2];
   const double gap = kSymClusterGap * tn;
   const double tiny = kSymEps * tn;
-  const size_t nn = (size_t)n * n;
   int c0 = ktop;
   while (c0 > kstop && lam[c0] - lam[c0 - 1] < gap) --c0;
   double sig_prev = 1e300;
   for (int k = ktop; k >= c0; --k) {
-#define XK(i) xw[(size_t)(i) * xstride]
-#define FK(f, i) F[(f) * nn + (size_t)(i) * n + k]
+#define XK(i) xw[(size_t)(i) * xs]
+#define FK(f, i) fw[(f) * fs + (size_t)(i) * is]
     // distinct shifts inside a cluster
     double sig = lam[k];
     if (k < ktop && sig > sig_prev - 10.0 * tiny) sig = sig_prev - 10.0 * tiny;
@@ -255,8 +256,12 @@ KA_HD inline void sym_inverse_iteration(const double* d, const double* e, int n,
     FK(0, n - 1) = a;
     FK(1, n - 1) = 0.0;
     FK(2, n - 1) = 0.0;
-    for (int i = 0; i < n; ++i)
-      if (fabs(FK(0, i)) < tiny) FK(0, i) = sym_copysign(tiny, FK(0, i));
+    // store reciprocal pivots (tiny ones raised to the floor)
+    for (int i = 0; i < n; ++i) {
+      double u = FK(0, i);
+      if (fabs(u) < tiny) u = sym_copysign(tiny, u);
+      FK(0, i) = 1.0 / u;
+    }
     for (int i = 0; i < n; ++i) XK(i) = sym_hash_unit((uint64_t)k + 1, (uint64_t)i);
     for (int iter = 0; iter < 3; ++iter) {
       // forward: row interchanges and multipliers (running value in a register)
@@ -276,7 +281,7 @@ KA_HD inline void sym_inverse_iteration(const double* d, const double* e, int n,
       // back substitution with the three bands of U
       double x1 = 0.0, x2 = 0.0;   // x[i+1], x[i+2]
       for (int i = n - 1; i >= 0; --i) {
-        double s = (XK(i) - FK(1, i) * x1 - FK(2, i) * x2) / FK(0, i);
+        double s = (XK(i) - FK(1, i) * x1 - FK(2, i) * x2) * FK(0, i);
         if (fabs(s) > 1e150) {                      // keep the growth representable
           for (int r = i + 1; r < n; ++r) XK(r) *= 1e-150;
           for (int r = 0; r < i; ++r) XK(r) *= 1e-150;
@@ -288,12 +293,22 @@ KA_HD inline void sym_inverse_iteration(const double* d, const double* e, int n,
         x2 = x1;
         x1 = s;
       }
-      // orthogonalise against the cluster's members computed before (two passes)
+      // orthogonalise against the cluster's members computed before (two
+      // passes; four partial sums keep several loads of V in flight)
       for (int pass = 0; pass < (k < ktop ? 2 : 0); ++pass)
         for (int j = k + 1; j <= ktop; ++j) {
-          double dot = 0.0;
-          for (int i = 0; i < n; ++i) dot += XK(i) * V[(size_t)i * n + j];
-          for (int i = 0; i < n; ++i) XK(i) -= dot * V[(size_t)i * n + j];
+          const double* vj = V + j;
+          double d0 = 0.0, d1 = 0.0, d2 = 0.0, d3 = 0.0;
+          int i = 0;
+          for (; i + 3 < n; i += 4) {
+            d0 += XK(i) * vj[(size_t)i * n];
+            d1 += XK(i + 1) * vj[(size_t)(i + 1) * n];
+            d2 += XK(i + 2) * vj[(size_t)(i + 2) * n];
+            d3 += XK(i + 3) * vj[(size_t)(i + 3) * n];
+          }
+          for (; i < n; ++i) d0 += XK(i) * vj[(size_t)i * n];
+          const double dot = (d0 + d1) + (d2 + d3);
+          for (i = 0; i < n; ++i) XK(i) -= dot * vj[(size_t)i * n];
         }
       double nr = 0.0;
       for (int i = 0; i < n; ++i) nr += XK(i) * XK(i);

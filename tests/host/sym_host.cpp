@@ -37,11 +37,12 @@ extern "C" int ka_host_sym_eig(const double* H, int n, int nvec, double* theta, 
     sw.lam[k] = 0.5 * (lo + hi);
   }
   int clusters = 0;
-  std::vector<double> xw(n);
+  std::vector<double> xw(n), fw(5 * (size_t)n);
   for (int k = n - 1; k >= n - nvec; --k)
     if (ka::sym_cluster_top(sw.lam, n, k, sw.bnd)) {
       ++clusters;
-      ka::sym_inverse_iteration(sw.d, sw.e, n, sw.lam, k, n - nvec, sw.bnd, sw.V, sw.F, xw.data(), 1);
+      ka::sym_inverse_iteration(sw.d, sw.e, n, sw.lam, k, n - nvec, sw.bnd, sw.V, fw.data(), (size_t)n, 1, xw.data(),
+                                1);
     }
   for (int k = n - nvec; k < n; ++k) ka::sym_back_transform(sw.A, sw.beta, n, sw.V + k, n);
   for (int k = 0; k < n; ++k) theta[k] = sw.lam[n - 1 - k];

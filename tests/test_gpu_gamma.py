@@ -60,9 +60,11 @@ def test_gamma_matches_oracle_ragged(precision, kernel, ell, b):
 
 
 @pytest.mark.parametrize("precision", [K.KA_FP32, K.KA_BF16X3])
-def test_gamma_split_k_path(precision):
-    # few rows, many columns: the column range is split over workgroups
-    nr, nc, b = 200, 20011, 16
+@pytest.mark.parametrize("nr,nc", [(200, 20011), (600, 50000)])
+def test_gamma_split_k_path(precision, nr, nc):
+    # few rows, many columns: the column range is split over workgroups (16
+    # and 24 splits: the XCD-grouped grid, with one and three row blocks)
+    b = 16
     assert K.ka_gamma_workspace(nr, nc, b, precision) > 0
     Xr = uniform_points(4, nr)
     Xc = uniform_points(5, nc)
