@@ -144,7 +144,7 @@ def serve_benchmark(n_requests, rhos, cap, tol, seed=210100629):
                                  seed=1 + d["id"]) for d in trace]
     cplx = [d["method"] == "collocation" for d in trace]
     # sequential plain solves
-    service, lam_seq = [], []
+    service, lam_seq, seq_status = [], [], []
     for i, d in enumerate(trace):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -154,8 +154,15 @@ def serve_benchmark(n_requests, rhos, cap, tol, seed=210100629):
         torch.cuda.synchronize()
         service.append(time.perf_counter() - t0)
         lam_seq.append(lam)
+        seq_status.append((rc, info))
+        if (i + 1) % 32 == 0:
+            print(f"[serve] sequential {i + 1}/{n_requests} solves, {sum(service):.1f} s", file=sys.stderr, flush=True)
     service = np.array(service)
-    out = {"requests": n_requests, "pair_cap_per_block_product": cap,
+    def brief(d):
+        return {k: d[k] for k in ("method", "domain", "p", "nel", "kernel", "ell", "M", "block")}
+    seq_fail = [{"request": i, "status": rc, "iterations": info["iterations"], "converged": info["converged"],
+                 **brief(trace[i])} for i, (rc, info) in enumerate(seq_status) if rc != 0]
+    out = {"requests": n_requests, "pair_cap_per_block_product": cap, "sequential_nonzero_status": seq_fail,
            "mean_service_ms": float(service.mean() * 1e3),
            "pairs_per_block_product": {"p50": float(np.median([request_pairs(d) for d in trace])),
                                        "max": float(max(request_pairs(d) for d in trace))}}
@@ -177,17 +184,31 @@ def serve_benchmark(n_requests, rhos, cap, tol, seed=210100629):
             lam = np.zeros(2 * d["M"])
             lams.append(lam)
             K.ka_server_submit(srv, descs[i], d["M"], lam, tol=tol, maxit=60, arrival_s=float(arrivals[i]), tag=i)
+        print(f"[serve] server run, rho {rho:g}", file=sys.stderr, flush=True)
+        import threading
         t0 = time.perf_counter()
-        K.ka_server_run(srv, 1200.0)
+        runner = threading.Thread(target=K.ka_server_run, args=(srv, 1200.0))
+        runner.start()
+        res = []
+        while runner.is_alive():            # progress while the server runs (results are mutex-guarded)
+            runner.join(timeout=15.0)
+            res.extend(K.ka_server_poll(srv))
+            print(f"[serve] rho {rho:g}: {len(res)}/{n_requests} done, {time.perf_counter() - t0:.0f} s",
+                  file=sys.stderr, flush=True)
         wall = time.perf_counter() - t0
-        res = sorted(K.ka_server_poll(srv), key=lambda r: r["tag"])
+        res.extend(K.ka_server_poll(srv))
+        print(f"[serve] server run done in {wall:.1f} s", file=sys.stderr, flush=True)
+        res = sorted(res, key=lambda r: r["tag"])
         stats = K.ka_server_stats(srv)
         K.ka_server_destroy(srv)
         ok = [r for r in res if r["status"] == 0]
         lat = np.array([r["done_s"] - r["arrival_s"] for r in res])
         makespan = max(r["done_s"] for r in res)
         diff = 0.0
+        okset = {r["tag"] for r in ok}
         for i, d in enumerate(trace):
+            if i not in okset or seq_status[i][0] != 0:
+                continue
             a = lams[i][0::2][:d["M"]] if cplx[i] else lams[i][:d["M"]]
             b = lam_seq[i][0::2] if cplx[i] else lam_seq[i]
             diff = max(diff, float(np.abs(a - b).max() / abs(b[0])))
@@ -199,7 +220,64 @@ def serve_benchmark(n_requests, rhos, cap, tol, seed=210100629):
             "sequential": {"solves_per_s": n_requests / done[-1], "p50_ms": float(np.percentile(seq_lat, 50) * 1e3),
                            "p99_ms": float(np.percentile(seq_lat, 99) * 1e3), "makespan_s": float(done[-1])},
             "max_eig_diff_vs_alone_rel_lambda1": diff,
+            "server_nonzero_status": [{"request": r["tag"], "status": r["status"],
+                                       "iterations": r["info"]["iterations"], "converged": r["info"]["converged"],
+                                       **brief(trace[r["tag"]])} for r in res if r["status"] != 0],
         }
+    return out
+
+
+def kernel_rates(warm=3, reps=10):
+    """Raw fused kernel product (ka_gamma_apply) at the workload shapes, both
+    precisions: median per-launch device time over `reps` launches after
+    `warm` warm-up launches, HIP events on the launch stream.  Points are
+    uniform in the unit cube (the kernel's cost does not depend on where the
+    points are); Y is N(0,1)."""
+    import torch
+    import paper_2101_00629_amd as K
+    from workloads import normal_block, uniform_points
+
+    shapes = [  # (name, kernel, ell, rows, cols, b)
+        ("cube p3 20^3 Galerkin Gaussian", "gaussian", 0.5, 12167, 12167, 16),
+        ("cube p3 20^3 Galerkin exponential (C0)", "exponential", 1.0, 226981, 226981, 16),
+        ("cube p3 20^3 collocation", "gaussian", 0.5, 12167, 512000, 16),
+        ("annulus p4 32x32x16 Galerkin Gaussian", "gaussian", 0.5, 25920, 25920, 32),
+        ("annulus p4 32x32x16 Galerkin exponential (C0)", "exponential", 0.25, 1081665, 1081665, 32),
+        ("annulus p4 32x32x16 collocation", "gaussian", 0.5, 25920, 2048000, 32),
+        ("cube p2 64^3 Galerkin Gaussian", "gaussian", 0.2, 287496, 287496, 64),
+    ]
+    out = []
+    for name, kern, ell, nr, nc, b in shapes:
+        xc = torch.tensor(uniform_points(7, nc), dtype=torch.float32, device="cuda")
+        xr = xc[:nr] if nr <= nc else torch.tensor(uniform_points(8, nr), dtype=torch.float32, device="cuda")
+        y = torch.tensor(normal_block(9, nc, b, dtype=np.float32), device="cuda")
+        z = torch.empty((nr, b), dtype=torch.float32, device="cuda")
+        for prec, pname in ((K.KA_FP32, "fp32"), (K.KA_BF16X3, "bf16x3")):
+            nbytes = K.ka_gamma_workspace(nr, nc, b, prec)
+            work = torch.empty(max(nbytes // 4, 1), dtype=torch.float32, device="cuda")
+            big = nr * nc > 2e11
+            nrep = 3 if big else reps
+            for _ in range(1 if big else warm):
+                K.ka_gamma_apply(K.KERNELS[kern], 1.0, ell, xr, xc, y, z, prec, work)
+            torch.cuda.synchronize()
+            ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(nrep)]
+            for e0, e1 in ev:
+                e0.record()
+                K.ka_gamma_apply(K.KERNELS[kern], 1.0, ell, xr, xc, y, z, prec, work)
+                e1.record()
+            torch.cuda.synchronize()
+            ms = float(np.median([e0.elapsed_time(e1) for e0, e1 in ev]))
+            rate = nr * nc / (ms / 1e3)
+            rec = {"shape": name, "rows": nr, "cols": nc, "b": b, "kernel": kern, "precision": pname,
+                   "launches": nrep, "median_ms": ms, "pairs_per_s": rate,
+                   "frac_valu_peak": rate / peak_pairs(kern)}
+            if pname == "fp32":
+                rec["frac_serial_peak"] = rate / serial_peak_pairs(kern, b)
+            out.append(rec)
+            print(f"[rates] {name} b={b} {pname}: {ms:.3f} ms, {rate / 1e12:.3f} Tpairs/s", file=sys.stderr,
+                  flush=True)
+            del work
+        del xc, xr, y, z
     return out
 
 
@@ -212,9 +290,11 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serve", action="store_true", help="run the serving benchmark instead")
-    ap.add_argument("--requests", type=int, default=128)
+    ap.add_argument("--requests", type=int, default=512)
     ap.add_argument("--rho", default="0.5,1.5")
     ap.add_argument("--pair-cap", type=float, default=1e11)
+    ap.add_argument("--kernel-rates", action="store_true",
+                    help="time the raw kernel product at every workload shape instead")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first run one plain device copy of MIB MiB (reference for HBM traffic counters)")
     args = ap.parse_args()
@@ -233,6 +313,11 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    if args.kernel_rates:
+        print(json.dumps({"metric": "fused kernel product pairs/s at the workload shapes", "n_gpus": 1,
+                          "data": "synthetic (uniform points, N(0,1) blocks)", "unit": "pairs/s",
+                          "rates": kernel_rates()}), flush=True)
+        return
     if args.serve:
         res = serve_benchmark(args.requests, [float(r) for r in args.rho.split(",")], args.pair_cap, args.tol)
         print(json.dumps({"metric": "K-L solves/s + p99 latency (serving)", "n_gpus": 1, "data": "synthetic",

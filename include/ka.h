@@ -70,8 +70,9 @@ enum ka_solve_op { KA_ZINV = 0,   /* X <- Z^-1 X                                
  *              is allowed for KA_GAUSSIAN and gives the constant kernel).
  * nq           collocation: Gauss points per element and direction (0 = p+1).
  * precision    contraction precision of the kernel product.
- * block        eigensolver block size b (1..64); also the largest nvec that
- *              one internal pass of ka_apply_A handles (larger nvec loops).
+ * block        eigensolver block size b: 16, 32 or 64 (KA_ERR_ARG otherwise);
+ *              also the largest nvec that one internal pass of ka_apply_A
+ *              handles (larger nvec loops).
  * seed         seeds the eigensolver's start block.                          */
 typedef struct ka_desc {
   int method;
@@ -138,9 +139,15 @@ int ka_solve_Z(ka_problem* p, int op, double* X_dev, int64_t ld, int nvec, void*
 
 /* Leading M eigenpairs of A v = lambda Z v by a block Krylov method with thick
  * restarts (FP64 basis, orthogonalisation and Rayleigh-Ritz on the device).
- * Stops when |A'x - theta x| <= tol * max(|theta|, 1e-2 |theta_1|) for the
- * first M Ritz pairs (M extended to the end of its cluster), or after maxit
- * restart cycles (returns KA_NOT_CONVERGED; results are still written).
+ * Stops when, for the first M Ritz pairs (M extended to the end of its
+ * cluster), |A'x - theta x| <= max(tol |theta|, max(1e-2 tol, nu) |theta_1|),
+ * where nu is the arithmetic noise floor of the operator (Galerkin: 4e-6 FP32,
+ * 1e-4 BF16x3; collocation: 2e-7 FP32, 5e-6 BF16x3).  A Galerkin pair accepted
+ * only through that floor must also satisfy r^2 / gap <= 0.1 tol
+ * max(|theta|, 1e-2 |theta_1|) (gap: distance to the nearest Ritz value that
+ * r and nu can separate from theta).  Also stops after maxit restart cycles,
+ * or after three cycles without a 10% drop of the largest scaled residual
+ * (both return KA_NOT_CONVERGED; results are still written).
  * lambda_host: M doubles (Galerkin), or 2M doubles re/im interleaved
  *   (collocation), sorted by descending real part.
  * V_dev: N x M column-major device array or NULL.  Galerkin eigenvectors are

@@ -145,3 +145,75 @@ def test_annulus_p4_reduced_mesh(method, kernel, ell, precision, bar):
     err = errors.floored_rel_errors(ref, lam)
     print(method, kernel, precision, info, err.max())
     assert rc == 0 and err.max() < bar
+
+
+# ---- eigenvectors as subspaces, per degenerate cluster ------------------------------------
+@pytest.mark.parametrize("method", ["galerkin", "collocation"])
+def test_eigenvector_subspaces_match_oracle(method):
+    """Largest principal angle between the returned eigenvectors and the dense
+    FP64 oracle's, per cluster of the reference spectrum (relative gap < 1e-8)
+    lying wholly within the first M; Z inner product for Galerkin."""
+    from oracle import collocation
+    M = 10
+    if method == "galerkin":
+        o = galerkin.GalerkinIBQ("cube", 2, (8, 8, 8), "exponential", 1.0)
+        lam_ref, V_ref = o.eig_dense(M + 6)
+        G = o.Z_dense()
+        rc, lam, V, info = _solve(K.make_desc("galerkin", "cube", 2, (8, 8, 8), "exponential", 1.0, seed=21), M)
+    else:
+        o = collocation.Collocation("cube", 2, (8, 8, 8), "exponential", 1.0)
+        lam_c, V_c = o.eig_dense(M + 6)
+        lam_ref, V_ref, G = lam_c.real, V_c.real, None
+        rc, lam, V, info = _solve_c(K.make_desc("collocation", "cube", 2, (8, 8, 8), "exponential", 1.0, seed=22), M)
+        lam = lam[0::2]
+    assert rc == 0
+    worst, checked = 0.0, 0
+    for grp in errors.clusters(lam_ref, 1e-8):
+        if grp[-1] >= M:
+            break
+        ang = errors.subspace_angle(V[:, grp], V_ref[:, grp], G)
+        worst = max(worst, ang)
+        checked += len(grp)
+    print(method, "clusters up to", checked, "largest angle", worst)
+    assert checked >= 7 and worst < 1e-4
+
+
+# ---- trace: sum of all eigenvalues (tr Z^-1 A) -----------------------------------------------
+def test_trace_brute_force_tiny_cube():
+    """tr(A') from A' applied to every unit vector, against the product of the
+    univariate traces (exact on the cube for a separable kernel)."""
+    desc = K.make_desc("galerkin", "cube", 2, (3, 3, 3), "gaussian", 0.5, seed=1)
+    prob = K.Problem(desc)
+    N = prob.N
+    X = torch.eye(N, dtype=torch.float64, device="cuda")
+    Y = torch.empty_like(X)
+    K.ka_apply_A(prob.h, K.KA_APRIME, X, Y)
+    torch.cuda.synchronize()
+    tr = float(torch.diagonal(Y).sum())
+    prob.close()
+    ref = product1d.galerkin_box_trace(2, (3, 3, 3), "gaussian", 0.5)
+    print("N", N, "trace", tr, "ref", ref)
+    assert abs(tr - ref) <= 1e-6 * ref
+
+
+def test_trace_hutchinson_full_size():
+    """Hutchinson estimate of tr(A') with 1024 Rademacher probes on the
+    p = 3, 20^3 cube (Gaussian l = 0.5), against the exact product-of-1D trace;
+    bar: 5 standard errors of the sample."""
+    c = cube_p3_20("galerkin", "gaussian")
+    prob = K.Problem(K.desc_from_problem(c, seed=5))
+    N = prob.N
+    rng = np.random.default_rng(77)
+    samples = []
+    for _ in range(64):
+        Zr = rng.integers(0, 2, size=(16, N)).astype(np.float64) * 2.0 - 1.0
+        X = torch.tensor(Zr, device="cuda")
+        Y = torch.empty_like(X)
+        K.ka_apply_A(prob.h, K.KA_APRIME, X, Y)
+        samples.extend((X * Y).sum(dim=1).cpu().numpy().tolist())
+    prob.close()
+    s = np.array(samples)
+    est, se = s.mean(), s.std(ddof=1) / np.sqrt(len(s))
+    ref = product1d.galerkin_box_trace(3, (20, 20, 20), "gaussian", 0.5)
+    print("Hutchinson", est, "+-", se, "ref", ref)
+    assert abs(est - ref) <= 5 * se and se < 0.05 * ref
