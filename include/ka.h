@@ -142,10 +142,11 @@ int ka_solve_Z(ka_problem* p, int op, double* X_dev, int64_t ld, int nvec, void*
  * Stops when, for the first M Ritz pairs (M extended to the end of its
  * cluster), |A'x - theta x| <= max(tol |theta|, max(1e-2 tol, nu) |theta_1|),
  * where nu is the arithmetic noise floor of the operator (Galerkin: 4e-6 FP32,
- * 1e-4 BF16x3; collocation: 2e-7 FP32, 5e-6 BF16x3).  A Galerkin pair accepted
- * only through that floor must also satisfy r^2 / gap <= 0.1 tol
- * max(|theta|, 1e-2 |theta_1|) (gap: distance to the nearest Ritz value that
- * r and nu can separate from theta).  Also stops after maxit restart cycles,
+ * 1e-4 BF16x3; collocation: 2e-7 FP32, 5e-6 BF16x3).  A Galerkin pair with
+ * |theta| > nu |theta_1| accepted only through that floor must also satisfy
+ * r^2 / gap <= 0.1 tol max(|theta|, 1e-2 |theta_1|) (gap: distance to the
+ * nearest Ritz value that r and nu can separate from theta); pairs below the
+ * floor carry an absolute error of order nu |theta_1|.  Also stops after maxit restart cycles,
  * or after three cycles without a 10% drop of the largest scaled residual
  * (both return KA_NOT_CONVERGED; results are still written).
  * lambda_host: M doubles (Galerkin), or 2M doubles re/im interleaved

@@ -97,16 +97,30 @@ __global__ void split_reduce_kernel(const double* __restrict__ part, int nsplit,
   const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (id >= (int64_t)m * n) return;
   const int i = (int)(id % m), j = (int)(id / m);
-  double s = 0.0;
-  for (int z = 0; z < nsplit; ++z) s += part[((size_t)z * n + j) * m + i];
+  // four interleaved partial sums (fixed order), so several loads are in flight
+  const size_t stride = (size_t)n * m;
+  const double* p = part + (size_t)j * m + i;
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  int z = 0;
+  for (; z + 3 < nsplit; z += 4) {
+    s0 += p[(size_t)z * stride];
+    s1 += p[(size_t)(z + 1) * stride];
+    s2 += p[(size_t)(z + 2) * stride];
+    s3 += p[(size_t)(z + 3) * stride];
+  }
+  for (; z < nsplit; ++z) s0 += p[(size_t)z * stride];
+  const double s = (s0 + s1) + (s2 + s3);
   double* c = C + i + (int64_t)j * ldc;
   *c = (beta == 0.0) ? alpha * s : alpha * s + beta * *c;
 }
 
+// Split the long dimension so that about 1024 workgroups run, each over at
+// least 128 rows (eight TK steps): the products here are short and wide
+// (K ~ 10^4 .. 10^6 rows, m, n <= a few hundred) and otherwise latency-bound.
 static int tn_splits(int m, int n, int64_t K) {
   const int64_t tiles = (int64_t)((m + TM - 1) / TM) * ((n + TN - 1) / TN);
-  int64_t ns = (512 + tiles - 1) / tiles;
-  const int64_t by_k = K / 512;
+  int64_t ns = (1024 + tiles - 1) / tiles;
+  const int64_t by_k = K / 128;
   if (ns > by_k) ns = by_k;
   if (ns > 256) ns = 256;
   if (ns < 1) ns = 1;

@@ -287,7 +287,9 @@ int EigRun::rayleigh_ritz(bool& stop) {
       if (!sym_) max_imag_ = std::max(max_imag_, std::fabs(thi_[i]) / modulus(i));
     }
     bool ok = rn_[i] <= crit;
-    if (sym_ && ok && rn_[i] > tol_ * modulus(i)) {
+    // Ritz values below the noise floor cannot be resolved by the operator's
+    // arithmetic: they are accepted by the floor alone (absolute error <= nu |theta_1|)
+    if (sym_ && ok && rn_[i] > tol_ * modulus(i) && modulus(i) > noise_ * modulus(0)) {
       // accepted through the noise floor only: also require the Ritz value to be
       // accurate, |theta - lambda| <= r^2 / gap, to a tenth of tol on the floored
       // scale.  gap: distance to the nearest Ritz value (among all k) outside the
