@@ -42,7 +42,11 @@ extern "C" {
 #define KA_NOT_CONVERGED 1    /* ka_eigs: maxit reached; partial results    */
 
 /* ---- enumerations ------------------------------------------------------ */
-enum ka_method { KA_GALERKIN_IBQ = 0, KA_COLLOCATION = 1 };
+enum ka_method { KA_GALERKIN_IBQ = 0,   /* Galerkin with interpolation-based quadrature (Sec. 3.1) */
+                 KA_COLLOCATION = 1,    /* isogeometric collocation (Sec. 3.2, Algorithm 1)        */
+                 KA_GALERKIN_GAUSS = 2  /* standard Galerkin with Gauss quadrature (Sec. 3.1, the
+                                           method IBQ replaces): same trial space and Z as IBQ,
+                                           Gamma between all quadrature points                   */ };
 enum ka_domain { KA_BOX = 0, KA_QUARTER_ANNULUS = 1 };
 enum ka_kernel { KA_GAUSSIAN = 0, /* sigma^2 exp(-|x-y|_2^2 / ell^2) */
                  KA_EXP_L1 = 1    /* sigma^2 exp(-|x-y|_1 / ell)     */ };
@@ -57,7 +61,9 @@ enum ka_solve_op { KA_ZINV = 0,   /* X <- Z^-1 X                                
                    KA_LTINV = 2   /* X <- L^-T X   (Galerkin)                        */ };
 
 /* ---- problem description (paper Sec. 3; Sec. 4 for the spaces) ---------
- * method       KA_GALERKIN_IBQ (Sec. 3.1) or KA_COLLOCATION (Sec. 3.2).
+ * method       KA_GALERKIN_IBQ (Sec. 3.1), KA_COLLOCATION (Sec. 3.2) or
+ *              KA_GALERKIN_GAUSS (standard Galerkin, nq Gauss points per element
+ *              and direction on both sides of Gamma: O((N_e nq^3)^2) pairs).
  * domain       KA_BOX: [lo, hi] (affine map); KA_QUARTER_ANNULUS: radii r0 < r1,
  *              quarter circle in the x-y plane extruded to `height` (exact
  *              rational quadratic NURBS map).
@@ -68,7 +74,8 @@ enum ka_solve_op { KA_ZINV = 0,   /* X <- Z^-1 X                                
  *              KA_GAUSSIAN (Sec. 4.2); otherwise 0 .. p-1.
  * kernel/sigma/ell  covariance kernel and its parameters (ell > 0; ell = +inf
  *              is allowed for KA_GAUSSIAN and gives the constant kernel).
- * nq           collocation: Gauss points per element and direction (0 = p+1).
+ * nq           collocation and Gauss Galerkin: Gauss points per element and
+ *              direction (0 = p+1).
  * precision    contraction precision of the kernel product.
  * block        eigensolver block size b: 16, 32 or 64 (KA_ERR_ARG otherwise);
  *              also the largest nvec that one internal pass of ka_apply_A
@@ -113,9 +120,10 @@ typedef struct ka_problem ka_problem;
  * stream for ka_eigs.  On error *out is NULL. */
 int ka_setup(const ka_desc* desc, void* stream, ka_problem** out);
 
-/* Sizes: N degrees of freedom, Ntilde Galerkin interpolation points (0 for
- * collocation), Nquad collocation quadrature points (0 for Galerkin), and the
- * device bytes the problem holds.  Any output pointer may be NULL. */
+/* Sizes: N degrees of freedom, Ntilde IBQ interpolation points (0 for the
+ * other methods), Nquad quadrature points (collocation and Gauss Galerkin; 0
+ * for IBQ), and the device bytes the problem holds.  Any output pointer may be
+ * NULL. */
 int ka_size(const ka_problem* p, int64_t* N, int64_t* Ntilde, int64_t* Nquad,
             size_t* device_bytes);
 

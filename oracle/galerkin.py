@@ -214,6 +214,7 @@ class GalerkinGauss:
         self.W = (w1 * w2 * w3).ravel()
         self.J = np.abs(self.domain.detJ(self.xhat))
         self.Zk = Zk
+        self.N = self.Bq.shape[1]
 
     def A_dense(self):
         if callable(self.kernel):
@@ -226,6 +227,16 @@ class GalerkinGauss:
 
     def Z_dense(self):
         return kron.kron3(*self.Zk)
+
+    def apply_A(self, V):
+        """A V with the assembled A (small meshes)."""
+        return self.A_dense() @ V
+
+    def apply_Aprime(self, Vp):
+        """A' V' = L^-1 A L^-T V' with Z = L L^T, L = L_3 x L_2 x L_1 (Sec. 3.1)."""
+        Lk = [np.linalg.cholesky(Z) for Z in self.Zk]
+        W = kron.kron_solve([_TriSolve(L, True, 1) for L in Lk], Vp)
+        return kron.kron_solve([_TriSolve(L, True, 0) for L in Lk], self.apply_A(W))
 
     def eig_dense(self, M=None):
         lam, V = sla.eigh(self.A_dense(), self.Z_dense())

@@ -33,6 +33,21 @@ def galerkin_pencil_1d(p, nel, kind, ell, interp_mult=None, a=0.0, b=1.0):
     return BinvM.T @ G @ BinvM, Z
 
 
+def galerkin_gauss_pencil_1d(p, nel, kind, ell, nq=None, a=0.0, b=1.0):
+    """Univariate standard-Galerkin pencil with Gauss quadrature on both sides
+    of the kernel (sigma = 1), trial space B_i / sqrt(b - a):
+    A_k = B_q^T diag(w) (j Gamma_k j) diag(w) B_q with j = sqrt(b - a)."""
+    nq = nq or p + 1
+    t = splines.open_knots(p, nel, 1)
+    xq, wq = splines.element_quadrature(t, nq)
+    Bq = splines.basis_matrix(t, p, xq)
+    Z = splines.mass_matrix(t, p, t, p)
+    x = a + (b - a) * xq
+    G = (b - a) * kernels.kernel_1d_factor(kind, x, x, ell)
+    P = Bq * wq[:, None]
+    return P.T @ G @ P, Z
+
+
 def collocation_pencil_1d(p, nel, kind, ell, nq=None, a=0.0, b=1.0):
     """Univariate collocation pencil (A_k, Z_k) on [a, b] (sigma = 1)."""
     nq = nq or p + 1
@@ -58,6 +73,14 @@ def galerkin_box_spectrum(p, nel, kind, ell, sigma=1.0, M=None, lo=(0, 0, 0), hi
     lams = []
     for k in range(3):
         A, Z = galerkin_pencil_1d(p, nel[k], kind, ell, interp_mult, lo[k], hi[k])
+        lams.append(np.sort(sla.eigh(A, Z, eigvals_only=True))[::-1])
+    return sigma ** 2 * _top_products(lams, M)
+
+
+def galerkin_gauss_box_spectrum(p, nel, kind, ell, sigma=1.0, M=None, lo=(0, 0, 0), hi=(1, 1, 1), nq=None):
+    lams = []
+    for k in range(3):
+        A, Z = galerkin_gauss_pencil_1d(p, nel[k], kind, ell, nq, lo[k], hi[k])
         lams.append(np.sort(sla.eigh(A, Z, eigvals_only=True))[::-1])
     return sigma ** 2 * _top_products(lams, M)
 

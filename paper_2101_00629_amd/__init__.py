@@ -22,14 +22,14 @@ KA_ERR_SINGULAR = -4
 KA_ERR_STATE = -5
 KA_NOT_CONVERGED = 1
 
-KA_GALERKIN_IBQ, KA_COLLOCATION = 0, 1
+KA_GALERKIN_IBQ, KA_COLLOCATION, KA_GALERKIN_GAUSS = 0, 1, 2
 KA_BOX, KA_QUARTER_ANNULUS = 0, 1
 KA_GAUSSIAN, KA_EXP_L1 = 0, 1
 KA_FP32, KA_BF16X3 = 0, 1
 KA_A, KA_APRIME = 0, 1
 KA_ZINV, KA_LINV, KA_LTINV = 0, 1, 2
 
-METHODS = {"galerkin": KA_GALERKIN_IBQ, "collocation": KA_COLLOCATION}
+METHODS = {"galerkin": KA_GALERKIN_IBQ, "collocation": KA_COLLOCATION, "galerkin_gauss": KA_GALERKIN_GAUSS}
 DOMAINS = {"cube": KA_BOX, "box": KA_BOX, "quarter_annulus": KA_QUARTER_ANNULUS}
 KERNELS = {"gaussian": KA_GAUSSIAN, "exponential": KA_EXP_L1}
 PRECISIONS = {"fp32": KA_FP32, "bf16x3": KA_BF16X3}

@@ -55,7 +55,8 @@ struct Sizes {
 
 static int check_desc(const ka_desc* d, Sizes& z) {
   if (!d) return fail(KA_ERR_ARG, "desc is NULL");
-  if (d->method != KA_GALERKIN_IBQ && d->method != KA_COLLOCATION) return fail(KA_ERR_ARG, "bad method");
+  if (d->method != KA_GALERKIN_IBQ && d->method != KA_COLLOCATION && d->method != KA_GALERKIN_GAUSS)
+    return fail(KA_ERR_ARG, "bad method");
   if (d->domain != KA_BOX && d->domain != KA_QUARTER_ANNULUS) return fail(KA_ERR_ARG, "bad domain");
   if (d->kernel != KA_GAUSSIAN && d->kernel != KA_EXP_L1) return fail(KA_ERR_ARG, "bad kernel");
   if (d->precision != KA_FP32 && d->precision != KA_BF16X3) return fail(KA_ERR_ARG, "bad precision");
@@ -93,6 +94,9 @@ static int check_desc(const ka_desc* d, Sizes& z) {
   if (d->method == KA_GALERKIN_IBQ) {
     z.Nq = 0;
     z.n_rows = z.n_cols = z.Nt;
+  } else if (d->method == KA_GALERKIN_GAUSS) {
+    z.Nt = 0;
+    z.n_rows = z.n_cols = z.Nq;
   } else {
     z.Nt = 0;
     z.n_rows = z.N;
@@ -107,7 +111,7 @@ static size_t align_up(size_t x) { return (x + 255) / 256 * 256; }
 // Largest point count of any intermediate tensor of the Kronecker transfers
 // (forward n -> m direction by direction, and back): sizes the FP32 buffers.
 static int64_t transfer_points(const ka_desc* d, const Sizes& z) {
-  const int* m = d->method == KA_GALERKIN_IBQ ? z.nt : z.nq;
+  const int* m = d->method == KA_GALERKIN_IBQ ? z.nt : z.nq;   // Gauss Galerkin and collocation: quadrature points
   const int64_t n0 = z.n[0], n1 = z.n[1], n2 = z.n[2], m0 = m[0], m1 = m[1], m2 = m[2];
   int64_t big = n0 * n1 * n2;
   for (int64_t v : {m0 * n1 * n2, m0 * m1 * n2, m0 * m1 * m2, n0 * m1 * m2, n0 * n1 * m2}) big = std::max(big, v);
@@ -207,7 +211,26 @@ static int setup_impl(const ka_desc* d, hipStream_t stream, Problem** out) {
   for (int k = 0; k < 3; ++k) {
     const int p = d->degree[k], e = d->nel[k];
     const Vec t = open_knots(p, e, 1);
-    if (d->method == KA_GALERKIN_IBQ) {
+    if (d->method == KA_GALERKIN_GAUSS) {
+      // standard Galerkin (Sec. 3.1): basis values at the element Gauss points
+      Mat Zk = mass_matrix(t, p, t, p), Lk;
+      if (!cholesky_lower(Zk, Lk)) {
+        free_problem(P);
+        return fail(KA_ERR_SINGULAR, "mass matrix is not SPD");
+      }
+      const Mat Li = lower_inverse(Lk);
+      const Mat LiT = transpose(Li);
+      P->Linv[k] = upload(P, to_vec(Li), ok);
+      P->LinvT[k] = upload(P, to_vec(LiT), ok);
+      P->Zinv[k] = upload(P, to_vec(matmul(LiT, Li)), ok);
+      Vec xq, wq;
+      element_gauss(t, d->nq > 0 ? d->nq : p + 1, xq, wq);
+      const Mat Rq = bspline_matrix(t, p, xq);                 // nq x n
+      P->T[k] = upload(P, to_vec32(Rq), ok);
+      P->TT[k] = upload(P, to_vec32(transpose(Rq)), ok);
+      q1d[k] = xq;
+      w1d[k] = wq;
+    } else if (d->method == KA_GALERKIN_IBQ) {
       Mat Zk = mass_matrix(t, p, t, p), Lk;
       if (!cholesky_lower(Zk, Lk)) {
         free_problem(P);
@@ -295,6 +318,22 @@ static int setup_impl(const ka_desc* d, hipStream_t stream, Problem** out) {
     P->cols = P->rows;
     P->rscale = upload(P, J, ok);
     P->cscale = P->rscale;
+  } else if (d->method == KA_GALERKIN_GAUSS) {
+    // trial space B_i / sqrt|det DF| (as for IBQ): both sides of Gamma carry
+    // the quadrature weight times sqrt|det DF|
+    std::vector<float> xyz;
+    std::vector<double> dj;
+    tensor_points(q1d, xyz, &dj);
+    std::vector<float> ws(dj.size());
+    const int64_t m1 = q1d[0].size(), m2 = q1d[1].size();
+    for (size_t i = 0; i < dj.size(); ++i) {
+      const int64_t a1 = i % m1, a2 = (i / m1) % m2, a3 = i / (m1 * m2);
+      ws[i] = (float)(std::sqrt(dj[i]) * w1d[0][a1] * w1d[1][a2] * w1d[2][a3]);
+    }
+    P->rows = upload(P, xyz, ok);
+    P->cols = P->rows;
+    P->rscale = upload(P, ws, ok);
+    P->cscale = P->rscale;
   } else {
     std::vector<float> xr, xq;
     tensor_points(pts1d, xr, nullptr);
@@ -358,7 +397,7 @@ int gamma_step(Problem* P, const float* Y, float* Z, hipStream_t s) {
   GammaLaunch g;
   g.xr = P->rows;
   g.xr_stride = 4;
-  g.rs = P->d.method == KA_GALERKIN_IBQ ? P->rscale : nullptr;
+  g.rs = P->d.method != KA_COLLOCATION ? P->rscale : nullptr;
   g.nr = P->n_rows;
   g.xc = P->cols;
   g.xc_stride = 4;
@@ -431,7 +470,7 @@ int apply_pre(Problem* P, int form, const double* X, int64_t ldx, int nv, hipStr
   int rc;
   const double* src = X;
   int64_t lds = ldx;
-  if (P->d.method == KA_GALERKIN_IBQ && form == KA_APRIME) {
+  if (P->d.method != KA_COLLOCATION && form == KA_APRIME) {
     if ((rc = kron64(P, P->LinvT, X, ldx, P->w64a, N, nv, s))) return rc;
     src = P->w64a;
     lds = N;
@@ -447,8 +486,8 @@ int apply_post(Problem* P, int form, double* Y, int64_t ldy, int nv, hipStream_t
   const int* n = P->n;
   const int64_t N = P->N;
   const int nn[3] = {n[0], n[1], n[2]};
-  if (P->d.method == KA_GALERKIN_IBQ) {
-    const int* m = P->nt;
+  if (P->d.method != KA_COLLOCATION) {
+    const int* m = P->d.method == KA_GALERKIN_IBQ ? P->nt : P->nq;
     int d0[3] = {m[0], m[1], m[2]};
     HIP_TRY(launch_mode_f32(mode_args(P->w32a, LAYOUT_PT, b, P->w32b, LAYOUT_PT, b, d0, 0, n[0], P->TT[0], nv, nullptr), s));
     int d1[3] = {n[0], m[1], m[2]};
@@ -480,7 +519,7 @@ GammaLaunch gamma_job(Problem* P) {
   GammaLaunch g;
   g.xr = P->rows;
   g.xr_stride = 4;
-  g.rs = P->d.method == KA_GALERKIN_IBQ ? P->rscale : nullptr;
+  g.rs = P->d.method != KA_COLLOCATION ? P->rscale : nullptr;
   g.nr = P->n_rows;
   g.xc = P->cols;
   g.xc_stride = 4;
@@ -505,7 +544,7 @@ int apply_block(Problem* P, int form, const double* X, int64_t ldx, double* Y, i
 
 int solve_block(Problem* P, int op, double* X, int64_t ld, int nv, hipStream_t s) {
   if (op == KA_ZINV) return kron64(P, P->Zinv, X, ld, X, ld, nv, s);
-  if (P->d.method != KA_GALERKIN_IBQ) return fail(KA_ERR_STATE, "L solves exist for the Galerkin method only");
+  if (P->d.method == KA_COLLOCATION) return fail(KA_ERR_STATE, "L solves exist for the Galerkin methods only");
   if (op == KA_LINV) return kron64(P, P->Linv, X, ld, X, ld, nv, s);
   if (op == KA_LTINV) return kron64(P, P->LinvT, X, ld, X, ld, nv, s);
   return fail(KA_ERR_ARG, "bad solve op");

@@ -174,7 +174,7 @@ int EigRun::orth_block(int k, int pw) {
 
 int EigRun::start() {
   t_start_ = std::chrono::steady_clock::now();
-  sym_ = P_->d.method == KA_GALERKIN_IBQ;
+  sym_ = P_->d.method != KA_COLLOCATION;
   const int64_t N = P_->N;
   const int b = P_->b;
   if (M_ < 1 || M_ > N) return fail(KA_ERR_ARG, "M must be in 1..N");

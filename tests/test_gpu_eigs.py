@@ -234,3 +234,70 @@ def test_spectrum_tail_below_noise_floor_converges():
     assert rc == 0
     assert errors.floored_rel_errors(ref[big], lam[big]).max() < 1e-6
     assert np.abs(lam - ref).max() < 1e-6 * ref[0]
+
+
+# ---- degenerate sizes -----------------------------------------------------------------------
+@pytest.mark.parametrize("method", ["galerkin", "collocation"])
+def test_full_spectrum_tiny_mesh(method):
+    """M = N on a one-element mesh (N = 27): the Krylov basis covers the whole
+    space, so every eigenvalue comes from one Rayleigh-Ritz step; compared with
+    the dense oracle over the whole spectrum (absolute, relative to lambda_1)."""
+    from oracle import collocation
+    if method == "galerkin":
+        o = galerkin.GalerkinIBQ("cube", 2, (1, 1, 1), "gaussian", 0.5)
+        ref, _ = o.eig_dense()
+    else:
+        o = collocation.Collocation("cube", 2, (1, 1, 1), "gaussian", 0.5)
+        ref, _ = o.eig_dense()
+        ref = ref.real
+    desc = K.make_desc(method, "cube", 2, (1, 1, 1), "gaussian", 0.5, seed=27)
+    prob = K.Problem(desc)
+    assert prob.N == 27
+    rc, lam, info = K.ka_eigs(prob.h, 27, tol=1e-6, maxit=20, complex_values=(method == "collocation"))
+    prob.close()
+    if method == "collocation":
+        lam = lam[0::2]
+    print(method, info, np.abs(lam - ref).max() / ref[0])
+    assert rc in (0, 1)
+    assert np.abs(lam - ref).max() < 1e-6 * ref[0]
+
+
+def test_single_eigenpair():
+    c = small_cube("galerkin", "exponential", 1.0)
+    desc = K.desc_from_problem(c, seed=2)
+    rc, lam, V, info = _solve(desc, 1)
+    ref = product1d.galerkin_box_spectrum(2, (8, 8, 8), "exponential", 1.0, M=1)
+    assert rc == 0 and abs(lam[0] - ref[0]) < 1e-6 * ref[0]
+
+
+# ---- standard Galerkin with Gauss quadrature (the method IBQ replaces) ----------------------
+def test_gauss_galerkin_small_meshes_vs_dense_oracle():
+    for dom_name, nel, kernel, ell in (("cube", (4, 3, 3), "exponential", 1.0),
+                                       ("quarter_annulus", (3, 3, 2), "gaussian", 0.5)):
+        o = galerkin.GalerkinGauss(geometry.make_domain(dom_name), 3, nel, kernel, ell)
+        ref, Vref = o.eig_dense(12)
+        desc = K.make_desc("galerkin_gauss", dom_name, 3, nel, kernel, ell, seed=31)
+        rc, lam, V, info = _solve(desc, 12)
+        err = errors.floored_rel_errors(ref, lam)
+        print(dom_name, info, err.max())
+        assert rc == 0 and err.max() < 1e-6
+        G = V.T @ o.Z_dense() @ V
+        assert np.abs(G - np.eye(12)).max() < 1e-6
+
+
+@pytest.mark.parametrize("precision,bar", [("fp32", 1e-6), ("bf16x3", 1e-5)])
+def test_gauss_galerkin_full_size_cube(precision, bar):
+    """p = 3, 20^3 cube, Gaussian l = 0.5, M = 50: Gamma between all 512,000
+    quadrature points (2.6e11 pairs per block product), against the exact
+    product-of-1D spectrum of the same discretisation."""
+    c = cube_p3_20("galerkin", "gaussian", precision=precision)
+    c["method"] = "galerkin_gauss"
+    prob = K.Problem(K.desc_from_problem(c, seed=41))
+    N, Nt, Nq, _ = K.ka_size(prob.h)
+    assert N == 12167 and Nq == 512000
+    rc, lam, info = K.ka_eigs(prob.h, 50, tol=1e-5, maxit=60)
+    prob.close()
+    ref = product1d.galerkin_gauss_box_spectrum(3, (20, 20, 20), "gaussian", 0.5, M=50)
+    err = errors.floored_rel_errors(ref, lam)
+    print(precision, info, "floored", err.max(), "raw", errors.rel_errors(ref, lam).max())
+    assert rc == 0 and err.max() < bar

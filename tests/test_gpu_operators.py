@@ -25,6 +25,9 @@ CASES = [
     dict(method="collocation", domain="quarter_annulus", p=3, nel=(3, 4, 2), kernel="exponential", ell=0.7),
     dict(method="collocation", domain="quarter_annulus", p=4, nel=(4, 2, 3), kernel="gaussian", ell=0.5,
          sigma=0.8),
+    dict(method="galerkin_gauss", domain="cube", p=2, nel=(4, 3, 5), kernel="exponential", ell=1.0),
+    dict(method="galerkin_gauss", domain="quarter_annulus", p=3, nel=(3, 2, 2), kernel="gaussian", ell=0.5,
+         sigma=1.3),
 ]
 
 
@@ -34,6 +37,8 @@ def _ids(c):
 
 def _oracle(c):
     dom = geometry.make_domain(c["domain"])
+    if c["method"] == "galerkin_gauss":
+        return galerkin.GalerkinGauss(dom, c["p"], c["nel"], c["kernel"], c["ell"], c.get("sigma", 1.0))
     if c["method"] == "galerkin":
         return galerkin.GalerkinIBQ(dom, c["p"], c["nel"], c["kernel"], c["ell"], c.get("sigma", 1.0))
     return collocation.Collocation(dom, c["p"], c["nel"], c["kernel"], c["ell"], c.get("sigma", 1.0))

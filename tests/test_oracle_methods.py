@@ -81,6 +81,50 @@ def test_ibq_equals_gauss_galerkin_for_kernels_in_interpolation_space():
     assert 1e-9 < d < 1e-1
 
 
+def test_gauss_galerkin_finite_rank_kernel_closed_form():
+    # standard Galerkin with (p+1)-point Gauss rules is exact for this kernel
+    dom = geometry.Box(LO, HI)
+    ref = _poly_kernel_spectrum()
+    for p in (1, 2, 3):
+        g = galerkin.GalerkinGauss(dom, p, (2, 3, 2), _poly_kernel, None)
+        lam, _ = g.eig_dense()
+        assert np.abs(lam[:4] - ref).max() < 1e-11 * ref[0]
+        assert np.abs(lam[4:]).max() < 1e-11 * ref[0]
+
+
+@pytest.mark.parametrize("kind,ell", [(EXPONENTIAL, 1.0), (GAUSSIAN, 0.5)])
+def test_gauss_galerkin_3d_dense_equals_product_of_1d(kind, ell):
+    g = galerkin.GalerkinGauss(geometry.Box(LO, HI), 2, (3, 2, 2), kind, ell, sigma=1.2)
+    lam, _ = g.eig_dense(15)
+    ref = product1d.galerkin_gauss_box_spectrum(2, (3, 2, 2), kind, ell, sigma=1.2, M=15, lo=LO, hi=HI)
+    assert np.abs(lam - ref).max() < 1e-12 * ref[0]
+    # a different rule (4 points per element) changes the discretisation, consistently
+    g4 = galerkin.GalerkinGauss(geometry.Box(LO, HI), 2, (3, 2, 2), kind, ell, sigma=1.2, q1d=4)
+    ref4 = product1d.galerkin_gauss_box_spectrum(2, (3, 2, 2), kind, ell, sigma=1.2, M=15, lo=LO, hi=HI, nq=4)
+    assert np.abs(g4.eig_dense(15)[0] - ref4).max() < 1e-12 * ref4[0]
+
+
+def test_gauss_galerkin_standard_form_operator():
+    # A' applied through the Kronecker Cholesky factors equals the assembled
+    # L^-1 A L^-T with L the Cholesky factor of the assembled Z
+    g = galerkin.GalerkinGauss(geometry.QuarterAnnulus(), 2, (2, 3, 2), GAUSSIAN, 0.6)
+    L = np.linalg.cholesky(g.Z_dense())
+    Ap = sla.solve_triangular(L, sla.solve_triangular(L, g.A_dense().T, lower=True).T, lower=True)
+    X = np.random.default_rng(3).standard_normal((g.Bq.shape[1], 4))
+    assert np.abs(g.apply_Aprime(X) - Ap @ X).max() < 1e-12 * np.abs(Ap @ X).max()
+    # and its eigenvalues are those of the pencil (A, Z)
+    lam = np.sort(np.linalg.eigvalsh(0.5 * (Ap + Ap.T)))[::-1][:8]
+    assert np.abs(lam - g.eig_dense(8)[0]).max() < 1e-12 * lam[0]
+
+
+def test_gauss_galerkin_constant_kernel_rank_one():
+    g = galerkin.GalerkinGauss(geometry.Box(LO, HI), 2, (2, 3, 2), GAUSSIAN, np.inf, sigma=1.5)
+    lam, _ = g.eig_dense()
+    vol = np.prod(np.array(HI) - np.array(LO))
+    assert abs(lam[0] - 2.25 * vol) < 1e-12 * lam[0]
+    assert np.abs(lam[1:]).max() < 1e-12 * lam[0]
+
+
 def test_constant_kernel_rank_one():
     # Gamma = sigma^2: lambda_1 = sigma^2 |D|, the rest vanish
     for dom, exact in ((geometry.Box(LO, HI), True), (geometry.QuarterAnnulus(), False)):
