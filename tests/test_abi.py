@@ -66,3 +66,37 @@ def test_single_hip_runtime_whatever_the_import_order():
     out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, cwd=ROOT, timeout=300)
     assert out.returncode == 0, out.stderr
     assert out.stdout.strip().splitlines()[-1] == "1"
+
+
+def test_bench_uses_the_oracle_only_in_the_cpu_baseline():
+    import ast
+    tree = ast.parse(open(os.path.join(ROOT, "bench.py")).read())
+    offenders = []
+    for fn in ast.walk(tree):
+        if isinstance(fn, ast.FunctionDef):
+            for node in ast.walk(fn):
+                mod = None
+                if isinstance(node, ast.ImportFrom):
+                    mod = node.module or ""
+                elif isinstance(node, ast.Import):
+                    mod = ",".join(a.name for a in node.names)
+                if mod is not None and "oracle" in mod and fn.name != "cpu_baseline":
+                    offenders.append((fn.name, mod))
+    top = [n for n in tree.body if isinstance(n, (ast.Import, ast.ImportFrom))]
+    offenders += [("<module>", getattr(n, "module", "")) for n in top if "oracle" in (getattr(n, "module", "") or "")]
+    assert not offenders, offenders
+
+
+def test_stored_cube_reference_matches_the_oracle():
+    import json
+    import numpy as np
+    import sys
+    sys.path.insert(0, ROOT)
+    from oracle import product1d
+    rec = json.load(open(os.path.join(ROOT, "tests", "golden", "cube_p3_20_reference_spectra.json")))
+    ref = product1d.galerkin_box_spectrum(3, (20, 20, 20), "exponential", 1.0, M=50)
+    got = np.array(rec["spectra"]["galerkin-exponential"]["lambda"])
+    assert np.abs(got - ref).max() <= 1e-14 * ref[0]
+    ref = product1d.collocation_box_spectrum(3, (20, 20, 20), "gaussian", 0.5, M=50).real
+    got = np.array(rec["spectra"]["collocation-gaussian"]["lambda"])
+    assert np.abs(got - ref).max() <= 1e-14 * ref[0]
