@@ -290,6 +290,50 @@ def kernel_rates(warm=3, reps=10):
     return out
 
 
+def compare_methods(reps=3):
+    """The paper's comparison (Sec. 4) on the unit cube: eigensolver time
+    against the mean relative error of the 20 largest eigenvalues (eps-bar),
+    for Galerkin-IBQ, collocation and standard Gauss-quadrature Galerkin.
+    Example-1 analogue: L1-exponential kernel (ell = 1), p = 2, h-refinement.
+    Example-2 analogue: Gaussian kernel (ell = 0.5), 6^3 elements, k-refinement
+    p = 2..6.  References: the continuous spectra stored in
+    tests/golden/cube_continuum_spectra.json.  Time = median over `reps` solves
+    of ka_eigs (set-up excluded, as the paper times the eigensolver), FP32."""
+    import torch
+    import paper_2101_00629_amd as K
+
+    with open(os.path.join(ROOT, "tests", "golden", "cube_continuum_spectra.json")) as f:
+        cont = json.load(f)
+    series = [("exponential", 1.0, cont["exponential_l1"]["lambda"], [(2, n) for n in (4, 6, 8, 12, 16, 24)]),
+              ("gaussian", 0.5, cont["gaussian_l0.5"]["lambda"], [(p, 6) for p in (2, 3, 4, 5, 6)])]
+    out = []
+    for kernel, ell, ref, meshes in series:
+        ref = np.array(ref)
+        for p, nel in meshes:
+            for method in ("galerkin", "collocation", "galerkin_gauss"):
+                desc = K.make_desc(method, "cube", p, (nel, nel, nel), kernel, ell, block=16, seed=5)
+                prob = K.Problem(desc)
+                times = []
+                for _ in range(reps):
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    rc, lam, info = K.ka_eigs(prob.h, 20, tol=1e-6, maxit=80,
+                                              complex_values=(method == "collocation"))
+                    times.append(time.perf_counter() - t0)
+                N, Nt, Nq, _ = K.ka_size(prob.h)
+                prob.close()
+                lr = lam[0::2] if method == "collocation" else lam
+                eps = np.abs(lr[:20] - ref) / ref
+                rec = {"kernel": kernel, "ell": ell, "p": p, "nel": nel, "method": method, "N": N,
+                       "points": Nt if method == "galerkin" else Nq, "status": rc,
+                       "eps_bar": float(eps.mean()), "eps_max": float(eps.max()),
+                       "solve_s": float(np.median(times)), "matvecs": info["matvecs"], "pairs": info["pairs"]}
+                out.append(rec)
+                print(f"[compare] {kernel} p={p} nel={nel} {method}: N={N} eps_bar={rec['eps_bar']:.2e} "
+                      f"t={rec['solve_s'] * 1e3:.1f} ms", file=sys.stderr, flush=True)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -302,6 +346,8 @@ def main():
     ap.add_argument("--requests", type=int, default=512)
     ap.add_argument("--rho", default="0.5,1.5")
     ap.add_argument("--pair-cap", type=float, default=1e11)
+    ap.add_argument("--compare", action="store_true",
+                    help="the paper's method comparison (time vs eigenvalue error) on the cube instead")
     ap.add_argument("--kernel-rates", action="store_true",
                     help="time the raw kernel product at every workload shape instead")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -322,6 +368,10 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    if args.compare:
+        print(json.dumps({"metric": "eigensolver time vs mean relative error of 20 eigenvalues", "n_gpus": 1,
+                          "data": "synthetic (unit cube)", "dtype": "f32", "runs": compare_methods()}), flush=True)
+        return
     if args.kernel_rates:
         print(json.dumps({"metric": "fused kernel product pairs/s at the workload shapes", "n_gpus": 1,
                           "data": "synthetic (uniform points, N(0,1) blocks)", "unit": "pairs/s",
