@@ -409,6 +409,8 @@ int gamma_step(Problem* P, const float* Y, float* Z, hipStream_t s) {
   g.out_scale = P->out_scale;
   g.nsplit = 1;
   g.cols_per_split = 0;
+  g.row_blocks = 0;
+  g.xcd_splits = 0;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (P->profile) {
     if (P->prof_launches < (int)P->ev_start.size()) {
@@ -532,6 +534,8 @@ GammaLaunch gamma_job(Problem* P) {
   const GammaPlan gp = gamma_plan(g.nr, g.nc, P->b, P->d.precision);
   g.nsplit = gp.nsplit;
   g.cols_per_split = gp.cols_per_split;
+  g.row_blocks = gp.row_blocks;
+  g.xcd_splits = 0;   // batched launches enumerate (row block, split) items explicitly
   return g;
 }
 

@@ -106,6 +106,8 @@ int ka_gamma_apply(int kernel, double sigma, double ell, const float* xr_dev, in
   g.out_scale = (float)(sigma * sigma);
   g.nsplit = 1;
   g.cols_per_split = 0;
+  g.row_blocks = 0;
+  g.xcd_splits = 0;   // launch_gamma fills the plan
   const hipError_t e = launch_gamma(g, kernel, b, precision, (hipStream_t)stream);
   if (e != hipSuccess) return fail(KA_ERR_HIP, std::string("kernel product launch: ") + hipGetErrorString(e));
   return KA_OK;
