@@ -137,7 +137,6 @@ __device__ __forceinline__ void gamma_f32_tile(const GammaLaunch& a, int64_t rbl
         acc[rb][t] = (f4v){0.f, 0.f, 0.f, 0.f};
       }
   };
-  int tiles_since_flush = 0;
 
   // per-thread staging registers for one tile
   constexpr int YV = kCT * B / 4 / kThreads;   // float4 of Y per thread per tile
@@ -173,15 +172,23 @@ __device__ __forceinline__ void gamma_f32_tile(const GammaLaunch& a, int64_t rbl
   };
 
   int buf = 0;
-  if (c_begin < c_end) {
-    fetch(c_begin);
-    stash(0);
-  }
+  fetch(c_begin);
+  stash(0);
   __syncthreads();
-  for (int64_t ct = c_begin; ct < c_end; ct += kCT) {
-    const bool more = ct + kCT < c_end;
-    if (more) fetch(ct + kCT);
-#pragma unroll 2
+  // Tiles go in groups of kFlushTiles with an unconditional flush after each
+  // group, so the MFMA accumulators enter every group at zero and are never
+  // carried around the loop.  The next tile is always fetched: beyond c_end
+  // it is zero-filled (Y = 0), so a padding tile in the last group adds
+  // exactly zero.
+  for (int64_t cg = c_begin; cg < c_end; cg += kFlushTiles * kCT) {
+#pragma unroll
+  for (int f = 0; f < kFlushTiles; ++f) {
+    const int64_t ct = cg + f * kCT;
+    fetch(ct + kCT);
+    // Fully unrolled: with a rolled loop the register allocator rotates the
+    // accumulators through AGPR copies every step (measured at b = 64: 40
+    // extra VALU instructions per 16 MFMAs).
+#pragma unroll
     for (int k = 0; k < kCT; k += 4) {
       const int c = k + (lane >> 4);
       const float4 p = s_x[buf][c];
@@ -196,15 +203,12 @@ __device__ __forceinline__ void gamma_f32_tile(const GammaLaunch& a, int64_t rbl
           acc[rb][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(g, yv[t], acc[rb][t], 0, 0, 0);
       }
     }
-    if (more) stash(buf ^ 1);
-    if (++tiles_since_flush == kFlushTiles) {
-      flush();
-      tiles_since_flush = 0;
-    }
+    stash(buf ^ 1);
     __syncthreads();
     buf ^= 1;
   }
-  flush();
+    flush();
+  }
 
   float* out = a.nsplit > 1 ? a.partial + (size_t)split * a.nr * B : a.Z;
 #pragma unroll
@@ -221,8 +225,16 @@ __device__ __forceinline__ void gamma_f32_tile(const GammaLaunch& a, int64_t rbl
   }
 }
 
+// Occupancy target of the FP32 path (waves per SIMD).  FP32 MFMA and VALU
+// work do not overlap on gfx950, so the kernel is issue bound; the target
+// trades latency hiding against registers for scheduling.  Measured best on
+// the workload shapes: 4 at b = 16, 3 at b = 32, 2 at b = 64.
+template <int B>
+constexpr int f32_waves() { return B == 16 ? 4 : (B == 32 ? 3 : 2); }
+
 template <int KERNEL, int B, int RB>
-__global__ __launch_bounds__(kThreads) void gamma_f32_kernel(GammaLaunch a) {
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(f32_waves<B>(), f32_waves<B>())))
+void gamma_f32_kernel(GammaLaunch a) {
   __shared__ float4 s_x[2][kCT];
   __shared__ float s_y[2][kCT * y_stride<B>()];
   int64_t rblk;
@@ -243,7 +255,9 @@ __device__ __forceinline__ uint32_t pack_bf16x2(float lo_elem, float hi_elem) {
 // even for both; x - hi is exact in FP32).
 __device__ __forceinline__ void split2(float x0, float x1, uint32_t& hi, uint32_t& lo) {
   hi = pack_bf16x2(x0, x1);
-  const float h0 = __builtin_bit_cast(float, hi << 16);
+  // low half of hi moved to the top, zeros below (one v_perm_b32; written as
+  // a shift the compiler re-converts x0 instead)
+  const float h0 = __builtin_bit_cast(float, __builtin_amdgcn_perm(0u, hi, 0x01000c0cu));
   const float h1 = __builtin_bit_cast(float, hi & 0xffff0000u);
   lo = pack_bf16x2(x0 - h0, x1 - h1);
 }
@@ -297,7 +311,6 @@ __device__ __forceinline__ void gamma_bf16x3_tile(const GammaLaunch& a, int64_t 
         acc[rb][t] = (f4v){0.f, 0.f, 0.f, 0.f};
       }
   };
-  int tiles_since_flush = 0;
 
   // staging: item = (g8, j): 8 consecutive columns 8*g8..8*g8+7 of Y column j
   constexpr int ITEMS = (kCT / 8) * B;
@@ -350,14 +363,15 @@ __device__ __forceinline__ void gamma_bf16x3_tile(const GammaLaunch& a, int64_t 
   };
 
   int buf = 0;
-  if (c_begin < c_end) {
-    fetch(c_begin);
-    stash(0);
-  }
+  fetch(c_begin);
+  stash(0);
   __syncthreads();
-  for (int64_t ct = c_begin; ct < c_end; ct += kCT) {
-    const bool more = ct + kCT < c_end;
-    if (more) fetch(ct + kCT);
+  // Tile groups with an unconditional flush, as in the FP32 path.
+  for (int64_t cg = c_begin; cg < c_end; cg += kFlushTiles * kCT) {
+#pragma unroll
+  for (int f = 0; f < kFlushTiles; ++f) {
+    const int64_t ct = cg + f * kCT;
+    fetch(ct + kCT);
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) {
       float4 p[8];
@@ -390,15 +404,12 @@ __device__ __forceinline__ void gamma_bf16x3_tile(const GammaLaunch& a, int64_t 
         }
       }
     }
-    if (more) stash(buf ^ 1);
-    if (++tiles_since_flush == kFlushTiles) {
-      flush();
-      tiles_since_flush = 0;
-    }
+    stash(buf ^ 1);
     __syncthreads();
     buf ^= 1;
   }
-  flush();
+    flush();
+  }
 
   float* out = a.nsplit > 1 ? a.partial + (size_t)split * a.nr * B : a.Z;
 #pragma unroll
@@ -496,8 +507,9 @@ GammaPlan gamma_plan(int64_t nr, int64_t nc, int b, int precision) {
   // of the XCD count: the grouped grid then keeps every split on one XCD, so
   // its column range is fetched from HBM into that XCD's L2 once.
   if (ns >= kXcds) ns = (ns + kXcds - 1) / kXcds * kXcds;
+  // Whole tile groups per split: only the last split can end in a padding tile.
   int64_t cps = (nc + ns - 1) / ns;
-  cps = (cps + kCT - 1) / kCT * kCT;
+  cps = (cps + kFlushTiles * kCT - 1) / (kFlushTiles * kCT) * (kFlushTiles * kCT);
   const int64_t ns_grid = ns;
   ns = (nc + cps - 1) / cps;
   if (ns < 1) ns = 1;
