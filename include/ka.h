@@ -171,8 +171,10 @@ int ka_eigs(ka_problem* p, int M, double tol, int maxit, double* lambda_host,
  * Algorithm 1 step 3): Z[i, :] = sigma^2 sum_c Gamma(xr_i, xc_c) Y[c, :].
  * xr: nr x 3, xc: nc x 3 FP32 row-major physical coordinates; Y: nc x b and
  * Z: nr x b FP32 row-major (point-major, b contiguous); b in {16, 32, 64}.
- * precision KA_FP32 or KA_BF16X3.  Requires nr * b * 4 * nsplit bytes of
- * split-K scratch from `work_dev` (work_bytes); pass ka_gamma_workspace() bytes.
+ * precision KA_FP32 or KA_BF16X3.  Scratch from `work_dev` (work_bytes,
+ * 16-byte aligned): the split-K partial sums (nsplit * nr * b * 4 bytes when
+ * the columns are split) and, for KA_BF16X3, Y split into hi/lo BF16 parts
+ * (ceil(nc / 64) * 64 * b * 4 bytes); pass ka_gamma_workspace() bytes.
  * Async on `stream`. */
 int ka_gamma_apply(int kernel, double sigma, double ell, const float* xr_dev, int64_t nr,
                    const float* xc_dev, int64_t nc, const float* Y_dev, int b, float* Z_dev,

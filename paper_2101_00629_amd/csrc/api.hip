@@ -130,7 +130,7 @@ static size_t setup_bytes(const ka_desc* d, const Sizes& z) {
   s += align_up((size_t)z.n_rows * 4) + align_up((size_t)z.n_cols * 4);
   s += 2 * align_up((size_t)z.N * b * 8);
   s += 2 * align_up((size_t)transfer_points(d, z) * b * 4);
-  s += align_up(gamma_plan(z.n_rows, z.n_cols, b, d->precision).partial_bytes);
+  s += align_up(gamma_plan(z.n_rows, z.n_cols, b, d->precision).work_bytes);
   return s;
 }
 
@@ -357,8 +357,8 @@ static int setup_impl(const ka_desc* d, hipStream_t stream, Problem** out) {
   P->w32a = (float*)dev_alloc(P, (size_t)big * b * 4, ok);
   P->w32b = (float*)dev_alloc(P, (size_t)big * b * 4, ok);
   const GammaPlan gp = gamma_plan(P->n_rows, P->n_cols, b, d->precision);
-  P->gpart_bytes = gp.partial_bytes;
-  P->gpart = (float*)dev_alloc(P, gp.partial_bytes, ok);
+  P->gpart_bytes = gp.work_bytes;
+  P->gpart = (float*)dev_alloc(P, gp.work_bytes, ok);
   if (!ok) {
     free_problem(P);
     return fail(KA_ERR_OOM, "device allocation failed in ka_setup");
@@ -405,6 +405,7 @@ int gamma_step(Problem* P, const float* Y, float* Z, hipStream_t s) {
   g.Y = Y;
   g.Z = Z;
   g.partial = P->gpart;
+  g.ys = nullptr;   // launch_gamma places it in the scratch
   g.coord_scale = P->coord_scale;
   g.out_scale = P->out_scale;
   g.nsplit = 1;
@@ -535,6 +536,7 @@ GammaLaunch gamma_job(Problem* P) {
   g.nsplit = gp.nsplit;
   g.cols_per_split = gp.cols_per_split;
   g.row_blocks = gp.row_blocks;
+  g.ys = gamma_ysplit_ptr(P->gpart, gp);   // batched launches run the split pre-pass themselves
   g.xcd_splits = 0;   // batched launches enumerate (row block, split) items explicitly
   return g;
 }

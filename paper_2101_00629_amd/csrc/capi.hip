@@ -74,7 +74,7 @@ int ka_eigs(ka_problem* p, int M, double tol, int maxit, double* lambda_host, do
 
 size_t ka_gamma_workspace(int64_t nr, int64_t nc, int b, int precision) {
   if (nr <= 0 || nc <= 0) return 0;
-  return gamma_plan(nr, nc, b, precision).partial_bytes;
+  return gamma_plan(nr, nc, b, precision).work_bytes;
 }
 
 int ka_gamma_apply(int kernel, double sigma, double ell, const float* xr_dev, int64_t nr, const float* xc_dev,
@@ -89,8 +89,9 @@ int ka_gamma_apply(int kernel, double sigma, double ell, const float* xr_dev, in
   if (!xr_dev || !Z_dev || (nc > 0 && (!xc_dev || !Y_dev))) return fail(KA_ERR_ARG, "NULL pointer");
   if (((uintptr_t)Y_dev & 15) != 0) return fail(KA_ERR_ARG, "Y must be 16-byte aligned");
   const GammaPlan gp = gamma_plan(nr, nc, b, precision);
-  if (gp.partial_bytes > work_bytes || (gp.partial_bytes > 0 && !work_dev))
+  if (gp.work_bytes > work_bytes || (gp.work_bytes > 0 && !work_dev))
     return fail(KA_ERR_ARG, "workspace too small (see ka_gamma_workspace)");
+  if (((uintptr_t)work_dev & 15) != 0) return fail(KA_ERR_ARG, "workspace must be 16-byte aligned");
   GammaLaunch g;
   g.xr = xr_dev;
   g.xr_stride = 3;
@@ -102,6 +103,7 @@ int ka_gamma_apply(int kernel, double sigma, double ell, const float* xr_dev, in
   g.Y = Y_dev;
   g.Z = Z_dev;
   g.partial = (float*)work_dev;
+  g.ys = nullptr;   // launch_gamma places it in the workspace
   g.coord_scale = kernel_coord_scale(kernel, ell);
   g.out_scale = (float)(sigma * sigma);
   g.nsplit = 1;

@@ -28,6 +28,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+
 #include "ka_internal.hpp"
 
 namespace ka {
@@ -264,6 +266,45 @@ __device__ __forceinline__ void split2(float x0, float x1, uint32_t& hi, uint32_
 
 constexpr int kKS = kCT / 32;   // BF16 MFMA k-steps per tile
 
+// Y split once per product for the BF16x3 path, straight into the order the
+// kernel's LDS buffers hold the MFMA B operands.  Entry r of 64-column tile T
+// (r = (ks * NT + t) * 64 + lane, lane = 16 * grp + n) is the fragment of Y
+// column j = 16 t + n over the 8 tile columns 32 ks + 8 grp + u, u = 0..7,
+// as 8 BF16 values; hi parts at ys[2 E T + r], lo parts at ys[2 E T + E + r]
+// (E entries per tile and part).  Columns past nc are zero.
+template <int B>
+__device__ __forceinline__ void split_y_entry(const float* __restrict__ Y, int64_t nc, uint4* __restrict__ ys,
+                                              int64_t e) {
+  constexpr int NT = B / 16;
+  constexpr int E = kKS * NT * 64;
+  const int64_t T = e / E;
+  const int r = (int)(e - T * E);
+  const int lane = r & 63, t = (r >> 6) % NT, ks = r / (64 * NT);
+  const int j = 16 * t + (lane & 15);
+  const int64_t c0 = kCT * T + 32 * ks + 8 * (lane >> 4);
+  float y[8];
+#pragma unroll
+  for (int u = 0; u < 8; ++u) y[u] = (c0 + u < nc) ? Y[(c0 + u) * B + j] : 0.f;
+  uint4 h, l;
+  split2(y[0], y[1], h.x, l.x);
+  split2(y[2], y[3], h.y, l.y);
+  split2(y[4], y[5], h.z, l.z);
+  split2(y[6], y[7], h.w, l.w);
+  ys[2 * E * T + r] = h;
+  ys[2 * E * T + E + r] = l;
+}
+
+template <int B>
+constexpr int64_t split_entries(int64_t nc) { return (nc + kCT - 1) / kCT * (kKS * (B / 16) * 64); }
+
+template <int B>
+__global__ __launch_bounds__(256) void gamma_split_kernel(const float* __restrict__ Y, int64_t nc,
+                                                          uint4* __restrict__ ys) {
+  const int64_t n = split_entries<B>(nc);
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+    split_y_entry<B>(Y, nc, ys, e);
+}
+
 // B-operand fragments in LDS: [k-step][t][lane] -> 4 dwords (8 bf16)
 template <int KERNEL, int B, int RB>
 __device__ __forceinline__ void gamma_bf16x3_tile(const GammaLaunch& a, int64_t rblk, int split,
@@ -312,29 +353,22 @@ __device__ __forceinline__ void gamma_bf16x3_tile(const GammaLaunch& a, int64_t 
       }
   };
 
-  // staging: item = (g8, j): 8 consecutive columns 8*g8..8*g8+7 of Y column j
-  constexpr int ITEMS = (kCT / 8) * B;
-  constexpr int IPT = ITEMS / kThreads;      // items per thread (B=16: 0.5 -> handled below)
-  constexpr int IPT_R = IPT > 0 ? IPT : 1;
-  uint4 hbuf[IPT_R], lbuf[IPT_R];
+  // staging: the tile's hi and lo B fragments are contiguous in the
+  // pre-split Y (gamma_split_y), in the order the LDS buffers hold them.
+  constexpr int E = KS * NT * 64;                    // uint4 per tile and part
+  constexpr int FPT = (E + kThreads - 1) / kThreads; // per thread (b = 16: threads 0..127 only)
+  uint4 hbuf[FPT], lbuf[FPT];
   float4 xbuf;
 
   auto fetch = [&](int64_t ct) {
+    const uint4* src = a.ys + (ct / kCT) * (2 * E);
+    const bool in = ct < c_end;   // uniform: tiles past the split end stage zeros
 #pragma unroll
-    for (int v = 0; v < IPT_R; ++v) {
-      const int item = threadIdx.x + v * kThreads;
-      if (item < ITEMS) {
-        const int g8 = item / B, j = item % B;
-        float y[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-          const int64_t c = ct + 8 * g8 + u;
-          y[u] = (c < c_end) ? a.Y[c * B + j] : 0.f;
-        }
-        split2(y[0], y[1], hbuf[v].x, lbuf[v].x);
-        split2(y[2], y[3], hbuf[v].y, lbuf[v].y);
-        split2(y[4], y[5], hbuf[v].z, lbuf[v].z);
-        split2(y[6], y[7], hbuf[v].w, lbuf[v].w);
+    for (int v = 0; v < FPT; ++v) {
+      const int e = threadIdx.x + v * kThreads;
+      if (e < E) {
+        hbuf[v] = in ? src[e] : make_uint4(0u, 0u, 0u, 0u);
+        lbuf[v] = in ? src[E + e] : make_uint4(0u, 0u, 0u, 0u);
       }
     }
     if (threadIdx.x < kCT) {
@@ -349,14 +383,11 @@ __device__ __forceinline__ void gamma_bf16x3_tile(const GammaLaunch& a, int64_t 
   };
   auto stash = [&](int buf) {
 #pragma unroll
-    for (int v = 0; v < IPT_R; ++v) {
-      const int item = threadIdx.x + v * kThreads;
-      if (item < ITEMS) {
-        const int g8 = item / B, j = item % B;
-        const int ks = g8 / 4, grp = g8 % 4, t = j / 16;
-        const int ln = grp * 16 + (j & 15);
-        s_yh[buf][(ks * NT + t) * 64 + ln] = hbuf[v];
-        s_yl[buf][(ks * NT + t) * 64 + ln] = lbuf[v];
+    for (int v = 0; v < FPT; ++v) {
+      const int e = threadIdx.x + v * kThreads;
+      if (e < E) {
+        s_yh[buf][e] = hbuf[v];
+        s_yl[buf][e] = lbuf[v];
       }
     }
     if (threadIdx.x < kCT) s_x[buf][threadIdx.x] = xbuf;
@@ -426,8 +457,14 @@ __device__ __forceinline__ void gamma_bf16x3_tile(const GammaLaunch& a, int64_t 
   }
 }
 
+// Occupancy target of the BF16x3 path (waves per SIMD), measured best on the
+// workload shapes: 3 at b = 16, 2 at b = 32 and 64.
+template <int B>
+constexpr int bf16x3_waves() { return B == 16 ? 3 : 2; }
+
 template <int KERNEL, int B, int RB>
-__global__ __launch_bounds__(kThreads) void gamma_bf16x3_kernel(GammaLaunch a) {
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(bf16x3_waves<B>(), bf16x3_waves<B>())))
+void gamma_bf16x3_kernel(GammaLaunch a) {
   __shared__ float4 s_x[2][kCT];
   __shared__ uint4 s_yh[2][kKS * (B / 16) * 64];
   __shared__ uint4 s_yl[2][kKS * (B / 16) * 64];
@@ -442,7 +479,9 @@ __global__ __launch_bounds__(kThreads) void gamma_bf16x3_kernel(GammaLaunch a) {
 // product keeps its own split-K partition, so its result does not depend on
 // what else is in the batch.
 template <int B, int RB, int PREC>
-__global__ __launch_bounds__(kThreads) void gamma_batch_kernel(const GammaJob* __restrict__ jobs,
+__global__ __launch_bounds__(kThreads)
+__attribute__((amdgpu_waves_per_eu(bf16x3_waves<B>(), bf16x3_waves<B>())))   // both kernels inlined: 3/2/2
+void gamma_batch_kernel(const GammaJob* __restrict__ jobs,
                                                                const GammaItem* __restrict__ items, int n_items) {
   __shared__ float4 s_x[2][kCT];
   __shared__ float s_y[PREC == KA_FP32 ? 2 : 1][PREC == KA_FP32 ? kCT * y_stride<B>() : 1];
@@ -464,6 +503,15 @@ __global__ __launch_bounds__(kThreads) void gamma_batch_kernel(const GammaJob* _
     }
     __syncthreads();
   }
+}
+
+// BF16x3 pre-pass of a batched launch: job blockIdx.y splits its own Y.
+template <int B>
+__global__ __launch_bounds__(256) void gamma_split_jobs_kernel(const GammaJob* __restrict__ jobs) {
+  const GammaLaunch& a = jobs[blockIdx.y].a;
+  const int64_t n = split_entries<B>(a.nc);
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+    split_y_entry<B>(a.Y, a.nc, a.ys, e);
 }
 
 // Sum of split-K partials in fixed order: Z = sum_s partial[s].
@@ -493,6 +541,8 @@ GammaPlan gamma_plan(int64_t nr, int64_t nc, int b, int precision) {
     p.nsplit = 1;
     p.cols_per_split = nc > 0 ? nc : 0;
     p.partial_bytes = 0;
+    p.ysplit_bytes = 0;
+    p.work_bytes = 0;
     return p;
   }
   // Fill the chip: aim for >= 2048 workgroups, but keep >= 2048 columns per
@@ -516,8 +566,28 @@ GammaPlan gamma_plan(int64_t nr, int64_t nc, int b, int precision) {
   p.nsplit = (int)ns;
   p.cols_per_split = cps;
   p.partial_bytes = ns > 1 ? (size_t)ns * nr * b * sizeof(float) : 0;
+  p.ysplit_bytes = precision == KA_BF16X3 ? (size_t)((nc + kCT - 1) / kCT) * kCT * b * 4 : 0;
+  p.work_bytes = (p.partial_bytes + 255) / 256 * 256 + p.ysplit_bytes;
   p.xcd_splits = ns_grid >= kXcds ? (int)ns_grid : 0;
   return p;
+}
+
+uint4* gamma_ysplit_ptr(float* work, const GammaPlan& p) {
+  if (p.ysplit_bytes == 0 || !work) return nullptr;
+  return reinterpret_cast<uint4*>(reinterpret_cast<char*>(work) + (p.partial_bytes + 255) / 256 * 256);
+}
+
+static hipError_t launch_split(const float* Y, int64_t nc, uint4* ys, int b, hipStream_t s) {
+  const int64_t n = nc <= 0 ? 0 : (b == 16 ? split_entries<16>(nc) : b == 32 ? split_entries<32>(nc) : split_entries<64>(nc));
+  if (n == 0) return hipSuccess;
+  const unsigned grid = (unsigned)std::min<int64_t>((n + 255) / 256, 8192);
+  switch (b) {
+    case 16: hipLaunchKernelGGL(gamma_split_kernel<16>, dim3(grid), dim3(256), 0, s, Y, nc, ys); break;
+    case 32: hipLaunchKernelGGL(gamma_split_kernel<32>, dim3(grid), dim3(256), 0, s, Y, nc, ys); break;
+    case 64: hipLaunchKernelGGL(gamma_split_kernel<64>, dim3(grid), dim3(256), 0, s, Y, nc, ys); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
 }
 
 template <int KERNEL>
@@ -550,6 +620,12 @@ hipError_t launch_gamma(GammaLaunch a, int kernel, int b, int precision, hipStre
   a.xcd_splits = p.xcd_splits;
   if (a.nc <= 0) {
     return fill_zero_f32(a.Z, a.nr * b, s);
+  }
+  if (precision == KA_BF16X3) {
+    a.ys = gamma_ysplit_ptr(a.partial, p);
+    if (!a.ys) return hipErrorInvalidValue;
+    const hipError_t e = launch_split(a.Y, a.nc, a.ys, b, s);
+    if (e != hipSuccess) return e;
   }
   const dim3 grid = p.xcd_splits > 0 ? dim3((unsigned)(p.row_blocks * p.xcd_splits), 1u)
                                      : dim3((unsigned)p.row_blocks, (unsigned)p.nsplit);
@@ -585,6 +661,18 @@ hipError_t launch_gamma_batch(const GammaJob* jobs_dev, const GammaItem* items_d
       case 64: hipLaunchKernelGGL((gamma_batch_kernel<64, 2, KA_BF16X3>), dim3(grid), dim3(kThreads), 0, s, jobs_dev, items_dev, n_items); break;
       default: return hipErrorInvalidValue;
     }
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_gamma_split_jobs(const GammaJob* jobs_dev, int n_jobs, int b, hipStream_t s) {
+  if (n_jobs <= 0) return hipSuccess;
+  const dim3 grid(256, (unsigned)n_jobs);
+  switch (b) {
+    case 16: hipLaunchKernelGGL(gamma_split_jobs_kernel<16>, grid, dim3(256), 0, s, jobs_dev); break;
+    case 32: hipLaunchKernelGGL(gamma_split_jobs_kernel<32>, grid, dim3(256), 0, s, jobs_dev); break;
+    case 64: hipLaunchKernelGGL(gamma_split_jobs_kernel<64>, grid, dim3(256), 0, s, jobs_dev); break;
+    default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }

@@ -22,6 +22,7 @@ struct GammaLaunch {
   const float* Y;         // nc x b, b contiguous
   float* Z;               // nr x b, b contiguous
   float* partial;         // split-K scratch, nsplit * nr * b floats
+  uint4* ys;              // BF16X3: Y split into hi/lo BF16 MFMA fragments (gamma_split_y); filled by launch_gamma
   float coord_scale;      // applied to every coordinate on load
   float out_scale;        // sigma^2
   int nsplit;             // filled by launch_gamma
@@ -36,10 +37,14 @@ struct GammaPlan {
   int nsplit;
   int64_t cols_per_split;
   size_t partial_bytes;
+  size_t ysplit_bytes;    // BF16X3: pre-split Y, ceil(nc / 64) * 64 * b * 4 bytes; 0 for FP32
+  size_t work_bytes;      // scratch of one product: partials (256-byte aligned), then the pre-split Y
   int xcd_splits;         // 0, or the split count rounded up to the XCD count (grouped grid)
 };
 
 GammaPlan gamma_plan(int64_t nr, int64_t nc, int b, int precision);
+// Start of the pre-split Y inside a product's scratch `work` (BF16X3), or nullptr.
+uint4* gamma_ysplit_ptr(float* work, const GammaPlan& p);
 
 // One kernel product of a batched launch, and one work item of it.
 struct GammaJob {
@@ -55,6 +60,8 @@ int gamma_rows_per_block(int b);
 hipError_t launch_gamma_batch(const GammaJob* jobs_dev, const GammaItem* items_dev, int n_items, int b,
                               int precision, hipStream_t s);
 hipError_t launch_gamma_reduce(const float* partial, int nsplit, int64_t n, float* Z, hipStream_t s);
+// BF16X3 pre-pass of a batched launch: splits Y of jobs [0, n_jobs) into their ys arrays.
+hipError_t launch_gamma_split_jobs(const GammaJob* jobs_dev, int n_jobs, int b, hipStream_t s);
 hipError_t launch_gamma(GammaLaunch a, int kernel, int b, int precision, hipStream_t s);
 float kernel_coord_scale(int kernel, double ell);
 

@@ -168,6 +168,8 @@ int launch_batch(Server* S, std::vector<PendingGamma*>& batch, hipEvent_t done_e
   for (auto& L : launches) {
     const int b = std::get<0>(L), prec = std::get<1>(L);
     const size_t j0 = std::get<2>(L), j1 = std::get<3>(L), i0 = std::get<4>(L), i1 = std::get<5>(L);
+    if (prec == KA_BF16X3)
+      HIP_TRY(launch_gamma_split_jobs(S->jobs_dev[slot] + j0, (int)(j1 - j0), b, S->stream));
     HIP_TRY(launch_gamma_batch(S->jobs_dev[slot] + j0, S->items_dev[slot] + i0, (int)(i1 - i0), b, prec, S->stream));
     for (size_t q = j0; q < j1; ++q) {
       const GammaLaunch& a = jobs[q].a;

@@ -42,6 +42,12 @@ def test_host_side_validation_and_footprint():
     # sizes: C^0 interpolation space for the exponential kernel
     assert K.ka_gamma_workspace(200, 20000, 16, K.KA_FP32) > 0
     assert K.ka_gamma_workspace(1000000, 10000, 16, K.KA_FP32) == 0
+    # split BF16: the partial sums (256-byte aligned), then Y split into hi/lo
+    # BF16 over whole 64-column tiles (4 bytes per Y entry)
+    for nr, nc, b in [(1000000, 10000, 16), (200, 20000, 16), (5000, 777, 64), (12167, 512000, 32)]:
+        part = K.ka_gamma_workspace(nr, nc, b, K.KA_FP32)
+        ysplit = -(-nc // 64) * 64 * b * 4
+        assert K.ka_gamma_workspace(nr, nc, b, K.KA_BF16X3) == -(-part // 256) * 256 + ysplit
 
 
 def test_product_path_has_no_oracle_dependency():
