@@ -189,14 +189,27 @@ __device__ __forceinline__ void gamma_f32_tile(const GammaLaunch& a, int64_t rbl
     fetch(ct + kCT);
     // Fully unrolled: with a rolled loop the register allocator rotates the
     // accumulators through AGPR copies every step (measured at b = 64: 40
-    // extra VALU instructions per 16 MFMAs).
+    // extra VALU instructions per 16 MFMAs).  The LDS operands of step k + 1
+    // are read before step k is computed, and a scheduling barrier keeps the
+    // compiler from sinking those reads back to their use, so every LDS read
+    // has one whole step of work to complete in (measured: +4-5% at b = 16).
+    float4 pc = s_x[buf][lane >> 4];
+    float yc[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) yc[t] = s_y[buf][(lane >> 4) * YS + 16 * t + (lane & 15)];
 #pragma unroll
     for (int k = 0; k < kCT; k += 4) {
-      const int c = k + (lane >> 4);
-      const float4 p = s_x[buf][c];
+      const float4 p = pc;
       float yv[NT];
 #pragma unroll
-      for (int t = 0; t < NT; ++t) yv[t] = s_y[buf][c * YS + 16 * t + (lane & 15)];
+      for (int t = 0; t < NT; ++t) yv[t] = yc[t];
+      if (k + 4 < kCT) {
+        const int cn = k + 4 + (lane >> 4);
+        pc = s_x[buf][cn];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) yc[t] = s_y[buf][cn * YS + 16 * t + (lane & 15)];
+      }
+      __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
       for (int rb = 0; rb < RB; ++rb) {
         const float g = __builtin_amdgcn_exp2f(-pair_exponent<KERNEL>(rx[rb] - p.x, ry[rb] - p.y, rz[rb] - p.z));
