@@ -55,7 +55,7 @@ def peak_pairs(kernel):
 # WRITE_SIZE (profiles/gamma_f32_cube_p3_20_traffic.md), scaled by what the
 # same counters read for a plain 256 MiB device copy (FETCH x 2.0, WRITE x 1.0).
 # Valid only for the kernel source it was measured on.
-TRAFFIC = {"gamma_src_sha256_16": "ae0275a3b4f573f6", "fetch_bytes": 196.9e6, "write_bytes": 31.9e6,
+TRAFFIC = {"gamma_src_sha256_16": "d40dc5bffd600dc6", "fetch_bytes": 193.6e6, "write_bytes": 31.9e6,
            "algorithmic_bytes": 33.2e6}
 
 
@@ -334,6 +334,76 @@ def compare_methods(reps=3):
     return out
 
 
+def measure(K, torch, precision, steps, warmup, tol):
+    """Solve the workload's problems `warmup` + `steps` times in one precision;
+    returns rates, latencies, accuracy and the kernel product's roofline."""
+    probs = workload(precision=precision)
+    handles = []
+    for i, p in enumerate(probs):
+        h = K.Problem(K.desc_from_problem(p, seed=1000 + i))
+        handles.append(h)
+
+    def one_step(record):
+        out = []
+        for p, h in zip(probs, handles):
+            t0 = time.perf_counter()
+            rc, lam, info = K.ka_eigs(h.h, p["M"], tol=tol, maxit=60,
+                                      complex_values=(p["method"] == "collocation"))
+            dt = time.perf_counter() - t0
+            if rc != 0:
+                raise RuntimeError(f"ka_eigs returned {rc} for {p['name']}: {info}")
+            out.append((lam, info, dt))
+        return out
+
+    for _ in range(warmup):
+        one_step(False)
+    for h in handles:
+        K.ka_profile_reset(h.h)
+        K.ka_profile_enable(h.h, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    results = []
+    for _ in range(steps):
+        results.append(one_step(True))
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    prof = [K.ka_profile_read(h.h) for h in handles]
+    for h in handles:
+        K.ka_profile_enable(h.h, False)
+
+    pairs = sum(info["pairs"] for step in results for (_, info, _) in step)
+    lat = np.array([dt for step in results for (_, _, dt) in step]) * 1e3
+    nsolves = len(lat)
+    # eigenvalue accuracy of the last step against the stored FP64 reference spectra
+    eig = {}
+    worst = 0.0
+    for p, (lam, info, _) in zip(probs, results[-1]):
+        ref = reference_spectrum(p)
+        lr = lam[0::2] if p["method"] == "collocation" else lam
+        e = floored_rel_errors(ref, lr)
+        worst = max(worst, float(e.max()))
+        eig[f"{p['method']}-{p['kernel']}"] = {"max_floored_rel_err": float(e.max()),
+                                               "max_raw_rel_err": float(floored_rel_errors(ref, lr, 0.0).max()),
+                                               "matvecs": info["matvecs"], "cycles": info["iterations"]}
+    # roofline of the fused kernel product
+    gl_pairs = sum(pp for (_, _, pp) in prof)
+    gl_ms = sum(ms for (_, ms, _) in prof)
+    launches = sum(n for (n, _, _) in prof)
+    achieved = gl_pairs / (gl_ms / 1e3)
+    peak = gl_pairs / sum(pp / peak_pairs(p["kernel"]) for p, (_, _, pp) in zip(probs, prof))
+    speak = gl_pairs / sum(pp / serial_peak_pairs(p["kernel"], p["block"]) for p, (_, _, pp) in zip(probs, prof))
+    out = {"probs": probs, "pairs": pairs, "elapsed": elapsed, "lat": lat, "nsolves": nsolves, "eig": eig,
+           "worst": worst, "achieved": achieved, "peak": peak, "speak": speak, "launches": launches,
+           "gl_ms": gl_ms}
+    for h in handles:
+        h.close()
+    return out
+
+
+def latency(lat):
+    return {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)), "max": float(lat.max())}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -342,6 +412,8 @@ def main():
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16x3"])
     ap.add_argument("--tol", type=float, default=1e-5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-split-bf16", action="store_true",
+                    help="skip the second pass of the workload in split-BF16 precision")
     ap.add_argument("--serve", action="store_true", help="run the serving benchmark instead")
     ap.add_argument("--requests", type=int, default=512)
     ap.add_argument("--rho", default="0.5,1.5")
@@ -382,69 +454,16 @@ def main():
         print(json.dumps({"metric": "K-L solves/s + p99 latency (serving)", "n_gpus": 1, "data": "synthetic",
                           "dtype": "f32", **res}), flush=True)
         return
-    probs = workload(precision=args.precision)
-    handles = []
-    for i, p in enumerate(probs):
-        h = K.Problem(K.desc_from_problem(p, seed=1000 + i))
-        handles.append(h)
-
-    def one_step(record):
-        out = []
-        for p, h in zip(probs, handles):
-            t0 = time.perf_counter()
-            rc, lam, info = K.ka_eigs(h.h, p["M"], tol=args.tol, maxit=60,
-                                      complex_values=(p["method"] == "collocation"))
-            dt = time.perf_counter() - t0
-            if rc != 0:
-                raise RuntimeError(f"ka_eigs returned {rc} for {p['name']}: {info}")
-            out.append((lam, info, dt))
-        return out
-
-    for _ in range(args.warmup):
-        one_step(False)
-    for h in handles:
-        K.ka_profile_reset(h.h)
-        K.ka_profile_enable(h.h, True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    results = []
-    for _ in range(args.steps):
-        results.append(one_step(True))
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    prof = [K.ka_profile_read(h.h) for h in handles]
-    for h in handles:
-        K.ka_profile_enable(h.h, False)
-
-    pairs = sum(info["pairs"] for step in results for (_, info, _) in step)
-    lat = np.array([dt for step in results for (_, _, dt) in step]) * 1e3
-    nsolves = len(lat)
-    # eigenvalue accuracy of the last step against the stored FP64 reference spectra
-    eig = {}
-    worst = 0.0
-    for p, (lam, info, _) in zip(probs, results[-1]):
-        ref = reference_spectrum(p)
-        lr = lam[0::2] if p["method"] == "collocation" else lam
-        e = floored_rel_errors(ref, lr)
-        worst = max(worst, float(e.max()))
-        eig[f"{p['method']}-{p['kernel']}"] = {"max_floored_rel_err": float(e.max()),
-                                               "max_raw_rel_err": float(floored_rel_errors(ref, lr, 0.0).max()),
-                                               "matvecs": info["matvecs"], "cycles": info["iterations"]}
-    # roofline of the fused kernel product
-    gl_pairs = sum(pp for (_, _, pp) in prof)
-    gl_ms = sum(ms for (_, ms, _) in prof)
-    launches = sum(n for (n, _, _) in prof)
-    achieved = gl_pairs / (gl_ms / 1e3)
-    peak = gl_pairs / sum(pp / peak_pairs(p["kernel"]) for p, (_, _, pp) in zip(probs, prof))
-    speak = gl_pairs / sum(pp / serial_peak_pairs(p["kernel"], p["block"]) for p, (_, _, pp) in zip(probs, prof))
+    res = measure(K, torch, args.precision, args.steps, args.warmup, args.tol)
+    probs = res["probs"]
     line = {
         "metric": METRIC,
-        "value": pairs / elapsed,
+        "value": res["pairs"] / res["elapsed"],
         "unit": "pairs/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": elapsed / args.steps * 1e3,
+        "ms_per_step": res["elapsed"] / args.steps * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -453,25 +472,35 @@ def main():
         "config": {"workload": "unit cube p=3 20^3 (N=12167), M=50, b=16: Galerkin-IBQ + collocation x "
                                "Gaussian(l=0.5) + exponential-L1(l=1), one full K-L solve each",
                    "solves_per_step": len(probs), "tol": args.tol, "precision": args.precision},
-        "solves_per_s": nsolves / elapsed,
-        "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
-                       "max": float(lat.max())},
-        "eig_err": {"max_floored_rel_err": worst, "per_problem": eig},
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "pairs/s",
-                     "frac": achieved / peak,
+        "solves_per_s": res["nsolves"] / res["elapsed"],
+        "latency_ms": latency(res["lat"]),
+        "eig_err": {"max_floored_rel_err": res["worst"], "per_problem": res["eig"]},
+        "roofline": {"bound": "alu", "achieved": res["achieved"], "peak": res["peak"], "unit": "pairs/s",
+                     "frac": res["achieved"] / res["peak"],
                      "traffic": measured_traffic() if args.precision == "fp32" else None,
                      "traffic_unit": "HBM bytes per launch",
                      "algorithmic_bytes_per_launch": TRAFFIC["algorithmic_bytes"],
-                     "serial_valu_mfma_peak": speak if args.precision == "fp32" else None,
-                     "frac_of_serial_peak": achieved / speak if args.precision == "fp32" else None,
+                     "serial_valu_mfma_peak": res["speak"] if args.precision == "fp32" else None,
+                     "frac_of_serial_peak": res["achieved"] / res["speak"] if args.precision == "fp32" else None,
                      "kernel": "gamma_f32_kernel" if args.precision == "fp32" else "gamma_bf16x3_kernel",
-                     "launches": launches, "kernel_ms": gl_ms, "kernel_share_of_step": gl_ms / 1e3 / elapsed},
+                     "launches": res["launches"], "kernel_ms": res["gl_ms"],
+                     "kernel_share_of_step": res["gl_ms"] / 1e3 / res["elapsed"]},
     }
+    if args.precision == "fp32" and not args.no_split_bf16:
+        # the same workload with the contraction in split hi/lo BF16 (its bar: 1e-5)
+        nb = max(1, min(args.steps, 3))
+        rb = measure(K, torch, "bf16x3", nb, 1, args.tol)
+        line["split_bf16"] = {
+            "value": rb["pairs"] / rb["elapsed"], "unit": "pairs/s", "steps": nb,
+            "solves_per_s": rb["nsolves"] / rb["elapsed"], "latency_ms": latency(rb["lat"]),
+            "eig_err": {"max_floored_rel_err": rb["worst"],
+                        "per_problem": {k: v["max_floored_rel_err"] for k, v in rb["eig"].items()}},
+            "roofline": {"bound": "alu", "achieved": rb["achieved"], "peak": rb["peak"], "unit": "pairs/s",
+                         "frac": rb["achieved"] / rb["peak"], "kernel": "gamma_bf16x3_kernel",
+                         "launches": rb["launches"], "kernel_ms": rb["gl_ms"]}}
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(probs)
     print(json.dumps(line), flush=True)
-    for h in handles:
-        h.close()
 
 
 if __name__ == "__main__":
