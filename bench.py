@@ -55,7 +55,7 @@ def peak_pairs(kernel):
 # WRITE_SIZE (profiles/gamma_f32_cube_p3_20_traffic.md), scaled by what the
 # same counters read for a plain 256 MiB device copy (FETCH x 2.0, WRITE x 1.0).
 # Valid only for the kernel source it was measured on.
-TRAFFIC = {"gamma_src_sha256_16": "d40dc5bffd600dc6", "fetch_bytes": 193.6e6, "write_bytes": 31.9e6,
+TRAFFIC = {"gamma_src_sha256_16": "81efab07a96bcf05", "fetch_bytes": 37.5e6, "write_bytes": 52.4e6,
            "algorithmic_bytes": 33.2e6}
 
 

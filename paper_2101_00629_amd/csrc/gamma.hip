@@ -49,6 +49,7 @@ constexpr int kCT = 64;         // columns per LDS tile
 // of 200 eigenvalues (1.4% of the largest), 2-tile chains 3.8e-7, at the same
 // speed within 1%.
 constexpr int kFlushTiles = 2;
+constexpr double kL2FitBytes = 3.0 * (1 << 20);   // column data per split that an XCD's L2 keeps
 
 
 // (row block, split) of this workgroup.  Grouped grid (xcd_splits > 0): a 1-D
@@ -566,6 +567,18 @@ GammaPlan gamma_plan(int64_t nr, int64_t nc, int b, int precision) {
   if (ns > max_by_cols) ns = max_by_cols;
   if (ns > 64) ns = 64;
   if (ns < 1) ns = 1;
+  // L2 fit.  With fewer than 8 splits every XCD streams every split's column
+  // range, and a range larger than an XCD's L2 (4 MB) is then re-read from
+  // HBM by each round of workgroups.  Eight or more XCD-grouped splits of at
+  // most kL2FitBytes each are fetched about once, at the price of more
+  // partial sums; taken when those cost fewer bytes than one re-read of the
+  // columns per XCD.
+  const double col_bytes = 16.0 + 4.0 * b;   // a point (float4) and its row of Y
+  if (ns < kXcds && (double)nc * col_bytes / ns > kL2FitBytes) {
+    int64_t ns2 = kXcds;
+    while ((double)((nc + ns2 - 1) / ns2) * col_bytes > kL2FitBytes && ns2 + kXcds <= 64) ns2 += kXcds;
+    if (ns2 <= max_by_cols && (double)ns2 * nr * b * 4 < (double)nc * col_bytes * kXcds) ns = ns2;
+  }
   // With at least one split per XCD, round the split count up to a multiple
   // of the XCD count: the grouped grid then keeps every split on one XCD, so
   // its column range is fetched from HBM into that XCD's L2 once.
