@@ -22,6 +22,13 @@ function D(xi), a quadratic; its control weights w in the degree-p space are
 obtained by interpolation at the Greville points (exact, as D lies in the
 space), and R_j = w_j B_j / (sum_l w_l B_l).  Because the weights are a
 tensor product, Z = Z_3 x Z_2 x Z_1 (remark in Sec. 3.3).
+
+General NURBS volume (domain.rational): the weights need not be a tensor
+product.  The trial space is spanned by B_j / W (W the geometry's weight
+function, B_j the tensor B-splines), the span of the NURBS functions
+w_j B_j / W.  The oracle assembles R_q and Z point by point and, as the paper
+does when Z has no Kronecker structure, factors the full Z with a complete-
+pivoting LU (P Z Q = L U) to apply Z^-1.
 """
 import numpy as np
 import scipy.linalg as sla
@@ -54,17 +61,22 @@ class Collocation:
         self.nel = tuple(int(e) for e in nel)
         self.kernel, self.ell, self.sigma = kernel, ell, sigma
         self.nq = int(nq or (self.p + 1))
+        self.rational = bool(getattr(self.domain, "rational", False))
         self.gk, self.Rqk, self.Zk, self.xqk, self.wqk = [], [], [], [], []
         for k, e in enumerate(self.nel):
             t = splines.open_knots(self.p, e, 1)
             g = splines.greville(t, self.p)
             xq, wq = splines.element_quadrature(t, self.nq)
-            wf = (lambda s, k=k: self.domain.weight1d(k, s))
             self.gk.append(g)
             self.xqk.append(xq)
             self.wqk.append(wq)
-            self.Rqk.append(nurbs_basis_1d(t, self.p, wf, xq))
-            self.Zk.append(nurbs_basis_1d(t, self.p, wf, g))
+            if self.rational:
+                self.Rqk.append(splines.basis_matrix(t, self.p, xq))
+                self.Zk.append(splines.basis_matrix(t, self.p, g))
+            else:
+                wf = (lambda s, k=k: self.domain.weight1d(k, s))
+                self.Rqk.append(nurbs_basis_1d(t, self.p, wf, xq))
+                self.Zk.append(nurbs_basis_1d(t, self.p, wf, g))
         self.n = tuple(len(g) for g in self.gk)
         self.nqk = tuple(len(x) for x in self.xqk)
         self.N = int(np.prod(self.n))
@@ -78,7 +90,12 @@ class Collocation:
         w3, w2, w1 = np.meshgrid(self.wqk[2], self.wqk[1], self.wqk[0], indexing="ij")
         self.W = (w1 * w2 * w3).ravel()
         self.J = np.abs(self.domain.detJ(self.qhat))
-        self._zlu = [_LUSolve(Z) for Z in self.Zk]
+        if self.rational:
+            self.Wq = self.domain.weight(self.qhat)       # B_j / W at the quadrature points
+            self.Wg = self.domain.weight(self.ghat)       # and at the collocation points
+            self._zfull = None
+        else:
+            self._zlu = [_LUSolve(Z) for Z in self.Zk]
 
     def gamma_matrix(self, rows=None):
         Xr = self.Xc if rows is None else self.Xc[rows]
@@ -95,10 +112,12 @@ class Collocation:
 
     # -- dense (tiny meshes) ---------------------------------------------
     def Rq_dense(self):
-        return kron.kron3(*self.Rqk)
+        R = kron.kron3(*self.Rqk)
+        return R / self.Wq[:, None] if self.rational else R
 
     def Z_dense(self):
-        return kron.kron3(*self.Zk)
+        Z = kron.kron3(*self.Zk)
+        return Z / self.Wg[:, None] if self.rational else Z
 
     def A_dense(self):
         return self.gamma_matrix() @ ((self.J * self.W)[:, None] * self.Rq_dense())
@@ -120,12 +139,21 @@ class Collocation:
         if vec:
             V = V[:, None]
         y = kron.kron_apply(self.Rqk, V)                       # 1
+        if self.rational:
+            y = y / self.Wq[:, None]
         y = (self.J * self.W)[:, None] * y                      # 2
         z = (gamma_apply or self.gamma_apply)(y)                # 3
         return z[:, 0] if vec else z
 
     def solve_Z(self, X):
-        return kron.kron_solve(self._zlu, np.asarray(X, dtype=np.float64))
+        X = np.asarray(X, dtype=np.float64)
+        if self.rational:
+            if self._zfull is None:
+                self._zfull = _complete_pivot_lu(self.Z_dense())
+            P, L, U, Q = self._zfull
+            T = sla.solve_triangular(L, P @ X, lower=True, unit_diagonal=True)
+            return Q @ sla.solve_triangular(U, T, lower=False)
+        return kron.kron_solve(self._zlu, X)
 
     def apply_Aprime(self, V, gamma_apply=None):
         return self.solve_Z(self.apply_A(V, gamma_apply))       # 4

@@ -1,7 +1,7 @@
 """Geometry maps F : [0,1]^3 -> D and |det DF| (paper Sec. 3.1, the map F
 from the reference to the physical domain; Sec. 3.2, NURBS geometry).
 
-Two domains are used by the workloads:
+Three kinds of domain are used by the workloads:
 
 * Box [lo, hi]: F(xh) = lo + (hi - lo) * xh, |det DF| = prod(hi - lo).
 * Quarter annulus r in [r0, r1], angle in [0, pi/2], extruded to `height`:
@@ -9,6 +9,7 @@ Two domains are used by the workloads:
   exact rational quadratic quarter circle with control points (1,0), (1,1),
   (0,1) and weights 1, 1/sqrt(2), 1.  Since C is a unit vector and C' is
   orthogonal to it, |det DF| = (r1 - r0) * r(eta) * |C'(xi)| * height.
+* A general single-patch NURBS volume, given by its control net (NurbsVolume).
 """
 import numpy as np
 
@@ -95,9 +96,84 @@ class QuarterAnnulus:
         return np.ones(np.shape(t))
 
 
+class NurbsVolume:
+    """Single-patch NURBS volume (paper Sec. 3.2: NURBS geometry):
+    F(xh) = sum_j w_j P_j N_j(xh) / W(xh),  W(xh) = sum_j w_j N_j(xh),
+    N_j the tensor-product B-splines of the given degrees and knot vectors.
+    ctrl has shape (n3, n2, n1, 4) with rows (x, y, z, w).
+
+    The collocation trial space on such a volume is spanned by B_j / W
+    (B_j the analysis B-splines): the same space as the NURBS functions
+    w_j B_j / W, so `rational` tells the collocation oracle to use it."""
+    kind = "nurbs"
+    rational = True
+
+    def __init__(self, degree, knots, ctrl):
+        self.p = tuple(int(d) for d in degree)
+        self.t = [np.asarray(k, dtype=np.float64) for k in knots]
+        ctrl = np.asarray(ctrl, dtype=np.float64)
+        self.ctrl = ctrl
+        # homogeneous control points (w x, w y, w z, w)
+        self.H = np.concatenate([ctrl[..., :3] * ctrl[..., 3:4], ctrl[..., 3:4]], axis=-1)
+
+    def _sums(self, xh):
+        """Homogeneous sum and its three parametric derivatives at points xh (m, 3)."""
+        from . import splines
+        B = [splines.basis_matrix(self.t[k], self.p[k], xh[:, k]) for k in range(3)]
+        D = [splines.basis_derivative_matrix(self.t[k], self.p[k], xh[:, k]) for k in range(3)]
+        S = np.einsum("ma,mb,mc,cbad->md", B[0], B[1], B[2], self.H)
+        S1 = np.einsum("ma,mb,mc,cbad->md", D[0], B[1], B[2], self.H)
+        S2 = np.einsum("ma,mb,mc,cbad->md", B[0], D[1], B[2], self.H)
+        S3 = np.einsum("ma,mb,mc,cbad->md", B[0], B[1], D[2], self.H)
+        return S, (S1, S2, S3)
+
+    def _eval(self, xh, chunk=4096):
+        xh = np.asarray(xh, dtype=np.float64)
+        shape = xh.shape[:-1]
+        flat = xh.reshape(-1, 3)
+        X = np.empty((len(flat), 3))
+        J = np.empty(len(flat))
+        W = np.empty(len(flat))
+        for s0 in range(0, len(flat), chunk):
+            S, dS = self._sums(flat[s0:s0 + chunk])
+            w = S[:, 3]
+            x = S[:, :3] / w[:, None]
+            # dF[:, c, k] = (dS_k[c] - x_c dS_k[w]) / w
+            dF = np.stack([(d[:, :3] - x * d[:, 3:4]) / w[:, None] for d in dS], axis=-1)
+            X[s0:s0 + chunk] = x
+            J[s0:s0 + chunk] = np.linalg.det(dF)
+            W[s0:s0 + chunk] = w
+        return X.reshape(shape + (3,)), J.reshape(shape), W.reshape(shape)
+
+    def map(self, xh):
+        return self._eval(xh)[0]
+
+    def detJ(self, xh):
+        return np.abs(self._eval(xh)[1])
+
+    def weight(self, xh):
+        """The weight function W at parametric points."""
+        return self._eval(xh)[2]
+
+    def volume(self, q=None):
+        """Integral of |det DF| by Gauss-Legendre on every knot span (q per span and direction)."""
+        from . import splines
+        rules = []
+        for k in range(3):
+            x, w = splines.element_quadrature(self.t[k], q or (2 * self.p[k] + 6))
+            rules.append((x, w))
+        g3, g2, g1 = np.meshgrid(rules[2][0], rules[1][0], rules[0][0], indexing="ij")
+        w3, w2, w1 = np.meshgrid(rules[2][1], rules[1][1], rules[0][1], indexing="ij")
+        xh = np.stack([g1.ravel(), g2.ravel(), g3.ravel()], axis=-1)
+        return float(np.sum(self.detJ(xh) * (w1 * w2 * w3).ravel()))
+
+
 def make_domain(name, **kw):
     if name in ("cube", "box"):
         return Box(kw.get("lo", (0.0, 0.0, 0.0)), kw.get("hi", (1.0, 1.0, 1.0)))
     if name in ("quarter_annulus", "annulus"):
         return QuarterAnnulus(kw.get("r0", 1.0), kw.get("r1", 2.0), kw.get("height", 1.0))
+    if name == "nurbs":
+        n = kw["nurbs"]
+        return NurbsVolume(n["degree"], n["knots"], n["ctrl"])
     raise ValueError(name)

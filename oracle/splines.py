@@ -55,6 +55,25 @@ def basis_matrix(knots, p, x):
     return B
 
 
+def basis_derivative_matrix(knots, p, x):
+    """First derivatives of all degree-p B-splines at x, shape (len(x), n):
+    B'_{i,p} = p B_{i,p-1} / (t_{i+p} - t_i) - p B_{i+1,p-1} / (t_{i+p+1} - t_{i+1})
+    (terms with a zero denominator dropped)."""
+    t = np.asarray(knots, dtype=np.float64)
+    x = np.atleast_1d(np.asarray(x, dtype=np.float64))
+    n = num_basis(t, p)
+    Bl = basis_matrix(t, p - 1, x)          # degree p-1: n + 1 functions
+    D = np.zeros((len(x), n))
+    for i in range(n):
+        d1 = t[i + p] - t[i]
+        d2 = t[i + p + 1] - t[i + 1]
+        if d1 > 0:
+            D[:, i] += p * Bl[:, i] / d1
+        if d2 > 0:
+            D[:, i] -= p * Bl[:, i + 1] / d2
+    return D
+
+
 def greville(knots, p):
     """Greville abscissae gamma_i = (t_{i+1} + ... + t_{i+p}) / p."""
     t = np.asarray(knots, dtype=np.float64)

@@ -53,6 +53,41 @@ def cube_p2_64(method=GALERKIN, precision="fp32"):
                    name=f"cube_p2_64^3_gaussian_l0.2_{method}")
 
 
+def nurbs_annulus_net(r0=1.0, r1=2.0, height=1.0):
+    """Control net of the quarter annulus as a general NURBS volume: the
+    rational quadratic quarter circle (control points (1,0), (1,1), (0,1),
+    weights 1, 1/sqrt(2), 1) along xi, linear in the radius (eta) and in z
+    (zeta).  Same map as the closed-form quarter annulus."""
+    w = (1.0, 1.0 / math.sqrt(2.0), 1.0)
+    cx, cy = (1.0, 1.0, 0.0), (0.0, 1.0, 1.0)
+    ctrl = np.zeros((2, 2, 3, 4))
+    for j3 in range(2):
+        for j2, r in enumerate((r0, r1)):
+            for j1 in range(3):
+                ctrl[j3, j2, j1] = (r * cx[j1], r * cy[j1], height * j3, w[j1])
+    return dict(degree=(2, 1, 1), knots=([0, 0, 0, 1, 1, 1], [0, 0, 1, 1], [0, 0, 1, 1]), ctrl=ctrl)
+
+
+def nurbs_blob_net(seed=0, n=(4, 4, 4), degree=(2, 2, 2), wiggle=0.06, wrange=(0.6, 1.6)):
+    """Seeded curved volume near the unit cube: open uniform knots with
+    n[k] - degree[k] spans, control points at the knot averages (Greville
+    abscissae) each moved by up to `wiggle` per coordinate (faces included),
+    weights drawn independently per control point in `wrange` (so they are
+    not a tensor product)."""
+    rng = np.random.default_rng(seed)
+    knots, grev = [], []
+    for k in range(3):
+        p, m = int(degree[k]), int(n[k])
+        nel = m - p
+        t = [0.0] * (p + 1) + [e / nel for e in range(1, nel)] + [1.0] * (p + 1)
+        knots.append(t)
+        grev.append([sum(t[i + 1:i + p + 1]) / p for i in range(m)])
+    g3, g2, g1 = np.meshgrid(grev[2], grev[1], grev[0], indexing="ij")
+    xyz = np.stack([g1, g2, g3], axis=-1) + rng.uniform(-wiggle, wiggle, g1.shape + (3,))
+    w = rng.uniform(wrange[0], wrange[1], g1.shape + (1,))
+    return dict(degree=tuple(int(d) for d in degree), knots=tuple(knots), ctrl=np.concatenate([xyz, w], axis=-1))
+
+
 def normal_block(seed, n, b, dtype=np.float64):
     """Seeded N(0, 1) block of shape (n, b)."""
     return np.random.default_rng(seed).standard_normal((n, b)).astype(dtype)
