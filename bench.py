@@ -400,6 +400,64 @@ def measure(K, torch, precision, steps, warmup, tol):
     return out
 
 
+def nurbs_benchmark(reps=2):
+    """General NURBS volumes at workload size: the quarter annulus given as a
+    control net against the closed-form annulus (p = 4, 32 x 32 x 16, the
+    annulus workload's mesh), and a curved volume with per-point weights
+    (p = 3, 20^3 elements).  Per problem: set-up time (ka_setup, host geometry
+    evaluation included), median solve time of ka_eigs, the kernel product's
+    rate and roofline fraction (HIP events), and for the annulus the largest
+    floored eigenvalue difference between the two descriptions."""
+    import torch
+    import paper_2101_00629_amd as K
+    from workloads import nurbs_annulus_net, nurbs_blob_net
+
+    blob = nurbs_blob_net(11, n=(6, 6, 6), degree=(3, 3, 3), wiggle=0.04)
+    cases = []
+    for method, M, b in (("collocation", 100, 32), ("galerkin", 100, 32)):
+        base = dict(method=method, p=4, nel=(32, 32, 16), kernel="gaussian", ell=0.5, block=b)
+        cases.append((f"annulus p4 32x32x16 {method}, closed form", base | dict(domain="quarter_annulus"), M, "ann"))
+        cases.append((f"annulus p4 32x32x16 {method}, NURBS control net", base | dict(domain="nurbs", nurbs=nurbs_annulus_net()),
+                      M, "ann"))
+    for method in ("collocation", "galerkin"):
+        cases.append((f"curved volume (per-point weights) p3 20^3 {method}",
+                      dict(method=method, domain="nurbs", nurbs=blob, p=3, nel=(20, 20, 20), kernel="gaussian",
+                           ell=0.5, block=16), 50, None))
+    out, ann = [], {}
+    for name, kw, M, group in cases:
+        cplx = kw["method"] == "collocation"
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        prob = K.Problem(K.make_desc(seed=3, **kw))
+        torch.cuda.synchronize()
+        setup_s = time.perf_counter() - t0
+        times = []
+        for r in range(reps + 1):
+            if r == 1:
+                K.ka_profile_reset(prob.h)
+                K.ka_profile_enable(prob.h, True)
+            t0 = time.perf_counter()
+            rc, lam, info = K.ka_eigs(prob.h, M, tol=1e-5, maxit=80, complex_values=cplx)
+            if r >= 1:
+                times.append(time.perf_counter() - t0)
+        n_l, ms, pairs = K.ka_profile_read(prob.h)
+        prob.close()
+        lr = lam[0::2] if cplx else lam
+        rec = {"problem": name, "status": rc, "M": M, "block": kw["block"], "setup_s": setup_s,
+               "solve_s": float(np.median(times)), "matvecs": info["matvecs"],
+               "kernel_pairs_per_s": pairs / (ms / 1e3), "kernel_frac_valu": pairs / (ms / 1e3) / peak_pairs("gaussian")}
+        if group:
+            key = kw["method"]
+            if key in ann:
+                rec["max_floored_diff_vs_closed_form"] = float(floored_rel_errors(ann[key], lr).max())
+            else:
+                ann[key] = lr
+        out.append(rec)
+        print(f"[nurbs] {name}: setup {setup_s:.2f} s, solve {rec['solve_s'] * 1e3:.1f} ms, "
+              f"kernel {rec['kernel_pairs_per_s'] / 1e12:.2f} Tpairs/s", file=sys.stderr, flush=True)
+    return out
+
+
 def latency(lat):
     return {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)), "max": float(lat.max())}
 
@@ -422,6 +480,8 @@ def main():
                     help="the paper's method comparison (time vs eigenvalue error) on the cube instead")
     ap.add_argument("--kernel-rates", action="store_true",
                     help="time the raw kernel product at every workload shape instead")
+    ap.add_argument("--nurbs", action="store_true",
+                    help="general NURBS volumes at workload size (annulus as a control net, curved volume) instead")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first run one plain device copy of MIB MiB (reference for HBM traffic counters)")
     args = ap.parse_args()
@@ -448,6 +508,10 @@ def main():
         print(json.dumps({"metric": "fused kernel product pairs/s at the workload shapes", "n_gpus": 1,
                           "data": "synthetic (uniform points, N(0,1) blocks)", "unit": "pairs/s",
                           "rates": kernel_rates()}), flush=True)
+        return
+    if args.nurbs:
+        print(json.dumps({"metric": "K-L solves on general NURBS volumes", "n_gpus": 1, "data": "synthetic",
+                          "dtype": "f32", "runs": nurbs_benchmark()}), flush=True)
         return
     if args.serve:
         res = serve_benchmark(args.requests, [float(r) for r in args.rho.split(",")], args.pair_cap, args.tol)

@@ -47,7 +47,7 @@ enum ka_method { KA_GALERKIN_IBQ = 0,   /* Galerkin with interpolation-based qua
                  KA_GALERKIN_GAUSS = 2  /* standard Galerkin with Gauss quadrature (Sec. 3.1, the
                                            method IBQ replaces): same trial space and Z as IBQ,
                                            Gamma between all quadrature points                   */ };
-enum ka_domain { KA_BOX = 0, KA_QUARTER_ANNULUS = 1 };
+enum ka_domain { KA_BOX = 0, KA_QUARTER_ANNULUS = 1, KA_NURBS = 2 /* general single-patch NURBS volume */ };
 enum ka_kernel { KA_GAUSSIAN = 0, /* sigma^2 exp(-|x-y|_2^2 / ell^2) */
                  KA_EXP_L1 = 1    /* sigma^2 exp(-|x-y|_1 / ell)     */ };
 enum ka_precision { KA_FP32 = 0,  /* FP32 kernel tiles, FP32 MFMA contraction        */
@@ -66,7 +66,18 @@ enum ka_solve_op { KA_ZINV = 0,   /* X <- Z^-1 X                                
  *              and direction on both sides of Gamma: O((N_e nq^3)^2) pairs).
  * domain       KA_BOX: [lo, hi] (affine map); KA_QUARTER_ANNULUS: radii r0 < r1,
  *              quarter circle in the x-y plane extruded to `height` (exact
- *              rational quadratic NURBS map).
+ *              rational quadratic NURBS map); KA_NURBS: the single-patch NURBS
+ *              volume of geo_* below (Sec. 3.2), any positive weights.
+ *              The analysis spaces live on the parametric cube [0,1]^3 with
+ *              their own uniform knots (degree/nel); for the usual isogeometric
+ *              setting those knots refine the geometry's.
+ *              Collocation on KA_NURBS uses the rational trial space spanned by
+ *              B_j / W (W the geometry's weight function, B_j the degree/nel
+ *              B-splines): the span of the NURBS functions w_j B_j / W, so the
+ *              eigenvalues are those of the NURBS basis, and the eigenvectors
+ *              are coefficients of B_j / W.  Its collocation matrix is
+ *              diag(1/W(g)) (Z_3 x Z_2 x Z_1) with B-spline factors Z_k, so no
+ *              full LU is formed.
  * degree/nel   B-spline degree and element count per parametric direction
  *              (solution space with C^{p-1} continuity, open uniform knots).
  * interp_cont  Galerkin only: continuity of the interpolation space S~;
@@ -95,6 +106,18 @@ typedef struct ka_desc {
   int precision;
   int block;
   unsigned long long seed;
+  /* KA_NURBS only (ignored otherwise).  Host arrays, read during ka_setup,
+   * ka_footprint and ka_server_submit (which copies them); not kept.
+   * geo_degree[k] in 1..30 and geo_nctrl[k] >= geo_degree[k] + 1 control
+   * points per direction; geo_knots: the three knot vectors one after the
+   * other, geo_nctrl[k] + geo_degree[k] + 1 values each, non-decreasing and
+   * open on [0, 1]; geo_ctrl: geo_nctrl[0] * geo_nctrl[1] * geo_nctrl[2]
+   * control points as (x, y, z, weight), weight > 0, index j1 fastest.
+   * Invalid data: KA_ERR_ARG. */
+  int geo_degree[3];
+  int geo_nctrl[3];
+  const double* geo_knots;
+  const double* geo_ctrl;
 } ka_desc;
 
 /* eigensolver report */

@@ -23,14 +23,14 @@ KA_ERR_STATE = -5
 KA_NOT_CONVERGED = 1
 
 KA_GALERKIN_IBQ, KA_COLLOCATION, KA_GALERKIN_GAUSS = 0, 1, 2
-KA_BOX, KA_QUARTER_ANNULUS = 0, 1
+KA_BOX, KA_QUARTER_ANNULUS, KA_NURBS = 0, 1, 2
 KA_GAUSSIAN, KA_EXP_L1 = 0, 1
 KA_FP32, KA_BF16X3 = 0, 1
 KA_A, KA_APRIME = 0, 1
 KA_ZINV, KA_LINV, KA_LTINV = 0, 1, 2
 
 METHODS = {"galerkin": KA_GALERKIN_IBQ, "collocation": KA_COLLOCATION, "galerkin_gauss": KA_GALERKIN_GAUSS}
-DOMAINS = {"cube": KA_BOX, "box": KA_BOX, "quarter_annulus": KA_QUARTER_ANNULUS}
+DOMAINS = {"cube": KA_BOX, "box": KA_BOX, "quarter_annulus": KA_QUARTER_ANNULUS, "nurbs": KA_NURBS}
 KERNELS = {"gaussian": KA_GAUSSIAN, "exponential": KA_EXP_L1}
 PRECISIONS = {"fp32": KA_FP32, "bf16x3": KA_BF16X3}
 
@@ -43,7 +43,9 @@ class ka_desc(ctypes.Structure):
                 ("interp_cont", ctypes.c_int), ("kernel", ctypes.c_int),
                 ("sigma", ctypes.c_double), ("ell", ctypes.c_double),
                 ("nq", ctypes.c_int), ("precision", ctypes.c_int), ("block", ctypes.c_int),
-                ("seed", ctypes.c_ulonglong)]
+                ("seed", ctypes.c_ulonglong),
+                ("geo_degree", ctypes.c_int * 3), ("geo_nctrl", ctypes.c_int * 3),
+                ("geo_knots", ctypes.POINTER(ctypes.c_double)), ("geo_ctrl", ctypes.POINTER(ctypes.c_double))]
 
 
 class ka_info(ctypes.Structure):
@@ -139,8 +141,12 @@ def _ptr(t):
 
 def make_desc(method, domain, p, nel, kernel, ell, sigma=1.0, block=16, precision="fp32", interp_mult=None,
               interp_cont=None, nq=None, seed=0, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), r0=1.0, r1=2.0,
-              height=1.0, **_ignored):
-    """ka_desc from a plain problem descriptor (see workloads.problem)."""
+              height=1.0, nurbs=None, **_ignored):
+    """ka_desc from a plain problem descriptor (see workloads.problem).
+
+    nurbs (domain "nurbs"): dict(degree=(p1, p2, p3), knots=(t1, t2, t3),
+    ctrl=array of shape (n3, n2, n1, 4) holding x, y, z, weight).  The arrays
+    are kept on the returned descriptor, so they outlive the pointers in it."""
     d = ka_desc()
     d.method = METHODS[method] if isinstance(method, str) else int(method)
     d.domain = DOMAINS[domain] if isinstance(domain, str) else int(domain)
@@ -160,6 +166,17 @@ def make_desc(method, domain, p, nel, kernel, ell, sigma=1.0, block=16, precisio
     d.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     d.block = int(block)
     d.seed = int(seed)
+    if nurbs is not None:
+        ctrl = np.ascontiguousarray(nurbs["ctrl"], dtype=np.float64)
+        if ctrl.ndim != 4 or ctrl.shape[3] != 4:
+            raise ValueError("nurbs ctrl must have shape (n3, n2, n1, 4)")
+        knots = np.ascontiguousarray(np.concatenate([np.asarray(t, dtype=np.float64) for t in nurbs["knots"]]))
+        for k in range(3):
+            d.geo_degree[k] = int(nurbs["degree"][k])
+            d.geo_nctrl[k] = int(ctrl.shape[2 - k])
+        d.geo_knots = knots.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        d.geo_ctrl = ctrl.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        d._keep = (knots, ctrl)
     return d
 
 

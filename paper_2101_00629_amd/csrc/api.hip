@@ -53,11 +53,37 @@ struct Sizes {
   int mult[3];
 };
 
+// Geometry data of a KA_NURBS description; empty string, or why it is invalid.
+static std::string nurbs_from_desc(const ka_desc* d, NurbsVolume& nv) {
+  if (!d->geo_knots || !d->geo_ctrl) return "KA_NURBS needs geo_knots and geo_ctrl";
+  size_t off = 0, ncw = 1;
+  for (int k = 0; k < 3; ++k) {
+    nv.p[k] = d->geo_degree[k];
+    nv.n[k] = d->geo_nctrl[k];
+    if (nv.p[k] < 1 || nv.p[k] > 30 || nv.n[k] < nv.p[k] + 1 || nv.n[k] > 100000)
+      return "KA_NURBS needs geo_degree in 1..30 and geo_degree < geo_nctrl <= 100000";
+    const size_t len = (size_t)nv.n[k] + nv.p[k] + 1;
+    nv.t[k].assign(d->geo_knots + off, d->geo_knots + off + len);
+    off += len;
+    ncw *= (size_t)nv.n[k];
+  }
+  if (ncw > ((size_t)1 << 26)) return "KA_NURBS control net too large";
+  // homogeneous coordinates (w x, w y, w z, w)
+  nv.cw.resize(4 * ncw);
+  for (size_t j = 0; j < ncw; ++j) {
+    const double w = d->geo_ctrl[4 * j + 3];
+    for (int c = 0; c < 3; ++c) nv.cw[4 * j + c] = w * d->geo_ctrl[4 * j + c];
+    nv.cw[4 * j + 3] = w;
+  }
+  return nv.check();
+}
+
 static int check_desc(const ka_desc* d, Sizes& z) {
   if (!d) return fail(KA_ERR_ARG, "desc is NULL");
   if (d->method != KA_GALERKIN_IBQ && d->method != KA_COLLOCATION && d->method != KA_GALERKIN_GAUSS)
     return fail(KA_ERR_ARG, "bad method");
-  if (d->domain != KA_BOX && d->domain != KA_QUARTER_ANNULUS) return fail(KA_ERR_ARG, "bad domain");
+  if (d->domain != KA_BOX && d->domain != KA_QUARTER_ANNULUS && d->domain != KA_NURBS)
+    return fail(KA_ERR_ARG, "bad domain");
   if (d->kernel != KA_GAUSSIAN && d->kernel != KA_EXP_L1) return fail(KA_ERR_ARG, "bad kernel");
   if (d->precision != KA_FP32 && d->precision != KA_BF16X3) return fail(KA_ERR_ARG, "bad precision");
   if (!(d->ell > 0)) return fail(KA_ERR_ARG, "ell must be > 0");
@@ -67,6 +93,10 @@ static int check_desc(const ka_desc* d, Sizes& z) {
   if (d->domain == KA_BOX) {
     for (int k = 0; k < 3; ++k)
       if (!(d->hi[k] > d->lo[k])) return fail(KA_ERR_ARG, "box needs hi > lo");
+  } else if (d->domain == KA_NURBS) {
+    NurbsVolume nv;
+    const std::string why = nurbs_from_desc(d, nv);
+    if (!why.empty()) return fail(KA_ERR_ARG, why);
   } else {
     if (!(d->r1 > d->r0 && d->r0 > 0 && d->height > 0)) return fail(KA_ERR_ARG, "annulus needs 0 < r0 < r1, height > 0");
   }
@@ -131,6 +161,7 @@ static size_t setup_bytes(const ka_desc* d, const Sizes& z) {
   s += 2 * align_up((size_t)z.N * b * 8);
   s += 2 * align_up((size_t)transfer_points(d, z) * b * 4);
   s += align_up(gamma_plan(z.n_rows, z.n_cols, b, d->precision).work_bytes);
+  if (d->domain == KA_NURBS && d->method == KA_COLLOCATION) s += align_up((size_t)z.n_rows * 8);   // W(g), FP64
   return s;
 }
 
@@ -198,6 +229,10 @@ static int setup_impl(const ka_desc* d, hipStream_t stream, Problem** out) {
   geo.r0 = d->r0;
   geo.r1 = d->r1;
   geo.height = d->height;
+  if (d->domain == KA_NURBS) (void)nurbs_from_desc(d, geo.nurbs);   // validated in check_desc
+  // the caller's geometry arrays are not kept
+  P->d.geo_knots = nullptr;
+  P->d.geo_ctrl = nullptr;
   const double cs = coord_scale64(d->kernel, d->ell);
   // The kernel depends on differences only: coordinates are centred on the
   // domain before rounding to FP32, which halves their absolute rounding error.
@@ -293,19 +328,22 @@ static int setup_impl(const ka_desc* d, hipStream_t stream, Problem** out) {
     }
   }
   // point sets
-  auto tensor_points = [&](const std::vector<Vec>& g, std::vector<float>& xyz, std::vector<double>* detJ) {
+  // mapped points (centred, prescaled FP32), optionally |det DF| and the
+  // NURBS weight function W at the tensor grid g[0] x g[1] x g[2]
+  auto tensor_points = [&](const std::vector<Vec>& g, std::vector<float>& xyz, std::vector<double>* detJ,
+                           std::vector<double>* W = nullptr) {
     const int64_t n1 = g[0].size(), n2 = g[1].size(), n3 = g[2].size();
     xyz.assign((size_t)n1 * n2 * n3 * 4, 0.f);
     if (detJ) detJ->assign((size_t)n1 * n2 * n3, 0.0);
+    if (W) W->assign((size_t)n1 * n2 * n3, 1.0);
     for (int64_t a3 = 0; a3 < n3; ++a3)
       for (int64_t a2 = 0; a2 < n2; ++a2)
         for (int64_t a1 = 0; a1 < n1; ++a1) {
           const int64_t i = a1 + n1 * (a2 + n2 * a3);
           const double xh[3] = {g[0][a1], g[1][a2], g[2][a3]};
           double x[3];
-          geo.map(xh, x);
+          geo.eval(xh, x, detJ ? &(*detJ)[i] : nullptr, W ? &(*W)[i] : nullptr);
           for (int c = 0; c < 3; ++c) xyz[i * 4 + c] = (float)((x[c] - ctr[c]) * cs);
-          if (detJ) (*detJ)[i] = geo.detJ(xh);
         }
   };
   if (d->method == KA_GALERKIN_IBQ) {
@@ -335,19 +373,30 @@ static int setup_impl(const ka_desc* d, hipStream_t stream, Problem** out) {
     P->rscale = upload(P, ws, ok);
     P->cscale = P->rscale;
   } else {
+    // General NURBS volume: trial functions B_j / W (W the geometry's weight
+    // function, B_j the tensor B-splines of the univariate factors above).
+    // Then R_q = diag(1/W(q)) (R_q,3 x R_q,2 x R_q,1) and Z = diag(1/W(g))
+    // (Z_3 x Z_2 x Z_1): 1/W(q) joins |det DF| W on the columns, and
+    // Z^-1 = (Z_3^-1 x Z_2^-1 x Z_1^-1) diag(W(g)), whose diagonal is the row
+    // scale of the kernel product.
     std::vector<float> xr, xq;
-    tensor_points(pts1d, xr, nullptr);
+    std::vector<double> wg, wq;
+    tensor_points(pts1d, xr, nullptr, &wg);
     std::vector<double> dj;
-    tensor_points(q1d, xq, &dj);
+    tensor_points(q1d, xq, &dj, &wq);
     std::vector<float> jw(dj.size());
     const int64_t m1 = q1d[0].size(), m2 = q1d[1].size();
     for (size_t i = 0; i < dj.size(); ++i) {
       const int64_t a1 = i % m1, a2 = (i / m1) % m2, a3 = i / (m1 * m2);
-      jw[i] = (float)(dj[i] * w1d[0][a1] * w1d[1][a2] * w1d[2][a3]);
+      jw[i] = (float)(dj[i] * w1d[0][a1] * w1d[1][a2] * w1d[2][a3] / wq[i]);
     }
     P->rows = upload(P, xr, ok);
     P->cols = upload(P, xq, ok);
     P->rscale = nullptr;
+    if (d->domain == KA_NURBS) {
+      P->rscale = upload(P, std::vector<float>(wg.begin(), wg.end()), ok);
+      P->wrow64 = upload(P, wg, ok);
+    }
     P->cscale = upload(P, jw, ok);
   }
   const int b = P->b;
@@ -397,7 +446,7 @@ int gamma_step(Problem* P, const float* Y, float* Z, hipStream_t s) {
   GammaLaunch g;
   g.xr = P->rows;
   g.xr_stride = 4;
-  g.rs = P->d.method != KA_COLLOCATION ? P->rscale : nullptr;
+  g.rs = P->rscale;
   g.nr = P->n_rows;
   g.xc = P->cols;
   g.xc_stride = 4;
@@ -511,7 +560,7 @@ int apply_post(Problem* P, int form, double* Y, int64_t ldy, int nv, hipStream_t
     HIP_TRY(launch_mode_f64(mode_args(P->w64a, LAYOUT_COL, N, P->w64b, LAYOUT_COL, N, nn, 1, n[1], P->Zinv[1], nv, nullptr), s));
     HIP_TRY(launch_mode_f64(mode_args(P->w64b, LAYOUT_COL, N, Y, LAYOUT_COL, ldy, nn, 2, n[2], P->Zinv[2], nv, nullptr), s));
   } else {
-    HIP_TRY(cast_pt32_to_col64(P->w32a, b, Y, ldy, N, nv, s));
+    HIP_TRY(cast_pt32_to_col64(P->w32a, b, Y, ldy, N, nv, P->wrow64, s));   // A itself: W(g) divided out
   }
   return KA_OK;
 }
@@ -522,7 +571,7 @@ GammaLaunch gamma_job(Problem* P) {
   GammaLaunch g;
   g.xr = P->rows;
   g.xr_stride = 4;
-  g.rs = P->d.method != KA_COLLOCATION ? P->rscale : nullptr;
+  g.rs = P->rscale;
   g.nr = P->n_rows;
   g.xc = P->cols;
   g.xc_stride = 4;
@@ -549,7 +598,10 @@ int apply_block(Problem* P, int form, const double* X, int64_t ldx, double* Y, i
 }
 
 int solve_block(Problem* P, int op, double* X, int64_t ld, int nv, hipStream_t s) {
-  if (op == KA_ZINV) return kron64(P, P->Zinv, X, ld, X, ld, nv, s);
+  if (op == KA_ZINV) {
+    if (P->wrow64) HIP_TRY(scale_rows(X, P->N, nv, ld, P->wrow64, s));   // general NURBS: diag(W(g)) first
+    return kron64(P, P->Zinv, X, ld, X, ld, nv, s);
+  }
   if (P->d.method == KA_COLLOCATION) return fail(KA_ERR_STATE, "L solves exist for the Galerkin methods only");
   if (op == KA_LINV) return kron64(P, P->Linv, X, ld, X, ld, nv, s);
   if (op == KA_LTINV) return kron64(P, P->LinvT, X, ld, X, ld, nv, s);

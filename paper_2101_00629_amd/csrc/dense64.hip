@@ -532,6 +532,21 @@ hipError_t scale_cols(double* V, int64_t N, int n, int64_t ld, const double* sca
   return hipGetLastError();
 }
 
+__global__ void scale_rows_kernel(double* V, int64_t N, int n, int64_t ld, const double* scale) {
+  const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= N * n) return;
+  const int64_t i = id % N;
+  const int j = (int)(id / N);
+  V[i + j * ld] *= scale[i];
+}
+
+hipError_t scale_rows(double* V, int64_t N, int n, int64_t ld, const double* scale, hipStream_t s) {
+  const int64_t tot = N * n;
+  if (tot == 0) return hipSuccess;
+  hipLaunchKernelGGL(scale_rows_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, V, N, n, ld, scale);
+  return hipGetLastError();
+}
+
 __global__ void fill_zero_f32_kernel(float* p, int64_t n) {
   const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (id < n) p[id] = 0.f;

@@ -241,42 +241,125 @@ static void quarter_circle(double xi, double* C, double* dC) {
   dC[1] = (dny * D - ny * dD) / (D * D);
 }
 
-void Geometry::map(const double* xh, double* x) const {
+// B-splines of degree p on span s at x and their first derivatives:
+// N[r] = B_{s-p+r}(x), dN[r] = B'_{s-p+r}(x), r = 0..p.  The degree p-1 values
+// on the span give the derivatives by dB_{i,p} = p (B_{i,p-1} / (t_{i+p} - t_i)
+// - B_{i+1,p-1} / (t_{i+p+1} - t_{i+1})).
+static void basis_with_derivative(const Vec& t, int p, int s, double x, double* N, double* dN) {
+  double lower[32];
+  nonzero_basis(t, p - 1, s, x, lower);      // B_{s-p+1..s, p-1}
+  nonzero_basis(t, p, s, x, N);
+  for (int r = 0; r <= p; ++r) {
+    const int i = s - p + r;
+    double d = 0.0;
+    if (r >= 1) {
+      const double den = t[i + p] - t[i];
+      if (den > 0) d += lower[r - 1] / den;
+    }
+    if (r <= p - 1) {
+      const double den = t[i + p + 1] - t[i + 1];
+      if (den > 0) d -= lower[r] / den;
+    }
+    dN[r] = p * d;
+  }
+}
+
+std::string NurbsVolume::check() const {
+  size_t ncw = 1;
+  for (int k = 0; k < 3; ++k) {
+    if (p[k] < 1 || p[k] > 30) return "NURBS degree must be in 1..30";
+    if (n[k] < p[k] + 1) return "NURBS needs at least degree + 1 control points per direction";
+    if ((int)t[k].size() != n[k] + p[k] + 1) return "NURBS knot vector has the wrong length";
+    for (size_t i = 1; i < t[k].size(); ++i)
+      if (!(t[k][i] >= t[k][i - 1])) return "NURBS knots must be non-decreasing";
+    for (int i = 0; i <= p[k]; ++i)
+      if (t[k][i] != 0.0 || t[k][n[k] + i] != 1.0) return "NURBS knot vectors must be open on [0, 1]";
+    ncw *= (size_t)n[k];
+  }
+  if (cw.size() != 4 * ncw) return "NURBS control net has the wrong size";
+  for (size_t j = 0; j < ncw; ++j) {
+    if (!(cw[4 * j + 3] > 0) || !std::isfinite(cw[4 * j + 3])) return "NURBS weights must be finite and > 0";
+    for (int c = 0; c < 3; ++c)
+      if (!std::isfinite(cw[4 * j + c])) return "NURBS control points must be finite";
+  }
+  return "";
+}
+
+void NurbsVolume::eval(const double* xh, double* x, double* dF, double* W) const {
+  double N[3][32], dN[3][32];
+  int s[3];
+  for (int k = 0; k < 3; ++k) {
+    s[k] = find_span(t[k], p[k], xh[k]);
+    basis_with_derivative(t[k], p[k], s[k], xh[k], N[k], dN[k]);
+  }
+  // homogeneous sums A = sum w P N, w = sum w N, and their derivatives
+  double A[4] = {0, 0, 0, 0}, dA[3][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}};
+  for (int c = 0; c <= p[2]; ++c) {
+    const int j3 = s[2] - p[2] + c;
+    for (int b = 0; b <= p[1]; ++b) {
+      const int j2 = s[1] - p[1] + b;
+      const double v23 = N[1][b] * N[2][c], d2 = dN[1][b] * N[2][c], d3 = N[1][b] * dN[2][c];
+      for (int a = 0; a <= p[0]; ++a) {
+        const int j1 = s[0] - p[0] + a;
+        const double* q = &cw[4 * ((size_t)j1 + (size_t)n[0] * (j2 + (size_t)n[1] * j3))];
+        const double v = N[0][a] * v23, v1 = dN[0][a] * v23, v2 = N[0][a] * d2, v3 = N[0][a] * d3;
+        for (int m = 0; m < 4; ++m) {
+          A[m] += v * q[m];
+          dA[0][m] += v1 * q[m];
+          dA[1][m] += v2 * q[m];
+          dA[2][m] += v3 * q[m];
+        }
+      }
+    }
+  }
+  const double w = A[3];
+  for (int c = 0; c < 3; ++c) x[c] = A[c] / w;
+  if (dF)
+    for (int c = 0; c < 3; ++c)
+      for (int k = 0; k < 3; ++k) dF[3 * c + k] = (dA[k][c] - x[c] * dA[k][3]) / w;
+  if (W) *W = w;
+}
+
+void Geometry::eval(const double* xh, double* x, double* detJ, double* W) const {
+  if (W) *W = 1.0;
   if (domain == 0) {
     for (int k = 0; k < 3; ++k) x[k] = lo[k] + (hi[k] - lo[k]) * xh[k];
-  } else {
+    if (detJ) *detJ = std::fabs((hi[0] - lo[0]) * (hi[1] - lo[1]) * (hi[2] - lo[2]));
+  } else if (domain == 1) {
     double C[2], dC[2];
     quarter_circle(xh[0], C, dC);
     const double r = r0 + (r1 - r0) * xh[1];
     x[0] = r * C[0];
     x[1] = r * C[1];
     x[2] = height * xh[2];
+    // columns dF/dxi = r C', dF/deta = (r1-r0) C, dF/dzeta = height e_z
+    if (detJ) *detJ = std::fabs(r * (r1 - r0) * height * (C[0] * dC[1] - C[1] * dC[0]));
+  } else {
+    double F[9];
+    nurbs.eval(xh, x, detJ ? F : nullptr, W);
+    if (detJ)
+      *detJ = std::fabs(F[0] * (F[4] * F[8] - F[5] * F[7]) - F[1] * (F[3] * F[8] - F[5] * F[6]) +
+                        F[2] * (F[3] * F[7] - F[4] * F[6]));
   }
 }
 
 void Geometry::center(double* c) const {
   if (domain == 0) {
     for (int k = 0; k < 3; ++k) c[k] = 0.5 * (lo[k] + hi[k]);
-  } else {
+  } else if (domain == 1) {
     // the quarter annulus lies in [0, r1] x [0, r1] x [0, height]
     c[0] = c[1] = 0.5 * r1;
     c[2] = 0.5 * height;
+  } else {
+    double lo3[3] = {INFINITY, INFINITY, INFINITY}, hi3[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (size_t j = 0; j + 3 < nurbs.cw.size(); j += 4)
+      for (int k = 0; k < 3; ++k) {
+        const double v = nurbs.cw[j + k] / nurbs.cw[j + 3];
+        lo3[k] = std::min(lo3[k], v);
+        hi3[k] = std::max(hi3[k], v);
+      }
+    for (int k = 0; k < 3; ++k) c[k] = 0.5 * (lo3[k] + hi3[k]);
   }
-}
-
-double Geometry::detJ(const double* xh) const {
-  if (domain == 0) return std::fabs((hi[0] - lo[0]) * (hi[1] - lo[1]) * (hi[2] - lo[2]));
-  double C[2], dC[2];
-  quarter_circle(xh[0], C, dC);
-  const double r = r0 + (r1 - r0) * xh[1];
-  // columns dF/dxi = r C', dF/deta = (r1-r0) C, dF/dzeta = height e_z
-  const double cross = C[0] * dC[1] - C[1] * dC[0];
-  return std::fabs(r * (r1 - r0) * height * cross);
-}
-
-double Geometry::volume() const {
-  if (domain == 0) return detJ(lo);
-  return M_PI / 4 * (r1 * r1 - r0 * r0) * height;
 }
 
 double Geometry::weight1d(int k, double t) const {

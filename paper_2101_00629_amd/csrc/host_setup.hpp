@@ -52,17 +52,35 @@ Mat matmul(const Mat& A, const Mat& B);
 // pivot falls below tol * max|A|.
 bool lu_inverse(const Mat& A, Mat& Ainv, double tol = 1e-13);
 
+// Single-patch NURBS volume (paper Sec. 3.2: the geometry is given by NURBS):
+// F(xh) = sum_j w_j P_j N_j(xh) / W(xh) with W(xh) = sum_j w_j N_j(xh), N_j the
+// tensor-product B-splines of the geometry's own degrees and knot vectors.
+struct NurbsVolume {
+  int p[3] = {0, 0, 0};
+  int n[3] = {0, 0, 0};        // control points per direction
+  Vec t[3];                    // open knot vectors on [0, 1]
+  Vec cw;                      // homogeneous control points (w x, w y, w z, w), index j1 + n1 (j2 + n2 j3)
+  // Empty string if the data describe a valid volume, else the reason.
+  std::string check() const;
+  // Point x, Jacobian dF[3 c + k] = d x_c / d xh_k and weight function W at xh.
+  void eval(const double* xh, double* x, double* dF, double* W) const;
+};
+
 // Geometry: parametric point -> physical point, |det DF|.
 struct Geometry {
-  int domain = 0;              // 0 box, 1 quarter annulus
+  int domain = 0;              // 0 box, 1 quarter annulus, 2 general NURBS volume
   double lo[3] = {0, 0, 0}, hi[3] = {1, 1, 1};
   double r0 = 1, r1 = 2, height = 1;
-  void map(const double* xh, double* x) const;
-  double detJ(const double* xh) const;
-  double volume() const;
-  // midpoint of the axis-aligned bounding box of the mapped domain
+  NurbsVolume nurbs;
+  // Mapped point, and optionally |det DF| and the NURBS weight function W
+  // (general NURBS volume; 1 for the closed-form domains).
+  void eval(const double* xh, double* x, double* detJ, double* W) const;
+  // midpoint of the axis-aligned bounding box of the mapped domain (of the
+  // control points for a NURBS volume, which contain it)
   void center(double* c) const;
-  // NURBS weight function of parametric direction k (1 for B-spline directions).
+  // Weight function of parametric direction k when the weights are a tensor
+  // product (the quarter annulus); 1 for B-spline directions and for the
+  // general NURBS volume, whose weight function enters through eval().
   double weight1d(int k, double t) const;
 };
 

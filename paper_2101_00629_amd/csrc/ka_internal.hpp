@@ -93,9 +93,9 @@ hipError_t launch_mode_f64_to_f32(const ModeArgs& a, hipStream_t s);           /
 hipError_t launch_mode_f32(const ModeArgs& a, hipStream_t s);                  // all float
 hipError_t launch_mode_f32_to_f64(const ModeArgs& a, hipStream_t s);           // in/mat float, out double
 hipError_t launch_mode_f32in_f64(const ModeArgs& a, hipStream_t s);            // in float, mat/out double
-// point-major FP32 (point stride ld_in) -> column-major FP64
+// point-major FP32 (point stride ld_in) -> column-major FP64, divided by div[i] if div is not NULL
 hipError_t cast_pt32_to_col64(const float* in, int64_t ld_in, double* out, int64_t ld_out, int64_t npts, int nv,
-                              hipStream_t s);
+                              const double* div, hipStream_t s);
 
 // ---- FP64 dense helpers (eigensolver) ----------------------------------
 // C(m x n) = alpha * A^T B + beta * C, A: K x m (lda), B: K x n (ldb); split-K
@@ -139,6 +139,8 @@ hipError_t residual_combine(const double* AXS, const double* XS, int64_t N, int 
                             const double* wr, const double* wi, double* R, hipStream_t s);
 hipError_t sign_fix(double* V, int64_t N, int n, int64_t ld, const double* wi, hipStream_t s);
 hipError_t scale_cols(double* V, int64_t N, int n, int64_t ld, const double* scale, hipStream_t s);
+// V[i + j ld] *= scale[i], i < N, j < n
+hipError_t scale_rows(double* V, int64_t N, int n, int64_t ld, const double* scale, hipStream_t s);
 hipError_t fill_zero_f32(float* p, int64_t n, hipStream_t s);
 
 // ---- problem ----------------------------------------------------------------
@@ -165,7 +167,8 @@ struct Problem {
   float* TT[3] = {nullptr, nullptr, nullptr};       // transposes (n x nt)
   float* rows = nullptr;     // row points (x, y, z, 0), prescaled
   float* cols = nullptr;     // column points (Galerkin: == rows)
-  float* rscale = nullptr;   // row scale (Galerkin: J)
+  float* rscale = nullptr;   // row scale (Galerkin: J; collocation on a NURBS volume: W at the collocation points)
+  double* wrow64 = nullptr;  // collocation on a NURBS volume: W at the collocation points, FP64
   float* cscale = nullptr;   // column scale folded into Y (Galerkin: J, collocation: |det DF| W)
   int64_t n_rows = 0, n_cols = 0;
   // workspace

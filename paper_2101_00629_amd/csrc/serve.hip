@@ -66,6 +66,7 @@ struct Request {
   uint64_t tag = 0;
   double* lambda_host = nullptr;
   size_t bytes = 0;
+  std::vector<double> geo_knots, geo_ctrl;   // KA_NURBS: copies that desc points to
 };
 
 struct BatchDone {
@@ -407,6 +408,17 @@ int ka_server_submit(ka_server* s, const ka_desc* desc, int M, double tol, int m
   if (int rc = ka_request_bytes(desc, M, &need)) return rc;
   std::unique_ptr<Request> r(new Request());
   r->desc = *desc;
+  if (desc->domain == KA_NURBS) {   // validated above: copy the geometry, the caller's arrays are not kept
+    size_t nk = 0, nc = 4;
+    for (int k = 0; k < 3; ++k) {
+      nk += (size_t)desc->geo_nctrl[k] + desc->geo_degree[k] + 1;
+      nc *= (size_t)desc->geo_nctrl[k];
+    }
+    r->geo_knots.assign(desc->geo_knots, desc->geo_knots + nk);
+    r->geo_ctrl.assign(desc->geo_ctrl, desc->geo_ctrl + nc);
+    r->desc.geo_knots = r->geo_knots.data();
+    r->desc.geo_ctrl = r->geo_ctrl.data();
+  }
   r->M = M;
   r->tol = tol;
   r->maxit = maxit;

@@ -70,19 +70,20 @@ hipError_t launch_mode_f32_to_f64(const ModeArgs& a, hipStream_t s) { return lau
 hipError_t launch_mode_f32in_f64(const ModeArgs& a, hipStream_t s) { return launch_mode<float, double, double>(a, s); }
 
 __global__ void cast_pt32_col64_kernel(const float* __restrict__ in, int64_t ld_in, double* __restrict__ out,
-                                       int64_t ld_out, int64_t npts, int nv) {
+                                       int64_t ld_out, int64_t npts, int nv, const double* __restrict__ div) {
   const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (id >= npts * nv) return;
   const int64_t i = id % npts, j = id / npts;
-  out[i + j * ld_out] = (double)in[i * ld_in + j];
+  const double v = (double)in[i * ld_in + j];
+  out[i + j * ld_out] = div ? v / div[i] : v;
 }
 
 hipError_t cast_pt32_to_col64(const float* in, int64_t ld_in, double* out, int64_t ld_out, int64_t npts, int nv,
-                              hipStream_t s) {
+                              const double* div, hipStream_t s) {
   const int64_t tot = npts * nv;
   if (tot == 0) return hipSuccess;
   hipLaunchKernelGGL(cast_pt32_col64_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, in, ld_in, out,
-                     ld_out, npts, nv);
+                     ld_out, npts, nv, div);
   return hipGetLastError();
 }
 

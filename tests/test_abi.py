@@ -106,3 +106,26 @@ def test_stored_cube_reference_matches_the_oracle():
     ref = product1d.collocation_box_spectrum(3, (20, 20, 20), "gaussian", 0.5, M=50).real
     got = np.array(rec["spectra"]["collocation-gaussian"]["lambda"])
     assert np.abs(got - ref).max() <= 1e-14 * ref[0]
+
+
+def test_nurbs_descriptor_validation():
+    """KA_NURBS control nets are checked on the host (no device work)."""
+    import paper_2101_00629_amd as K
+    from workloads import nurbs_annulus_net, nurbs_blob_net
+    good = dict(method="collocation", domain="nurbs", p=2, nel=(4, 3, 4), kernel="gaussian", ell=0.5)
+    assert K.ka_footprint(K.make_desc(nurbs=nurbs_blob_net(1), **good)) > 0
+    assert K.ka_footprint(K.make_desc(nurbs=nurbs_annulus_net(), **good)) > 0
+    net = nurbs_blob_net(1)
+    bad_w = dict(net, ctrl=net["ctrl"].copy())
+    bad_w["ctrl"][0, 0, 0, 3] = 0.0
+    bad_knots = dict(net, knots=([0, 0, 0.2, 0.5, 1, 1, 1],) + tuple(net["knots"][1:]))
+    bad_nan = dict(net, ctrl=net["ctrl"].copy())
+    bad_nan["ctrl"][1, 1, 1, 0] = float("nan")
+    for bad in (bad_w, bad_knots, bad_nan):
+        with pytest.raises(K.KAError) as e:
+            K.ka_footprint(K.make_desc(nurbs=bad, **good))
+        assert e.value.code == K.KA_ERR_ARG
+    # KA_NURBS without a control net
+    with pytest.raises(K.KAError) as e:
+        K.ka_footprint(K.make_desc(**good))
+    assert e.value.code == K.KA_ERR_ARG
