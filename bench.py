@@ -458,6 +458,55 @@ def nurbs_benchmark(reps=2):
     return out
 
 
+def kl_sample_benchmark(reps=3):
+    """K-L field sampling at workload size: eigenpairs by ka_eigs on the
+    device, then ka_kl_sample of S fields on a parametric tensor grid
+    (N(0,1) draws from a seeded generator, passed in).  Reported per case:
+    median wall time of the whole call (norms, eigenfunction values, field
+    product; it synchronizes), fields/s, and the rates the field product
+    alone would need at that time (2 P S M flops; P S 8 bytes written)."""
+    import torch
+    import paper_2101_00629_amd as K
+    from workloads import annulus_p4, cube_p3_20
+
+    cases = []
+    p = annulus_p4("galerkin", "gaussian")
+    cases.append(("annulus p4 32x32x16 Galerkin Gaussian, M=100", p, p["M"], (64, 64, 32), 1000))
+    p = cube_p3_20("galerkin", "exponential")
+    cases.append(("cube p3 20^3 Galerkin exponential (C0), M=50", p, p["M"], (64, 64, 64), 1000))
+    p = cube_p3_20("collocation", "gaussian")
+    cases.append(("cube p3 20^3 collocation Gaussian, M=50", p, p["M"], (64, 64, 64), 1000))
+    out = []
+    for name, prob_d, M, npts, S in cases:
+        cplx = prob_d["method"] == "collocation"
+        prob = K.Problem(K.desc_from_problem(prob_d, seed=17))
+        V = torch.zeros((M, prob.N), dtype=torch.float64, device="cuda")
+        rc, lam, info = K.ka_eigs(prob.h, M, tol=1e-5, maxit=80, V=V, complex_values=cplx)
+        lam = lam[0::2] if cplx else lam
+        grid = [np.linspace(0.0, 1.0, n) for n in npts]
+        P = int(np.prod(npts))
+        gen = torch.Generator(device="cuda")
+        gen.manual_seed(23)
+        xi = torch.randn((S, M), dtype=torch.float64, device="cuda", generator=gen)
+        F = torch.empty((S, P), dtype=torch.float64, device="cuda")
+        times = []
+        for r in range(reps + 1):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            K.ka_kl_sample(prob.h, np.maximum(lam, 0.0), V, grid, xi, F, mu=0.0)
+            if r:
+                times.append(time.perf_counter() - t0)
+        prob.close()
+        t = float(np.median(times))
+        rec = {"case": name, "eigs_status": rc, "M": M, "grid": list(npts), "points": P, "samples": S,
+               "call_ms": t * 1e3, "fields_per_s": S / t, "product_tflops_at_call_time": 2.0 * P * S * M / t / 1e12,
+               "output_gb_per_s_at_call_time": P * S * 8 / t / 1e9}
+        out.append(rec)
+        print(f"[kl] {name}: {P} points x {S} samples, {t * 1e3:.1f} ms per call", file=sys.stderr, flush=True)
+        del V, xi, F
+    return out
+
+
 def latency(lat):
     return {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)), "max": float(lat.max())}
 
@@ -480,6 +529,8 @@ def main():
                     help="the paper's method comparison (time vs eigenvalue error) on the cube instead")
     ap.add_argument("--kernel-rates", action="store_true",
                     help="time the raw kernel product at every workload shape instead")
+    ap.add_argument("--kl-sample", action="store_true",
+                    help="K-L field sampling at workload size (ka_kl_sample) instead")
     ap.add_argument("--nurbs", action="store_true",
                     help="general NURBS volumes at workload size (annulus as a control net, curved volume) instead")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -508,6 +559,10 @@ def main():
         print(json.dumps({"metric": "fused kernel product pairs/s at the workload shapes", "n_gpus": 1,
                           "data": "synthetic (uniform points, N(0,1) blocks)", "unit": "pairs/s",
                           "rates": kernel_rates()}), flush=True)
+        return
+    if args.kl_sample:
+        print(json.dumps({"metric": "K-L field samples on a parametric grid", "n_gpus": 1, "data": "synthetic",
+                          "dtype": "f64", "runs": kl_sample_benchmark()}), flush=True)
         return
     if args.nurbs:
         print(json.dumps({"metric": "K-L solves on general NURBS volumes", "n_gpus": 1, "data": "synthetic",

@@ -206,6 +206,30 @@ int ka_gamma_apply(int kernel, double sigma, double ell, const float* xr_dev, in
 /* Scratch bytes ka_gamma_apply needs for these sizes. */
 size_t ka_gamma_workspace(int64_t nr, int64_t nc, int b, int precision);
 
+/* ---- K-L field sampling (paper Sec. 2, eq. kle) --------------------------
+ * Truncated expansion alpha_M(x, s) = mu + sum_{i<M} sqrt(lambda_i) phi_i(x) xi_i(s)
+ * at the tensor grid of parametric points (grid[0][i1], grid[1][i2], grid[2][i3])
+ * of the problem's domain, for nsamples draws.
+ * phi_i: the eigenfunction with coefficient column i of V in the problem's
+ *   trial space, as ka_eigs returns V (Galerkin: v = L^-T v', phi = sum_j v_j
+ *   B_j / sqrt|det DF|; collocation: phi = sum_j v_j R_j, R_j = B_j / W on a
+ *   KA_NURBS volume), scaled here to unit L2(D) norm.  The norm is taken with
+ *   a Gauss rule per element and direction: p + 1 points for the Galerkin
+ *   methods (exact), the collocation rule's nq points for collocation.
+ * lambda_host: M finite eigenvalues >= 0 (collocation: their real parts).
+ * V_dev: N x M column-major FP64 (ldv >= N).  grid_host: npts[0] + npts[1] +
+ *   npts[2] coordinates in [0, 1], direction 1 first.  xi_dev: M x nsamples
+ *   column-major FP64 (ldxi >= M), the draws (N(0,1) for a Gaussian field).
+ * field_dev: P x nsamples column-major FP64 (ldf >= P), P = npts[0] npts[1]
+ *   npts[2], grid point index i1 + npts[0] (i2 + npts[1] i3).
+ * Allocates its device workspace (about (P + quadrature points) x M doubles)
+ * and synchronizes `stream` before it returns.  Errors: KA_ERR_ARG (bad
+ * sizes or values), KA_ERR_SINGULAR (an eigenfunction of zero norm),
+ * KA_ERR_OOM, KA_ERR_HIP. */
+int ka_kl_sample(ka_problem* p, int M, const double* lambda_host, const double* V_dev, int64_t ldv,
+                 const int npts[3], const double* grid_host, int nsamples, const double* xi_dev,
+                 int64_t ldxi, double mu, double* field_dev, int64_t ldf, void* stream);
+
 /* Timing of kernel-product launches issued through a problem since the last
  * reset (HIP events on the launch stream; enabled by ka_profile_enable). */
 int ka_profile_enable(ka_problem* p, int on);

@@ -89,6 +89,8 @@ def _load():
         "ka_profile_enable": ([vp, ctypes.c_int], ctypes.c_int),
         "ka_profile_read": ([vp, ctypes.POINTER(ctypes.c_int), dp, dp], ctypes.c_int),
         "ka_profile_reset": ([vp], ctypes.c_int),
+        "ka_kl_sample": ([vp, ctypes.c_int, dp, vp, i64, ctypes.POINTER(ctypes.c_int), dp, ctypes.c_int, vp, i64,
+                          ctypes.c_double, vp, i64, vp], ctypes.c_int),
         "ka_destroy": ([vp], None),
         "ka_server_create": ([ctypes.c_size_t, ctypes.c_int, ctypes.POINTER(vp)], ctypes.c_int),
         "ka_server_submit": ([vp, ctypes.POINTER(ka_desc), ctypes.c_int, ctypes.c_double, ctypes.c_int,
@@ -112,7 +114,7 @@ _lib = _load()
 EXPORTED = ("ka_setup", "ka_size", "ka_footprint", "ka_apply_A", "ka_solve_Z", "ka_eigs", "ka_gamma_apply",
             "ka_gamma_workspace", "ka_profile_enable", "ka_profile_read", "ka_profile_reset", "ka_destroy",
             "ka_last_error", "ka_server_create", "ka_server_submit", "ka_server_run", "ka_server_poll",
-            "ka_server_stats", "ka_server_destroy", "ka_request_bytes")
+            "ka_server_stats", "ka_server_destroy", "ka_request_bytes", "ka_kl_sample")
 
 
 class KAError(RuntimeError):
@@ -224,6 +226,27 @@ def ka_eigs(h, M, tol=1e-6, maxit=100, V=None, complex_values=False):
     rc = _check(_lib.ka_eigs(h, M, tol, maxit, lam.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), _ptr(V),
                              ctypes.byref(info)), "ka_eigs")
     return rc, lam, info.as_dict()
+
+
+def ka_kl_sample(h, lam, V, grid, xi, field, mu=0.0, stream=None):
+    """K-L fields at a parametric tensor grid.  lam: M real eigenvalues (numpy);
+    V: FP64 CUDA tensor (M, N) (row i = coefficient column i); grid: three 1-D
+    arrays of parametric coordinates; xi: FP64 CUDA tensor (S, M) (row s =
+    draws of sample s); field: FP64 CUDA tensor (S, P) receiving the fields
+    (row s = sample s over the grid points, direction 1 fastest)."""
+    lam = np.ascontiguousarray(lam, dtype=np.float64)
+    M = len(lam)
+    g = [np.ascontiguousarray(x, dtype=np.float64) for x in grid]
+    npts = (ctypes.c_int * 3)(*[len(x) for x in g])
+    gcat = np.ascontiguousarray(np.concatenate(g))
+    P = int(np.prod([len(x) for x in g]))
+    S = xi.shape[0]
+    if V.shape[0] < M or xi.shape[1] < M or field.shape[0] != S or field.shape[1] < P:
+        raise ValueError("shapes: V (M, N), xi (S, M), field (S, P)")
+    return _check(_lib.ka_kl_sample(h, M, lam.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), _ptr(V), V.shape[1],
+                                    npts, gcat.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), S, _ptr(xi),
+                                    xi.shape[1], float(mu), _ptr(field), field.shape[1], _stream(stream)),
+                  "ka_kl_sample")
 
 
 def ka_gamma_workspace(nr, nc, b, precision=KA_FP32):

@@ -152,7 +152,7 @@ static size_t setup_bytes(const ka_desc* d, const Sizes& z) {
   const int b = d->block;
   size_t s = 0;
   for (int k = 0; k < 3; ++k) {
-    s += 3 * align_up((size_t)z.n[k] * z.n[k] * 8);          // LinvT, Linv, Zinv
+    s += 4 * align_up((size_t)z.n[k] * z.n[k] * 8);          // LinvT, Linv, Zinv, Z_k
     const int mk = d->method == KA_GALERKIN_IBQ ? z.nt[k] : z.nq[k];
     s += 2 * align_up((size_t)mk * z.n[k] * 4);               // T, TT
   }
@@ -220,7 +220,7 @@ static int setup_impl(const ka_desc* d, hipStream_t stream, Problem** out) {
   P->n_cols = z.n_cols;
   P->out_scale = (float)(d->sigma * d->sigma);
   P->coord_scale = 1.0f;   // coordinates are prescaled in FP64 below
-  Geometry geo;
+  Geometry& geo = P->geo;   // kept: K-L sampling evaluates the trial space at new points
   geo.domain = d->domain;
   for (int k = 0; k < 3; ++k) {
     geo.lo[k] = d->lo[k];
@@ -258,6 +258,7 @@ static int setup_impl(const ka_desc* d, hipStream_t stream, Problem** out) {
       P->Linv[k] = upload(P, to_vec(Li), ok);
       P->LinvT[k] = upload(P, to_vec(LiT), ok);
       P->Zinv[k] = upload(P, to_vec(matmul(LiT, Li)), ok);
+      P->Zk[k] = upload(P, to_vec(Zk), ok);   // mass matrix: exact L2 norms of eigenfunctions
       Vec xq, wq;
       element_gauss(t, d->nq > 0 ? d->nq : p + 1, xq, wq);
       const Mat Rq = bspline_matrix(t, p, xq);                 // nq x n
@@ -276,6 +277,7 @@ static int setup_impl(const ka_desc* d, hipStream_t stream, Problem** out) {
       P->Linv[k] = upload(P, to_vec(Li), ok);
       P->LinvT[k] = upload(P, to_vec(LiT), ok);
       P->Zinv[k] = upload(P, to_vec(matmul(LiT, Li)), ok);
+      P->Zk[k] = upload(P, to_vec(Zk), ok);   // mass matrix: exact L2 norms of eigenfunctions
       const Vec ti = open_knots(p, e, z.mult[k]);
       const Vec g = greville(ti, p);
       const Mat Mk = mass_matrix(ti, p, t, p);               // nt x n
@@ -293,27 +295,12 @@ static int setup_impl(const ka_desc* d, hipStream_t stream, Problem** out) {
       const Vec g = greville(t, p);
       Vec xq, wq;
       element_gauss(t, d->nq > 0 ? d->nq : p + 1, xq, wq);
-      // NURBS weights: interpolate the weight function at the Greville points
-      Mat Bg = bspline_matrix(t, p, g), Bgi;
-      if (!lu_inverse(Bg, Bgi)) {
+      // NURBS functions of the direction (weights interpolating its weight function)
+      Mat Rq, Zc;
+      if (!trial_matrix_1d(geo, true, p, e, k, xq, Rq) || !trial_matrix_1d(geo, true, p, e, k, g, Zc)) {
         free_problem(P);
         return fail(KA_ERR_SINGULAR, "Greville collocation matrix is singular");
       }
-      Vec wf(g.size()), w(g.size(), 0.0);
-      for (size_t i = 0; i < g.size(); ++i) wf[i] = geo.weight1d(k, g[i]);
-      for (size_t i = 0; i < g.size(); ++i)
-        for (size_t j = 0; j < g.size(); ++j) w[i] += Bgi(i, j) * wf[j];
-      auto nurbs = [&](const Vec& x) {
-        Mat B = bspline_matrix(t, p, x);
-        for (int a = 0; a < B.rows; ++a) {
-          double den = 0;
-          for (int j = 0; j < B.cols; ++j) den += w[j] * B(a, j);
-          for (int j = 0; j < B.cols; ++j) B(a, j) = w[j] * B(a, j) / den;
-        }
-        return B;
-      };
-      const Mat Rq = nurbs(xq);                               // nq x n
-      const Mat Zc = nurbs(g);                                // n x n
       Mat Zci;
       if (!lu_inverse(Zc, Zci)) {
         free_problem(P);

@@ -368,3 +368,26 @@ double Geometry::weight1d(int k, double t) const {
 }
 
 }  // namespace ka
+
+namespace ka {
+
+bool trial_matrix_1d(const Geometry& geo, bool dir_weights, int p, int nel, int k, const Vec& x, Mat& out) {
+  const Vec t = open_knots(p, nel, 1);
+  out = bspline_matrix(t, p, x);
+  if (!dir_weights) return true;
+  const Vec g = greville(t, p);
+  Mat Bg = bspline_matrix(t, p, g), Bgi;
+  if (!lu_inverse(Bg, Bgi)) return false;
+  Vec wf(g.size()), w(g.size(), 0.0);
+  for (size_t i = 0; i < g.size(); ++i) wf[i] = geo.weight1d(k, g[i]);
+  for (size_t i = 0; i < g.size(); ++i)
+    for (size_t j = 0; j < g.size(); ++j) w[i] += Bgi(i, j) * wf[j];
+  for (int a = 0; a < out.rows; ++a) {
+    double den = 0;
+    for (int j = 0; j < out.cols; ++j) den += w[j] * out(a, j);
+    for (int j = 0; j < out.cols; ++j) out(a, j) = w[j] * out(a, j) / den;
+  }
+  return true;
+}
+
+}  // namespace ka

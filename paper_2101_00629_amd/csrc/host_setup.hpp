@@ -66,6 +66,14 @@ struct NurbsVolume {
   void eval(const double* xh, double* x, double* dF, double* W) const;
 };
 
+// Trial-space factor of parametric direction k at points x (rows are points):
+// the degree-p B-splines on nel uniform elements, or, with dir_weights, the
+// NURBS functions w_j B_j / sum_l w_l B_l whose weights interpolate the
+// direction's weight function (geo.weight1d) at the Greville points.
+// Returns false if that interpolation matrix is singular.
+struct Geometry;
+bool trial_matrix_1d(const Geometry& geo, bool dir_weights, int p, int nel, int k, const Vec& x, Mat& out);
+
 // Geometry: parametric point -> physical point, |det DF|.
 struct Geometry {
   int domain = 0;              // 0 box, 1 quarter annulus, 2 general NURBS volume

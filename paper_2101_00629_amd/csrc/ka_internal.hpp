@@ -7,6 +7,7 @@
 #include <vector>
 
 #include "../../include/ka.h"
+#include "host_setup.hpp"
 
 namespace ka {
 
@@ -151,6 +152,7 @@ struct DevBuf {
 
 struct Problem {
   ka_desc d;
+  Geometry geo;              // host copy of the domain map
   hipStream_t stream = nullptr;
   int device = 0;
   int N = 0, n[3] = {0, 0, 0};
@@ -163,6 +165,7 @@ struct Problem {
   double* LinvT[3] = {nullptr, nullptr, nullptr};   // (L_k^-T) n x n  (Galerkin)
   double* Linv[3] = {nullptr, nullptr, nullptr};    // (L_k^-1)
   double* Zinv[3] = {nullptr, nullptr, nullptr};    // (Z_k^-1) (collocation LU inverse / Galerkin mass inverse)
+  double* Zk[3] = {nullptr, nullptr, nullptr};      // Galerkin: mass matrices Z_k (n x n)
   float* T[3] = {nullptr, nullptr, nullptr};        // Galerkin: B~_k^-T M_k (nt x n); collocation: R_q,k (nq x n)
   float* TT[3] = {nullptr, nullptr, nullptr};       // transposes (n x nt)
   float* rows = nullptr;     // row points (x, y, z, 0), prescaled
