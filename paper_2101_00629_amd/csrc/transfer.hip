@@ -22,7 +22,13 @@ __global__ void mode_product_kernel(ModeArgs a, int64_t total) {
   no[a.mode] = a.m;
   const int64_t Nout = (int64_t)no[0] * no[1] * no[2];
   int64_t i, j;
-  if (a.out_layout == LAYOUT_COL) { i = id % Nout; j = id / Nout; }
+  // Threads follow the input's memory order, so the reads coalesce; when the
+  // output layout differs, the scattered stores of a workgroup fill whole
+  // lines in the write-back L2 before they reach HBM.  (Following the
+  // output's order instead made every input read stride over whole point
+  // rows: 19 ms instead of about 1 ms for a 287,496 x 64 point-major FP32 to
+  // column-major FP64 product.)
+  if (a.in_layout == LAYOUT_COL) { i = id % Nout; j = id / Nout; }
   else { i = id / a.nv; j = id % a.nv; }   // threads over the nv live columns
   const int o1 = (int)(i % no[0]);
   const int o2 = (int)((i / no[0]) % no[1]);
