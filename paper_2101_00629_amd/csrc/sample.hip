@@ -79,12 +79,13 @@ __global__ void xi_scale_kernel(const double* __restrict__ Xi, int64_t ldxi, int
 // (columns: points), so a lane's 16 consecutive points land in consecutive
 // addresses.  Operand layout (gfx950): A lane l holds (row l % 16, k = l / 16),
 // B lane l holds (k = l / 16, column l % 16), accumulator register r of lane l
-// holds (row l / 16 + 4 r, column l % 16).  A workgroup of 4 waves covers
-// 64 samples x 128 points (each wave 32 x 64: 2 x 4 MFMA tiles).  Workgroups
+// holds (row l / 16 + 4 r, column l % 16).  A workgroup of 2 x 2 waves covers
+// kFS samples x kFP points (each wave kU x kT MFMA tiles).  Workgroups
 // are dealt to the 8 XCDs round-robin by id; the id mapping gives each XCD
 // whole point-tiles (all their sample tiles back to back), so a tile of Phi
 // is fetched from HBM into one L2 once.
-constexpr int kFS = 64, kFP = 128;
+constexpr int kU = 2, kT = 4;                       // 16 x 16 MFMA tiles per wave: samples x points
+constexpr int kFS = 2 * 16 * kU, kFP = 2 * 16 * kT;  // workgroup tile (2 x 2 waves)
 
 __global__ __launch_bounds__(256) void kl_field_kernel(const double* __restrict__ Phi, int64_t ldp, int64_t P,
                                                        const double* __restrict__ XiT, int S, int K, double mu,
@@ -96,48 +97,48 @@ __global__ __launch_bounds__(256) void kl_field_kernel(const double* __restrict_
   if (pt >= n_pt) return;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int li = lane & 15, lk = lane >> 4;
-  const int64_t p0 = pt * kFP + (wave & 1) * 64;
-  const int s0 = st * kFS + (wave >> 1) * 32;
-  d4v acc[2][4];
+  const int64_t p0 = pt * kFP + (wave & 1) * (16 * kT);
+  const int s0 = st * kFS + (wave >> 1) * (16 * kU);
+  d4v acc[kU][kT];
 #pragma unroll
-  for (int u = 0; u < 2; ++u)
+  for (int u = 0; u < kU; ++u)
 #pragma unroll
-    for (int t = 0; t < 4; ++t) acc[u][t] = (d4v){0.0, 0.0, 0.0, 0.0};
+    for (int t = 0; t < kT; ++t) acc[u][t] = (d4v){0.0, 0.0, 0.0, 0.0};
   // operands of k-step k0 (rows k0 + lk of XiT^T and Phi^T); zero past the edges
   auto load = [&](int k0, double* a, double* b) {
     const int k = k0 + lk;
 #pragma unroll
-    for (int u = 0; u < 2; ++u) {
+    for (int u = 0; u < kU; ++u) {
       const int s = s0 + 16 * u + li;
       a[u] = (k < K && s < S) ? XiT[s + (int64_t)k * S] : 0.0;
     }
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
+    for (int t = 0; t < kT; ++t) {
       const int64_t p = p0 + 16 * t + li;
       b[t] = (k < K && p < P) ? Phi[p + (int64_t)k * ldp] : 0.0;
     }
   };
-  double a[2], b[4];
+  double a[kU], b[kT];
   load(0, a, b);
   for (int k0 = 0; k0 < K; k0 += 4) {
     // the next step's operands are requested before this step's MFMAs; the
     // scheduling barrier keeps the compiler from sinking the loads
-    double an[2], bn[4];
+    double an[kU], bn[kT];
     load(k0 + 4, an, bn);
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-    for (int u = 0; u < 2; ++u)
+    for (int u = 0; u < kU; ++u)
 #pragma unroll
-      for (int t = 0; t < 4; ++t) acc[u][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], b[t], acc[u][t], 0, 0, 0);
+      for (int t = 0; t < kT; ++t) acc[u][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], b[t], acc[u][t], 0, 0, 0);
 #pragma unroll
-    for (int u = 0; u < 2; ++u) a[u] = an[u];
+    for (int u = 0; u < kU; ++u) a[u] = an[u];
 #pragma unroll
-    for (int t = 0; t < 4; ++t) b[t] = bn[t];
+    for (int t = 0; t < kT; ++t) b[t] = bn[t];
   }
 #pragma unroll
-  for (int u = 0; u < 2; ++u)
+  for (int u = 0; u < kU; ++u)
 #pragma unroll
-    for (int t = 0; t < 4; ++t)
+    for (int t = 0; t < kT; ++t)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int s = s0 + 16 * u + lk + 4 * r;
