@@ -34,7 +34,7 @@ import numpy as np
 import scipy.linalg as sla
 
 from . import splines, kernels, kron
-from .geometry import make_domain
+from .geometry import make_domain, c0_lines
 
 
 class _LUSolve:
@@ -62,9 +62,11 @@ class Collocation:
         self.kernel, self.ell, self.sigma = kernel, ell, sigma
         self.nq = int(nq or (self.p + 1))
         self.rational = bool(getattr(self.domain, "rational", False))
-        self.gk, self.Rqk, self.Zk, self.xqk, self.wqk = [], [], [], [], []
+        self.gk, self.Rqk, self.Zk, self.xqk, self.wqk, self.knots = [], [], [], [], [], []
         for k, e in enumerate(self.nel):
-            t = splines.open_knots(self.p, e, 1)
+            # the solution space is C^0 where the geometry is (Sec. 4.1)
+            t = splines.open_knots(self.p, e, 1, lines=c0_lines(self.domain, k), line_mult=self.p)
+            self.knots.append(t)
             g = splines.greville(t, self.p)
             xq, wq = splines.element_quadrature(t, self.nq)
             self.gk.append(g)

@@ -16,6 +16,12 @@ and C^0 for the exponential kernel), J = diag(sqrt|det DF(g_a)|),
 B~ = B~_3 x B~_2 x B~_1 with (B~_k)[a, c] = B~_c(g_a) (rows are points), and
 M = M_3 x M_2 x M_1 with (M_k)[a, j] = integral of B~_a B_j.
 
+Where the geometry is only C^0 (a line xh_k = c, e.g. where two patches
+meet), |det DF| jumps.  There the solution space is C^0 (knot multiplicity p)
+and the interpolation space C^-1 (multiplicity p+1), Sec. 4.1; the two
+interpolation points that then share the abscissa c are evaluated from their
+own sides (basis rows and |det DF| as one-sided limits).
+
 The standard-form operator (eq. standard with A' = L^-1 A L^-T, C = L^-T) is
 applied in nine steps:
     L^-T, M, B~^-T, J, Gamma, J, B~^-1, M^T, L^-1.
@@ -26,7 +32,7 @@ import numpy as np
 import scipy.linalg as sla
 
 from . import splines, kernels, kron
-from .geometry import make_domain
+from .geometry import make_domain, c0_lines
 
 
 class _TriSolve:
@@ -65,9 +71,10 @@ class GalerkinIBQ:
     kernel : "gaussian" | "exponential", or a callable Gamma(X, Y) -> matrix
     ell, sigma : kernel parameters
     interp_mult : interior knot multiplicity of the interpolation space
+    lines  : per direction, the C^0 lines of the geometry (None: the domain's own)
     """
 
-    def __init__(self, domain, p, nel, kernel, ell, sigma=1.0, interp_mult=None):
+    def __init__(self, domain, p, nel, kernel, ell, sigma=1.0, interp_mult=None, lines=None):
         self.domain = make_domain(domain) if isinstance(domain, str) else domain
         self.p = int(p)
         self.nel = tuple(int(e) for e in nel)
@@ -75,20 +82,25 @@ class GalerkinIBQ:
         if interp_mult is None:
             interp_mult = default_interp_mult(kernel, self.p) if isinstance(kernel, str) else 1
         self.interp_mult = interp_mult
+        if lines is None:
+            lines = [c0_lines(self.domain, k) for k in range(3)]
+        self.lines = [tuple(l) for l in lines]
         self.knots, self.iknots = [], []
-        self.Zk, self.Lk, self.Mk, self.Btk, self.gk = [], [], [], [], []
-        for e in self.nel:
-            t = splines.open_knots(self.p, e, 1)
-            ti = splines.open_knots(self.p, e, interp_mult)
+        self.Zk, self.Lk, self.Mk, self.Btk, self.gk, self.leftk = [], [], [], [], [], []
+        for k, e in enumerate(self.nel):
+            t = splines.open_knots(self.p, e, 1, lines=self.lines[k], line_mult=self.p)
+            ti = splines.open_knots(self.p, e, interp_mult, lines=self.lines[k], line_mult=self.p + 1)
             g = splines.greville(ti, self.p)
+            gl = splines.greville_left(ti, self.p)
             Zk = splines.mass_matrix(t, self.p, t, self.p)
             self.knots.append(t)
             self.iknots.append(ti)
             self.Zk.append(Zk)
             self.Lk.append(np.linalg.cholesky(Zk))
             self.Mk.append(splines.mass_matrix(ti, self.p, t, self.p))
-            self.Btk.append(splines.collocation_matrix(ti, self.p, g))
+            self.Btk.append(splines.basis_matrix(ti, self.p, g, left=gl))
             self.gk.append(g)
+            self.leftk.append(gl)
         self.n = tuple(Z.shape[0] for Z in self.Zk)
         self.nt = tuple(len(g) for g in self.gk)
         self.N = int(np.prod(self.n))
@@ -96,8 +108,10 @@ class GalerkinIBQ:
         # interpolation points, flat index a = a1 + n1 (a2 + n2 a3)
         g3, g2, g1 = np.meshgrid(self.gk[2], self.gk[1], self.gk[0], indexing="ij")
         self.xhat = np.stack([g1.ravel(), g2.ravel(), g3.ravel()], axis=-1)
-        self.X = self.domain.map(self.xhat)
-        self.J = np.sqrt(np.abs(self.domain.detJ(self.xhat)))
+        l3, l2, l1 = np.meshgrid(self.leftk[2], self.leftk[1], self.leftk[0], indexing="ij")
+        self.left = np.stack([l1.ravel(), l2.ravel(), l3.ravel()], axis=-1)
+        self.X = self.domain.map(self.xhat, self.left)
+        self.J = np.sqrt(np.abs(self.domain.detJ(self.xhat, self.left)))
 
     # -- kernel -----------------------------------------------------------
     def gamma_matrix(self, rows=None):
@@ -199,8 +213,11 @@ class GalerkinGauss:
         self.kernel, self.ell, self.sigma = kernel, ell, sigma
         q1d = q1d or (self.p + 1)
         Bq, xq, wq, Zk = [], [], [], []
-        for e in self.nel:
-            t = splines.open_knots(self.p, e, 1)
+        self.knots = []
+        for k, e in enumerate(self.nel):
+            # C^0 at the geometry's C^0 lines, as for IBQ
+            t = splines.open_knots(self.p, e, 1, lines=c0_lines(self.domain, k), line_mult=self.p)
+            self.knots.append(t)
             x, w = splines.element_quadrature(t, q1d)
             Bq.append(splines.basis_matrix(t, self.p, x))
             xq.append(x)

@@ -23,13 +23,17 @@ class Box:
         self.lo = np.asarray(lo, dtype=np.float64)
         self.hi = np.asarray(hi, dtype=np.float64)
 
-    def map(self, xh):
+    def map(self, xh, left=None):
         xh = np.asarray(xh, dtype=np.float64)
         return self.lo + (self.hi - self.lo) * xh
 
-    def detJ(self, xh):
+    def detJ(self, xh, left=None):
         xh = np.asarray(xh, dtype=np.float64)
         return np.full(xh.shape[:-1], np.prod(self.hi - self.lo))
+
+    def c0_lines(self, k):
+        """Interior parametric positions where the map is only C^0 (none)."""
+        return ()
 
     def volume(self):
         return float(np.prod(self.hi - self.lo))
@@ -74,13 +78,13 @@ class QuarterAnnulus:
     def __init__(self, r0=1.0, r1=2.0, height=1.0):
         self.r0, self.r1, self.height = float(r0), float(r1), float(height)
 
-    def map(self, xh):
+    def map(self, xh, left=None):
         xh = np.asarray(xh, dtype=np.float64)
         C, _ = quarter_circle(xh[..., 0])
         r = self.r0 + (self.r1 - self.r0) * xh[..., 1]
         return np.stack([r * C[..., 0], r * C[..., 1], self.height * xh[..., 2]], axis=-1)
 
-    def detJ(self, xh):
+    def detJ(self, xh, left=None):
         xh = np.asarray(xh, dtype=np.float64)
         _, dC = quarter_circle(xh[..., 0])
         r = self.r0 + (self.r1 - self.r0) * xh[..., 1]
@@ -88,6 +92,9 @@ class QuarterAnnulus:
 
     def volume(self):
         return np.pi / 4 * (self.r1 ** 2 - self.r0 ** 2) * self.height
+
+    def c0_lines(self, k):
+        return ()
 
     def weight1d(self, k, t):
         """NURBS weight function of direction k: D(xi) along xi, 1 otherwise."""
@@ -116,26 +123,36 @@ class NurbsVolume:
         # homogeneous control points (w x, w y, w z, w)
         self.H = np.concatenate([ctrl[..., :3] * ctrl[..., 3:4], ctrl[..., 3:4]], axis=-1)
 
-    def _sums(self, xh):
-        """Homogeneous sum and its three parametric derivatives at points xh (m, 3)."""
+    def c0_lines(self, k):
+        """Interior knots of direction k repeated at least p_k times: there the
+        map is only C^0 (Sec. 4.1), e.g. where two patches meet."""
+        t, p = self.t[k], self.p[k]
+        vals, counts = np.unique(t, return_counts=True)
+        return tuple(float(v) for v, c in zip(vals, counts) if t[0] < v < t[-1] and c >= p)
+
+    def _sums(self, xh, left=None):
+        """Homogeneous sum and its three parametric derivatives at points xh (m, 3);
+        left (m, 3) booleans take direction k's limit from the left."""
         from . import splines
-        B = [splines.basis_matrix(self.t[k], self.p[k], xh[:, k]) for k in range(3)]
-        D = [splines.basis_derivative_matrix(self.t[k], self.p[k], xh[:, k]) for k in range(3)]
+        lf = [None if left is None else left[:, k] for k in range(3)]
+        B = [splines.basis_matrix(self.t[k], self.p[k], xh[:, k], lf[k]) for k in range(3)]
+        D = [splines.basis_derivative_matrix(self.t[k], self.p[k], xh[:, k], lf[k]) for k in range(3)]
         S = np.einsum("ma,mb,mc,cbad->md", B[0], B[1], B[2], self.H)
         S1 = np.einsum("ma,mb,mc,cbad->md", D[0], B[1], B[2], self.H)
         S2 = np.einsum("ma,mb,mc,cbad->md", B[0], D[1], B[2], self.H)
         S3 = np.einsum("ma,mb,mc,cbad->md", B[0], B[1], D[2], self.H)
         return S, (S1, S2, S3)
 
-    def _eval(self, xh, chunk=4096):
+    def _eval(self, xh, left=None, chunk=4096):
         xh = np.asarray(xh, dtype=np.float64)
         shape = xh.shape[:-1]
         flat = xh.reshape(-1, 3)
+        lflat = None if left is None else np.broadcast_to(np.asarray(left, dtype=bool), xh.shape).reshape(-1, 3)
         X = np.empty((len(flat), 3))
         J = np.empty(len(flat))
         W = np.empty(len(flat))
         for s0 in range(0, len(flat), chunk):
-            S, dS = self._sums(flat[s0:s0 + chunk])
+            S, dS = self._sums(flat[s0:s0 + chunk], None if lflat is None else lflat[s0:s0 + chunk])
             w = S[:, 3]
             x = S[:, :3] / w[:, None]
             # dF[:, c, k] = (dS_k[c] - x_c dS_k[w]) / w
@@ -145,15 +162,16 @@ class NurbsVolume:
             W[s0:s0 + chunk] = w
         return X.reshape(shape + (3,)), J.reshape(shape), W.reshape(shape)
 
-    def map(self, xh):
-        return self._eval(xh)[0]
+    def map(self, xh, left=None):
+        return self._eval(xh, left)[0]
 
-    def detJ(self, xh):
-        return np.abs(self._eval(xh)[1])
+    def detJ(self, xh, left=None):
+        """|det DF|; at a C^0 line it jumps, and `left` picks the side."""
+        return np.abs(self._eval(xh, left)[1])
 
-    def weight(self, xh):
+    def weight(self, xh, left=None):
         """The weight function W at parametric points."""
-        return self._eval(xh)[2]
+        return self._eval(xh, left)[2]
 
     def volume(self, q=None):
         """Integral of |det DF| by Gauss-Legendre on every knot span (q per span and direction)."""
@@ -166,6 +184,12 @@ class NurbsVolume:
         w3, w2, w1 = np.meshgrid(rules[2][1], rules[1][1], rules[0][1], indexing="ij")
         xh = np.stack([g1.ravel(), g2.ravel(), g3.ravel()], axis=-1)
         return float(np.sum(self.detJ(xh) * (w1 * w2 * w3).ravel()))
+
+
+def c0_lines(domain, k):
+    """The domain's C^0 lines in parametric direction k (none for closed-form maps)."""
+    f = getattr(domain, "c0_lines", None)
+    return tuple(f(k)) if f else ()
 
 
 def make_domain(name, **kw):

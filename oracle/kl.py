@@ -29,7 +29,7 @@ def _is_collocation(disc):
 
 def _trial_1d(disc, k, x):
     """Univariate factor of the trial space in direction k, rows are points."""
-    t = splines.open_knots(disc.p, disc.nel[k], 1)
+    t = disc.knots[k]
     if _is_collocation(disc) and not disc.rational:
         return nurbs_basis_1d(t, disc.p, lambda s: disc.domain.weight1d(k, s), np.asarray(x))
     return splines.basis_matrix(t, disc.p, np.asarray(x))
@@ -57,7 +57,7 @@ def eigenfunctions(disc, V, grid):
 def l2_norms(disc, V):
     """||phi_i||_{L^2(D)} by the Gauss rule described in the module docstring."""
     q = disc.nq if _is_collocation(disc) else disc.p + 1
-    rules = [splines.element_quadrature(splines.open_knots(disc.p, e, 1), q) for e in disc.nel]
+    rules = [splines.element_quadrature(t, q) for t in disc.knots]
     grid = [r[0] for r in rules]
     w3, w2, w1 = np.meshgrid(rules[2][1], rules[1][1], rules[0][1], indexing="ij")
     w = (w1 * w2 * w3).ravel() * np.abs(disc.domain.detJ(grid_points(grid)))

@@ -68,6 +68,36 @@ def nurbs_annulus_net(r0=1.0, r1=2.0, height=1.0):
     return dict(degree=(2, 1, 1), knots=([0, 0, 0, 1, 1, 1], [0, 0, 1, 1], [0, 0, 1, 1]), ctrl=ctrl)
 
 
+def half_cylinder_net(r0=8.0, r1=10.0, length=15.0):
+    """Control net of a thick-walled half cylinder as one NURBS patch: along
+    xi the half circle as two rational quadratic quarter arcs (knots
+    0,0,0,1/2,1/2,1,1,1; control points (1,0), (1,1), (0,1), (-1,1), (-1,0)
+    with weights 1, 1/sqrt(2), 1, 1/sqrt(2), 1), so the map is only C^0 in
+    the knot sense at xi = 1/2; linear in the radius (eta, r0..r1) and along
+    the axis (zeta, 0..length)."""
+    s = 1.0 / math.sqrt(2.0)
+    w = (1.0, s, 1.0, s, 1.0)
+    cx, cy = (1.0, 1.0, 0.0, -1.0, -1.0), (0.0, 1.0, 1.0, 1.0, 0.0)
+    ctrl = np.zeros((2, 2, 5, 4))
+    for j3 in range(2):
+        for j2, r in enumerate((r0, r1)):
+            for j1 in range(5):
+                ctrl[j3, j2, j1] = (r * cx[j1], r * cy[j1], length * j3, w[j1])
+    return dict(degree=(2, 1, 1), knots=([0, 0, 0, 0.5, 0.5, 1, 1, 1], [0, 0, 1, 1], [0, 0, 1, 1]), ctrl=ctrl)
+
+
+def kinked_box_net(kink=0.5, at=0.3, hi=(1.0, 1.0, 1.0)):
+    """The box [0, hi] as a NURBS patch whose xi direction is piecewise
+    linear: parameter `kink` maps to x = at * hi[0], so dx/dxi (and |det DF|)
+    jumps there, a C^0 line.  Linear in eta and zeta, unit weights."""
+    ctrl = np.zeros((2, 2, 3, 4))
+    for j3 in range(2):
+        for j2 in range(2):
+            for j1, x in enumerate((0.0, at * hi[0], hi[0])):
+                ctrl[j3, j2, j1] = (x, hi[1] * j2, hi[2] * j3, 1.0)
+    return dict(degree=(1, 1, 1), knots=([0, 0, kink, 1, 1], [0, 0, 1, 1], [0, 0, 1, 1]), ctrl=ctrl)
+
+
 def nurbs_blob_net(seed=0, n=(4, 4, 4), degree=(2, 2, 2), wiggle=0.06, wrange=(0.6, 1.6)):
     """Seeded curved volume near the unit cube: open uniform knots with
     n[k] - degree[k] spans, control points at the knot averages (Greville
