@@ -80,9 +80,18 @@ enum ka_solve_op { KA_ZINV = 0,   /* X <- Z^-1 X                                
  *              full LU is formed.
  * degree/nel   B-spline degree and element count per parametric direction
  *              (solution space with C^{p-1} continuity, open uniform knots).
+ *              C^0 lines (Sec. 4.1): on KA_NURBS, an interior geometry knot
+ *              repeated at least geo_degree[k] times is a line where the map
+ *              is only C^0 (e.g. where two patches meet).  It is added to the
+ *              analysis mesh if it is not a uniform breakpoint, the solution
+ *              space is C^0 there (all methods), and the IBQ interpolation
+ *              space C^-1; its two interpolation points at the line are
+ *              evaluated from their own sides (|det DF| jumps there).
+ *              ka_desc_size gives the resulting N and Ntilde.
  * interp_cont  Galerkin only: continuity of the interpolation space S~;
  *              -1 = automatic: C^0 for KA_EXP_L1 (Sec. 4.1), C^{p-1} for
- *              KA_GAUSSIAN (Sec. 4.2); otherwise 0 .. p-1.
+ *              KA_GAUSSIAN (Sec. 4.2); otherwise 0 .. p-1 (C^-1 at C^0 lines
+ *              in any case).
  * kernel/sigma/ell  covariance kernel and its parameters (ell > 0; ell = +inf
  *              is allowed for KA_GAUSSIAN and gives the constant kernel).
  * nq           collocation and Gauss Galerkin: Gauss points per element and
@@ -149,6 +158,11 @@ int ka_setup(const ka_desc* desc, void* stream, ka_problem** out);
  * NULL. */
 int ka_size(const ka_problem* p, int64_t* N, int64_t* Ntilde, int64_t* Nquad,
             size_t* device_bytes);
+
+/* The sizes ka_size would report for a problem set up from `desc` (see
+ * degree/nel and the C^0 lines in ka_desc); host only, no device work.
+ * KA_ERR_ARG for an invalid description.  Any output pointer may be NULL. */
+int ka_desc_size(const ka_desc* desc, int64_t* N, int64_t* Ntilde, int64_t* Nquad);
 
 /* Device bytes ka_setup would allocate for `desc` (admission control); no
  * device work. */

@@ -99,10 +99,12 @@ def basis_derivative_matrix(knots, p, x, left=None):
 
 
 def greville(knots, p):
-    """Greville abscissae gamma_i = (t_{i+1} + ... + t_{i+p}) / p."""
+    """Greville abscissae gamma_i = (t_{i+1} + ... + t_{i+p}) / p; when the p
+    knots are equal the abscissa is that knot, exactly (a rounded mean could
+    land beside it)."""
     t = np.asarray(knots, dtype=np.float64)
     n = num_basis(t, p)
-    return np.array([t[i + 1:i + p + 1].mean() for i in range(n)])
+    return np.array([t[i + 1] if t[i + 1] == t[i + p] else t[i + 1:i + p + 1].mean() for i in range(n)])
 
 
 def greville_left(knots, p):

@@ -79,6 +79,8 @@ def _load():
         "ka_size": ([vp, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i64),
                      ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
         "ka_footprint": ([ctypes.POINTER(ka_desc), ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+        "ka_desc_size": ([ctypes.POINTER(ka_desc), ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i64)],
+                         ctypes.c_int),
         "ka_apply_A": ([vp, ctypes.c_int, vp, i64, vp, i64, ctypes.c_int, vp], ctypes.c_int),
         "ka_solve_Z": ([vp, ctypes.c_int, vp, i64, ctypes.c_int, vp], ctypes.c_int),
         "ka_eigs": ([vp, ctypes.c_int, ctypes.c_double, ctypes.c_int, dp, vp, ctypes.POINTER(ka_info)],
@@ -114,7 +116,7 @@ _lib = _load()
 EXPORTED = ("ka_setup", "ka_size", "ka_footprint", "ka_apply_A", "ka_solve_Z", "ka_eigs", "ka_gamma_apply",
             "ka_gamma_workspace", "ka_profile_enable", "ka_profile_read", "ka_profile_reset", "ka_destroy",
             "ka_last_error", "ka_server_create", "ka_server_submit", "ka_server_run", "ka_server_poll",
-            "ka_server_stats", "ka_server_destroy", "ka_request_bytes", "ka_kl_sample")
+            "ka_server_stats", "ka_server_destroy", "ka_request_bytes", "ka_kl_sample", "ka_desc_size")
 
 
 class KAError(RuntimeError):
@@ -199,6 +201,14 @@ def ka_size(h):
     N, Nt, Nq, nb = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64(), ctypes.c_size_t()
     _check(_lib.ka_size(h, ctypes.byref(N), ctypes.byref(Nt), ctypes.byref(Nq), ctypes.byref(nb)), "ka_size")
     return N.value, Nt.value, Nq.value, nb.value
+
+
+def ka_desc_size(desc):
+    """(N, Ntilde, Nquad) that ka_setup would produce for desc (host only)."""
+    N, Nt, Nq = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+    _check(_lib.ka_desc_size(ctypes.byref(desc), ctypes.byref(N), ctypes.byref(Nt), ctypes.byref(Nq)),
+           "ka_desc_size")
+    return N.value, Nt.value, Nq.value
 
 
 def ka_footprint(desc):

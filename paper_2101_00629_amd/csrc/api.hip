@@ -51,6 +51,7 @@ struct Sizes {
   int n[3], nt[3], nq[3];
   int64_t N, Nt, Nq, n_rows, n_cols;
   int mult[3];
+  Vec tsol[3], tint[3];   // knot vectors of the solution and (IBQ) interpolation spaces
 };
 
 // Geometry data of a KA_NURBS description; empty string, or why it is invalid.
@@ -93,11 +94,16 @@ static int check_desc(const ka_desc* d, Sizes& z) {
   if (d->domain == KA_BOX) {
     for (int k = 0; k < 3; ++k)
       if (!(d->hi[k] > d->lo[k])) return fail(KA_ERR_ARG, "box needs hi > lo");
-  } else if (d->domain == KA_NURBS) {
+  }
+  // The geometry's C^0 lines (Sec. 4.1): the solution space is C^0 there and
+  // the IBQ interpolation space C^-1 (a broken space).
+  Vec lines[3];
+  if (d->domain == KA_NURBS) {
     NurbsVolume nv;
     const std::string why = nurbs_from_desc(d, nv);
     if (!why.empty()) return fail(KA_ERR_ARG, why);
-  } else {
+    for (int k = 0; k < 3; ++k) lines[k] = nv.c0_lines(k);
+  } else if (d->domain == KA_QUARTER_ANNULUS) {
     if (!(d->r1 > d->r0 && d->r0 > 0 && d->height > 0)) return fail(KA_ERR_ARG, "annulus needs 0 < r0 < r1, height > 0");
   }
   z.N = z.Nt = z.Nq = 1;
@@ -105,7 +111,7 @@ static int check_desc(const ka_desc* d, Sizes& z) {
     const int p = d->degree[k], e = d->nel[k];
     if (p < 1 || p > 8) return fail(KA_ERR_ARG, "degree must be in 1..8");
     if (e < 1 || e > 4096) return fail(KA_ERR_ARG, "nel must be in 1..4096");
-    z.n[k] = p + e;
+    if (lines[k].size() > 4096) return fail(KA_ERR_ARG, "too many C0 lines in the geometry");
     int mult = 1;
     if (d->method == KA_GALERKIN_IBQ) {
       if (d->interp_cont < 0) mult = (d->kernel == KA_EXP_L1) ? p : 1;
@@ -113,10 +119,15 @@ static int check_desc(const ka_desc* d, Sizes& z) {
       else return fail(KA_ERR_ARG, "interp_cont must be -1 or 0..p-1");
     }
     z.mult[k] = mult;
-    z.nt[k] = p + 1 + mult * (e - 1);
+    z.tsol[k] = analysis_knots(p, e, 1, lines[k], p);
+    z.tint[k] = analysis_knots(p, e, mult, lines[k], p + 1);
+    z.n[k] = num_basis(z.tsol[k], p);
+    z.nt[k] = num_basis(z.tint[k], p);
+    int elems = 0;
+    for (size_t i = 0; i + 1 < z.tsol[k].size(); ++i) elems += z.tsol[k][i + 1] > z.tsol[k][i];
     const int q = d->nq > 0 ? d->nq : p + 1;
     if (q > 16) return fail(KA_ERR_ARG, "nq must be <= 16");
-    z.nq[k] = q * e;
+    z.nq[k] = q * elems;
     z.N *= z.n[k];
     z.Nt *= z.nt[k];
     z.Nq *= z.nq[k];
@@ -243,9 +254,11 @@ static int setup_impl(const ka_desc* d, hipStream_t stream, Problem** out) {
   // univariate factors
   std::vector<Vec> pts1d(3);      // Galerkin: interpolation Greville points; collocation: Greville points
   std::vector<Vec> q1d(3), w1d(3);
+  std::vector<std::vector<char>> left1d(3);   // IBQ: interpolation points taken from the left
   for (int k = 0; k < 3; ++k) {
-    const int p = d->degree[k], e = d->nel[k];
-    const Vec t = open_knots(p, e, 1);
+    const int p = d->degree[k];
+    const Vec& t = z.tsol[k];
+    P->tsol[k] = t;
     if (d->method == KA_GALERKIN_GAUSS) {
       // standard Galerkin (Sec. 3.1): basis values at the element Gauss points
       Mat Zk = mass_matrix(t, p, t, p), Lk;
@@ -278,10 +291,11 @@ static int setup_impl(const ka_desc* d, hipStream_t stream, Problem** out) {
       P->LinvT[k] = upload(P, to_vec(LiT), ok);
       P->Zinv[k] = upload(P, to_vec(matmul(LiT, Li)), ok);
       P->Zk[k] = upload(P, to_vec(Zk), ok);   // mass matrix: exact L2 norms of eigenfunctions
-      const Vec ti = open_knots(p, e, z.mult[k]);
+      const Vec& ti = z.tint[k];
       const Vec g = greville(ti, p);
+      left1d[k] = greville_left(ti, p);                      // one-sided at C^-1 knots
       const Mat Mk = mass_matrix(ti, p, t, p);               // nt x n
-      const Mat Bt = bspline_matrix(ti, p, g);               // nt x nt, rows are points
+      const Mat Bt = bspline_matrix(ti, p, g, &left1d[k]);   // nt x nt, rows are points
       Mat Bti;
       if (!lu_inverse(Bt, Bti)) {
         free_problem(P);
@@ -297,7 +311,7 @@ static int setup_impl(const ka_desc* d, hipStream_t stream, Problem** out) {
       element_gauss(t, d->nq > 0 ? d->nq : p + 1, xq, wq);
       // NURBS functions of the direction (weights interpolating its weight function)
       Mat Rq, Zc;
-      if (!trial_matrix_1d(geo, true, p, e, k, xq, Rq) || !trial_matrix_1d(geo, true, p, e, k, g, Zc)) {
+      if (!trial_matrix_1d(geo, true, t, p, k, xq, Rq) || !trial_matrix_1d(geo, true, t, p, k, g, Zc)) {
         free_problem(P);
         return fail(KA_ERR_SINGULAR, "Greville collocation matrix is singular");
       }
@@ -317,8 +331,9 @@ static int setup_impl(const ka_desc* d, hipStream_t stream, Problem** out) {
   // point sets
   // mapped points (centred, prescaled FP32), optionally |det DF| and the
   // NURBS weight function W at the tensor grid g[0] x g[1] x g[2]
+  // (`left`: per direction, points evaluated as limits from the left)
   auto tensor_points = [&](const std::vector<Vec>& g, std::vector<float>& xyz, std::vector<double>* detJ,
-                           std::vector<double>* W = nullptr) {
+                           std::vector<double>* W = nullptr, const std::vector<std::vector<char>>* left = nullptr) {
     const int64_t n1 = g[0].size(), n2 = g[1].size(), n3 = g[2].size();
     xyz.assign((size_t)n1 * n2 * n3 * 4, 0.f);
     if (detJ) detJ->assign((size_t)n1 * n2 * n3, 0.0);
@@ -328,15 +343,22 @@ static int setup_impl(const ka_desc* d, hipStream_t stream, Problem** out) {
         for (int64_t a1 = 0; a1 < n1; ++a1) {
           const int64_t i = a1 + n1 * (a2 + n2 * a3);
           const double xh[3] = {g[0][a1], g[1][a2], g[2][a3]};
+          char side[3] = {0, 0, 0};
+          if (left)
+            for (int k = 0; k < 3; ++k) {
+              const auto& lk = (*left)[k];
+              const int64_t a = k == 0 ? a1 : (k == 1 ? a2 : a3);
+              side[k] = lk.empty() ? 0 : lk[a];
+            }
           double x[3];
-          geo.eval(xh, x, detJ ? &(*detJ)[i] : nullptr, W ? &(*W)[i] : nullptr);
+          geo.eval(xh, x, detJ ? &(*detJ)[i] : nullptr, W ? &(*W)[i] : nullptr, side);
           for (int c = 0; c < 3; ++c) xyz[i * 4 + c] = (float)((x[c] - ctr[c]) * cs);
         }
   };
   if (d->method == KA_GALERKIN_IBQ) {
     std::vector<float> xyz;
     std::vector<double> dj;
-    tensor_points(pts1d, xyz, &dj);
+    tensor_points(pts1d, xyz, &dj, nullptr, &left1d);   // |det DF| one-sided where it jumps
     std::vector<float> J(dj.size());
     for (size_t i = 0; i < dj.size(); ++i) J[i] = (float)std::sqrt(dj[i]);
     P->rows = upload(P, xyz, ok);
@@ -605,6 +627,16 @@ int footprint(const ka_desc* d, size_t* bytes) {
   int rc = check_desc(d, z);
   if (rc) return rc;
   *bytes = setup_bytes(d, z);
+  return KA_OK;
+}
+
+int desc_sizes(const ka_desc* d, int64_t* N, int64_t* Nt, int64_t* Nq) {
+  Sizes z;
+  int rc = check_desc(d, z);
+  if (rc) return rc;
+  if (N) *N = z.N;
+  if (Nt) *Nt = z.Nt;
+  if (Nq) *Nq = z.Nq;
   return KA_OK;
 }
 

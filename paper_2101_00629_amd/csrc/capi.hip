@@ -30,6 +30,10 @@ int ka_size(const ka_problem* p, int64_t* N, int64_t* Ntilde, int64_t* Nquad, si
   return KA_OK;
 }
 
+int ka_desc_size(const ka_desc* desc, int64_t* N, int64_t* Ntilde, int64_t* Nquad) {
+  return desc_sizes(desc, N, Ntilde, Nquad);
+}
+
 int ka_footprint(const ka_desc* desc, size_t* device_bytes) {
   if (!device_bytes) return fail(KA_ERR_ARG, "device_bytes is NULL");
   return footprint(desc, device_bytes);

@@ -2,6 +2,7 @@
 #include "host_setup.hpp"
 
 #include <algorithm>
+#include <utility>
 #include <cmath>
 #include <stdexcept>
 
@@ -16,17 +17,39 @@ Vec open_knots(int p, int nel, int mult) {
   return t;
 }
 
+Vec analysis_knots(int p, int nel, int mult, const Vec& lines, int line_mult) {
+  std::vector<std::pair<double, int>> inner;
+  for (int e = 1; e < nel; ++e) inner.push_back({(double)e / nel, mult});
+  for (double c : lines) {
+    bool merged = false;
+    for (auto& b : inner)
+      if (std::fabs(b.first - c) <= 1e-12) {
+        b = {c, line_mult};
+        merged = true;
+      }
+    if (!merged) inner.push_back({c, line_mult});
+  }
+  std::sort(inner.begin(), inner.end());
+  Vec t(p + 1, 0.0);
+  for (const auto& b : inner)
+    for (int m = 0; m < b.second; ++m) t.push_back(b.first);
+  for (int i = 0; i <= p; ++i) t.push_back(1.0);
+  return t;
+}
+
 int num_basis(const Vec& t, int p) { return (int)t.size() - p - 1; }
 
-// Knot span s with t[s] <= x < t[s+1]; the right end belongs to the last span.
-static int find_span(const Vec& t, int p, double x) {
+// Knot span s with t[s] <= x < t[s+1] (left: t[s] < x <= t[s+1], the limit
+// from the left); the right end belongs to the last span, the left end to
+// the first.
+static int find_span(const Vec& t, int p, double x, bool left = false) {
   const int n = num_basis(t, p);
   if (x >= t[n]) return n - 1;
   if (x <= t[p]) return p;
   int lo = p, hi = n;
   while (hi - lo > 1) {
     int mid = (lo + hi) / 2;
-    if (x < t[mid]) hi = mid; else lo = mid;
+    if (left ? x <= t[mid] : x < t[mid]) hi = mid; else lo = mid;
   }
   return lo;
 }
@@ -48,18 +71,18 @@ static void nonzero_basis(const Vec& t, int p, int s, double x, double* N) {
   }
 }
 
-void bspline_row(const Vec& t, int p, double x, double* row) {
+void bspline_row(const Vec& t, int p, double x, double* row, bool left) {
   const int n = num_basis(t, p);
   std::fill(row, row + n, 0.0);
   double N[32];
-  const int s = find_span(t, p, x);
+  const int s = find_span(t, p, x, left);
   nonzero_basis(t, p, s, x, N);
   for (int r = 0; r <= p; ++r) row[s - p + r] = N[r];
 }
 
-Mat bspline_matrix(const Vec& t, int p, const Vec& x) {
+Mat bspline_matrix(const Vec& t, int p, const Vec& x, const std::vector<char>* left) {
   Mat B((int)x.size(), num_basis(t, p));
-  for (size_t a = 0; a < x.size(); ++a) bspline_row(t, p, x[a], &B.a[a * B.cols]);
+  for (size_t a = 0; a < x.size(); ++a) bspline_row(t, p, x[a], &B.a[a * B.cols], left && (*left)[a]);
   return B;
 }
 
@@ -69,9 +92,18 @@ Vec greville(const Vec& t, int p) {
   for (int i = 0; i < n; ++i) {
     double s = 0;
     for (int k = 1; k <= p; ++k) s += t[i + k];
-    g[i] = s / p;
+    // p equal knots: the abscissa is that knot exactly (the rounded mean may
+    // miss it, and a C^-1 abscissa must sit on its knot)
+    g[i] = t[i + 1] == t[i + p] ? t[i + 1] : s / p;
   }
   return g;
+}
+
+std::vector<char> greville_left(const Vec& t, int p) {
+  const Vec g = greville(t, p);
+  std::vector<char> left(g.size(), 0);
+  for (size_t i = 0; i < g.size(); ++i) left[i] = g[i] == t[i + p + 1] && t[i + p + 1] < t.back();
+  return left;
 }
 
 void gauss_legendre(int q, double a, double b, Vec& x, Vec& w) {
@@ -285,11 +317,23 @@ std::string NurbsVolume::check() const {
   return "";
 }
 
-void NurbsVolume::eval(const double* xh, double* x, double* dF, double* W) const {
+Vec NurbsVolume::c0_lines(int k) const {
+  Vec lines;
+  const Vec& tk = t[k];
+  for (size_t i = 0; i < tk.size();) {
+    size_t j = i;
+    while (j < tk.size() && tk[j] == tk[i]) ++j;
+    if (tk[i] > tk.front() && tk[i] < tk.back() && (int)(j - i) >= p[k]) lines.push_back(tk[i]);
+    i = j;
+  }
+  return lines;
+}
+
+void NurbsVolume::eval(const double* xh, double* x, double* dF, double* W, const char* left) const {
   double N[3][32], dN[3][32];
   int s[3];
   for (int k = 0; k < 3; ++k) {
-    s[k] = find_span(t[k], p[k], xh[k]);
+    s[k] = find_span(t[k], p[k], xh[k], left && left[k]);
     basis_with_derivative(t[k], p[k], s[k], xh[k], N[k], dN[k]);
   }
   // homogeneous sums A = sum w P N, w = sum w N, and their derivatives
@@ -320,7 +364,9 @@ void NurbsVolume::eval(const double* xh, double* x, double* dF, double* W) const
   if (W) *W = w;
 }
 
-void Geometry::eval(const double* xh, double* x, double* detJ, double* W) const {
+Vec Geometry::c0_lines(int k) const { return domain == 2 ? nurbs.c0_lines(k) : Vec(); }
+
+void Geometry::eval(const double* xh, double* x, double* detJ, double* W, const char* left) const {
   if (W) *W = 1.0;
   if (domain == 0) {
     for (int k = 0; k < 3; ++k) x[k] = lo[k] + (hi[k] - lo[k]) * xh[k];
@@ -336,7 +382,7 @@ void Geometry::eval(const double* xh, double* x, double* detJ, double* W) const 
     if (detJ) *detJ = std::fabs(r * (r1 - r0) * height * (C[0] * dC[1] - C[1] * dC[0]));
   } else {
     double F[9];
-    nurbs.eval(xh, x, detJ ? F : nullptr, W);
+    nurbs.eval(xh, x, detJ ? F : nullptr, W, left);
     if (detJ)
       *detJ = std::fabs(F[0] * (F[4] * F[8] - F[5] * F[7]) - F[1] * (F[3] * F[8] - F[5] * F[6]) +
                         F[2] * (F[3] * F[7] - F[4] * F[6]));
@@ -371,8 +417,7 @@ double Geometry::weight1d(int k, double t) const {
 
 namespace ka {
 
-bool trial_matrix_1d(const Geometry& geo, bool dir_weights, int p, int nel, int k, const Vec& x, Mat& out) {
-  const Vec t = open_knots(p, nel, 1);
+bool trial_matrix_1d(const Geometry& geo, bool dir_weights, const Vec& t, int p, int k, const Vec& x, Mat& out) {
   out = bspline_matrix(t, p, x);
   if (!dir_weights) return true;
   const Vec g = greville(t, p);

@@ -26,14 +26,26 @@ struct Mat {
 // Open uniform knot vector on [0,1]: p+1 end knots, interior breakpoints of
 // multiplicity `mult` (continuity C^{p-mult}).
 Vec open_knots(int p, int nel, int mult);
+// Knot vector of an analysis space (paper Sec. 4.1): nel uniform elements
+// with interior multiplicity `mult`, plus `lines` (positions where the
+// geometry is only C^0) with multiplicity `line_mult` (p: C^0, p+1: C^-1),
+// added to the mesh where they are not uniform breakpoints already.
+Vec analysis_knots(int p, int nel, int mult, const Vec& lines, int line_mult);
 int num_basis(const Vec& t, int p);
 
-// Values of all num_basis B-splines at x (dense row of length n).
-void bspline_row(const Vec& t, int p, double x, double* row);
-// n x len(x) evaluation matrix B[a][c] = B_c(x_a).
-Mat bspline_matrix(const Vec& t, int p, const Vec& x);
+// Values of all num_basis B-splines at x (dense row of length n); `left`
+// takes the limit from the left, which differs only at a knot of
+// multiplicity p+1 (a broken space).
+void bspline_row(const Vec& t, int p, double x, double* row, bool left = false);
+// n x len(x) evaluation matrix B[a][c] = B_c(x_a), optionally one-sided per point.
+Mat bspline_matrix(const Vec& t, int p, const Vec& x, const std::vector<char>* left = nullptr);
 
 Vec greville(const Vec& t, int p);
+// Greville abscissae taken as limits from the left: at a knot of
+// multiplicity p+1 the last function of the left piece and the first of the
+// right piece share one abscissa; each is evaluated from its own side, which
+// keeps the interpolation matrix non-singular.
+std::vector<char> greville_left(const Vec& t, int p);
 
 // q-point Gauss-Legendre rule on [a,b].
 void gauss_legendre(int q, double a, double b, Vec& x, Vec& w);
@@ -62,17 +74,22 @@ struct NurbsVolume {
   Vec cw;                      // homogeneous control points (w x, w y, w z, w), index j1 + n1 (j2 + n2 j3)
   // Empty string if the data describe a valid volume, else the reason.
   std::string check() const;
-  // Point x, Jacobian dF[3 c + k] = d x_c / d xh_k and weight function W at xh.
-  void eval(const double* xh, double* x, double* dF, double* W) const;
+  // Point x, Jacobian dF[3 c + k] = d x_c / d xh_k and weight function W at
+  // xh; left[k] (optional) takes direction k's limit from the left, where dF
+  // jumps across a C^0 line.
+  void eval(const double* xh, double* x, double* dF, double* W, const char* left = nullptr) const;
+  // Interior knots of direction k repeated at least p[k] times: the map is
+  // only C^0 there (for instance where two patches meet).
+  Vec c0_lines(int k) const;
 };
 
 // Trial-space factor of parametric direction k at points x (rows are points):
-// the degree-p B-splines on nel uniform elements, or, with dir_weights, the
-// NURBS functions w_j B_j / sum_l w_l B_l whose weights interpolate the
-// direction's weight function (geo.weight1d) at the Greville points.
-// Returns false if that interpolation matrix is singular.
+// the degree-p B-splines on knots t, or, with dir_weights, the NURBS functions
+// w_j B_j / sum_l w_l B_l whose weights interpolate the direction's weight
+// function (geo.weight1d) at the Greville points.  Returns false if that
+// interpolation matrix is singular.
 struct Geometry;
-bool trial_matrix_1d(const Geometry& geo, bool dir_weights, int p, int nel, int k, const Vec& x, Mat& out);
+bool trial_matrix_1d(const Geometry& geo, bool dir_weights, const Vec& t, int p, int k, const Vec& x, Mat& out);
 
 // Geometry: parametric point -> physical point, |det DF|.
 struct Geometry {
@@ -81,8 +98,11 @@ struct Geometry {
   double r0 = 1, r1 = 2, height = 1;
   NurbsVolume nurbs;
   // Mapped point, and optionally |det DF| and the NURBS weight function W
-  // (general NURBS volume; 1 for the closed-form domains).
-  void eval(const double* xh, double* x, double* detJ, double* W) const;
+  // (general NURBS volume; 1 for the closed-form domains).  left[k]
+  // (optional) takes direction k's limit from the left at a C^0 line.
+  void eval(const double* xh, double* x, double* detJ, double* W, const char* left = nullptr) const;
+  // C^0 lines of parametric direction k (general NURBS volume only).
+  Vec c0_lines(int k) const;
   // midpoint of the axis-aligned bounding box of the mapped domain (of the
   // control points for a NURBS volume, which contain it)
   void center(double* c) const;

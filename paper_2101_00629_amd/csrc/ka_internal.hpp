@@ -156,6 +156,7 @@ struct Problem {
   hipStream_t stream = nullptr;
   int device = 0;
   int N = 0, n[3] = {0, 0, 0};
+  Vec tsol[3];                       // knot vectors of the solution space (host)
   int Nt = 0, nt[3] = {0, 0, 0};     // Galerkin interpolation space
   int64_t Nq = 0; int nq[3] = {0, 0, 0};  // collocation quadrature points
   int b = 16;
@@ -209,6 +210,8 @@ GammaLaunch gamma_job(Problem* P);
 int gamma_step(Problem* P, const float* Y, float* Z, hipStream_t s);
 int setup_problem(const ka_desc* d, hipStream_t stream, Problem** out);
 int footprint(const ka_desc* d, size_t* bytes);
+// N, Ntilde, Nquad that setup_problem would produce (host only).
+int desc_sizes(const ka_desc* d, int64_t* N, int64_t* Nt, int64_t* Nq);
 void destroy_problem(Problem* P);
 int eigs(Problem* P, int M, double tol, int maxit, double* lambda_host, double* V_dev, ka_info* info);
 

@@ -253,15 +253,16 @@ extern "C" int ka_kl_sample(ka_problem* p, int M, const double* lambda_host, con
   std::vector<Vec> xq(3), wq(3);
   int n[3], mq[3], mg[3];
   for (int k = 0; k < 3; ++k) {
-    const int pk = d.degree[k], e = d.nel[k];
+    const int pk = d.degree[k];
+    const Vec& t = P->tsol[k];
     n[k] = P->n[k];
     mg[k] = npts[k];
     mq[k] = n[k];
-    if (!trial_matrix_1d(geo, dir_weights, pk, e, k, grid[k], Eg[k]))
+    if (!trial_matrix_1d(geo, dir_weights, t, pk, k, grid[k], Eg[k]))
       return fail(KA_ERR_SINGULAR, "weight interpolation matrix is singular");
     if (coll) {
-      element_gauss(open_knots(pk, e, 1), d.nq > 0 ? d.nq : pk + 1, xq[k], wq[k]);
-      if (!trial_matrix_1d(geo, dir_weights, pk, e, k, xq[k], Eq[k]))
+      element_gauss(t, d.nq > 0 ? d.nq : pk + 1, xq[k], wq[k]);
+      if (!trial_matrix_1d(geo, dir_weights, t, pk, k, xq[k], Eq[k]))
         return fail(KA_ERR_SINGULAR, "weight interpolation matrix is singular");
       mq[k] = (int)xq[k].size();
     }

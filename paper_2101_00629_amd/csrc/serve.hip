@@ -372,8 +372,8 @@ int ka_request_bytes(const ka_desc* desc, int M, size_t* bytes) {
   if (!desc || !bytes) return fail(KA_ERR_ARG, "NULL argument");
   size_t fp = 0;
   if (int rc = footprint(desc, &fp)) return rc;
-  int64_t N = 1;
-  for (int k = 0; k < 3; ++k) N *= desc->degree[k] + desc->nel[k];
+  int64_t N = 0;
+  if (int rc = desc_sizes(desc, &N, nullptr, nullptr)) return rc;
   if (M < 1 || M > N) return fail(KA_ERR_ARG, "M must be in 1..N");
   *bytes = fp + eig_workspace_bytes(N, M, desc->block);
   return KA_OK;

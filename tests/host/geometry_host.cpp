@@ -14,9 +14,10 @@ extern "C" const char* ka_host_geometry_error() { return g_err; }
 // volume (degree, nctrl, concatenated knots, control points x, y, z, w with
 // index j1 fastest).  Writes x (npts x 3), detJ and W; returns 0, or -1 with
 // the reason in ka_host_geometry_error().
+// left (optional, npts x 3): take direction k's limit from the left.
 extern "C" int ka_host_geometry_eval(int domain, const double* ann, const int* degree, const int* nctrl,
                                      const double* knots, const double* ctrl, int npts, const double* xh, double* x,
-                                     double* detJ, double* W) {
+                                     double* detJ, double* W, const char* left) {
   ka::Geometry geo;
   geo.domain = domain;
   if (domain == 1) {
@@ -45,6 +46,43 @@ extern "C" int ka_host_geometry_eval(int domain, const double* ann, const int* d
       return -1;
     }
   }
-  for (int i = 0; i < npts; ++i) geo.eval(xh + 3 * i, x + 3 * i, detJ + i, W + i);
+  for (int i = 0; i < npts; ++i) geo.eval(xh + 3 * i, x + 3 * i, detJ + i, W + i, left ? left + 3 * i : nullptr);
   return 0;
+}
+
+// C^0 lines of direction k of a NURBS volume (same arguments as above); returns their count, written to out.
+extern "C" int ka_host_c0_lines(const int* degree, const int* nctrl, const double* knots, int k, double* out,
+                                int maxn) {
+  ka::NurbsVolume nv;
+  size_t off = 0;
+  for (int d = 0; d < 3; ++d) {
+    nv.p[d] = degree[d];
+    nv.n[d] = nctrl[d];
+    const size_t len = (size_t)nctrl[d] + degree[d] + 1;
+    nv.t[d].assign(knots + off, knots + off + len);
+    off += len;
+  }
+  const ka::Vec l = nv.c0_lines(k);
+  for (size_t i = 0; i < l.size() && (int)i < maxn; ++i) out[i] = l[i];
+  return (int)l.size();
+}
+
+// Knot vector of an analysis space; returns its length (written to out up to maxn).
+extern "C" int ka_host_analysis_knots(int p, int nel, int mult, const double* lines, int nlines, int line_mult,
+                                      double* out, int maxn) {
+  const ka::Vec t = ka::analysis_knots(p, nel, mult, ka::Vec(lines, lines + nlines), line_mult);
+  for (size_t i = 0; i < t.size() && (int)i < maxn; ++i) out[i] = t[i];
+  return (int)t.size();
+}
+
+// B-spline rows at x (npts x n, row-major), one-sided where left[a] != 0,
+// and the Greville abscissae taken from the left (n flags).
+extern "C" void ka_host_bspline_rows(const double* knots, int nknots, int p, const double* x, int npts,
+                                     const char* left, double* out, char* greville_left) {
+  const ka::Vec t(knots, knots + nknots);
+  const std::vector<char> lf(left, left + npts);
+  const ka::Mat B = ka::bspline_matrix(t, p, ka::Vec(x, x + npts), &lf);
+  std::memcpy(out, B.a.data(), B.a.size() * sizeof(double));
+  const std::vector<char> gl = ka::greville_left(t, p);
+  std::memcpy(greville_left, gl.data(), gl.size());
 }

@@ -129,3 +129,31 @@ def test_nurbs_descriptor_validation():
     with pytest.raises(K.KAError) as e:
         K.ka_footprint(K.make_desc(**good))
     assert e.value.code == K.KA_ERR_ARG
+
+
+def test_desc_size_reproduces_the_paper_tables():
+    """ka_desc_size (host only) on the half cylinder: the C^0 line at the middle
+    of the half circle gives the N and Ntilde printed in Tables 1 and 2
+    (tests/golden/half_cylinder_dof_tables.json), and the same N for every
+    method; the quadrature grid counts the extra element of a line that is no
+    uniform breakpoint."""
+    import json
+    import paper_2101_00629_amd as K
+    from workloads import half_cylinder_net, kinked_box_net
+    rec = json.load(open(os.path.join(ROOT, "tests", "golden", "half_cylinder_dof_tables.json")))
+    hc = half_cylinder_net()
+    for table, kernel in (("table1", "exponential"), ("table2", "gaussian")):
+        for row in rec[table]:
+            d = K.make_desc("galerkin", "nurbs", row["p"], row["nel"], kernel, 5.0, nurbs=hc)
+            N, Nt, Nq = K.ka_desc_size(d)
+            assert N == row["N"] and Nq == 0
+            if row.get("ntilde_follows_rule", True):
+                assert Nt == row["Ntilde"]
+            for method in ("collocation", "galerkin_gauss"):
+                d = K.make_desc(method, "nurbs", row["p"], row["nel"], kernel, 5.0, nurbs=hc)
+                N2, Nt2, Nq2 = K.ka_desc_size(d)
+                q = [(row["p"] + 1) * e for e in row["nel"]]
+                assert (N2, Nt2, Nq2) == (row["N"], 0, q[0] * q[1] * q[2])
+    # a line off the uniform mesh adds a breakpoint: 3 + 1 elements along xi
+    d = K.make_desc("collocation", "nurbs", 2, (3, 1, 1), "gaussian", 0.5, nurbs=kinked_box_net(0.5, 0.3))
+    assert K.ka_desc_size(d) == ((2 + 4 + 1) * 3 * 3, 0, (3 * 4) * 3 * 3)

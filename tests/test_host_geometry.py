@@ -38,14 +38,14 @@ def _eval(lib, xh, net=None, ann=None):
     x, J, W = np.zeros((n, 3)), np.zeros(n), np.zeros(n)
     if net is None:
         a = np.array(ann, dtype=np.float64)
-        rc = lib.ka_host_geometry_eval(1, _p(a), None, None, None, None, n, _p(xh), _p(x), _p(J), _p(W))
+        rc = lib.ka_host_geometry_eval(1, _p(a), None, None, None, None, n, _p(xh), _p(x), _p(J), _p(W), None)
     else:
         ctrl = np.ascontiguousarray(net["ctrl"], dtype=np.float64)
         deg = np.array(net["degree"], dtype=np.int32)
         nct = np.array([ctrl.shape[2], ctrl.shape[1], ctrl.shape[0]], dtype=np.int32)
         kn = np.ascontiguousarray(np.concatenate([np.asarray(t, dtype=np.float64) for t in net["knots"]]))
         rc = lib.ka_host_geometry_eval(2, None, _p(deg, ctypes.c_int), _p(nct, ctypes.c_int), _p(kn), _p(ctrl), n,
-                                       _p(xh), _p(x), _p(J), _p(W))
+                                       _p(xh), _p(x), _p(J), _p(W), None)
     return rc, x, J, W
 
 
@@ -115,3 +115,74 @@ def test_invalid_nets_are_rejected(lib):
     for net, word in ((bad_w, "weights"), (bad_open, "open"), (bad_order, "non-decreasing")):
         rc = _eval(lib, xh, net=net)[0]
         assert rc == -1 and word in lib.ka_host_geometry_error().decode()
+
+
+# ---- C^0 lines (paper Sec. 4.1) -------------------------------------------------------------
+
+def _net_args(net):
+    deg = np.array(net["degree"], dtype=np.int32)
+    ctrl = np.asarray(net["ctrl"])
+    nct = np.array([ctrl.shape[2], ctrl.shape[1], ctrl.shape[0]], dtype=np.int32)
+    kn = np.ascontiguousarray(np.concatenate([np.asarray(t, dtype=np.float64) for t in net["knots"]]))
+    return deg, nct, kn
+
+
+@pytest.mark.parametrize("which", ["half_cylinder", "kinked", "blob", "annulus"])
+def test_c0_lines_match_oracle(lib, which):
+    from workloads import half_cylinder_net, kinked_box_net
+    net = {"half_cylinder": half_cylinder_net(), "kinked": kinked_box_net(0.25, 0.6), "blob": nurbs_blob_net(3),
+           "annulus": nurbs_annulus_net()}[which]
+    deg, nct, kn = _net_args(net)
+    nv = geometry.NurbsVolume(net["degree"], net["knots"], net["ctrl"])
+    for k in range(3):
+        out = np.zeros(16)
+        n = lib.ka_host_c0_lines(_p(deg, ctypes.c_int), _p(nct, ctypes.c_int), _p(kn), k, _p(out), 16)
+        assert tuple(out[:n]) == nv.c0_lines(k)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_analysis_knots_match_oracle(lib, seed):
+    from oracle import splines
+    rng = np.random.default_rng(seed)
+    p, nel = int(rng.integers(1, 5)), int(rng.integers(1, 9))
+    mult = int(rng.integers(1, p + 2))
+    lines = sorted({float(rng.integers(1, 8)) / 8 if rng.random() < 0.5 else float(rng.random()) for _ in range(2)})
+    lines = np.array([l for l in lines if 0 < l < 1])
+    lm = int(rng.choice([p, p + 1]))
+    ref = splines.open_knots(p, nel, mult, lines=tuple(lines), line_mult=lm)
+    out = np.zeros(512)
+    n = lib.ka_host_analysis_knots(p, nel, mult, _p(np.ascontiguousarray(lines)), len(lines), lm, _p(out), 512)
+    assert n == len(ref)
+    assert np.abs(out[:n] - ref).max() < 1e-15
+
+
+@pytest.mark.parametrize("p,c", [(1, 0.5), (2, 0.5), (3, 0.1), (4, 0.7)])
+def test_one_sided_rows_match_oracle(lib, p, c):
+    from oracle import splines
+    t = splines.open_knots(p, 5, 1, lines=(c,), line_mult=p + 1)
+    rng = np.random.default_rng(p)
+    x = np.concatenate([np.unique(t), rng.random(20)])
+    left = (rng.random(len(x)) < 0.5).astype(np.int8)
+    n = splines.num_basis(t, p)
+    out = np.zeros((len(x), n))
+    gl = np.zeros(n, dtype=np.int8)
+    lib.ka_host_bspline_rows(_p(t), len(t), p, _p(x), len(x), _p(left, ctypes.c_char), _p(out),
+                             _p(gl, ctypes.c_char))
+    assert np.abs(out - splines.basis_matrix(t, p, x, left=left.astype(bool))).max() < 1e-14
+    assert np.array_equal(gl.astype(bool), splines.greville_left(t, p))
+
+
+def test_one_sided_jacobian(lib):
+    from workloads import kinked_box_net
+    net = kinked_box_net(0.5, 0.3)
+    xh = np.array([[0.5, 0.2, 0.7], [0.5, 0.2, 0.7], [0.3, 0.5, 0.5]])
+    left = np.array([[1, 0, 0], [0, 0, 0], [1, 1, 1]], dtype=np.int8)
+    deg, nct, kn = _net_args(net)
+    ctrl = np.ascontiguousarray(net["ctrl"], dtype=np.float64)
+    x, J, W = np.zeros((3, 3)), np.zeros(3), np.zeros(3)
+    rc = lib.ka_host_geometry_eval(2, None, _p(deg, ctypes.c_int), _p(nct, ctypes.c_int), _p(kn), _p(ctrl), 3,
+                                   _p(xh), _p(x), _p(J), _p(W), _p(left, ctypes.c_char))
+    assert rc == 0
+    nv = geometry.NurbsVolume(net["degree"], net["knots"], net["ctrl"])
+    assert np.abs(J - nv.detJ(xh, left.astype(bool))).max() < 1e-14
+    assert abs(J[0] - 0.6) < 1e-14 and abs(J[1] - 1.4) < 1e-14

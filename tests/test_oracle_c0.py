@@ -74,10 +74,10 @@ def test_discretisations_use_the_rule():
     assert gg.N == g.N
 
 
-@pytest.mark.parametrize("p", [1, 2, 3])
-def test_one_sided_rows(p):
-    t = splines.open_knots(p, 4, 1, lines=(0.5,), line_mult=p + 1)     # C^-1 at 1/2
-    x = np.array([0.5])
+@pytest.mark.parametrize("p,c", [(1, 0.5), (2, 0.5), (3, 0.5), (3, 0.1), (4, 0.7)])
+def test_one_sided_rows(p, c):
+    t = splines.open_knots(p, 4, 1, lines=(c,), line_mult=p + 1)       # C^-1 at c
+    x = np.array([c])
     L = splines.basis_matrix(t, p, x, left=[True])
     R = splines.basis_matrix(t, p, x)
     d = 1e-9
@@ -87,9 +87,10 @@ def test_one_sided_rows(p):
     assert np.abs(L - R).max() > 0.5                                    # the space is broken there
     gl = splines.greville_left(t, p)
     g = splines.greville(t, p)
-    assert gl.sum() == 1 and g[gl][0] == 0.5
+    assert gl.sum() == 1 and g[gl][0] == c
+    assert np.sum(g == c) == 2                                           # both sides sit on the line
     assert np.linalg.matrix_rank(splines.basis_matrix(t, p, g, left=gl)) == len(g)
-    tc = splines.open_knots(p, 4, 1, lines=(0.5,), line_mult=p)          # C^0: the sides agree
+    tc = splines.open_knots(p, 4, 1, lines=(c,), line_mult=p)            # C^0: the sides agree
     assert np.abs(splines.basis_matrix(tc, p, x, left=[True]) - splines.basis_matrix(tc, p, x)).max() < 1e-14
     assert not splines.greville_left(tc, p).any()
 
