@@ -334,6 +334,72 @@ def compare_methods(reps=3):
     return out
 
 
+def half_cylinder_benchmark(reps=2):
+    """The paper's numerical examples (Sec. 4) on the thick-walled half
+    cylinder (workloads.HALF_CYLINDER; one C^0 line, the middle of the half
+    circle), sigma = 1, ell = 5.  Example 1: L1-exponential kernel, p = 2, the
+    five meshes of Table 1 (C^0 interpolation space).  Example 2: Gaussian
+    kernel, the Case 1 mesh with p = 2..6 (Table 2).  Per case and method
+    (Galerkin-IBQ, collocation): N, interpolation or quadrature points, set-up
+    time, eigensolver time (median of `reps` ka_eigs; the paper times the
+    eigensolver), and the mean relative error eps-bar of the 20 largest
+    eigenvalues against a standard Gauss-quadrature Galerkin reference on a
+    finer mesh, solved on the GPU as well.  A second, coarser reference gives
+    the first one's own eps-bar as a bound on how far eps-bar can be trusted."""
+    import torch
+    import paper_2101_00629_amd as K
+    from workloads import HALF_CYLINDER, HALF_CYLINDER_EXAMPLE1, HALF_CYLINDER_EXAMPLE2, half_cylinder_net
+
+    hc = half_cylinder_net(HALF_CYLINDER["r0"], HALF_CYLINDER["r1"], HALF_CYLINDER["length"])
+    ell = HALF_CYLINDER["ell"]
+    M = 20
+
+    def solve(method, p, nel, kernel, block, n_rep, maxit=80):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        prob = K.Problem(K.make_desc(method, "nurbs", p, nel, kernel, ell, block=block, seed=11, nurbs=hc))
+        torch.cuda.synchronize()
+        setup_s = time.perf_counter() - t0
+        times = []
+        for _ in range(n_rep):
+            t0 = time.perf_counter()
+            rc, lam, info = K.ka_eigs(prob.h, M, tol=1e-6, maxit=maxit, complex_values=(method == "collocation"))
+            times.append(time.perf_counter() - t0)
+        N, Nt, Nq, _ = K.ka_size(prob.h)
+        prob.close()
+        lr = np.asarray(lam[0::2] if method == "collocation" else lam)[:M]
+        return dict(method=method, p=p, nel=list(nel), N=N, points=Nt if method == "galerkin" else Nq,
+                    status=rc, setup_s=setup_s, solve_s=float(np.median(times)), matvecs=info["matvecs"],
+                    pairs=info["pairs"]), lr
+
+    examples = [("example1", "exponential", [(2, nel) for nel in HALF_CYLINDER_EXAMPLE1],
+                 [(2, (126, 9, 69)), (2, (84, 6, 46))]),
+                ("example2", "gaussian", HALF_CYLINDER_EXAMPLE2, [(6, (64, 2, 16)), (5, (64, 2, 16))])]
+    runs, refs = [], []
+    for name, kernel, cases, ref_meshes in examples:
+        ref_lams = []
+        for p, nel in ref_meshes:
+            rec, lam = solve("galerkin_gauss", p, nel, kernel, 32, 1)
+            ref_lams.append(lam)
+            rec.update(example=name, kernel=kernel)
+            refs.append(rec)
+            print(f"[half-cylinder] {name} reference p={p} nel={nel}: N={rec['N']} points={rec['points']} "
+                  f"solve {rec['solve_s']:.2f} s", file=sys.stderr, flush=True)
+        ref = ref_lams[0]
+        refs[-1]["eps_bar_vs_first_reference"] = float(np.mean(np.abs(ref_lams[1] - ref) / ref))
+        for case, (p, nel) in enumerate(cases, 1):
+            for method in ("galerkin", "collocation"):
+                rec, lam = solve(method, p, nel, kernel, 16, reps)
+                eps = np.abs(lam - ref) / ref
+                rec.update(example=name, case=case, kernel=kernel, eps_bar=float(eps.mean()),
+                           eps_first5=[float(e) for e in eps[:5]])
+                runs.append(rec)
+                print(f"[half-cylinder] {name} case {case} {method}: N={rec['N']} points={rec['points']} "
+                      f"eps_bar={rec['eps_bar']:.2e} solve {rec['solve_s'] * 1e3:.1f} ms", file=sys.stderr,
+                      flush=True)
+    return dict(runs=runs, references=refs)
+
+
 def measure(K, torch, precision, steps, warmup, tol):
     """Solve the workload's problems `warmup` + `steps` times in one precision;
     returns rates, latencies, accuracy and the kernel product's roofline."""
@@ -533,6 +599,8 @@ def main():
                     help="K-L field sampling at workload size (ka_kl_sample) instead")
     ap.add_argument("--nurbs", action="store_true",
                     help="general NURBS volumes at workload size (annulus as a control net, curved volume) instead")
+    ap.add_argument("--half-cylinder", action="store_true",
+                    help="the paper's Examples 1 and 2 on the half cylinder (time vs eps-bar) instead")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first run one plain device copy of MIB MiB (reference for HBM traffic counters)")
     args = ap.parse_args()
@@ -567,6 +635,11 @@ def main():
     if args.nurbs:
         print(json.dumps({"metric": "K-L solves on general NURBS volumes", "n_gpus": 1, "data": "synthetic",
                           "dtype": "f32", "runs": nurbs_benchmark()}), flush=True)
+        return
+    if args.half_cylinder:
+        print(json.dumps({"metric": "half-cylinder examples: eigensolver time vs eps-bar of 20 eigenvalues",
+                          "n_gpus": 1, "data": "synthetic (half cylinder, Sec. 4 meshes)", "dtype": "f32",
+                          **half_cylinder_benchmark()}), flush=True)
         return
     if args.serve:
         res = serve_benchmark(args.requests, [float(r) for r in args.rho.split(",")], args.pair_cap, args.tol)

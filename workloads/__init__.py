@@ -86,6 +86,18 @@ def half_cylinder_net(r0=8.0, r1=10.0, length=15.0):
     return dict(degree=(2, 1, 1), knots=([0, 0, 0, 0.5, 0.5, 1, 1, 1], [0, 0, 1, 1], [0, 0, 1, 1]), ctrl=ctrl)
 
 
+# The paper's numerical examples (Sec. 4) on the half cylinder: element counts
+# (circumferential, radial, axial).  Example 1 (exponential kernel, p = 2,
+# h-refinement): the five meshes that reproduce Table 1's N (and Ntilde for
+# Cases 2-5) under the C^0-line rule; Example 2 (Gaussian kernel,
+# k-refinement): the Case 1 mesh with p = 2..6 (Table 2).  The correlation
+# length 5 is used throughout; the dimensions r0 = 8, r1 = 10, length 15 are
+# a fit to the mesh sizes h of Table 1 read as element diagonals.
+HALF_CYLINDER = dict(r0=8.0, r1=10.0, length=15.0, ell=5.0)
+HALF_CYLINDER_EXAMPLE1 = [(32, 1, 8), (28, 2, 15), (32, 2, 18), (38, 2, 21), (42, 3, 23)]
+HALF_CYLINDER_EXAMPLE2 = [(p, (32, 1, 8)) for p in (2, 3, 4, 5, 6)]
+
+
 def kinked_box_net(kink=0.5, at=0.3, hi=(1.0, 1.0, 1.0)):
     """The box [0, hi] as a NURBS patch whose xi direction is piecewise
     linear: parameter `kink` maps to x = at * hi[0], so dx/dxi (and |det DF|)
