@@ -63,6 +63,258 @@ __global__ __launch_bounds__(kNsThreads) void ns_hess_kernel(const double* __res
       for (int i = threadIdx.x; i < n; i += kNsThreads) ws.A[i + (size_t)j * n] = A[i + (size_t)j * ld];
 }
 
+// ---- eigenvalue QR by one wave, matrix in LDS --------------------------------------------
+// The Francis double-shift iteration of ns_qr_values (nonsym_core.hpp) with
+// the same arithmetic, arranged for the 64 lanes of one wave:
+//  - the two searches of each iteration (the negligible sub-diagonal that
+//    splits the active window, and the start m of the double step) test 64
+//    positions at once and take the first hit with a ballot, instead of a
+//    serial scan with one LDS round trip per position;
+//  - in the bulge chase each lane keeps the column update's new values of
+//    column k in registers, and the next step reads its reflector input
+//    (rows k+1..k+3 of that column) with readlane instead of through LDS;
+//  - the loads of an update phase are issued together, then the arithmetic,
+//    then the stores.
+// LDS operations of one wave complete in issue order, so ordering between
+// the phases needs only a compiler fence at wavefront scope (no wait).
+constexpr int kNsQrIt = (kNsBandLds + 63) / 64;   // lane iterations over a window of <= kNsBandLds
+
+__device__ inline void ns_wave_fence() { __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront"); }
+
+__device__ inline double ns_readlane(double v, int lane) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+  return __hiloint2double(hi, lo);
+}
+
+// value of row index `idx` (relative to the window start) from the registers
+// c0, c1, c2 (row idx, idx - 64, idx - 128) of lane idx % 64; named scalars,
+// so the selection stays in registers
+static_assert(kNsQrIt == 3, "the register selection below covers three lane iterations");
+__device__ inline double ns_lane_value(double c0, double c1, double c2, int idx) {
+  const int it = idx >> 6;
+  const double v = it == 0 ? c0 : (it == 1 ? c1 : c2);
+  return ns_readlane(v, idx & 63);
+}
+
+__device__ int ns_qr_values_wave(double* hb, int n, double* wr, double* wi, double* anorm_out) {
+  const int t = threadIdx.x;
+#define HB(i, j) hb[(j) * ((j) + 7) / 2 + (i)]
+  double anorm = 0.0;
+  for (int j = t; j < n; j += 64)
+    for (int i = 0; i <= j + 1 && i < n; ++i) anorm += fabs(HB(i, j));
+  for (int off = 32; off > 0; off >>= 1) anorm += __shfl_xor(anorm, off);
+  if (anorm_out && t == 0) *anorm_out = anorm;
+  int nn = n - 1;
+  double shift = 0.0;
+  int fail = 0;
+  while (nn >= 0 && !fail) {
+    int its = 0;
+    while (true) {
+      ns_wave_fence();
+      // largest l in [1, nn] with a negligible sub-diagonal H(l, l-1), else 0
+      int l = 0;
+      for (int base = nn; base >= 1; base -= 64) {
+        const int l0 = base - t;
+        bool hit = false;
+        if (l0 >= 1) {
+          double s = fabs(HB(l0 - 1, l0 - 1)) + fabs(HB(l0, l0));
+          if (s == 0.0) s = anorm;
+          hit = fabs(HB(l0, l0 - 1)) <= kNsEps * s;
+        }
+        const unsigned long long mask = __ballot(hit);
+        if (mask) {
+          l = base - (__ffsll(mask) - 1);
+          break;
+        }
+      }
+      double x = HB(nn, nn);
+      if (l == nn) {                                   // one real eigenvalue
+        if (t == 0) {
+          wr[nn] = x + shift;
+          wi[nn] = 0.0;
+        }
+        --nn;
+        break;
+      }
+      double y = HB(nn - 1, nn - 1);
+      double w = HB(nn, nn - 1) * HB(nn - 1, nn);
+      if (l == nn - 1) {                               // a 2 x 2 block
+        const double p = 0.5 * (y - x);
+        const double q = p * p + w;
+        double z = sqrt(fabs(q));
+        x += shift;
+        if (t == 0) {
+          if (q >= 0.0) {
+            z = p + ns_sgn(z, p);
+            wr[nn - 1] = wr[nn] = x + z;
+            if (z != 0.0) wr[nn] = x - w / z;
+            wi[nn - 1] = wi[nn] = 0.0;
+          } else {
+            wr[nn - 1] = wr[nn] = x + p;
+            wi[nn - 1] = z;
+            wi[nn] = -z;
+          }
+        }
+        nn -= 2;
+        break;
+      }
+      if (its >= 60) {
+        fail = 1;
+        break;
+      }
+      if (its == 10 || its == 20 || its == 40) {       // exceptional shift
+        shift += x;
+        for (int i = t; i <= nn; i += 64) HB(i, i) -= x;
+        ns_wave_fence();
+        const double s = fabs(HB(nn, nn - 1)) + fabs(HB(nn - 1, nn - 2));
+        x = y = 0.75 * s;
+        w = -0.4375 * s * s;
+      }
+      ++its;
+      // start of the double step: largest m in [l, nn-2] where two consecutive
+      // sub-diagonals are small enough, m = l otherwise
+      int m = l;
+      for (int base = nn - 2; base >= l; base -= 64) {
+        const int m0 = base - t;
+        bool hit = m0 == l;
+        if (m0 > l) {
+          const double z0 = HB(m0, m0);
+          double r0 = x - z0;
+          const double s0 = y - z0;
+          double p0 = (r0 * s0 - w) / HB(m0 + 1, m0) + HB(m0, m0 + 1);
+          double q0 = HB(m0 + 1, m0 + 1) - z0 - r0 - s0;
+          r0 = HB(m0 + 2, m0 + 1);
+          const double ss = fabs(p0) + fabs(q0) + fabs(r0);
+          p0 /= ss;
+          q0 /= ss;
+          r0 /= ss;
+          const double u = fabs(HB(m0, m0 - 1)) * (fabs(q0) + fabs(r0));
+          const double vv = fabs(p0) * (fabs(HB(m0 - 1, m0 - 1)) + fabs(z0) + fabs(HB(m0 + 1, m0 + 1)));
+          hit = u <= kNsEps * vv;
+        }
+        const unsigned long long mask = __ballot(hit);
+        if (mask) {
+          m = base - (__ffsll(mask) - 1);
+          break;
+        }
+      }
+      double p, q, r;
+      {
+        const double z = HB(m, m);
+        r = x - z;
+        const double s0 = y - z;
+        p = (r * s0 - w) / HB(m + 1, m) + HB(m, m + 1);
+        q = HB(m + 1, m + 1) - z - r - s0;
+        r = HB(m + 2, m + 1);
+        const double s = fabs(p) + fabs(q) + fabs(r);
+        p /= s;
+        q /= s;
+        r /= s;
+      }
+      for (int i = m + 2 + t; i <= nn; i += 64) {
+        HB(i, i - 2) = 0.0;
+        if (i != m + 2) HB(i, i - 3) = 0.0;
+      }
+      ns_wave_fence();
+      // bulge chase over the active window [l, nn]; c[it]: column k-1 after the
+      // previous step's column update, row l + t + 64 it
+      double c[kNsQrIt];
+#pragma unroll
+      for (int it = 0; it < kNsQrIt; ++it) c[it] = 0.0;
+#define NS_LANE(idx) ns_lane_value(c[0], c[1], c[2], (idx))
+      for (int k = m; k <= nn - 1; ++k) {
+        const bool notlast = (k != nn - 1);
+        double xx = 0.0;
+        if (k != m) {
+          p = NS_LANE(k - l);
+          q = NS_LANE(k + 1 - l);
+          r = notlast ? NS_LANE(k + 2 - l) : 0.0;
+          xx = fabs(p) + fabs(q) + fabs(r);
+          if (xx != 0.0) {
+            const double ixx = 1.0 / xx;
+            p *= ixx;
+            q *= ixx;
+            r *= ixx;
+          }
+        }
+        const double s = ns_sgn(sqrt(p * p + q * q + r * r), p);
+        const int imax = (nn < k + 3) ? nn : k + 3;
+        if (s == 0.0) {
+          // no reflection at this step: the next one reads column k from memory
+#pragma unroll
+          for (int it = 0; it < kNsQrIt; ++it) {
+            const int i = l + t + 64 * it;
+            if (i <= imax) c[it] = HB(i, k);
+          }
+          continue;
+        }
+        if (t == 0) {
+          if (k == m) {
+            if (l != m) HB(k, k - 1) = -HB(k, k - 1);
+          } else {
+            HB(k, k - 1) = -s * xx;
+          }
+        }
+        const double pp = p + s;
+        const double is = 1.0 / s, ipp = 1.0 / pp;
+        const double x1 = pp * is, y1 = q * is, z1 = r * is;
+        const double q1 = q * ipp, r1 = r * ipp;
+        // rows k..k+2, columns k..nn.  Loads are unconditional at clamped,
+        // valid addresses (a masked load would end its branch with a wait);
+        // on the last step the third row is a copy of the second, weighted
+        // by r1 = 0, and not stored.
+        const int k2 = notlast ? k + 2 : k + 1;
+        double a0[kNsQrIt], a1[kNsQrIt], a2[kNsQrIt];
+#pragma unroll
+        for (int it = 0; it < kNsQrIt; ++it) {
+          const int j = min(k + t + 64 * it, nn);
+          a0[it] = HB(k, j);
+          a1[it] = HB(k + 1, j);
+          a2[it] = HB(k2, j);
+        }
+#pragma unroll
+        for (int it = 0; it < kNsQrIt; ++it) {
+          const int j = k + t + 64 * it;
+          double pv = a0[it] + q1 * a1[it];
+          pv += r1 * a2[it];
+          if (j <= nn) {
+            if (notlast) HB(k + 2, j) = a2[it] - pv * z1;
+            HB(k + 1, j) = a1[it] - pv * y1;
+            HB(k, j) = a0[it] - pv * x1;
+          }
+        }
+        ns_wave_fence();
+        // columns k..k+2, rows l..min(nn, k+3), loaded the same way
+#pragma unroll
+        for (int it = 0; it < kNsQrIt; ++it) {
+          const int i = min(l + t + 64 * it, imax);
+          a0[it] = HB(i, k);
+          a1[it] = HB(i, k + 1);
+          a2[it] = HB(i, k2);
+        }
+#pragma unroll
+        for (int it = 0; it < kNsQrIt; ++it) {
+          const int i = l + t + 64 * it;
+          double pv = x1 * a0[it] + y1 * a1[it];
+          pv += z1 * a2[it];
+          c[it] = a0[it] - pv;
+          if (i <= imax) {
+            if (notlast) HB(i, k + 2) = a2[it] - pv * r1;
+            HB(i, k + 1) = a1[it] - pv * q1;
+            HB(i, k) = c[it];
+          }
+        }
+        ns_wave_fence();
+      }
+    }
+  }
+  ns_wave_fence();
+#undef NS_LANE
+#undef HB
+  return fail;
+}
+
 template <bool LDS>
 __global__ __launch_bounds__(64) void ns_qr_kernel(double* __restrict__ work, int n, int nv) {
   __shared__ double hb_lds[LDS ? (size_t)kNsBandLds * (kNsBandLds + 7) / 2 + 8 : 1];
@@ -71,7 +323,8 @@ __global__ __launch_bounds__(64) void ns_qr_kernel(double* __restrict__ work, in
   NsTeam<64> tm{nullptr};
   ns_band_fill(tm, ws.A, n, ws.hsub, n, hb, ws.HT);
   __syncthreads();
-  const int fail = ns_qr_values(tm, hb, n, ws.wr0, ws.wi0, ws.misc);
+  const int fail = LDS ? ns_qr_values_wave(hb, n, ws.wr0, ws.wi0, ws.misc)
+                       : ns_qr_values(tm, hb, n, ws.wr0, ws.wi0, ws.misc);
   if (threadIdx.x == 0) ws.misc[1] = fail;
 }
 
