@@ -386,19 +386,23 @@ KA_HD void ns_invit_team(Team& tm, const double* HT, const double* hsub, int n, 
     const double lr = wr[c], li = wi[c];
     const bool cplx = li > 0.0;
     // ---- LU of B = Hh - lambda I --------------------------------------------------------
-    for (int cc = t; cc < n; cc += NT) {
-      UR(0, cc) = HT[cc] - (cc == 0 ? lr : 0.0);
-      if (cplx) UI(0, cc) = (cc == 0 ? -li : 0.0);
-    }
+    // The planes start as the upper triangle of B (row r, columns >= r), so
+    // step j reads row j+1 of B from fast memory before overwriting it.
+    for (int r = 0; r < n; ++r)
+      for (int cc = r + t; cc < n; cc += NT) {
+        UR(r, cc) = HT[(size_t)r * n + cc] - (cc == r ? lr : 0.0);
+        if (cplx) UI(r, cc) = (cc == r ? -li : 0.0);
+      }
     tm.sync();
+    double sub_next = n > 1 ? hsub[0] : 0.0;
     for (int j = 0; j + 1 < n; ++j) {
       double ar = UR(j, j), ai = cplx ? UI(j, j) : 0.0;
       if (ns_cabs(ar, ai) < tiny) {                // keep the factorisation finite
         ar = tiny;
         ai = 0.0;
       }
-      const double sub = hsub[j];                   // B[j+1][j], real
-      const double* brow = HT + (size_t)(j + 1) * n;
+      const double sub = sub_next;                  // B[j+1][j], real
+      sub_next = (j + 2 < n) ? hsub[j + 1] : 0.0;   // read one step ahead
       const bool swap = fabs(sub) > ns_cabs(ar, ai);
       double l_r, l_i;
       if (swap) {
@@ -411,7 +415,7 @@ KA_HD void ns_invit_team(Team& tm, const double* HT, const double* hsub, int n, 
       }
       tm.sync();                                    // every thread has read the pivot
       for (int cc = j + 1 + t; cc < n; cc += NT) {
-        const double br = brow[cc] - (cc == j + 1 ? lr : 0.0), bi = (cc == j + 1 ? -li : 0.0);
+        const double br = UR(j + 1, cc), bi = cplx ? UI(j + 1, cc) : 0.0;   // row j+1 of B
         const double ur = UR(j, cc), ui = cplx ? UI(j, cc) : 0.0;
         if (swap) {
           // U row j <- B row j+1; new current row = old row - l B row j+1
@@ -469,31 +473,31 @@ KA_HD void ns_invit_team(Team& tm, const double* HT, const double* hsub, int n, 
         xi[n - 1] = ai;
       }
       tm.sync();
-      // back substitution, one row at a time, the row product split over the team
+      // back substitution by columns: x_i = x_i / U(i,i), then the rows above
+      // take their share of column i (split over the team)
       for (int i = n - 1; i >= 0; --i) {
-        double pr = 0.0, pi = 0.0;
-        for (int cc = i + 1 + t; cc < n; cc += NT) {
-          const double ur = UR(i, cc), ui = cplx ? UI(i, cc) : 0.0;
-          pr += ur * xr[cc] - ui * xi[cc];
-          pi += ur * xi[cc] + ui * xr[cc];
-        }
-        pr = tm.sum(pr);
-        if (cplx) pi = tm.sum(pi);
-        const double sr = xr[i] - pr, si = xi[i] - pi;
+        const double sr = xr[i], si = xi[i];
         const double dr = UR(i, i), di = cplx ? UI(i, i) : 0.0;
         const double den = dr * dr + di * di;
-        const double qr = (sr * dr + si * di) / den, qi = (si * dr - sr * di) / den;
-        tm.sync();
-        if (t == 0) {
-          xr[i] = qr;
-          xi[i] = qi;
-        }
+        double qr = (sr * dr + si * di) / den, qi = (si * dr - sr * di) / den;
+        tm.sync();                                  // every thread has read x_i
         if (fabs(qr) + fabs(qi) > 1e150) {          // keep the growth representable
-          tm.sync();
           for (int r = t; r < n; r += NT) {
             xr[r] *= 1e-150;
             xi[r] *= 1e-150;
           }
+          qr *= 1e-150;
+          qi *= 1e-150;
+          tm.sync();
+        }
+        if (t == 0) {
+          xr[i] = qr;
+          xi[i] = qi;
+        }
+        for (int r = t; r < i; r += NT) {
+          const double ur = UR(r, i), ui = cplx ? UI(r, i) : 0.0;
+          xr[r] -= ur * qr - ui * qi;
+          xi[r] -= ur * qi + ui * qr;
         }
         tm.sync();
       }
