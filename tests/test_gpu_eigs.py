@@ -301,3 +301,19 @@ def test_gauss_galerkin_full_size_cube(precision, bar):
     err = errors.floored_rel_errors(ref, lam)
     print(precision, info, "floored", err.max(), "raw", errors.rel_errors(ref, lam).max())
     assert rc == 0 and err.max() < bar
+
+
+@pytest.mark.parametrize("M", [60, 80])
+def test_collocation_rayleigh_ritz_orders_above_128(M):
+    """Rayleigh-Ritz orders 124 and 144 (M + b kept plus 3 blocks of 16): the
+    one-wave eigenvalue QR then spans two and three lane iterations of its
+    window.  Cube p = 2, 8^3, exponential l = 1, against the exact
+    product-of-1D collocation spectrum at the floored FP32 bar."""
+    desc = K.make_desc("collocation", "cube", 2, (8, 8, 8), "exponential", 1.0, block=16, seed=4)
+    prob = K.Problem(desc)
+    rc, lam, info = K.ka_eigs(prob.h, M, tol=1e-6, maxit=80, complex_values=True)
+    prob.close()
+    ref = product1d.collocation_box_spectrum(2, (8, 8, 8), "exponential", 1.0, M=M).real
+    err = errors.floored_rel_errors(ref, lam[0::2])
+    print("collocation M", M, info, err.max())
+    assert rc == 0 and err.max() < 1e-6
