@@ -236,8 +236,10 @@ size_t ka_gamma_workspace(int64_t nr, int64_t nc, int b, int precision);
  *   column-major FP64 (ldxi >= M), the draws (N(0,1) for a Gaussian field).
  * field_dev: P x nsamples column-major FP64 (ldf >= P), P = npts[0] npts[1]
  *   npts[2], grid point index i1 + npts[0] (i2 + npts[1] i3).
- * Allocates its device workspace (about (P + quadrature points) x M doubles)
- * and synchronizes `stream` before it returns.  Errors: KA_ERR_ARG (bad
+ * Its device workspace (about (P + quadrature points) x M doubles) is kept
+ * by the problem between calls, grown when a call needs more, and freed by
+ * ka_destroy; collocation also keeps the quadrature data of the norms from
+ * its first call.  Synchronizes `stream` before it returns.  Errors: KA_ERR_ARG (bad
  * sizes or values), KA_ERR_SINGULAR (an eigenfunction of zero norm),
  * KA_ERR_OOM, KA_ERR_HIP. */
 int ka_kl_sample(ka_problem* p, int M, const double* lambda_host, const double* V_dev, int64_t ldv,

@@ -205,6 +205,7 @@ static void free_problem(Problem* P) {
   if (!P) return;
   for (auto& b : P->allocs) (void)hipFree(b.p);
   for (auto& b : P->eig_allocs) (void)hipFree(b.p);
+  if (P->kl_buf) (void)hipFree(P->kl_buf);
   for (auto e : P->ev_start) (void)hipEventDestroy(e);
   for (auto e : P->ev_stop) (void)hipEventDestroy(e);
   delete P;

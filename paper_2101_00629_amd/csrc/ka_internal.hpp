@@ -193,6 +193,15 @@ struct Problem {
   double pairs_total = 0.0;
   // eigensolver workspace (lazily sized per call)
   std::vector<DevBuf> eig_allocs;
+  // K-L sampling: a workspace kept between calls (grown on demand, freed
+  // with the problem), and the collocation norm data that depend on the
+  // problem only: quadrature weights times |det DF| / W^2 at the Gauss
+  // points and the trial factors there (kept in allocs)
+  void* kl_buf = nullptr;
+  size_t kl_bytes = 0;
+  double* kl_omega = nullptr;
+  double* kl_Eq[3] = {nullptr, nullptr, nullptr};
+  int kl_mq[3] = {0, 0, 0};
   size_t eig_bytes = 0;
 };
 

@@ -152,28 +152,15 @@ __global__ __launch_bounds__(256) void kl_field_kernel(const double* __restrict_
 // ---------------------------------------------------------------------------
 namespace {
 
-struct Scratch {
-  std::vector<void*> ptrs;
-  bool ok = true;
-  template <typename T>
-  T* get(size_t n) {
-    void* p = nullptr;
-    if (hipMalloc(&p, std::max<size_t>(n, 1) * sizeof(T)) != hipSuccess) {
-      ok = false;
-      return nullptr;
-    }
-    ptrs.push_back(p);
-    return (T*)p;
-  }
-  template <typename T>
-  T* put(const std::vector<T>& v) {
-    T* p = get<T>(v.size());
-    if (p && !v.empty() && hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice) != hipSuccess)
-      ok = false;
-    return p;
-  }
-  ~Scratch() {
-    for (void* p : ptrs) (void)hipFree(p);
+// Workspace of one call, carved from the problem's kept buffer: sizes are
+// collected first (256-byte aligned), then the buffer grows if needed.
+struct KlArena {
+  std::vector<size_t> off;
+  size_t total = 0;
+  size_t add(size_t doubles) {
+    off.push_back(total);
+    total += (std::max<size_t>(doubles, 1) * sizeof(double) + 255) / 256 * 256;
+    return off.size() - 1;
   }
 };
 
@@ -260,17 +247,19 @@ extern "C" int ka_kl_sample(ka_problem* p, int M, const double* lambda_host, con
     mq[k] = n[k];
     if (!trial_matrix_1d(geo, dir_weights, t, pk, k, grid[k], Eg[k]))
       return fail(KA_ERR_SINGULAR, "weight interpolation matrix is singular");
-    if (coll) {
+    if (coll && !P->kl_omega) {
       element_gauss(t, d.nq > 0 ? d.nq : pk + 1, xq[k], wq[k]);
       if (!trial_matrix_1d(geo, dir_weights, t, pk, k, xq[k], Eq[k]))
         return fail(KA_ERR_SINGULAR, "weight interpolation matrix is singular");
       mq[k] = (int)xq[k].size();
+    } else if (coll) {
+      mq[k] = P->kl_mq[k];
     }
   }
   // collocation: weights of int_D phi^2 at the Gauss points, |det DF| (times 1 / W^2 on a NURBS volume)
   const int64_t Q = (int64_t)mq[0] * mq[1] * mq[2];
   std::vector<double> omega;
-  if (coll) {
+  if (coll && !P->kl_omega) {
     omega.resize(Q);
     for (int64_t i = 0; i < Q; ++i) {
       const int64_t a1 = i % mq[0], a2 = (i / mq[0]) % mq[1], a3 = i / ((int64_t)mq[0] * mq[1]);
@@ -293,29 +282,74 @@ extern "C" int ka_kl_sample(ka_problem* p, int M, const double* lambda_host, con
     }
   }
 
-  Scratch sc;
-  double* Eqd[3];
-  double* Egd[3];
-  for (int k = 0; k < 3; ++k) {
-    Eqd[k] = coll ? sc.put(to_rows(Eq[k])) : P->Zk[k];   // Galerkin: Z v with the mass matrices
-    Egd[k] = sc.put(to_rows(Eg[k]));
+  // collocation norm data: computed on the first call, kept by the problem
+  auto keep = [&](const std::vector<double>& v) -> double* {
+    void* p = nullptr;
+    const size_t bytes = std::max<size_t>(v.size(), 1) * sizeof(double);
+    if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
+    P->allocs.push_back({p, bytes});
+    P->device_bytes += bytes;
+    if (hipMemcpy(p, v.data(), v.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess) return nullptr;
+    return (double*)p;
+  };
+  if (coll && !P->kl_omega) {
+    for (int k = 0; k < 3; ++k) {
+      P->kl_Eq[k] = keep(to_rows(Eq[k]));
+      if (!P->kl_Eq[k]) return fail(KA_ERR_OOM, "device allocation failed in ka_kl_sample");
+      P->kl_mq[k] = mq[k];
+    }
+    P->kl_omega = keep(omega);
+    if (!P->kl_omega) return fail(KA_ERR_OOM, "device allocation failed in ka_kl_sample");
   }
+  // this call's workspace
   const int chunk = std::min(M, 32);
   const int64_t tq = std::max((int64_t)mq[0] * n[1] * n[2], (int64_t)mq[0] * mq[1] * n[2]);
   const int64_t tg = std::max((int64_t)mg[0] * n[1] * n[2], (int64_t)mg[0] * mg[1] * n[2]);
-  double* t1 = sc.get<double>((size_t)std::max(tq, tg) * chunk);
-  double* t2 = sc.get<double>((size_t)std::max(tq, tg) * chunk);
-  double* Uq = sc.get<double>((size_t)Q * chunk);
-  double* omega_d = coll ? sc.put(omega) : nullptr;
   const int64_t clen = std::max<int64_t>(8192, (Q + 255) / 256);
   const int nchunk = (int)((Q + clen - 1) / clen);
-  double* part = sc.get<double>((size_t)nchunk * chunk);
-  double* norms2 = sc.get<double>(M);
-  double* Phi = sc.get<double>((size_t)Pts * M);
-  double* gscale_d = gscale.empty() ? nullptr : sc.put(gscale);
-  double* fac_d = sc.get<double>(M);
-  double* XiT = sc.get<double>((size_t)M * nsamples);
-  if (!sc.ok) return fail(KA_ERR_OOM, "device allocation failed in ka_kl_sample");
+  std::vector<std::vector<double>> Eg_rows(3);
+  KlArena ar;
+  size_t iEg[3];
+  for (int k = 0; k < 3; ++k) {
+    Eg_rows[k] = to_rows(Eg[k]);
+    iEg[k] = ar.add(Eg_rows[k].size());
+  }
+  const size_t it1 = ar.add((size_t)std::max(tq, tg) * chunk), it2 = ar.add((size_t)std::max(tq, tg) * chunk);
+  const size_t iUq = ar.add((size_t)Q * chunk), ipart = ar.add((size_t)nchunk * chunk), inorm = ar.add(M);
+  const size_t iPhi = ar.add((size_t)Pts * M), igs = ar.add(gscale.size()), ifac = ar.add(M);
+  const size_t iXi = ar.add((size_t)M * nsamples);
+  if (P->kl_bytes < ar.total) {
+    if (P->kl_buf) {
+      (void)hipStreamSynchronize(s);
+      (void)hipFree(P->kl_buf);
+      P->kl_buf = nullptr;
+      P->kl_bytes = 0;
+    }
+    if (hipMalloc(&P->kl_buf, ar.total) != hipSuccess) {
+      P->kl_buf = nullptr;
+      return fail(KA_ERR_OOM, "device allocation failed in ka_kl_sample");
+    }
+    P->kl_bytes = ar.total;
+  }
+  auto at = [&](size_t i) { return (double*)((char*)P->kl_buf + ar.off[i]); };
+  double* Eqd[3];
+  double* Egd[3];
+  for (int k = 0; k < 3; ++k) {
+    Eqd[k] = coll ? P->kl_Eq[k] : P->Zk[k];   // Galerkin: Z v with the mass matrices
+    Egd[k] = at(iEg[k]);
+    HIP_TRY(hipMemcpyAsync(Egd[k], Eg_rows[k].data(), Eg_rows[k].size() * sizeof(double), hipMemcpyHostToDevice, s));
+  }
+  double* t1 = at(it1);
+  double* t2 = at(it2);
+  double* Uq = at(iUq);
+  const double* omega_d = coll ? P->kl_omega : nullptr;
+  double* part = at(ipart);
+  double* norms2 = at(inorm);
+  double* Phi = at(iPhi);
+  double* gscale_d = gscale.empty() ? nullptr : at(igs);
+  if (gscale_d) HIP_TRY(hipMemcpyAsync(gscale_d, gscale.data(), gscale.size() * sizeof(double), hipMemcpyHostToDevice, s));
+  double* fac_d = at(ifac);
+  double* XiT = at(iXi);
 
   for (int c0 = 0; c0 < M; c0 += chunk) {
     const int nv = std::min(chunk, M - c0);
@@ -349,6 +383,6 @@ extern "C" int ka_kl_sample(ka_problem* p, int M, const double* lambda_host, con
   hipLaunchKernelGGL(kl_field_kernel, dim3((unsigned)grid_wg), dim3(256), 0, s, Phi, Pts, Pts, XiT, nsamples, M, mu,
                      field_dev, ldf, n_pt, n_st);
   HIP_TRY(hipGetLastError());
-  HIP_TRY(hipStreamSynchronize(s));   // scratch is freed on return
+  HIP_TRY(hipStreamSynchronize(s));   // the host vectors copied above live until here
   return KA_OK;
 }

@@ -128,3 +128,24 @@ def test_sample_argument_errors():
         K.ka_kl_sample(prob.h, np.array([1.0, 0.5, 0.1]), V, grid, xi, F)
     assert e.value.code == K.KA_ERR_SINGULAR
     prob.close()
+
+
+@pytest.mark.parametrize("c", [CASES[0], CASES[2]], ids=_ids)
+def test_repeated_calls_reuse_the_workspace(c):
+    """One problem, three calls: a small grid, a larger one (the kept workspace
+    grows) and the small one again (reused; collocation also reuses its kept
+    quadrature data).  Every call against the oracle at the FP64 bar."""
+    o = _oracle(c)
+    lam, V = o.eig_dense(8)
+    lam, V = lam.real, V.real
+    prob = _problem(c)
+    rng = np.random.default_rng(11)
+    small = [np.sort(rng.random(4)), np.sort(rng.random(3)), np.sort(rng.random(5))]
+    large = [np.linspace(0, 1, 21), np.sort(rng.random(13)), np.linspace(0, 1, 9)]
+    for grid, S in ((small, 5), (large, 90), (small, 7)):
+        xi = rng.standard_normal((8, S))
+        F = _sample_gpu(prob, lam, V, grid, xi, -0.5)
+        ref = kl.sample(o, lam, V, grid, xi, mu=-0.5)
+        assert np.isfinite(F).all()
+        assert np.abs(F - ref).max() < 1e-12 * np.abs(ref).max(), np.abs(F - ref).max()
+    prob.close()
