@@ -294,12 +294,24 @@ KA_HD inline void sym_inverse_iteration(const double* d, const double* e, int n,
         x1 = s;
       }
       // orthogonalise against the cluster's members computed before (two
-      // passes; four partial sums keep several loads of V in flight)
+      // passes).  Elements of a stored vector are n apart, so every one is
+      // its own cache line: they are loaded 16 at a time, all in flight
+      // together, before any is used (four partial sums over i mod 4).
       for (int pass = 0; pass < (k < ktop ? 2 : 0); ++pass)
         for (int j = k + 1; j <= ktop; ++j) {
           const double* vj = V + j;
           double d0 = 0.0, d1 = 0.0, d2 = 0.0, d3 = 0.0;
           int i = 0;
+          for (; i + 15 < n; i += 16) {
+            double v[16];
+            for (int u = 0; u < 16; ++u) v[u] = vj[(size_t)(i + u) * n];
+            for (int u = 0; u < 16; u += 4) {
+              d0 += XK(i + u) * v[u];
+              d1 += XK(i + u + 1) * v[u + 1];
+              d2 += XK(i + u + 2) * v[u + 2];
+              d3 += XK(i + u + 3) * v[u + 3];
+            }
+          }
           for (; i + 3 < n; i += 4) {
             d0 += XK(i) * vj[(size_t)i * n];
             d1 += XK(i + 1) * vj[(size_t)(i + 1) * n];
@@ -308,7 +320,12 @@ KA_HD inline void sym_inverse_iteration(const double* d, const double* e, int n,
           }
           for (; i < n; ++i) d0 += XK(i) * vj[(size_t)i * n];
           const double dot = (d0 + d1) + (d2 + d3);
-          for (i = 0; i < n; ++i) XK(i) -= dot * vj[(size_t)i * n];
+          for (i = 0; i + 15 < n; i += 16) {
+            double v[16];
+            for (int u = 0; u < 16; ++u) v[u] = vj[(size_t)(i + u) * n];
+            for (int u = 0; u < 16; ++u) XK(i + u) -= dot * v[u];
+          }
+          for (; i < n; ++i) XK(i) -= dot * vj[(size_t)i * n];
         }
       double nr = 0.0;
       for (int i = 0; i < n; ++i) nr += XK(i) * XK(i);
