@@ -16,40 +16,30 @@ namespace ka {
 // ---------------------------------------------------------------------------
 constexpr int TM = 64, TN = 64, TK = 16;
 
-// TRANS_A: C_part(m x n) = A[k0:k1, :]^T B[k0:k1, :], A is K x m (lda).
-// else:    C(M x n) = alpha A B + beta C, A is M x k (lda).
-template <bool TRANS_A>
+// C(M x n) = alpha A B + beta C, A is M x k (lda), B is k x n (ldb).
 __global__ __launch_bounds__(256) void dgemm_tile_kernel(int64_t M, int n, int64_t K, const double* __restrict__ A,
                                                          int64_t lda, const double* __restrict__ B, int64_t ldb,
                                                          double* __restrict__ C, int64_t ldc, double alpha,
-                                                         double beta, int64_t k_per_split) {
+                                                         double beta) {
   __shared__ double sA[TK][TM + 1];
   __shared__ double sB[TK][TN + 1];
   const int tid = threadIdx.x;
   const int tx = tid % 16, ty = tid / 16;
   const int64_t i0 = (int64_t)blockIdx.x * TM;
   const int j0 = blockIdx.y * TN;
-  const int64_t kb = TRANS_A ? (int64_t)blockIdx.z * k_per_split : 0;
-  const int64_t ke = TRANS_A ? ((kb + k_per_split < K) ? kb + k_per_split : K) : K;
   double acc[4][4];
 #pragma unroll
   for (int u = 0; u < 4; ++u)
 #pragma unroll
     for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
 
-  for (int64_t k0 = kb; k0 < ke; k0 += TK) {
+  for (int64_t k0 = 0; k0 < K; k0 += TK) {
     // A tile -> sA[kk][i]
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      if (TRANS_A) {
-        const int kk = tid % 16, ii = tid / 16 + 16 * r;
-        const int64_t k = k0 + kk, i = i0 + ii;
-        sA[kk][ii] = (k < ke && i < M) ? A[k + i * lda] : 0.0;
-      } else {
-        const int ii = tid % 64, kk = tid / 64 + 4 * r;
-        const int64_t k = k0 + kk, i = i0 + ii;
-        sA[kk][ii] = (k < ke && i < M) ? A[i + k * lda] : 0.0;
-      }
+      const int ii = tid % 64, kk = tid / 64 + 4 * r;
+      const int64_t k = k0 + kk, i = i0 + ii;
+      sA[kk][ii] = (k < K && i < M) ? A[i + k * lda] : 0.0;
     }
     // B tile (K x n, column-major) -> sB[kk][j]
 #pragma unroll
@@ -57,7 +47,7 @@ __global__ __launch_bounds__(256) void dgemm_tile_kernel(int64_t M, int n, int64
       const int kk = tid % 16, jj = tid / 16 + 16 * r;
       const int64_t k = k0 + kk;
       const int j = j0 + jj;
-      sB[kk][jj] = (k < ke && j < n) ? B[k + (int64_t)j * ldb] : 0.0;
+      sB[kk][jj] = (k < K && j < n) ? B[k + (int64_t)j * ldb] : 0.0;
     }
     __syncthreads();
 #pragma unroll
@@ -82,12 +72,8 @@ __global__ __launch_bounds__(256) void dgemm_tile_kernel(int64_t M, int n, int64
     for (int v = 0; v < 4; ++v) {
       const int j = j0 + ty + 16 * v;
       if (j >= n) continue;
-      if (TRANS_A) {
-        C[((size_t)blockIdx.z * n + j) * M + i] = acc[u][v];   // partial[z][j][i]
-      } else {
-        double* c = C + i + (int64_t)j * ldc;
-        *c = (beta == 0.0) ? alpha * acc[u][v] : alpha * acc[u][v] + beta * *c;
-      }
+      double* c = C + i + (int64_t)j * ldc;
+      *c = (beta == 0.0) ? alpha * acc[u][v] : alpha * acc[u][v] + beta * *c;
     }
   }
 }
@@ -114,32 +100,116 @@ __global__ void split_reduce_kernel(const double* __restrict__ part, int nsplit,
   *c = (beta == 0.0) ? alpha * s : alpha * s + beta * *c;
 }
 
-// Split the long dimension so that about 1024 workgroups run, each over at
-// least 128 rows (eight TK steps): the products here are short and wide
-// (K ~ 10^4 .. 10^6 rows, m, n <= a few hundred) and otherwise latency-bound.
-static int tn_splits(int m, int n, int64_t K) {
-  const int64_t tiles = (int64_t)((m + TM - 1) / TM) * ((n + TN - 1) / TN);
-  int64_t ns = (1024 + tiles - 1) / tiles;
-  const int64_t by_k = K / 128;
-  if (ns > by_k) ns = by_k;
-  if (ns > 256) ns = 256;
-  if (ns < 1) ns = 1;
-  return (int)ns;
+// ---------------------------------------------------------------------------
+// C = alpha A^T B + beta C for tall A (K x m) and B (K x n): the projections
+// and Gram matrices of the block eigensolver (K = N up to ~10^6, m and n up to
+// a few hundred).  The product is bound by reading A and B once, so the aim is
+// many loads in flight, with the arithmetic on the FP64 matrix cores.
+//
+// v_mfma_f64_16x16x4f64, one wave per 16 x 16 output tile and 16-row group:
+// A lane l holds (i = l % 16, k = l / 16), B lane l holds (k = l / 16,
+// j = l % 16), accumulator register r of lane l holds (i = l / 16 + 4 r,
+// j = l % 16).  The four MFMAs of a group may take its 16 rows in any
+// partition, so lane l reads the four consecutive rows 4 (l / 16) .. + 3 of its
+// column of A and of B (MFMA s takes row 4 (l / 16) + s).  The 4 waves of a
+// workgroup take interleaved groups of its row range and are summed through LDS
+// in wave order; row ranges (splits) go to a partial array that
+// split_reduce_kernel sums in split order, or straight to C with one split.
+// ---------------------------------------------------------------------------
+typedef double tn_d4 __attribute__((ext_vector_type(4)));
+constexpr int kTnU = 2;                 // groups per wave per iteration (8 + 8 loads per lane in flight)
+constexpr int kTnRows = 64 * kTnU;      // rows per workgroup iteration; splits are multiples of it
+
+__global__ __launch_bounds__(256) void dgemm_tn_mfma_kernel(int m, int n, int64_t K, const double* __restrict__ A,
+                                                            int64_t lda, const double* __restrict__ B, int64_t ldb,
+                                                            int64_t k_per_split, double* __restrict__ part,
+                                                            double alpha, double beta, double* __restrict__ C,
+                                                            int64_t ldc) {
+  __shared__ double red[3][4][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, q = lane >> 4;
+  const int i = blockIdx.x * 16 + (lane & 15), j = blockIdx.y * 16 + (lane & 15);
+  const bool iok = i < m, jok = j < n;
+  const double* __restrict__ Ai = A + (int64_t)(iok ? i : 0) * lda;
+  const double* __restrict__ Bj = B + (int64_t)(jok ? j : 0) * ldb;
+  const int64_t kb = (int64_t)blockIdx.z * k_per_split;
+  const int64_t ke = (kb + k_per_split < K) ? kb + k_per_split : K;
+  tn_d4 acc = {0.0, 0.0, 0.0, 0.0};
+  // the loop bound is uniform over the wave (the matrix cores need all lanes)
+  for (int64_t g0 = kb + 16 * w; g0 < ke; g0 += kTnRows) {
+    // loads at clamped addresses (rows past the range are read at row ke - 1
+    // and weighted by zero), all issued before the first MFMA
+    double a[kTnU][4], bv[kTnU][4];
+#pragma unroll
+    for (int u = 0; u < kTnU; ++u)
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const int64_t r = g0 + 64 * u + 4 * q + s;
+        const int64_t rc = r < ke ? r : ke - 1;
+        a[u][s] = Ai[rc];
+        bv[u][s] = Bj[rc];
+      }
+#pragma unroll
+    for (int u = 0; u < kTnU; ++u)
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const bool ok = g0 + 64 * u + 4 * q + s < ke;
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(ok && iok ? a[u][s] : 0.0, ok && jok ? bv[u][s] : 0.0, acc,
+                                                   0, 0, 0);
+      }
+  }
+  if (w > 0)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) red[w - 1][r][lane] = acc[r];
+  __syncthreads();
+  if (w > 0) return;
+  const int jo = blockIdx.y * 16 + (lane & 15);
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const double v = ((acc[r] + red[0][r][lane]) + red[1][r][lane]) + red[2][r][lane];
+    const int io = blockIdx.x * 16 + q + 4 * r;
+    if (io >= m || jo >= n) continue;
+    if (part) {
+      part[((size_t)blockIdx.z * n + jo) * m + io] = v;   // partial[z][j][i]
+    } else {
+      double* c = C + io + (int64_t)jo * ldc;
+      *c = (beta == 0.0) ? alpha * v : alpha * v + beta * *c;
+    }
+  }
 }
 
-size_t dgemm_tn_work(int m, int n, int64_t K) { return (size_t)tn_splits(m, n, K) * m * n; }
+// Row splits: about 1024 workgroups, at least 256 rows each, whole multiples
+// of kTnRows, at most 256 splits; products with K < 1024 take one split.
+static int64_t tn_rows_per_split(int m, int n, int64_t K) {
+  if (K < 1024) return K > 0 ? K : 1;
+  const int64_t tiles = (int64_t)((m + 15) / 16) * ((n + 15) / 16);
+  int64_t ns = (1024 + tiles - 1) / tiles;
+  if (ns > K / 256) ns = K / 256;
+  if (ns > 256) ns = 256;
+  if (ns < 1) ns = 1;
+  int64_t kps = (K + ns - 1) / ns;
+  return (kps + kTnRows - 1) / kTnRows * kTnRows;
+}
+
+static int tn_splits(int m, int n, int64_t K) {
+  const int64_t kps = tn_rows_per_split(m, n, K);
+  return K > 0 ? (int)((K + kps - 1) / kps) : 1;
+}
+
+size_t dgemm_tn_work(int m, int n, int64_t K) {
+  const int ns = tn_splits(m, n, K);
+  return ns > 1 ? (size_t)ns * m * n : 0;
+}
 
 hipError_t dgemm_tn(int m, int n, int64_t K, double alpha, const double* A, int64_t lda, const double* B,
                     int64_t ldb, double beta, double* C, int64_t ldc, double* work, hipStream_t s) {
   if (m <= 0 || n <= 0) return hipSuccess;
+  const int64_t kps = tn_rows_per_split(m, n, K);
   const int ns = tn_splits(m, n, K);
-  int64_t kps = (K + ns - 1) / ns;
-  kps = (kps + TK - 1) / TK * TK;
-  const dim3 grid((m + TM - 1) / TM, (n + TN - 1) / TN, ns);
-  hipLaunchKernelGGL((dgemm_tile_kernel<true>), grid, dim3(256), 0, s, (int64_t)m, n, K, A, lda, B, ldb, work,
-                     (int64_t)m, 1.0, 0.0, kps);
+  const dim3 grid((m + 15) / 16, (n + 15) / 16, ns);
+  hipLaunchKernelGGL(dgemm_tn_mfma_kernel, grid, dim3(256), 0, s, m, n, K, A, lda, B, ldb, kps,
+                     ns > 1 ? work : nullptr, alpha, beta, C, ldc);
   hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
+  if (e != hipSuccess || ns == 1) return e;
   const int64_t tot = (int64_t)m * n;
   hipLaunchKernelGGL(split_reduce_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, work, ns, m, n,
                      alpha, beta, C, ldc);
@@ -150,8 +220,8 @@ hipError_t dgemm_nn(int64_t M, int n, int k, double alpha, const double* A, int6
                     int64_t ldb, double beta, double* C, int64_t ldc, hipStream_t s) {
   if (M <= 0 || n <= 0) return hipSuccess;
   const dim3 grid((unsigned)((M + TM - 1) / TM), (n + TN - 1) / TN, 1);
-  hipLaunchKernelGGL((dgemm_tile_kernel<false>), grid, dim3(256), 0, s, M, n, (int64_t)k, A, lda, B, ldb, C, ldc,
-                     alpha, beta, (int64_t)0);
+  hipLaunchKernelGGL(dgemm_tile_kernel, grid, dim3(256), 0, s, M, n, (int64_t)k, A, lda, B, ldb, C, ldc, alpha,
+                     beta);
   return hipGetLastError();
 }
 
