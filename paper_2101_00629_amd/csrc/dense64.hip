@@ -11,73 +11,6 @@
 
 namespace ka {
 
-// ---------------------------------------------------------------------------
-// tiled FP64 products: 64 x 64 output tile, 256 threads, 4 x 4 per thread
-// ---------------------------------------------------------------------------
-constexpr int TM = 64, TN = 64, TK = 16;
-
-// C(M x n) = alpha A B + beta C, A is M x k (lda), B is k x n (ldb).
-__global__ __launch_bounds__(256) void dgemm_tile_kernel(int64_t M, int n, int64_t K, const double* __restrict__ A,
-                                                         int64_t lda, const double* __restrict__ B, int64_t ldb,
-                                                         double* __restrict__ C, int64_t ldc, double alpha,
-                                                         double beta) {
-  __shared__ double sA[TK][TM + 1];
-  __shared__ double sB[TK][TN + 1];
-  const int tid = threadIdx.x;
-  const int tx = tid % 16, ty = tid / 16;
-  const int64_t i0 = (int64_t)blockIdx.x * TM;
-  const int j0 = blockIdx.y * TN;
-  double acc[4][4];
-#pragma unroll
-  for (int u = 0; u < 4; ++u)
-#pragma unroll
-    for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
-
-  for (int64_t k0 = 0; k0 < K; k0 += TK) {
-    // A tile -> sA[kk][i]
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int ii = tid % 64, kk = tid / 64 + 4 * r;
-      const int64_t k = k0 + kk, i = i0 + ii;
-      sA[kk][ii] = (k < K && i < M) ? A[i + k * lda] : 0.0;
-    }
-    // B tile (K x n, column-major) -> sB[kk][j]
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int kk = tid % 16, jj = tid / 16 + 16 * r;
-      const int64_t k = k0 + kk;
-      const int j = j0 + jj;
-      sB[kk][jj] = (k < K && j < n) ? B[k + (int64_t)j * ldb] : 0.0;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int kk = 0; kk < TK; ++kk) {
-      double av[4], bv[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) av[u] = sA[kk][tx + 16 * u];
-#pragma unroll
-      for (int v = 0; v < 4; ++v) bv[v] = sB[kk][ty + 16 * v];
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) acc[u][v] = __builtin_fma(av[u], bv[v], acc[u][v]);
-    }
-    __syncthreads();
-  }
-#pragma unroll
-  for (int u = 0; u < 4; ++u) {
-    const int64_t i = i0 + tx + 16 * u;
-    if (i >= M) continue;
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int j = j0 + ty + 16 * v;
-      if (j >= n) continue;
-      double* c = C + i + (int64_t)j * ldc;
-      *c = (beta == 0.0) ? alpha * acc[u][v] : alpha * acc[u][v] + beta * *c;
-    }
-  }
-}
-
 __global__ void split_reduce_kernel(const double* __restrict__ part, int nsplit, int m, int n, double alpha,
                                     double beta, double* __restrict__ C, int64_t ldc) {
   const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -216,12 +149,82 @@ hipError_t dgemm_tn(int m, int n, int64_t K, double alpha, const double* A, int6
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// C = alpha A B + beta C for tall A (M x k) and small B (k x n): basis
+// updates X C and restarts X S of the block eigensolver.  One workgroup per
+// 16-row tile of C and up to 64 columns (four 16-column MFMA tiles), its 4
+// waves taking interleaved 4-column steps of A (the same fragment layout as
+// the A^T B kernel above; lane l reads A at row l % 16, column 4 s + l / 16, so
+// 16 lanes read 128 contiguous bytes) and summed through LDS in wave order.
+// ---------------------------------------------------------------------------
+constexpr int kNnU = 4;   // 4-column steps per wave per iteration
+
+__global__ __launch_bounds__(256) void dgemm_nn_mfma_kernel(int64_t M, int n, int k, const double* __restrict__ A,
+                                                            int64_t lda, const double* __restrict__ B, int64_t ldb,
+                                                            double alpha, double beta, double* __restrict__ C,
+                                                            int64_t ldc) {
+  __shared__ double red[3][4][4][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, q = lane >> 4;
+  const int64_t i = (int64_t)blockIdx.x * 16 + (lane & 15);
+  const bool iok = i < M;
+  const double* __restrict__ Ai = A + (iok ? i : M - 1);
+  const int j0 = blockIdx.y * 64;
+  const int jt = (n - j0 + 15) / 16 < 4 ? (n - j0 + 15) / 16 : 4;   // column tiles of this workgroup
+  tn_d4 acc[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) acc[t] = (tn_d4){0.0, 0.0, 0.0, 0.0};
+  for (int base = 4 * w; base < k; base += 16 * kNnU) {   // uniform over the wave
+    double a[kNnU], bv[kNnU][4];
+#pragma unroll
+    for (int u = 0; u < kNnU; ++u) {
+      const int kr = base + 16 * u + q;
+      const int kc = kr < k ? kr : k - 1;
+      a[u] = Ai[(int64_t)kc * lda];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int j = j0 + 16 * t + (lane & 15);
+        bv[u][t] = (t < jt) ? B[kc + (int64_t)(j < n ? j : n - 1) * ldb] : 0.0;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kNnU; ++u) {
+      const int kr = base + 16 * u + q;
+      const double av = (kr < k && iok) ? a[u] : 0.0;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        if (t >= jt) break;
+        const int j = j0 + 16 * t + (lane & 15);
+        acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, j < n ? bv[u][t] : 0.0, acc[t], 0, 0, 0);
+      }
+    }
+  }
+  if (w > 0)
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) red[w - 1][t][r][lane] = acc[t][r];
+  __syncthreads();
+  if (w > 0) return;
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const int jo = j0 + 16 * t + (lane & 15);
+    if (t >= jt || jo >= n) continue;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int64_t io = (int64_t)blockIdx.x * 16 + q + 4 * r;
+      if (io >= M) continue;
+      const double v = ((acc[t][r] + red[0][t][r][lane]) + red[1][t][r][lane]) + red[2][t][r][lane];
+      double* c = C + io + (int64_t)jo * ldc;
+      *c = (beta == 0.0) ? alpha * v : alpha * v + beta * *c;
+    }
+  }
+}
+
 hipError_t dgemm_nn(int64_t M, int n, int k, double alpha, const double* A, int64_t lda, const double* B,
                     int64_t ldb, double beta, double* C, int64_t ldc, hipStream_t s) {
   if (M <= 0 || n <= 0) return hipSuccess;
-  const dim3 grid((unsigned)((M + TM - 1) / TM), (n + TN - 1) / TN, 1);
-  hipLaunchKernelGGL(dgemm_tile_kernel, grid, dim3(256), 0, s, M, n, (int64_t)k, A, lda, B, ldb, C, ldc, alpha,
-                     beta);
+  const dim3 grid((unsigned)((M + 15) / 16), (n + 63) / 64, 1);
+  hipLaunchKernelGGL(dgemm_nn_mfma_kernel, grid, dim3(256), 0, s, M, n, k, A, lda, B, ldb, alpha, beta, C, ldc);
   return hipGetLastError();
 }
 
