@@ -154,18 +154,18 @@ int EigRun::orth_block(int k, int pw) {
         HIP_TRY(dgemm_nn(N, pw, k, -1.0, w_.X, N, w_.C, k, 1.0, w_.P, N, s_));
       }
     }
-    int bad = 0;
-    for (int pass = 0; pass < 2 && !bad; ++pass) {
+    // both passes run before the one host read of their two status words (a
+    // block that fails the first pass is redrawn all the same)
+    for (int pass = 0; pass < 2; ++pass) {
       HIP_TRY(dgemm_tn(pw, pw, N, 1.0, w_.P, N, w_.P, N, 0.0, w_.G, pw, w_.tnwork, s_));
-      HIP_TRY(chol_upper_inv(w_.G, pw, pw, w_.Rinv, pw, w_.status, s_));
+      HIP_TRY(chol_upper_inv(w_.G, pw, pw, w_.Rinv, pw, w_.status + pass, s_));
       HIP_TRY(dgemm_nn(N, pw, pw, 1.0, w_.P, N, w_.Rinv, pw, 0.0, w_.T, N, s_));
       HIP_TRY(copy_cols(w_.T, N, w_.P, N, N, pw, s_));
-      int st = 0;
-      HIP_TRY(hipMemcpyAsync(&st, w_.status, sizeof(int), hipMemcpyDeviceToHost, s_));
-      HIP_TRY(hipStreamSynchronize(s_));
-      bad = st;
     }
-    if (!bad) return KA_OK;
+    int st[2] = {0, 0};
+    HIP_TRY(hipMemcpyAsync(st, w_.status, sizeof(st), hipMemcpyDeviceToHost, s_));
+    HIP_TRY(hipStreamSynchronize(s_));
+    if (!st[0] && !st[1]) return KA_OK;
     // Krylov space exhausted along some direction: continue with random ones
     HIP_TRY(fill_normal(w_.P, N, pw, N, P_->d.seed, ++rng_counter_, s_));
   }

@@ -111,9 +111,13 @@ KA_HD void ns_hessenberg(Team& tm, double* A, int ld, int n, double* hsub, doubl
         w[c] = b * (s0 + s1);
       }
       tm.sync();
-      for (int i = t; i < m; i += NT) {
-        const double vi = v[i];
-        for (int c = j + 1; c < n; ++c) AH(j + 1 + i, c) -= w[c] * vi;
+      // the rank-one updates are spread over the whole team, one element per
+      // thread and pass, in memory order (each element takes the same single
+      // update as in a row-by-row loop)
+      const int nc = n - j - 1;
+      for (int e = t; e < m * nc; e += NT) {
+        const int i = e % m, c = j + 1 + e / m;
+        AH(j + 1 + i, c) -= w[c] * v[i];
       }
       tm.sync();
       // right: A[r, j+1:] -= b (A[r, j+1:] v) v^T for every row
@@ -125,8 +129,12 @@ KA_HD void ns_hessenberg(Team& tm, double* A, int ld, int n, double* hsub, doubl
           s1 += AH(r, j + 2 + i) * v[i + 1];
         }
         if (i < m) s0 += AH(r, j + 1 + i) * v[i];
-        const double u = b * (s0 + s1);
-        for (i = 0; i < m; ++i) AH(r, j + 1 + i) -= u * v[i];
+        w[r] = b * (s0 + s1);
+      }
+      tm.sync();
+      for (int e = t; e < n * m; e += NT) {
+        const int r = e % n, i = e / n;
+        AH(r, j + 1 + i) -= w[r] * v[i];
       }
     }
     tm.sync();

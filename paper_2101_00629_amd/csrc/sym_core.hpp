@@ -111,10 +111,11 @@ KA_HD void sym_tridiagonalize(Team& tm, double* A, int n, double* d, double* e, 
       const double K = 0.5 * b * wv;
       for (int r = t; r < m; r += NT) w[r] -= K * v[r];
       tm.sync();
-      // A22 <- A22 - v w^T - w v^T  (= H A22 H), one row per thread
-      for (int r = t; r < m; r += NT) {
-        const double vr = v[r], wr = w[r];
-        for (int c = 0; c < m; ++c) A22[r + (size_t)c * n] -= vr * w[c] + wr * v[c];
+      // A22 <- A22 - v w^T - w v^T  (= H A22 H), spread over the whole team,
+      // one element per thread and pass in memory order
+      for (int q = t; q < m * m; q += NT) {
+        const int r = q % m, c = q / m;
+        A22[r + (size_t)c * n] -= v[r] * w[c] + w[r] * v[c];
       }
     }
     tm.sync();
