@@ -158,7 +158,10 @@ def serve_benchmark(n_requests, rhos, cap, tol, seed=210100629):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         prob = K.Problem(descs[i])
-        rc, lam, info = K.ka_eigs(prob.h, d["M"], tol=tol, maxit=60, complex_values=cplx[i])
+        try:
+            rc, lam, info = K.ka_eigs(prob.h, d["M"], tol=tol, maxit=60, complex_values=cplx[i])
+        except K.KAError as e:   # a failed solve is reported with its status, as the server does
+            rc, lam, info = e.code, np.zeros(2 * d["M"]), {"iterations": None, "converged": 0}
         prob.close()
         torch.cuda.synchronize()
         service.append(time.perf_counter() - t0)

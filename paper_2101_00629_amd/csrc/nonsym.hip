@@ -159,15 +159,16 @@ __device__ int ns_qr_values_wave(double* hb, int n, double* wr, double* wi, doub
         nn -= 2;
         break;
       }
-      if (its >= 60) {
+      if (its >= kNsQrMaxIts) {
         fail = 1;
         break;
       }
-      if (its == 10 || its == 20 || its == 40) {       // exceptional shift
+      if (ns_exceptional(its)) {                        // exceptional shift
         shift += x;
         for (int i = t; i <= nn; i += 64) HB(i, i) -= x;
         ns_wave_fence();
-        const double s = fabs(HB(nn, nn - 1)) + fabs(HB(nn - 1, nn - 2));
+        const double s = ns_exceptional_top(its) ? fabs(HB(l + 1, l)) + fabs(HB(l + 2, l + 1))
+                                                  : fabs(HB(nn, nn - 1)) + fabs(HB(nn - 1, nn - 2));
         x = y = 0.75 * s;
         w = -0.4375 * s * s;
       }

@@ -171,6 +171,15 @@ KA_HD void ns_band_fill(Team& tm, const double* A, int ld, const double* hsub, i
 // Scalar control flow is identical in every thread (all read the same values
 // after a barrier); row and column updates are split over the team.
 // Returns 0, or 1 when an eigenvalue needed more than 60 iterations.
+// Iteration control of the double-shift QR, per deflation: exceptional
+// shifts after 10 and 20 iterations and then after every further 10, from 30
+// on alternating between the sub-diagonals at the bottom and at the top of
+// the active window, so that a window that stalls under one shift gets a
+// different one; the iteration gives up after kNsQrMaxIts.
+constexpr int kNsQrMaxIts = 200;
+KA_HD inline bool ns_exceptional(int its) { return its > 0 && its % 10 == 0; }
+KA_HD inline bool ns_exceptional_top(int its) { return its >= 30 && (its / 10) % 2 == 1; }
+
 template <class Team>
 KA_HD int ns_qr_values(Team& tm, double* hb, int n, double* wr, double* wi, double* anorm_out) {
   const int t = tm.tid(), NT = tm.size();
@@ -224,16 +233,17 @@ KA_HD int ns_qr_values(Team& tm, double* hb, int n, double* wr, double* wi, doub
         nn -= 2;
         break;
       }
-      if (its >= 60) {
+      if (its >= kNsQrMaxIts) {
         fail = 1;
         break;
       }
-      if (its == 10 || its == 20 || its == 40) {       // exceptional shift
+      if (ns_exceptional(its)) {                        // exceptional shift
         shift += x;
         tm.sync();
         for (int i = t; i <= nn; i += NT) HB(i, i) -= x;
         tm.sync();
-        const double s = fabs(HB(nn, nn - 1)) + fabs(HB(nn - 1, nn - 2));
+        const double s = ns_exceptional_top(its) ? fabs(HB(l + 1, l)) + fabs(HB(l + 2, l + 1))
+                                                  : fabs(HB(nn, nn - 1)) + fabs(HB(nn - 1, nn - 2));
         x = y = 0.75 * s;
         w = -0.4375 * s * s;
       }
