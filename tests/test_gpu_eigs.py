@@ -12,6 +12,7 @@ import torch
 
 import paper_2101_00629_amd as K
 from oracle import errors, galerkin, geometry, product1d
+from oracle.kron import kron_apply
 from workloads import cube_p3_20, small_cube
 
 pytestmark = pytest.mark.gpu
@@ -176,6 +177,76 @@ def test_eigenvector_subspaces_match_oracle(method):
         checked += len(grp)
     print(method, "clusters up to", checked, "largest angle", worst)
     assert checked >= 7 and worst < 1e-4
+
+
+# ---- eigenvectors at the benchmark size, against the exact Kronecker vectors ----------------
+def _product_vectors(method, kind, ell, M, p=3, nel=20):
+    """Top-M generalized eigenpairs of the cube problem from the univariate
+    pencils: eigenvalues lambda1_i lambda2_j lambda3_k, eigenvectors
+    v3_k (x) v2_j (x) v1_i (direction 1 fastest), plus the univariate Z_k."""
+    import scipy.linalg as sla
+    if method == "galerkin":
+        A, Z = product1d.galerkin_pencil_1d(p, nel, kind, ell)
+        lam1, V1 = sla.eigh(A, Z)
+    else:
+        A, Z = product1d.collocation_pencil_1d(p, nel, kind, ell)
+        lam1, V1 = sla.eig(A, Z)
+        assert np.abs(lam1.imag).max() < 1e-12 * np.abs(lam1).max()
+        lam1, V1 = lam1.real, V1.real
+    o = np.argsort(-lam1, kind="stable")
+    lam1, V1 = lam1[o], V1[:, o]
+    n = len(lam1)
+    P = (lam1[:, None, None] * lam1[None, :, None] * lam1[None, None, :]).ravel()   # index (k, j, i)
+    top = np.argsort(-P, kind="stable")[:M]
+    vecs = [np.kron(V1[:, q // (n * n)], np.kron(V1[:, (q // n) % n], V1[:, q % n])) for q in top]
+    return P[top], np.stack(vecs, axis=1), Z
+
+
+def _largest_angle(U, V, Gapply):
+    """Largest principal angle between span(U) and span(V) in <x, y> = x^T G y."""
+    import scipy.linalg as sla
+    GU, GV = Gapply(U), Gapply(V)
+    Ru, Rv = sla.cholesky(U.T @ GU), sla.cholesky(V.T @ GV)
+    C = sla.solve_triangular(Ru, sla.solve_triangular(Rv, (U.T @ GV).T, trans="T").T, trans="T")
+    s = np.linalg.svd(C, compute_uv=False)
+    return float(np.arccos(np.clip(s.min(), -1.0, 1.0)))
+
+
+@pytest.mark.parametrize("method,kernel", [("galerkin", "gaussian"), ("galerkin", "exponential"),
+                                           ("collocation", "gaussian"), ("collocation", "exponential")])
+def test_cube_p3_20_eigenvectors_match_product_vectors(method, kernel):
+    """The benchmark problems (cube p = 3, 20^3, M = 50): the returned eigenvectors
+    against the exact Kronecker products of univariate eigenvectors, as the
+    largest principal angle per cluster of the reference spectrum (relative gap
+    < 1e-8) lying wholly within the first M; Z inner product for Galerkin.
+    Expected size: residual over relative gap, so the bound grows as 1/gap."""
+    c = cube_p3_20(method, kernel)
+    M = c["M"]
+    ref, Vref, Z1 = _product_vectors(method, kernel, c["ell"], M + 8)
+    desc = K.desc_from_problem(c, seed=31)
+    if method == "galerkin":
+        rc, lam, V, info = _solve(desc, M)
+        Gapply = lambda X: kron_apply((Z1, Z1, Z1), X)
+    else:
+        rc, lam, V, info = _solve_c(desc, M)
+        assert np.abs(lam[1::2]).max() <= 1e-6 * lam[0]
+        lam = lam[0::2]
+        Gapply = lambda X: X
+    assert rc == 0
+    assert errors.floored_rel_errors(ref[:M], lam).max() < 1e-6
+    worst, worst_bound, checked = 0.0, 0.0, 0
+    for grp in errors.clusters(ref, 1e-8):
+        if grp[-1] >= M:
+            break
+        ang = _largest_angle(V[:, grp], Vref[:, grp], Gapply)
+        lo, hi = grp[0], grp[-1]
+        gap = min(ref[lo - 1] - ref[lo] if lo > 0 else np.inf, ref[hi] - ref[hi + 1]) / ref[0]
+        worst = max(worst, ang)
+        worst_bound = max(worst_bound, ang * gap)
+        checked += len(grp)
+    print(method, kernel, "eigenvectors", checked, "largest angle", worst, "largest angle x relative gap", worst_bound)
+    assert checked >= 40
+    assert worst_bound < 1e-6 and worst < 1e-2
 
 
 # ---- trace: sum of all eigenvalues (tr Z^-1 A) -----------------------------------------------
