@@ -21,6 +21,9 @@ collocation  isogeometric collocation (Sec. 3.2, eq. colloc_system_matrices,
              Algorithm 1).
 product1d    exact spectra of separable kernels on boxes as products of 1D
              pencils.
+extruded     exact spectra of separable kernels on extruded domains (box,
+             quarter annulus) as products of a cross-section pencil and a 1D
+             pencil along the extrusion.
 analytic     closed-form eigenpairs of the 1D exponential kernel.
 errors       eigenvalue error measures (Sec. 4.1, eps_i and mean eps).
 cmatvec      ctypes wrapper of the plain C OpenMP FP64 Gamma-times-block product.
