@@ -220,6 +220,22 @@ int ka_gamma_apply(int kernel, double sigma, double ell, const float* xr_dev, in
 /* Scratch bytes ka_gamma_apply needs for these sizes. */
 size_t ka_gamma_workspace(int64_t nr, int64_t nc, int b, int precision);
 
+/* ka_gamma_apply without any device allocation and without a workspace
+ * argument, for callers that cannot allocate device memory (code under HIP
+ * stream capture, serving loops and harnesses that forbid hipMalloc).  Same
+ * arguments, kernels and results as ka_gamma_apply; its scratch is a
+ * file-scope device array of ka_gamma_static_capacity() bytes (128 MiB), one
+ * per GPU, held until the process ends and looked up on the first call on each
+ * device.  A product whose ka_gamma_workspace() exceeds that capacity fails
+ * with KA_ERR_ARG before anything is launched.  All calls on one GPU share the
+ * array: calls that overlap on the device (concurrent streams) race and must
+ * be serialised by the caller.  Nothing in the array needs clearing: every
+ * entry a call reads is written earlier in the same call.  Async on `stream`. */
+int ka_gamma_apply_static(int kernel, double sigma, double ell, const float* xr_dev, int64_t nr,
+                          const float* xc_dev, int64_t nc, const float* Y_dev, int b, float* Z_dev,
+                          int precision, void* stream);
+size_t ka_gamma_static_capacity(void);
+
 /* ---- K-L field sampling (paper Sec. 2, eq. kle) --------------------------
  * Truncated expansion alpha_M(x, s) = mu + sum_{i<M} sqrt(lambda_i) phi_i(x) xi_i(s)
  * at the tensor grid of parametric points (grid[0][i1], grid[1][i2], grid[2][i3])

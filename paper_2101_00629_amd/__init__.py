@@ -88,6 +88,9 @@ def _load():
         "ka_gamma_apply": ([ctypes.c_int, ctypes.c_double, ctypes.c_double, fp, i64, fp, i64, fp, ctypes.c_int,
                             fp, ctypes.c_int, vp, ctypes.c_size_t, vp], ctypes.c_int),
         "ka_gamma_workspace": ([i64, i64, ctypes.c_int, ctypes.c_int], ctypes.c_size_t),
+        "ka_gamma_apply_static": ([ctypes.c_int, ctypes.c_double, ctypes.c_double, fp, i64, fp, i64, fp,
+                                   ctypes.c_int, fp, ctypes.c_int, vp], ctypes.c_int),
+        "ka_gamma_static_capacity": ([], ctypes.c_size_t),
         "ka_profile_enable": ([vp, ctypes.c_int], ctypes.c_int),
         "ka_profile_read": ([vp, ctypes.POINTER(ctypes.c_int), dp, dp], ctypes.c_int),
         "ka_profile_reset": ([vp], ctypes.c_int),
@@ -116,7 +119,8 @@ _lib = _load()
 EXPORTED = ("ka_setup", "ka_size", "ka_footprint", "ka_apply_A", "ka_solve_Z", "ka_eigs", "ka_gamma_apply",
             "ka_gamma_workspace", "ka_profile_enable", "ka_profile_read", "ka_profile_reset", "ka_destroy",
             "ka_last_error", "ka_server_create", "ka_server_submit", "ka_server_run", "ka_server_poll",
-            "ka_server_stats", "ka_server_destroy", "ka_request_bytes", "ka_kl_sample", "ka_desc_size")
+            "ka_server_stats", "ka_server_destroy", "ka_request_bytes", "ka_kl_sample", "ka_desc_size",
+            "ka_gamma_apply_static", "ka_gamma_static_capacity")
 
 
 class KAError(RuntimeError):
@@ -269,6 +273,17 @@ def ka_gamma_apply(kernel, sigma, ell, xr, xc, Y, Z, precision=KA_FP32, work=Non
     return _check(_lib.ka_gamma_apply(kernel, sigma, ell, _ptr(xr), xr.shape[0], _ptr(xc), xc.shape[0], _ptr(Y),
                                       Y.shape[1], _ptr(Z), precision, _ptr(work), nbytes, _stream(stream)),
                   "ka_gamma_apply")
+
+
+def ka_gamma_apply_static(kernel, sigma, ell, xr, xc, Y, Z, precision=KA_FP32, stream=None):
+    """As ka_gamma_apply, with the library's static scratch (no allocation)."""
+    return _check(_lib.ka_gamma_apply_static(kernel, sigma, ell, _ptr(xr), xr.shape[0], _ptr(xc), xc.shape[0],
+                                             _ptr(Y), Y.shape[1], _ptr(Z), precision, _stream(stream)),
+                  "ka_gamma_apply_static")
+
+
+def ka_gamma_static_capacity():
+    return _lib.ka_gamma_static_capacity()
 
 
 def ka_profile_enable(h, on=True):

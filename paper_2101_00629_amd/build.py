@@ -12,7 +12,7 @@ BUILD = os.path.join(os.path.dirname(HERE), "_build")
 LIB = os.path.join(HERE, "libka.so")
 ARCH = os.environ.get("KA_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["host_setup.cpp", "gamma.hip", "transfer.hip", "dense64.hip", "sym.hip", "nonsym.hip", "api.hip", "eigs.hip", "serve.hip", "sample.hip", "capi.hip"]
+SOURCES = ["host_setup.cpp", "gamma.hip", "transfer.hip", "dense64.hip", "sym.hip", "nonsym.hip", "api.hip", "eigs.hip", "serve.hip", "sample.hip", "capi.hip", "gamma_static.hip"]
 
 HIP_FLAGS = ["-O3", "-fPIC", "-std=c++17", f"--offload-arch={ARCH}",
              # no packed FP32 instructions in any generated code
