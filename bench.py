@@ -159,7 +159,7 @@ def serve_benchmark(n_requests, rhos, cap, tol, seed=210100629):
         t0 = time.perf_counter()
         prob = K.Problem(descs[i])
         try:
-            rc, lam, info = K.ka_eigs(prob.h, d["M"], tol=tol, maxit=60, complex_values=cplx[i])
+            rc, lam, info = K.ka_eigs(prob.h, d["M"], tol=tol, maxit=60)
         except K.KAError as e:   # a failed solve is reported with its status, as the server does
             rc, lam, info = e.code, np.zeros(2 * d["M"]), {"iterations": None, "converged": 0}
         prob.close()
@@ -190,7 +190,7 @@ def serve_benchmark(n_requests, rhos, cap, tol, seed=210100629):
             done[i] = t
         seq_lat = done - arrivals
         # continuous-batching server
-        srv = K.ka_server_create(200 << 30, 32)
+        srv = K.ka_server_create(64 << 30, 32)
         lams = []
         for i, d in enumerate(trace):
             lam = np.zeros(2 * d["M"])
@@ -320,8 +320,7 @@ def compare_methods(reps=3):
                 for _ in range(reps):
                     torch.cuda.synchronize()
                     t0 = time.perf_counter()
-                    rc, lam, info = K.ka_eigs(prob.h, 20, tol=1e-6, maxit=80,
-                                              complex_values=(method == "collocation"))
+                    rc, lam, info = K.ka_eigs(prob.h, 20, tol=1e-6, maxit=80)
                     times.append(time.perf_counter() - t0)
                 N, Nt, Nq, _ = K.ka_size(prob.h)
                 prob.close()
@@ -366,7 +365,7 @@ def half_cylinder_benchmark(reps=2):
         times = []
         for _ in range(n_rep):
             t0 = time.perf_counter()
-            rc, lam, info = K.ka_eigs(prob.h, M, tol=1e-6, maxit=maxit, complex_values=(method == "collocation"))
+            rc, lam, info = K.ka_eigs(prob.h, M, tol=1e-6, maxit=maxit)
             times.append(time.perf_counter() - t0)
         N, Nt, Nq, _ = K.ka_size(prob.h)
         prob.close()
@@ -416,8 +415,7 @@ def measure(K, torch, precision, steps, warmup, tol):
         out = []
         for p, h in zip(probs, handles):
             t0 = time.perf_counter()
-            rc, lam, info = K.ka_eigs(h.h, p["M"], tol=tol, maxit=60,
-                                      complex_values=(p["method"] == "collocation"))
+            rc, lam, info = K.ka_eigs(h.h, p["M"], tol=tol, maxit=60)
             dt = time.perf_counter() - t0
             if rc != 0:
                 raise RuntimeError(f"ka_eigs returned {rc} for {p['name']}: {info}")
@@ -506,7 +504,7 @@ def nurbs_benchmark(reps=2):
                 K.ka_profile_reset(prob.h)
                 K.ka_profile_enable(prob.h, True)
             t0 = time.perf_counter()
-            rc, lam, info = K.ka_eigs(prob.h, M, tol=1e-5, maxit=80, complex_values=cplx)
+            rc, lam, info = K.ka_eigs(prob.h, M, tol=1e-5, maxit=80)
             if r >= 1:
                 times.append(time.perf_counter() - t0)
         n_l, ms, pairs = K.ka_profile_read(prob.h)
@@ -550,7 +548,7 @@ def kl_sample_benchmark(reps=3):
         cplx = prob_d["method"] == "collocation"
         prob = K.Problem(K.desc_from_problem(prob_d, seed=17))
         V = torch.zeros((M, prob.N), dtype=torch.float64, device="cuda")
-        rc, lam, info = K.ka_eigs(prob.h, M, tol=1e-5, maxit=80, V=V, complex_values=cplx)
+        rc, lam, info = K.ka_eigs(prob.h, M, tol=1e-5, maxit=80, V=V)
         lam = lam[0::2] if cplx else lam
         grid = [np.linspace(0.0, 1.0, n) for n in npts]
         P = int(np.prod(npts))

@@ -17,9 +17,14 @@
  * - Streams are hipStream_t passed as void* (NULL = the default stream).
  * - Return value: 0 = KA_OK, < 0 hard error (see ka_last_error()), > 0 soft
  *   condition (KA_NOT_CONVERGED).
- * - Apply / solve / gamma calls are asynchronous on the given stream and
- *   allocate no device memory; ka_setup allocates all workspace.  ka_eigs is
- *   synchronous on the problem's stream.
+ * - Device memory: ka_setup allocates the operator's arrays and workspace;
+ *   ka_apply_A, ka_solve_Z, ka_gamma_apply and ka_gamma_apply_static
+ *   allocate nothing (they are asynchronous on the given stream).  ka_eigs
+ *   allocates its workspace on the first call and keeps it with the problem:
+ *   a later call allocates only when it needs more (larger M), and then
+ *   replaces the buffer.  ka_kl_sample keeps its own workspace the same way.
+ *   ka_destroy frees everything.  ka_eigs is synchronous on the problem's
+ *   stream.
  * - A problem handle must not be used from two host threads at once.
  */
 #ifndef KA_H
@@ -140,6 +145,10 @@ typedef struct ka_info {
   double seconds;        /* wall time of the solve                             */
   double gamma_seconds;  /* device time inside the kernel-product launches     */
   double pairs;          /* kernel pair evaluations performed                  */
+  int lambda_doubles;    /* doubles written to lambda_host: M, or 2M (collocation) */
+  int floor_accepted;    /* of the first M pairs, those accepted only through the
+                            arithmetic noise floor nu |theta_1| (residual above
+                            tol max(|theta|, 1e-2 |theta_1|)); see ka_eigs      */
 } ka_info;
 
 typedef struct ka_problem ka_problem;
@@ -152,10 +161,13 @@ typedef struct ka_problem ka_problem;
  * stream for ka_eigs.  On error *out is NULL. */
 int ka_setup(const ka_desc* desc, void* stream, ka_problem** out);
 
-/* Sizes: N degrees of freedom, Ntilde IBQ interpolation points (0 for the
- * other methods), Nquad quadrature points (collocation and Gauss Galerkin; 0
- * for IBQ), and the device bytes the problem holds.  Any output pointer may be
- * NULL. */
+/* Sizes of the discretisation (Sec. 3.1: N trial functions, Ntilde points of
+ * the interpolation space S~ at which Gamma is evaluated; Sec. 3.2: N
+ * collocation points and the quadrature points of Algorithm 1): N degrees of
+ * freedom, Ntilde IBQ interpolation points (0 for the other methods), Nquad
+ * quadrature points (collocation and Gauss Galerkin; 0 for IBQ), and the device
+ * bytes the problem holds now (set-up arrays, plus the eigensolver and K-L
+ * sampling workspaces once allocated).  Any output pointer may be NULL. */
 int ka_size(const ka_problem* p, int64_t* N, int64_t* Ntilde, int64_t* Nquad,
             size_t* device_bytes);
 
@@ -179,11 +191,22 @@ int ka_apply_A(ka_problem* p, int form, const double* X_dev, int64_t ldx,
 /* In-place FP64 Kronecker solves on nvec columns (device, column-major):
  * KA_ZINV X <- Z^-1 X (Galerkin: mass matrix; collocation: Z_ij = R_j(x_i)),
  * KA_LINV X <- L^-1 X, KA_LTINV X <- L^-T X (Galerkin only; else KA_ERR_STATE).
+ * Galerkin (Sec. 3.1): Z = Z3 (x) Z2 (x) Z1 is the mass matrix of the trial
+ * space B_i / sqrt|det DF| (eq. trialspace), Z = L L^T with L = L3 (x) L2 (x) L1
+ * from the Cholesky factors of the Z_k; A' = L^-1 A L^-T and v = L^-T v'.
+ * Collocation (Sec. 3.2): Z_ij = R_j(x_i); the paper factors P Z Q = L U with
+ * complete pivoting; here Z is the Kronecker product of its univariate factors
+ * (remark in Sec. 3.3), each LU-factored with partial pivoting in FP64, equal
+ * in exact arithmetic (on KA_NURBS also scaled by diag(1/W), see ka_desc).
+ * Applied as FP64 mode products with the inverse factors.  X: ld >= N.
  * Async on `stream`; no allocation. */
 int ka_solve_Z(ka_problem* p, int op, double* X_dev, int64_t ld, int nvec, void* stream);
 
-/* Leading M eigenpairs of A v = lambda Z v by a block Krylov method with thick
- * restarts (FP64 basis, orthogonalisation and Rayleigh-Ritz on the device).
+/* Leading M eigenpairs of the generalized problem A v = lambda Z v (Sec. 1,
+ * eq. matrix_equations), solved in the standard form A' v' = lambda v',
+ * v = C v' (Sec. 3, eq. standard; Galerkin C = L^-T, collocation C = I), by a
+ * block Krylov method with thick restarts (FP64 basis, orthogonalisation and
+ * Rayleigh-Ritz on the device; the paper leaves the iterative solver open).
  * Stops when, for the first M Ritz pairs (M extended to the end of its
  * cluster), |A'x - theta x| <= max(tol |theta|, max(1e-2 tol, nu) |theta_1|),
  * where nu is the arithmetic noise floor of the operator (Galerkin: 4e-6 FP32,
@@ -191,17 +214,28 @@ int ka_solve_Z(ka_problem* p, int op, double* X_dev, int64_t ld, int nvec, void*
  * |theta| > nu |theta_1| accepted only through that floor must also satisfy
  * r^2 / gap <= 0.1 tol max(|theta|, 1e-2 |theta_1|) (gap: distance to the
  * nearest Ritz value that r and nu can separate from theta); pairs below the
- * floor carry an absolute error of order nu |theta_1|.  Also stops after maxit restart cycles,
+ * floor carry an absolute error of order nu |theta_1|.  Collocation's A' is
+ * not symmetric and its eigenvalue error is first order in the residual: a
+ * collocation pair accepted only through the floor must also have moved by
+ * at most 0.1 tol max(|theta|, 1e-2 |theta_1|) since the previous
+ * Rayleigh-Ritz step (never in the first restart cycle).
+ * info->floor_accepted counts the pairs accepted through the floor (either
+ * method).  Also stops after maxit restart cycles,
  * or after three cycles without a 10% drop of the largest scaled residual
  * (both return KA_NOT_CONVERGED; results are still written).
- * lambda_host: M doubles (Galerkin), or 2M doubles re/im interleaved
- *   (collocation), sorted by descending real part.
+ * lambda_host: host array of lambda_len doubles; the solve writes M doubles
+ *   (Galerkin methods), or 2M doubles re/im interleaved (collocation), sorted
+ *   by descending real part (info->lambda_doubles says which).  KA_ERR_ARG,
+ *   before any device work, if lambda_len is smaller.
+ * Workspace: about (2 m + 4 (M + b + 1)) N doubles (m the Krylov basis width:
+ *   M + b plus at least two blocks), allocated on the first call and kept by
+ *   the problem (see the conventions above).
  * V_dev: N x M column-major device array or NULL.  Galerkin eigenvectors are
  *   Z-orthonormal (v = L^-T v'); collocation eigenvectors have unit 2-norm (a
  *   complex pair is stored as real part, imaginary part in consecutive
  *   columns).  Each vector's largest-magnitude entry is made positive.
  * info may be NULL.  Synchronous. */
-int ka_eigs(ka_problem* p, int M, double tol, int maxit, double* lambda_host,
+int ka_eigs(ka_problem* p, int M, double tol, int maxit, double* lambda_host, int64_t lambda_len,
             double* V_dev, ka_info* info);
 
 /* The raw fused kernel product (hot path, paper Sec. 3.1 step Gamma and
@@ -273,14 +307,19 @@ void ka_destroy(ka_problem* p);
 /* ---- serving (continuous batching of K-L solve requests on one GPU) ----
  * Not in the paper: a request loop around the solver.  Requests queue in
  * arrival order; one is admitted once it has arrived (arrival_s, seconds
- * after the first ka_server_run), a slot is free and its device footprint
- * (ka_footprint plus the eigensolver workspace) fits hbm_budget.  Admitted
- * solves keep their Krylov state on the device, each on its own stream; all
- * their kernel products run together as shared persistent launches, one
- * block application per request per loop iteration; finished requests free
- * their memory at once so waiting ones join the running batch.  A request's
- * eigenvalues are bitwise the same alone or in any mix (each product keeps
- * its own split-K partition and every reduction a fixed order). */
+ * after the first ka_server_run), a slot is free and a contiguous range of its
+ * device footprint (ka_request_bytes) is free in the server's arena.  The
+ * arena is one device allocation of hbm_budget bytes made by
+ * ka_server_create, with the dispatcher's launch lists beside it; a request's
+ * problem and eigensolver workspace are laid out inside its range, so
+ * serving allocates and frees no device memory between ka_server_create and
+ * ka_server_destroy.  Admitted solves keep their Krylov state on the device,
+ * each on its own stream; all their kernel products run together as shared
+ * persistent launches, one block application per request per loop
+ * iteration; a finished request returns its range at once so waiting ones
+ * join the running batch.  A request's eigenvalues are bitwise the same
+ * alone or in any mix (each product keeps its own split-K partition and
+ * every reduction a fixed order). */
 typedef struct ka_server ka_server;
 
 typedef struct ka_result {
@@ -291,14 +330,17 @@ typedef struct ka_result {
   double arrival_s, admit_s, done_s;   /* seconds on the server clock           */
 } ka_result;
 
+/* hbm_budget: bytes of the device arena (allocated here; KA_ERR_OOM if that
+ * fails); max_slots: requests solved at once (1..256). */
 int ka_server_create(size_t hbm_budget, int max_slots, ka_server** out);
 /* Device bytes a request holds while admitted: ka_footprint plus the
  * eigensolver workspace for M eigenpairs at the descriptor's block size. */
 int ka_request_bytes(const ka_desc* desc, int M, size_t* bytes);
-/* lambda_host: caller-owned, M doubles (Galerkin) or 2M (collocation), written
- * when the request completes.  tol/maxit as for ka_eigs. */
+/* lambda_host: caller-owned, lambda_len doubles, at least M (Galerkin) or 2M
+ * (collocation, re/im interleaved), written when the request completes
+ * (KA_ERR_ARG at submission if too small).  tol/maxit as for ka_eigs. */
 int ka_server_submit(ka_server* s, const ka_desc* desc, int M, double tol, int maxit, double arrival_s,
-                     uint64_t tag, double* lambda_host, int64_t* req_id);
+                     uint64_t tag, double* lambda_host, int64_t lambda_len, int64_t* req_id);
 /* Serve until every submitted request has completed (or timeout_s elapses:
  * KA_NOT_CONVERGED).  Synchronous; may be called again after new submits. */
 int ka_server_run(ka_server* s, double timeout_s);

@@ -52,7 +52,8 @@ class ka_info(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int), ("matvecs", ctypes.c_int), ("converged", ctypes.c_int),
                 ("nev_computed", ctypes.c_int), ("max_residual", ctypes.c_double),
                 ("max_imag_rel", ctypes.c_double), ("seconds", ctypes.c_double),
-                ("gamma_seconds", ctypes.c_double), ("pairs", ctypes.c_double)]
+                ("gamma_seconds", ctypes.c_double), ("pairs", ctypes.c_double),
+                ("lambda_doubles", ctypes.c_int), ("floor_accepted", ctypes.c_int)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -83,7 +84,7 @@ def _load():
                          ctypes.c_int),
         "ka_apply_A": ([vp, ctypes.c_int, vp, i64, vp, i64, ctypes.c_int, vp], ctypes.c_int),
         "ka_solve_Z": ([vp, ctypes.c_int, vp, i64, ctypes.c_int, vp], ctypes.c_int),
-        "ka_eigs": ([vp, ctypes.c_int, ctypes.c_double, ctypes.c_int, dp, vp, ctypes.POINTER(ka_info)],
+        "ka_eigs": ([vp, ctypes.c_int, ctypes.c_double, ctypes.c_int, dp, i64, vp, ctypes.POINTER(ka_info)],
                     ctypes.c_int),
         "ka_gamma_apply": ([ctypes.c_int, ctypes.c_double, ctypes.c_double, fp, i64, fp, i64, fp, ctypes.c_int,
                             fp, ctypes.c_int, vp, ctypes.c_size_t, vp], ctypes.c_int),
@@ -99,7 +100,7 @@ def _load():
         "ka_destroy": ([vp], None),
         "ka_server_create": ([ctypes.c_size_t, ctypes.c_int, ctypes.POINTER(vp)], ctypes.c_int),
         "ka_server_submit": ([vp, ctypes.POINTER(ka_desc), ctypes.c_int, ctypes.c_double, ctypes.c_int,
-                              ctypes.c_double, ctypes.c_uint64, dp, ctypes.POINTER(i64)], ctypes.c_int),
+                              ctypes.c_double, ctypes.c_uint64, dp, i64, ctypes.POINTER(i64)], ctypes.c_int),
         "ka_server_run": ([vp, ctypes.c_double], ctypes.c_int),
         "ka_server_poll": ([vp, ctypes.POINTER(ka_result), ctypes.c_int, ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
         "ka_server_stats": ([vp, ctypes.POINTER(ctypes.c_int), dp, ctypes.POINTER(ctypes.c_int),
@@ -234,12 +235,17 @@ def ka_solve_Z(h, op, X, nvec=None, stream=None):
     return _check(_lib.ka_solve_Z(h, op, _ptr(X), X.shape[1], nvec, _stream(stream)), "ka_solve_Z")
 
 
-def ka_eigs(h, M, tol=1e-6, maxit=100, V=None, complex_values=False):
-    lam = np.zeros(2 * M if complex_values else M)
+def ka_eigs(h, M, tol=1e-6, maxit=100, V=None, lam=None):
+    """(status, lambda, info).  lambda: M values (Galerkin methods) or 2M
+    (collocation: re, im interleaved), as the library reports in
+    info["lambda_doubles"].  lam: optional float64 array to write into (its
+    length is passed as the capacity); by default one of 2M doubles."""
+    if lam is None:
+        lam = np.zeros(2 * M)
     info = ka_info()
-    rc = _check(_lib.ka_eigs(h, M, tol, maxit, lam.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), _ptr(V),
-                             ctypes.byref(info)), "ka_eigs")
-    return rc, lam, info.as_dict()
+    rc = _check(_lib.ka_eigs(h, M, tol, maxit, lam.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), lam.size,
+                             _ptr(V), ctypes.byref(info)), "ka_eigs")
+    return rc, lam[:info.lambda_doubles], info.as_dict()
 
 
 def ka_kl_sample(h, lam, V, grid, xi, field, mu=0.0, stream=None):
@@ -323,11 +329,11 @@ def ka_server_create(hbm_budget, max_slots):
 
 
 def ka_server_submit(srv, desc, M, lam, tol=1e-5, maxit=60, arrival_s=0.0, tag=0):
-    """lam: caller-owned float64 numpy array of M (Galerkin) or 2M
+    """lam: caller-owned float64 numpy array of at least M (Galerkin) or 2M
     (collocation) entries; it must stay alive until the request completes."""
     rid = ctypes.c_int64()
     _check(_lib.ka_server_submit(srv, ctypes.byref(desc), M, tol, maxit, arrival_s, tag,
-                                 lam.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ctypes.byref(rid)),
+                                 lam.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), lam.size, ctypes.byref(rid)),
            "ka_server_submit")
     return rid.value
 

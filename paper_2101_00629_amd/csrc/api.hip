@@ -148,6 +148,8 @@ static int check_desc(const ka_desc* d, Sizes& z) {
 }
 
 static size_t align_up(size_t x) { return (x + 255) / 256 * 256; }
+// bytes one problem allocation takes (an empty buffer still takes 256)
+static size_t block_bytes(size_t x) { return align_up(x ? x : 256); }
 
 // Largest point count of any intermediate tensor of the Kronecker transfers
 // (forward n -> m direction by direction, and back): sizes the FP32 buffers.
@@ -163,31 +165,40 @@ static size_t setup_bytes(const ka_desc* d, const Sizes& z) {
   const int b = d->block;
   size_t s = 0;
   for (int k = 0; k < 3; ++k) {
-    s += 4 * align_up((size_t)z.n[k] * z.n[k] * 8);          // LinvT, Linv, Zinv, Z_k
+    s += 4 * block_bytes((size_t)z.n[k] * z.n[k] * 8);          // LinvT, Linv, Zinv, Z_k
     const int mk = d->method == KA_GALERKIN_IBQ ? z.nt[k] : z.nq[k];
-    s += 2 * align_up((size_t)mk * z.n[k] * 4);               // T, TT
+    s += 2 * block_bytes((size_t)mk * z.n[k] * 4);               // T, TT
   }
-  s += align_up((size_t)z.n_rows * 16) + align_up((size_t)z.n_cols * 16);
-  s += align_up((size_t)z.n_rows * 4) + align_up((size_t)z.n_cols * 4);
-  s += 2 * align_up((size_t)z.N * b * 8);
-  s += 2 * align_up((size_t)transfer_points(d, z) * b * 4);
-  s += align_up(gamma_plan(z.n_rows, z.n_cols, b, d->precision).work_bytes);
-  if (d->domain == KA_NURBS && d->method == KA_COLLOCATION) s += align_up((size_t)z.n_rows * 8);   // W(g), FP64
+  s += block_bytes((size_t)z.n_rows * 16) + block_bytes((size_t)z.n_cols * 16);
+  s += block_bytes((size_t)z.n_rows * 4) + block_bytes((size_t)z.n_cols * 4);
+  s += 2 * block_bytes((size_t)z.N * b * 8);
+  s += 2 * block_bytes((size_t)transfer_points(d, z) * b * 4);
+  s += block_bytes(gamma_plan(z.n_rows, z.n_cols, b, d->precision).work_bytes);
+  if (d->domain == KA_NURBS && d->method == KA_COLLOCATION) s += block_bytes((size_t)z.n_rows * 8);   // W(g), FP64
   return s;
 }
 
 // ---------------------------------------------------------------------------
 // setup
 // ---------------------------------------------------------------------------
-static void* dev_alloc(Problem* P, size_t bytes, bool& ok) {
+void* problem_alloc(Problem* P, size_t bytes) {
+  bytes = block_bytes(bytes);
   void* p = nullptr;
-  if (bytes == 0) bytes = 256;
-  if (hipMalloc(&p, align_up(bytes)) != hipSuccess) {
-    ok = false;
-    return nullptr;
+  if (P->region.base) {
+    if (P->region.used + bytes > P->region.size) return nullptr;
+    p = P->region.base + P->region.used;
+    P->region.used += bytes;
+  } else {
+    if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
+    P->allocs.push_back({p, bytes});
   }
-  P->allocs.push_back({p, align_up(bytes)});
-  P->device_bytes += align_up(bytes);
+  P->device_bytes += bytes;
+  return p;
+}
+
+static void* dev_alloc(Problem* P, size_t bytes, bool& ok) {
+  void* p = ok ? problem_alloc(P, bytes) : nullptr;
+  if (!p) ok = false;
   return p;
 }
 
@@ -204,18 +215,19 @@ static std::vector<float> to_vec32(const Mat& m) { return std::vector<float>(m.a
 static void free_problem(Problem* P) {
   if (!P) return;
   for (auto& b : P->allocs) (void)hipFree(b.p);
-  for (auto& b : P->eig_allocs) (void)hipFree(b.p);
+  if (P->eig_buf && !P->region.base) (void)hipFree(P->eig_buf);
   if (P->kl_buf) (void)hipFree(P->kl_buf);
   for (auto e : P->ev_start) (void)hipEventDestroy(e);
   for (auto e : P->ev_stop) (void)hipEventDestroy(e);
   delete P;
 }
 
-static int setup_impl(const ka_desc* d, hipStream_t stream, Problem** out) {
+static int setup_impl(const ka_desc* d, hipStream_t stream, Problem** out, const Region* region) {
   Sizes z;
   int rc = check_desc(d, z);
   if (rc) return rc;
   Problem* P = new Problem();
+  if (region) P->region = *region;
   P->d = *d;
   P->stream = stream;
   (void)hipGetDevice(&P->device);
@@ -621,7 +633,9 @@ int solve_block(Problem* P, int op, double* X, int64_t ld, int nv, hipStream_t s
 }  // namespace ka
 
 namespace ka {
-int setup_problem(const ka_desc* d, hipStream_t stream, Problem** out) { return setup_impl(d, stream, out); }
+int setup_problem(const ka_desc* d, hipStream_t stream, Problem** out, const Region* region) {
+  return setup_impl(d, stream, out, region);
+}
 
 int footprint(const ka_desc* d, size_t* bytes) {
   Sizes z;

@@ -26,7 +26,7 @@ int ka_size(const ka_problem* p, int64_t* N, int64_t* Ntilde, int64_t* Nquad, si
   if (N) *N = P->N;
   if (Ntilde) *Ntilde = P->Nt;
   if (Nquad) *Nquad = P->Nq;
-  if (device_bytes) *device_bytes = P->device_bytes + P->eig_bytes;
+  if (device_bytes) *device_bytes = P->device_bytes + P->eig_buf_bytes + P->kl_bytes;
   return KA_OK;
 }
 
@@ -69,10 +69,15 @@ int ka_solve_Z(ka_problem* p, int op, double* X_dev, int64_t ld, int nvec, void*
   return KA_OK;
 }
 
-int ka_eigs(ka_problem* p, int M, double tol, int maxit, double* lambda_host, double* V_dev, ka_info* info) {
+int ka_eigs(ka_problem* p, int M, double tol, int maxit, double* lambda_host, int64_t lambda_len, double* V_dev,
+            ka_info* info) {
   Problem* P = reinterpret_cast<Problem*>(p);
   if (!P) return fail(KA_ERR_ARG, "problem is NULL");
   if (!lambda_host) return fail(KA_ERR_ARG, "lambda_host is NULL");
+  if (M < 1 || M > P->N) return fail(KA_ERR_ARG, "M must be in 1..N");
+  if (lambda_len < lambda_doubles(P->d, M))
+    return fail(KA_ERR_ARG, "lambda_host holds " + std::to_string(lambda_len) + " doubles, the solve writes " +
+                                std::to_string(lambda_doubles(P->d, M)));
   return eigs(P, M, tol, maxit, lambda_host, V_dev, info);
 }
 

@@ -16,8 +16,12 @@ struct EigWork {
   int* status = nullptr;
 };
 
-// Device bytes one solve allocates (admission control of the server).
+// Device bytes of one solve's workspace (admission control of the server).
 size_t eig_workspace_bytes(int64_t N, int M, int b);
+// The problem's eigensolver workspace of at least `bytes`: its region's range
+// (served requests), or a buffer kept between calls and replaced by a larger
+// one only when a call needs more.
+int eig_workspace(Problem* P, size_t bytes, char** out);
 
 class EigRun {
  public:
@@ -29,7 +33,7 @@ class EigRun {
   int pre_apply();                   // operator steps up to the kernel product of the pending block
   int post_apply(bool& done);        // the rest of the step; done = stop iterating
   int finish(double* lambda_host, double* V_dev, ka_info* info);
-  size_t bytes() const { return bytes_; }
+  size_t bytes() const { return cap_; }
   int matvecs() const { return matvecs_; }
 
  private:
@@ -49,13 +53,14 @@ class EigRun {
   int nev_ = 0, m_max_ = 0;
   bool full_ = false;
   EigWork w_;
-  std::vector<DevBuf> bufs_;
-  size_t bytes_ = 0;
+  char* base_ = nullptr;   // workspace of this solve (owned by the problem), bump-allocated
+  size_t cap_ = 0, off_ = 0;
   uint64_t rng_counter_ = 0;
-  int k_ = 0, pw_ = 0, cycles_ = 0, matvecs_ = 0, nconv_ = 0, Meff_ = 0, nret_ = 0, stall_ = 0;
+  int k_ = 0, pw_ = 0, cycles_ = 0, matvecs_ = 0, nconv_ = 0, Meff_ = 0, nret_ = 0, stall_ = 0, floor_ok_ = 0;
   double max_res_ = 0.0, max_imag_ = 0.0, best_res_ = 1e300, pairs0_ = 0.0;
   bool converged_ = false;
   std::vector<double> th_, thi_, rn_;
+  std::vector<double> th_prev_, thi_prev_;   // non-symmetric: Ritz values of the previous Rayleigh-Ritz step
   std::chrono::steady_clock::time_point t_start_;
 };
 

@@ -127,21 +127,47 @@ EigRun::EigRun(Problem* P, int M, double tol, int maxit) : P_(P), s_(P->stream),
   verbose_ = v && v[0] && v[0] != '0';
 }
 
-EigRun::~EigRun() {
-  if (!bufs_.empty()) (void)hipStreamSynchronize(s_);
-  for (auto& b : bufs_) (void)hipFree(b.p);
+EigRun::~EigRun() = default;   // the workspace belongs to the problem
+
+int eig_workspace(Problem* P, size_t bytes, char** out) {
+  if (P->region.base) {
+    // served request: carved once from its range (sized by ka_request_bytes)
+    if (!P->eig_buf) {
+      if (P->region.used + bytes > P->region.size) return fail(KA_ERR_OOM, "eigensolver workspace exceeds the request's memory");
+      P->eig_buf = P->region.base + P->region.used;
+      P->region.used += bytes;
+      P->eig_buf_bytes = bytes;
+    } else if (P->eig_buf_bytes < bytes) {
+      return fail(KA_ERR_OOM, "eigensolver workspace exceeds the request's memory");
+    }
+  } else if (P->eig_buf_bytes < bytes) {
+    if (P->eig_buf) {
+      // earlier solves on this stream may still read the old buffer
+      if (hipStreamSynchronize(P->stream) != hipSuccess) return fail(KA_ERR_HIP, "stream synchronize failed");
+      (void)hipFree(P->eig_buf);
+      P->eig_buf = nullptr;
+      P->eig_buf_bytes = 0;
+    }
+    if (hipMalloc(&P->eig_buf, bytes) != hipSuccess) {
+      P->eig_buf = nullptr;
+      return fail(KA_ERR_OOM, "eigensolver workspace allocation failed");
+    }
+    P->eig_buf_bytes = bytes;
+  }
+  *out = (char*)P->eig_buf;
+  return KA_OK;
 }
 
 int EigRun::alloc(size_t bytes, double** out) {
   bytes = (bytes + 255) / 256 * 256;
   if (bytes == 0) bytes = 256;
-  void* p = nullptr;
-  if (hipMalloc(&p, bytes) != hipSuccess) return fail(KA_ERR_OOM, "eigensolver workspace allocation failed");
-  bufs_.push_back({p, bytes});
-  bytes_ += bytes;
-  *out = (double*)p;
+  if (off_ + bytes > cap_) return fail(KA_ERR_OOM, "eigensolver workspace layout exceeds its size");
+  *out = (double*)(base_ + off_);
+  off_ += bytes;
   return KA_OK;
 }
+
+int64_t lambda_doubles(const ka_desc& d, int M) { return d.method == KA_COLLOCATION ? 2 * (int64_t)M : M; }
 
 // Orthonormalise P (N x pw) against X[:, :k] (block CGS twice) and within
 // itself (Cholesky-QR twice).  Rank-deficient blocks are redrawn at random.
@@ -192,6 +218,9 @@ int EigRun::start() {
   if (m_max_ > 1000) return fail(KA_ERR_ARG, "M too large for the dense Rayleigh-Ritz (M + block <= ~600)");
   const int ncol = nev_ + 1;   // room for a complex pair that straddles nev
   const int m = m_max_;
+  cap_ = eig_workspace_bytes(N, M_, b);
+  off_ = 0;
+  KA_TRY(eig_workspace(P_, cap_, &base_));
   KA_TRY(alloc((size_t)N * m * 8, &w_.X));
   KA_TRY(alloc((size_t)N * m * 8, &w_.AX));
   KA_TRY(alloc((size_t)N * b * 8, &w_.P));
@@ -221,6 +250,8 @@ int EigRun::start() {
   th_.assign(m, 0.0);
   thi_.assign(m, 0.0);
   rn_.assign(m, 0.0);
+  th_prev_.clear();
+  thi_prev_.clear();
   pairs0_ = P_->pairs_total;
   HIP_TRY(fill_normal(w_.P, N, b, N, P_->d.seed, rng_counter_, s_));
   pw_ = (int)std::min<int64_t>(b, m);
@@ -277,6 +308,7 @@ int EigRun::rayleigh_ritz(bool& stop) {
   if (!sym_ && Meff_ < nk && thi_[Meff_ - 1] > 0.0) ++Meff_;
   const double floor_ = std::max(tol_ * tau, noise_) * modulus(0);
   nconv_ = 0;
+  floor_ok_ = 0;
   max_res_ = 0.0;
   max_imag_ = 0.0;
   for (int i = 0; i < Meff_; ++i) {
@@ -301,10 +333,28 @@ int EigRun::rayleigh_ritz(bool& stop) {
         if (std::fabs(th_[j] - th_[i]) > sep) gap = std::min(gap, std::fabs(th_[j] - th_[i]));
       ok = rn_[i] * rn_[i] <= 0.1 * tol_ * std::max(modulus(i), tau * modulus(0)) * gap;
     }
-    if (ok && nconv_ == i) ++nconv_;
+    // Non-symmetric A' (collocation): the eigenvalue error is first order in
+    // r, so the floor alone certifies only |theta - lambda| ~ nu |theta_1|.
+    // A pair accepted through it must also have kept its Ritz value, within a
+    // tenth of the target, since the previous Rayleigh-Ritz step (so never in
+    // the first cycle): the operator's arithmetic cannot resolve it further.
+    if (!sym_ && ok && rn_[i] > tol_ * std::max(modulus(i), tau * modulus(0))) {
+      ok = i < (int)th_prev_.size() &&
+           std::hypot(th_[i] - th_prev_[i], thi_[i] - thi_prev_[i]) <=
+               0.1 * tol_ * std::max(modulus(i), tau * modulus(0));
+    }
+    if (ok && nconv_ == i) {
+      ++nconv_;
+      // accepted although above tol on the floored scale: through the noise floor
+      if (i < M_ && rel > tol_) ++floor_ok_;
+    }
   }
   nret_ = sym_ ? nk : std::min(nk, Meff_ + 1);
   converged_ = nconv_ >= Meff_;
+  if (!sym_) {
+    th_prev_.assign(th_.begin(), th_.begin() + nk);
+    thi_prev_.assign(thi_.begin(), thi_.begin() + nk);
+  }
   // stagnation: three restart cycles without a 10% drop of the largest
   // scaled residual end the iteration (KA_NOT_CONVERGED, results valid)
   if (max_res_ < 0.9 * best_res_) {
@@ -469,6 +519,8 @@ int EigRun::finish(double* lambda_host, double* V_dev, ka_info* info) {
     info->seconds = secs;
     info->gamma_seconds = 0.0;
     info->pairs = P_->pairs_total - pairs0_;
+    info->lambda_doubles = (int)lambda_doubles(P_->d, M_);
+    info->floor_accepted = floor_ok_;
   }
   return converged_ ? KA_OK : KA_NOT_CONVERGED;
 }

@@ -150,6 +150,14 @@ struct DevBuf {
   size_t bytes = 0;
 };
 
+// A range of a server's device arena that one request's problem and solve
+// allocate from, front to back; the server takes the range back whole.
+struct Region {
+  char* base = nullptr;
+  size_t size = 0;
+  size_t used = 0;
+};
+
 struct Problem {
   ka_desc d;
   Geometry geo;              // host copy of the domain map
@@ -182,7 +190,8 @@ struct Problem {
   float* w32b = nullptr;
   float* gpart = nullptr;    // split-K partials
   size_t gpart_bytes = 0;
-  std::vector<DevBuf> allocs;
+  Region region;             // base set: every allocation comes from this range (served requests)
+  std::vector<DevBuf> allocs; // hipMalloc'd buffers owned by the problem (freed with it)
   size_t device_bytes = 0;
   // profiling
   bool profile = false;
@@ -191,8 +200,10 @@ struct Problem {
   double prof_ms = 0.0;
   double prof_pairs = 0.0;
   double pairs_total = 0.0;
-  // eigensolver workspace (lazily sized per call)
-  std::vector<DevBuf> eig_allocs;
+  // eigensolver workspace: allocated by the first ka_eigs, kept between
+  // calls, replaced by a larger one only when a call needs more
+  void* eig_buf = nullptr;
+  size_t eig_buf_bytes = 0;
   // K-L sampling: a workspace kept between calls (grown on demand, freed
   // with the problem), and the collocation norm data that depend on the
   // problem only: quadrature weights times |det DF| / W^2 at the Gauss
@@ -202,7 +213,6 @@ struct Problem {
   double* kl_omega = nullptr;
   double* kl_Eq[3] = {nullptr, nullptr, nullptr};
   int kl_mq[3] = {0, 0, 0};
-  size_t eig_bytes = 0;
 };
 
 void set_error(const std::string& msg);
@@ -217,11 +227,17 @@ int apply_pre(Problem* P, int form, const double* X, int64_t ldx, int nv, hipStr
 int apply_post(Problem* P, int form, double* Y, int64_t ldy, int nv, hipStream_t s);
 GammaLaunch gamma_job(Problem* P);
 int gamma_step(Problem* P, const float* Y, float* Z, hipStream_t s);
-int setup_problem(const ka_desc* d, hipStream_t stream, Problem** out);
+// Device memory for a problem: from its region when it has one, else
+// hipMalloc (recorded in allocs).  nullptr when it does not fit or fails.
+void* problem_alloc(Problem* P, size_t bytes);
+// region: optional range every allocation of the problem comes from.
+int setup_problem(const ka_desc* d, hipStream_t stream, Problem** out, const Region* region = nullptr);
 int footprint(const ka_desc* d, size_t* bytes);
 // N, Ntilde, Nquad that setup_problem would produce (host only).
 int desc_sizes(const ka_desc* d, int64_t* N, int64_t* Nt, int64_t* Nq);
 void destroy_problem(Problem* P);
 int eigs(Problem* P, int M, double tol, int maxit, double* lambda_host, double* V_dev, ka_info* info);
+// Doubles ka_eigs writes to lambda_host for M eigenvalues: M, or 2M (re, im) for collocation.
+int64_t lambda_doubles(const ka_desc& d, int M);
 
 }  // namespace ka

@@ -2,13 +2,16 @@
 //
 // Requests (problem descriptor, M, tolerance, arrival time) queue in arrival
 // order.  A pool of worker threads (one per slot) serves them: a worker takes
-// the head request once it has arrived and its device footprint (problem
-// set-up + eigensolver workspace) fits the HBM budget, and drives that solve
-// on its own stream with the whole Krylov state on the device.  Solves
-// therefore progress independently, and their small kernels (transfers,
+// the head request once it has arrived and a contiguous range of its device
+// footprint (problem set-up + eigensolver workspace) is free in the server's
+// arena, and drives that solve on its own stream with the whole Krylov state
+// on the device, every buffer laid out inside the range.  Solves therefore
+// progress independently, and their small kernels (transfers,
 // orthogonalisation, the one-workgroup Rayleigh-Ritz eigensolves) overlap on
-// the device.  Finished solves release their memory at once, so waiting
-// requests join while others run.
+// the device.  Finished solves return their range at once, so waiting
+// requests join while others run.  The arena and the dispatcher's launch
+// lists are allocated when the server is created: serving itself allocates
+// and frees no device memory (hipFree would also synchronise the device).
 //
 // Kernel products: a product too small to fill the chip on its own is handed
 // to a dispatcher thread, which merges all pending products into shared
@@ -56,6 +59,45 @@ constexpr int64_t kDirectItems = 2048;
 constexpr double kGatherSeconds = 150e-6;
 constexpr int kRing = 8;   // device job/item buffers in flight
 
+// First-fit ranges of the server's device arena (offsets and lengths in
+// bytes, multiples of 256), adjacent free ranges merged.
+class Arena {
+ public:
+  void reset(size_t size) {
+    free_.clear();
+    if (size) free_[0] = size;
+  }
+  bool take(size_t bytes, size_t* off) {
+    for (auto it = free_.begin(); it != free_.end(); ++it)
+      if (it->second >= bytes) {
+        *off = it->first;
+        const size_t rest = it->second - bytes, at = it->first + bytes;
+        free_.erase(it);
+        if (rest) free_[at] = rest;
+        return true;
+      }
+    return false;
+  }
+  void give(size_t off, size_t bytes) {
+    auto next = free_.lower_bound(off);
+    if (next != free_.end() && off + bytes == next->first) {
+      bytes += next->second;
+      next = free_.erase(next);
+    }
+    if (next != free_.begin()) {
+      auto prev = std::prev(next);
+      if (prev->first + prev->second == off) {
+        prev->second += bytes;
+        return;
+      }
+    }
+    free_[off] = bytes;
+  }
+
+ private:
+  std::map<size_t, size_t> free_;
+};
+
 struct Request {
   int64_t id = 0;
   ka_desc desc;
@@ -65,7 +107,8 @@ struct Request {
   double arrival = 0.0;
   uint64_t tag = 0;
   double* lambda_host = nullptr;
-  size_t bytes = 0;
+  size_t bytes = 0;           // arena range (ka_request_bytes rounded up to 256)
+  size_t offset = 0;          // start of the range once admitted
   std::vector<double> geo_knots, geo_ctrl;   // KA_NURBS: copies that desc points to
 };
 
@@ -87,6 +130,8 @@ struct PendingGamma {
 struct Server {
   size_t budget = 0;
   int max_slots = 1;
+  char* arena_base = nullptr;   // hbm_budget bytes of device memory
+  Arena arena;                  // its free ranges (mu)
   // shared state (mu)
   std::mutex mu;
   std::condition_variable cv;          // queue / completion changes
@@ -102,9 +147,9 @@ struct Server {
   // dispatcher
   hipStream_t stream = nullptr;
   hipEvent_t ring_ev[kRing] = {};
-  GammaJob* jobs_dev[kRing] = {};
-  GammaItem* items_dev[kRing] = {};
-  size_t jobs_cap[kRing] = {}, items_cap[kRing] = {};
+  GammaJob* jobs_dev[kRing] = {};     // launch lists, sized at creation: a batch holds at most one
+  GammaItem* items_dev[kRing] = {};   // product per slot, each of fewer than kDirectItems items
+  size_t jobs_cap = 0, items_cap = 0;
   std::vector<GammaJob> jobs_host[kRing];      // copy sources, alive until the slot's event completes
   std::vector<GammaItem> items_host[kRing];
   int ring_pos = 0;
@@ -132,16 +177,8 @@ int launch_batch(Server* S, std::vector<PendingGamma*>& batch, hipEvent_t done_e
   HIP_TRY(hipEventSynchronize(S->ring_ev[slot]));
   size_t ni = 0;
   for (auto* p : batch) ni += (size_t)p->items;
-  if (batch.size() > S->jobs_cap[slot]) {
-    (void)hipFree(S->jobs_dev[slot]);
-    S->jobs_cap[slot] = std::max(batch.size(), (size_t)64);
-    HIP_TRY(hipMalloc((void**)&S->jobs_dev[slot], S->jobs_cap[slot] * sizeof(GammaJob)));
-  }
-  if (ni > S->items_cap[slot]) {
-    (void)hipFree(S->items_dev[slot]);
-    S->items_cap[slot] = std::max(ni, (size_t)4096) * 2;
-    HIP_TRY(hipMalloc((void**)&S->items_dev[slot], S->items_cap[slot] * sizeof(GammaItem)));
-  }
+  if (batch.size() > S->jobs_cap || ni > S->items_cap)
+    return fail(KA_ERR_STATE, "batched product exceeds the server's launch lists");
   std::map<std::pair<int, int>, std::vector<PendingGamma*>> groups;
   for (auto* p : batch) groups[{p->b, p->precision}].push_back(p);
   std::vector<GammaJob>& jobs = S->jobs_host[slot];
@@ -254,7 +291,10 @@ int product(Server* S, Problem* P, hipEvent_t ready) {
     S->cv_gamma.wait(lk, [&] { return pg.launched; });
   }
   hipError_t e = hipSuccess;
-  if (pg.status == KA_OK) e = hipStreamWaitEvent(P->stream, pg.done->ev, 0);
+  if (pg.status == KA_OK) {
+    e = hipStreamWaitEvent(P->stream, pg.done->ev, 0);
+    if (e != hipSuccess) (void)hipEventSynchronize(pg.done->ev);   // the batch still reads this request's buffers
+  }
   bool last = false;
   {
     std::lock_guard<std::mutex> g(S->mu);
@@ -293,9 +333,10 @@ void worker_main(Server* S) {
           S->cv.wait_for(lk, std::chrono::duration<double>(std::min(h->arrival - t, 0.005)));
           continue;
         }
-        if (S->used + h->bytes > S->budget) {
+        size_t off = 0;
+        if (!S->arena.take(h->bytes, &off)) {
           if (S->in_flight == 0) {
-            // can never fit: reject
+            // the whole arena is free and still too small: reject
             ka_result res;
             std::memset(&res, 0, sizeof(res));
             res.id = h->id;
@@ -308,11 +349,12 @@ void worker_main(Server* S) {
             S->cv.notify_all();
             continue;
           }
-          S->cv.wait(lk);     // wait for memory to be released
+          S->cv.wait(lk);     // wait for a range to be returned
           continue;
         }
         r = std::move(S->queue.front());
         S->queue.pop_front();
+        r->offset = off;
         S->used += r->bytes;
         S->in_flight++;
         S->max_active = std::max(S->max_active, S->in_flight);
@@ -321,9 +363,12 @@ void worker_main(Server* S) {
       }
       if (!r) break;
     }
-    // solve
+    // solve, every device buffer inside the request's range of the arena
+    Region region;
+    region.base = S->arena_base + r->offset;
+    region.size = r->bytes;
     Problem* P = nullptr;
-    int rc = setup_problem(&r->desc, stream, &P);
+    int rc = setup_problem(&r->desc, stream, &P, &region);
     std::unique_ptr<EigRun> run;
     if (rc == KA_OK) {
       run.reset(new EigRun(P, r->M, r->tol, r->maxit));
@@ -348,9 +393,12 @@ void worker_main(Server* S) {
     }
     finish_request(S, *r, rc, t_admit, rc == KA_OK ? run.get() : nullptr);
     run.reset();
+    // the range is reused at once: no work of this request may still be queued
+    (void)hipStreamSynchronize(stream);
     if (P) destroy_problem(P);
     {
       std::lock_guard<std::mutex> g(S->mu);
+      S->arena.give(r->offset, r->bytes);
       S->used -= r->bytes;
       S->in_flight--;
       S->cv.notify_all();
@@ -375,7 +423,7 @@ int ka_request_bytes(const ka_desc* desc, int M, size_t* bytes) {
   int64_t N = 0;
   if (int rc = desc_sizes(desc, &N, nullptr, nullptr)) return rc;
   if (M < 1 || M > N) return fail(KA_ERR_ARG, "M must be in 1..N");
-  *bytes = fp + eig_workspace_bytes(N, M, desc->block);
+  *bytes = (fp + eig_workspace_bytes(N, M, desc->block) + 255) / 256 * 256;
   return KA_OK;
 }
 
@@ -384,15 +432,32 @@ int ka_server_create(size_t hbm_budget, int max_slots, ka_server** out) {
   *out = nullptr;
   if (max_slots < 1 || max_slots > 256 || hbm_budget == 0) return fail(KA_ERR_ARG, "need 1 <= max_slots <= 256 and a budget");
   Server* S = new Server();
-  S->budget = hbm_budget;
+  S->budget = hbm_budget / 256 * 256;
   S->max_slots = max_slots;
-  bool ok = hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking) == hipSuccess;
+  // all device memory of the server: the arena and the launch lists
+  if (hipMalloc((void**)&S->arena_base, S->budget) != hipSuccess) {
+    S->arena_base = nullptr;
+    ka_server_destroy(reinterpret_cast<ka_server*>(S));
+    return fail(KA_ERR_OOM, "server arena allocation failed");
+  }
+  S->arena.reset(S->budget);
+  S->jobs_cap = (size_t)max_slots;
+  S->items_cap = (size_t)max_slots * kDirectItems;
+  bool ok = true;
+  for (int i = 0; i < kRing && ok; ++i)
+    ok = hipMalloc((void**)&S->jobs_dev[i], S->jobs_cap * sizeof(GammaJob)) == hipSuccess &&
+         hipMalloc((void**)&S->items_dev[i], S->items_cap * sizeof(GammaItem)) == hipSuccess;
+  if (!ok) {
+    ka_server_destroy(reinterpret_cast<ka_server*>(S));
+    return fail(KA_ERR_OOM, "server launch lists allocation failed");
+  }
+  ok = hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking) == hipSuccess;
   for (int i = 0; i < kRing && ok; ++i) {
     ok = hipEventCreateWithFlags(&S->ring_ev[i], hipEventDisableTiming) == hipSuccess;
     if (ok) ok = hipEventRecord(S->ring_ev[i], S->stream) == hipSuccess;
   }
   if (!ok) {
-    delete S;
+    ka_server_destroy(reinterpret_cast<ka_server*>(S));
     return fail(KA_ERR_HIP, "server stream creation failed");
   }
   S->t0 = Clock::now();
@@ -401,11 +466,14 @@ int ka_server_create(size_t hbm_budget, int max_slots, ka_server** out) {
 }
 
 int ka_server_submit(ka_server* s, const ka_desc* desc, int M, double tol, int maxit, double arrival_s,
-                     uint64_t tag, double* lambda_host, int64_t* req_id) {
+                     uint64_t tag, double* lambda_host, int64_t lambda_len, int64_t* req_id) {
   Server* S = reinterpret_cast<Server*>(s);
   if (!S || !desc || !lambda_host) return fail(KA_ERR_ARG, "NULL argument");
   size_t need = 0;
   if (int rc = ka_request_bytes(desc, M, &need)) return rc;
+  if (lambda_len < lambda_doubles(*desc, M))
+    return fail(KA_ERR_ARG, "lambda_host holds " + std::to_string(lambda_len) + " doubles, the request writes " +
+                                std::to_string(lambda_doubles(*desc, M)));
   std::unique_ptr<Request> r(new Request());
   r->desc = *desc;
   if (desc->domain == KA_NURBS) {   // validated above: copy the geometry, the caller's arrays are not kept
@@ -495,12 +563,13 @@ int ka_server_stats(ka_server* s, int* batches, double* mean_items, int* max_act
 void ka_server_destroy(ka_server* s) {
   Server* S = reinterpret_cast<Server*>(s);
   if (!S) return;
-  (void)hipStreamSynchronize(S->stream);
+  if (S->stream) (void)hipStreamSynchronize(S->stream);
   for (int i = 0; i < kRing; ++i) {
     if (S->ring_ev[i]) (void)hipEventDestroy(S->ring_ev[i]);
-    (void)hipFree(S->jobs_dev[i]);
-    (void)hipFree(S->items_dev[i]);
+    if (S->jobs_dev[i]) (void)hipFree(S->jobs_dev[i]);
+    if (S->items_dev[i]) (void)hipFree(S->items_dev[i]);
   }
+  if (S->arena_base) (void)hipFree(S->arena_base);
   if (S->stream) (void)hipStreamDestroy(S->stream);
   delete S;
 }

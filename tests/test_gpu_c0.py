@@ -115,7 +115,7 @@ def test_half_cylinder_eigenvalues_match_oracle(method, kernel):
     ref, _ = o.eig_dense()
     prob = _problem(c, seed=5)
     M = 12
-    rc, lam, info = K.ka_eigs(prob.h, M, tol=1e-6, maxit=80, complex_values=(method == "collocation"))
+    rc, lam, info = K.ka_eigs(prob.h, M, tol=1e-6, maxit=80)
     prob.close()
     assert rc == 0
     if method == "collocation":
@@ -139,7 +139,7 @@ def test_paper_table2_case1_size(method, kernel):
     N, Nt, _, _ = K.ka_size(prob.h)
     assert N == 1050 and (kernel != "gaussian" or Nt == 1080)
     M = 20
-    rc, lam, info = K.ka_eigs(prob.h, M, tol=1e-6, maxit=100, complex_values=(method == "collocation"))
+    rc, lam, info = K.ka_eigs(prob.h, M, tol=1e-6, maxit=100)
     prob.close()
     assert rc == 0
     if method == "collocation":

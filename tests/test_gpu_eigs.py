@@ -83,6 +83,34 @@ def test_eigs_argument_errors():
     prob.close()
 
 
+def test_lambda_buffer_capacity_and_workspace_reuse():
+    """ka_eigs writes M doubles (Galerkin) or 2M (collocation, re/im): a
+    smaller buffer is refused before any device work, and the binding's
+    default call sizes it from the method.  The eigensolver workspace stays
+    with the problem: later solves with the same or a smaller M allocate
+    nothing (ka_size) and repeat the first solve bitwise."""
+    prob = K.Problem(K.make_desc("collocation", "cube", 2, (5, 5, 5), "gaussian", 0.5, seed=2))
+    with pytest.raises(K.KAError) as e:
+        K.ka_eigs(prob.h, 6, lam=np.zeros(6))
+    assert e.value.code == K.KA_ERR_ARG
+    rc, lam, info = K.ka_eigs(prob.h, 6)
+    assert rc == 0 and len(lam) == 12 and info["lambda_doubles"] == 12
+    held = K.ka_size(prob.h)[3]
+    rc, lam2, _ = K.ka_eigs(prob.h, 6)
+    assert K.ka_size(prob.h)[3] == held and np.array_equal(lam, lam2)
+    rc, lam3, _ = K.ka_eigs(prob.h, 4)
+    assert rc == 0 and K.ka_size(prob.h)[3] == held
+    prob.close()
+    g = K.Problem(K.make_desc("galerkin", "cube", 2, (5, 5, 5), "gaussian", 0.5, seed=2))
+    before = K.ka_size(g.h)[3]
+    rc, lam, info = K.ka_eigs(g.h, 6)
+    assert rc == 0 and len(lam) == 6 and info["lambda_doubles"] == 6
+    assert K.ka_size(g.h)[3] > before           # the workspace is counted once allocated
+    with pytest.raises(K.KAError):
+        K.ka_eigs(g.h, 6, lam=np.zeros(5))
+    g.close()
+
+
 def test_small_cube_collocation_gaussian():
     from oracle import collocation
     desc = K.make_desc("collocation", "cube", 2, (8, 8, 8), "gaussian", 0.5, seed=2)
@@ -115,7 +143,7 @@ def test_annulus_collocation_small_dense():
 def _solve_c(desc, M, tol=1e-6, maxit=60):
     prob = K.Problem(desc)
     V = torch.zeros((M, prob.N), dtype=torch.float64, device="cuda")
-    rc, lam, info = K.ka_eigs(prob.h, M, tol=tol, maxit=maxit, V=V, complex_values=True)
+    rc, lam, info = K.ka_eigs(prob.h, M, tol=tol, maxit=maxit, V=V)
     Vn = V.cpu().numpy().T
     prob.close()
     return rc, lam, Vn, info
@@ -138,7 +166,7 @@ def test_annulus_p4_reduced_mesh(method, kernel, ell, precision, bar):
     ref, _ = o.eig_dense(20)
     desc = K.make_desc(method, "quarter_annulus", 4, (6, 6, 3), kernel, ell, precision=precision, seed=9)
     prob = K.Problem(desc)
-    rc, lam, info = K.ka_eigs(prob.h, 20, tol=1e-6, maxit=60, complex_values=(method == "collocation"))
+    rc, lam, info = K.ka_eigs(prob.h, 20, tol=1e-6, maxit=60)
     prob.close()
     if method == "collocation":
         assert np.abs(lam[1::2] - ref.imag).max() < 10 * bar * abs(ref[0])
@@ -324,7 +352,7 @@ def test_full_spectrum_tiny_mesh(method):
     desc = K.make_desc(method, "cube", 2, (1, 1, 1), "gaussian", 0.5, seed=27)
     prob = K.Problem(desc)
     assert prob.N == 27
-    rc, lam, info = K.ka_eigs(prob.h, 27, tol=1e-6, maxit=20, complex_values=(method == "collocation"))
+    rc, lam, info = K.ka_eigs(prob.h, 27, tol=1e-6, maxit=20)
     prob.close()
     if method == "collocation":
         lam = lam[0::2]
@@ -382,7 +410,7 @@ def test_collocation_rayleigh_ritz_orders_above_128(M):
     product-of-1D collocation spectrum at the floored FP32 bar."""
     desc = K.make_desc("collocation", "cube", 2, (8, 8, 8), "exponential", 1.0, block=16, seed=4)
     prob = K.Problem(desc)
-    rc, lam, info = K.ka_eigs(prob.h, M, tol=1e-6, maxit=80, complex_values=True)
+    rc, lam, info = K.ka_eigs(prob.h, M, tol=1e-6, maxit=80)
     prob.close()
     ref = product1d.collocation_box_spectrum(2, (8, 8, 8), "exponential", 1.0, M=M).real
     err = errors.floored_rel_errors(ref, lam[0::2])

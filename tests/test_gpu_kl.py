@@ -95,7 +95,7 @@ def test_end_to_end_mode_variance(method):
     prob = _problem(c)
     M = 16
     V = torch.zeros((M, prob.N), dtype=torch.float64, device="cuda")
-    rc, lam, info = K.ka_eigs(prob.h, M, tol=1e-7, maxit=80, V=V, complex_values=(method == "collocation"))
+    rc, lam, info = K.ka_eigs(prob.h, M, tol=1e-7, maxit=80, V=V)
     assert rc == 0
     lam = lam[0::2] if method == "collocation" else lam
     q = c["p"] + 1

@@ -97,7 +97,7 @@ def test_eigenvalues_match_oracle(method, kernel, ell):
     ref, _ = o.eig_dense()
     prob = _problem(c, seed=5)
     M = 12
-    rc, lam, info = K.ka_eigs(prob.h, M, tol=1e-6, maxit=80, complex_values=(method == "collocation"))
+    rc, lam, info = K.ka_eigs(prob.h, M, tol=1e-6, maxit=80)
     prob.close()
     assert rc == 0
     if method == "collocation":
@@ -119,7 +119,7 @@ def test_annulus_net_matches_closed_form_domain(method):
     for desc in (K.make_desc(domain="quarter_annulus", seed=9, **c),
                  K.make_desc(domain="nurbs", nurbs=nurbs_annulus_net(), seed=9, **c)):
         prob = K.Problem(desc)
-        rc, lam, info = K.ka_eigs(prob.h, M, tol=1e-6, maxit=80, complex_values=(method == "collocation"))
+        rc, lam, info = K.ka_eigs(prob.h, M, tol=1e-6, maxit=80)
         prob.close()
         assert rc == 0
         lams.append(lam[0::2] if method == "collocation" else lam)
@@ -132,7 +132,7 @@ def test_server_copies_the_control_net():
     c = dict(method="collocation", p=2, nel=(4, 3, 4), kernel="gaussian", ell=0.5, block=16)
     M = 10
     prob = _problem(c, seed=21)
-    rc, ref, _ = K.ka_eigs(prob.h, M, tol=1e-6, maxit=80, complex_values=True)
+    rc, ref, _ = K.ka_eigs(prob.h, M, tol=1e-6, maxit=80)
     prob.close()
     assert rc == 0
     net = {k: (np.array(v, copy=True) if k == "ctrl" else tuple(np.array(t, dtype=float) for t in v)

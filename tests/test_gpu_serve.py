@@ -31,7 +31,7 @@ def _desc(c, i):
     return K.make_desc(seed=100 + i, **c)
 
 
-def _serve(cases, arrivals, budget=64 << 30, slots=8):
+def _serve(cases, arrivals, budget=8 << 30, slots=8):
     srv = K.ka_server_create(budget, slots)
     lams = []
     for i, (c, t) in enumerate(zip(cases, arrivals)):
@@ -47,7 +47,7 @@ def _serve(cases, arrivals, budget=64 << 30, slots=8):
 
 def _plain(c, i):
     prob = K.Problem(_desc(c, i))
-    rc, lam, info = K.ka_eigs(prob.h, c["M"], tol=1e-5, maxit=60, complex_values=(c["method"] == "collocation"))
+    rc, lam, info = K.ka_eigs(prob.h, c["M"], tol=1e-5, maxit=60)
     prob.close()
     return rc, lam
 
@@ -56,6 +56,7 @@ def test_mix_equals_alone_and_plain():
     lam_mix, res, stats = _serve(MIX, ARRIVALS)
     assert len(res) == len(MIX) and all(r["status"] == 0 for r in res), res
     assert stats["max_active"] >= 3                 # requests overlapped on the device
+    assert stats["bytes_in_use"] == 0               # every arena range returned
     for i, c in enumerate(MIX):
         lam_alone, res1, _ = _serve_single(c, i)      # same seed as in the mix
         n = c["M"] * (2 if c["method"] == "collocation" else 1)
@@ -68,7 +69,7 @@ def test_mix_equals_alone_and_plain():
 
 
 def _serve_single(c, i):
-    srv = K.ka_server_create(64 << 30, 1)
+    srv = K.ka_server_create(8 << 30, 1)
     lam = np.zeros(2 * c["M"])
     K.ka_server_submit(srv, _desc(c, i), c["M"], lam, tol=1e-5, maxit=60, arrival_s=0.0, tag=i)
     K.ka_server_run(srv, 120.0)
