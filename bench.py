@@ -1,19 +1,22 @@
 """Benchmark: matrix-free isogeometric K-L solves on one MI355X.
 
-One step = the full hot path on the unit-cube workload (p = 3, 20^3
-elements, N = 12167, M = 50 eigenpairs, block b = 16, FP32 tiles + FP32
-MFMA contraction): four complete K-L solves, Galerkin-IBQ and collocation,
-each with the Gaussian kernel (ell = 0.5) and the L1-exponential kernel
-(ell = 1, C^0 interpolation space for Galerkin, N~ = 226981).  Every solve
-runs the block Krylov eigensolver on the device around the matrix-free
-operator (Kronecker transfers, fused on-the-fly kernel product, FP64 solves).
+One step = the full hot path on the largest single-GPU workload: the unit
+cube with p = 2 and 64^3 elements (N = 287,496 unknowns; a dense FP64 A
+would take 661 GB), Gaussian kernel ell = 0.2, M = 200 eigenpairs, block
+b = 64, Galerkin-IBQ, FP32 kernel tiles and FP32 MFMA contraction: one
+complete K-L solve (block Krylov eigensolver on the device around the
+matrix-free operator: Kronecker transfers, the fused on-the-fly kernel
+product of 287,496^2 pairs per block, FP64 Kronecker solves).
 
 Printed: one JSON line.  value = kernel-pair evaluations per second over the
-whole timed region (all steps), with K-L solves/s, per-solve latency
-percentiles, the eigenvalue error against stored FP64 product-of-1D reference
-spectra (tests/golden/cube_p3_20_reference_spectra.json),
+whole timed region (all steps, eigensolver included), with K-L solves/s,
+per-solve latency percentiles, the eigenvalue error against the stored exact
+FP64 product-of-1D spectrum (tests/golden/cube_p2_64_reference_spectra.json),
 the roofline of the fused kernel product (device time from HIP events on its
-launch stream) and the FP64 CPU oracle timed on a bounded sample.
+launch stream), a second pass in split-BF16 precision, a short serving leg
+(128 requests of the serving stream at 1.5x the one-at-a-time service rate,
+continuous batching against one-at-a-time solves) and the FP64 CPU oracle
+timed on a bounded sample of the same kernel product.
 """
 import argparse
 import json
@@ -41,6 +44,11 @@ SLOTS = {"gaussian": 8, "exponential": 7}
 MFMA_F32_FLOPS = 157.3e12
 
 
+def mfma_pairs(b):
+    """FP32 matrix-core bound of the contraction: 2 b flops per pair."""
+    return MFMA_F32_FLOPS / (2.0 * b)
+
+
 def serial_peak_pairs(kernel, b):
     mfma_pairs = MFMA_F32_FLOPS / 2048.0 * 64.0 * 16.0 / b
     return 1.0 / (1.0 / peak_pairs(kernel) + 1.0 / mfma_pairs)
@@ -50,41 +58,58 @@ def peak_pairs(kernel):
     return VALU_SLOTS_PER_S / SLOTS[kernel]
 
 
-# HBM traffic of the FP32 kernel product per launch, averaged over the 46
-# launches of one step of this workload: rocprofv3 --pmc FETCH_SIZE, then
-# WRITE_SIZE (profiles/gamma_f32_cube_p3_20_traffic.md), scaled by what the
-# same counters read for a plain 256 MiB device copy (FETCH x 2.0, WRITE x 1.0).
-# Valid only for the kernel source it was measured on.
-TRAFFIC = {"gamma_src_sha256_16": "81efab07a96bcf05", "fetch_bytes": 37.5e6, "write_bytes": 52.4e6,
-           "algorithmic_bytes": 33.2e6}
+# HBM traffic of the FP32 kernel product per launch: rocprofv3 --pmc
+# FETCH_SIZE, then WRITE_SIZE, averaged over the product's launches in a run
+# of this workload, each scaled by what the same counter reads for a plain
+# 256 MiB device copy (FETCH x 2.0, WRITE x 1.0); the profiles under profiles/
+# hold the runs.  Valid only for the kernel source it was measured on.
+# Algorithmic bytes per launch: every point's coordinates (16 B), Y row
+# (4 b B) and Z row (4 b B) once, plus the row and column scales.
+TRAFFIC = {
+    "cube20": {"gamma_src_sha256_16": "81efab07a96bcf05", "fetch_bytes": 37.5e6, "write_bytes": 52.4e6,
+               "algorithmic_bytes": 33.2e6},
+    "cube64": {"gamma_src_sha256_16": None, "fetch_bytes": None, "write_bytes": None,
+               "algorithmic_bytes": 287496 * (2 * 16 + 8 * 64 + 4)},
+}
 
 
-def measured_traffic():
+def measured_traffic(name):
     import hashlib
+    t = TRAFFIC[name]
     src = os.path.join(ROOT, "paper_2101_00629_amd", "csrc", "gamma.hip")
     with open(src, "rb") as f:
-        if hashlib.sha256(f.read()).hexdigest()[:16] != TRAFFIC["gamma_src_sha256_16"]:
+        if t["gamma_src_sha256_16"] is None or hashlib.sha256(f.read()).hexdigest()[:16] != t["gamma_src_sha256_16"]:
             return None
-    return TRAFFIC["fetch_bytes"] + TRAFFIC["write_bytes"]
+    return t["fetch_bytes"] + t["write_bytes"]
 
 
-def workload(M=50, b=16, precision="fp32"):
-    from workloads import cube_p3_20
+WORKLOADS = {
+    "cube64": "unit cube p=2 64^3 (N=287496), Gaussian l=0.2, M=200, b=64, Galerkin-IBQ: one full K-L solve "
+              "(287496^2 kernel pairs per block product)",
+    "cube20": "unit cube p=3 20^3 (N=12167), M=50, b=16: Galerkin-IBQ + collocation x Gaussian(l=0.5) + "
+              "exponential-L1(l=1), one full K-L solve each",
+}
+
+
+def workload(name, precision="fp32"):
+    from workloads import cube_p2_64, cube_p3_20
+    if name == "cube64":
+        return [cube_p2_64("galerkin", precision=precision)]
     probs = []
     for method in ("galerkin", "collocation"):
         for kernel in ("gaussian", "exponential"):
-            p = cube_p3_20(method, kernel, precision=precision)
-            p["M"], p["block"] = M, b
-            probs.append(p)
+            probs.append(cube_p3_20(method, kernel, precision=precision))
     return probs
 
 
-GOLDEN = os.path.join(ROOT, "tests", "golden", "cube_p3_20_reference_spectra.json")
+GOLDEN = {"cube64": os.path.join(ROOT, "tests", "golden", "cube_p2_64_reference_spectra.json"),
+          "cube20": os.path.join(ROOT, "tests", "golden", "cube_p3_20_reference_spectra.json")}
 
 
-def reference_spectrum(p):
-    """Stored FP64 reference (tests/golden/make_cube_reference.py writes it)."""
-    with open(GOLDEN) as f:
+def reference_spectrum(name, p):
+    """Stored FP64 reference (tests/golden/make_cube_p2_64_reference.py and
+    tests/golden/make_cube_reference.py write them from the oracle)."""
+    with open(GOLDEN[name]) as f:
         return np.array(json.load(f)["spectra"][f"{p['method']}-{p['kernel']}"]["lambda"])[:p["M"]]
 
 
@@ -110,7 +135,7 @@ def cpu_baseline(probs, seconds_target=20.0):
             o = collocation.Collocation("cube", p["p"], p["nel"], p["kernel"], p["ell"])
             Xr, Xc = o.Xc, o.Xq
         Y = rng.standard_normal((len(Xc), p["block"]))
-        nprobe = 512
+        nprobe = 256
         t0 = time.perf_counter()
         cmatvec.gamma_apply(p["kernel"], 1.0, p["ell"], Xr[:nprobe], Xc, Y)
         rate = nprobe * len(Xc) / max(time.perf_counter() - t0, 1e-6)
@@ -122,7 +147,7 @@ def cpu_baseline(probs, seconds_target=20.0):
         total_time += dt
         parts.append(f"{p['method']}-{p['kernel']}: {rows} rows x {len(Xc)} cols")
     return {"value": total_pairs / total_time, "unit": "pairs/s", "cores": cmatvec.max_threads(), "kind": "oracle",
-            "sample": "FP64 C/OpenMP kernel product (oracle/cmatvec.c), b=16, " + "; ".join(parts)
+            "sample": f"FP64 C/OpenMP kernel product (oracle/cmatvec.c), b={probs[0]['block']}, " + "; ".join(parts)
             + f"; {total_pairs:.3g} pairs in {total_time:.1f} s"}
 
 
@@ -402,16 +427,16 @@ def half_cylinder_benchmark(reps=2):
     return dict(runs=runs, references=refs)
 
 
-def measure(K, torch, precision, steps, warmup, tol):
+def measure(K, torch, name, precision, steps, warmup, tol):
     """Solve the workload's problems `warmup` + `steps` times in one precision;
     returns rates, latencies, accuracy and the kernel product's roofline."""
-    probs = workload(precision=precision)
+    probs = workload(name, precision=precision)
     handles = []
     for i, p in enumerate(probs):
         h = K.Problem(K.desc_from_problem(p, seed=1000 + i))
         handles.append(h)
 
-    def one_step(record):
+    def one_step():
         out = []
         for p, h in zip(probs, handles):
             t0 = time.perf_counter()
@@ -423,15 +448,17 @@ def measure(K, torch, precision, steps, warmup, tol):
         return out
 
     for _ in range(warmup):
-        one_step(False)
+        one_step()
     for h in handles:
         K.ka_profile_reset(h.h)
         K.ka_profile_enable(h.h, True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     results = []
-    for _ in range(steps):
-        results.append(one_step(True))
+    for k in range(steps):
+        results.append(one_step())
+        print(f"[bench] {name} {precision} step {k + 1}/{steps}: {time.perf_counter() - t0:.2f} s", file=sys.stderr,
+              flush=True)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     prof = [K.ka_profile_read(h.h) for h in handles]
@@ -445,26 +472,60 @@ def measure(K, torch, precision, steps, warmup, tol):
     eig = {}
     worst = 0.0
     for p, (lam, info, _) in zip(probs, results[-1]):
-        ref = reference_spectrum(p)
+        ref = reference_spectrum(name, p)
         lr = lam[0::2] if p["method"] == "collocation" else lam
         e = floored_rel_errors(ref, lr)
         worst = max(worst, float(e.max()))
         eig[f"{p['method']}-{p['kernel']}"] = {"max_floored_rel_err": float(e.max()),
                                                "max_raw_rel_err": float(floored_rel_errors(ref, lr, 0.0).max()),
-                                               "matvecs": info["matvecs"], "cycles": info["iterations"]}
-    # roofline of the fused kernel product
+                                               "matvecs": info["matvecs"], "cycles": info["iterations"],
+                                               "floor_accepted": info["floor_accepted"]}
+    # roofline of the fused kernel product: pairs of every timed launch over
+    # their summed device time (HIP events on the launch stream)
     gl_pairs = sum(pp for (_, _, pp) in prof)
     gl_ms = sum(ms for (_, ms, _) in prof)
     launches = sum(n for (n, _, _) in prof)
     achieved = gl_pairs / (gl_ms / 1e3)
-    peak = gl_pairs / sum(pp / peak_pairs(p["kernel"]) for p, (_, _, pp) in zip(probs, prof))
-    speak = gl_pairs / sum(pp / serial_peak_pairs(p["kernel"], p["block"]) for p, (_, _, pp) in zip(probs, prof))
+
+    def harmonic(rate):   # pairs-weighted harmonic mean of per-problem peaks
+        return gl_pairs / sum(pp / rate(p) for p, (_, _, pp) in zip(probs, prof))
+
     out = {"probs": probs, "pairs": pairs, "elapsed": elapsed, "lat": lat, "nsolves": nsolves, "eig": eig,
-           "worst": worst, "achieved": achieved, "peak": peak, "speak": speak, "launches": launches,
-           "gl_ms": gl_ms}
+           "worst": worst, "achieved": achieved, "launches": launches, "gl_ms": gl_ms,
+           "valu_peak": harmonic(lambda p: peak_pairs(p["kernel"])),
+           "mfma_peak": harmonic(lambda p: mfma_pairs(p["block"])),
+           "serial_peak": harmonic(lambda p: serial_peak_pairs(p["kernel"], p["block"])),
+           "flops_per_pair": gl_pairs and sum(2.0 * p["block"] * pp for p, (_, _, pp) in zip(probs, prof)) / gl_pairs}
     for h in handles:
         h.close()
     return out
+
+
+def roofline(res, name, precision):
+    """Roofline record of the fused kernel product.  FP32: the contraction's
+    2 b flops per pair on the FP32 matrix cores (157.3 TFLOP/s) and the tile
+    evaluation's VALU slots do not overlap on gfx950; whichever takes longer
+    per pair is the bound ("mfma" for b = 64).  BF16x3: VALU bound (the BF16
+    contraction is 16x faster), peak from the unit counts."""
+    a = res["achieved"]
+    rec = {"kernel": "gamma_f32_kernel" if precision == "fp32" else "gamma_bf16x3_kernel",
+           "launches": res["launches"], "kernel_ms": res["gl_ms"],
+           "kernel_share_of_step": res["gl_ms"] / 1e3 / res["elapsed"],
+           "pairs_per_s": a, "valu_peak_pairs_per_s": res["valu_peak"], "valu_frac": a / res["valu_peak"]}
+    if precision == "fp32":
+        rec.update(mfma_frac=a / res["mfma_peak"], serial_valu_mfma_peak_pairs_per_s=res["serial_peak"],
+                   serial_frac=a / res["serial_peak"])
+        if res["mfma_peak"] < res["valu_peak"]:
+            flops = a * res["flops_per_pair"]
+            rec.update(bound="mfma", achieved=flops / 1e12, peak=MFMA_F32_FLOPS / 1e12, unit="TFLOP/s",
+                       frac=flops / MFMA_F32_FLOPS)
+        else:
+            rec.update(bound="alu", achieved=a, peak=res["valu_peak"], unit="pairs/s", frac=a / res["valu_peak"])
+        rec.update(traffic=measured_traffic(name), traffic_unit="HBM bytes per launch",
+                   algorithmic_bytes_per_launch=TRAFFIC[name]["algorithmic_bytes"])
+    else:
+        rec.update(bound="alu", achieved=a, peak=res["valu_peak"], unit="pairs/s", frac=a / res["valu_peak"])
+    return rec
 
 
 def nurbs_benchmark(reps=2):
@@ -584,6 +645,10 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16x3"])
+    ap.add_argument("--workload", default="cube64", choices=sorted(WORKLOADS),
+                    help="cube64: the 64^3 cube (default); cube20: the four 20^3 cube problems")
+    ap.add_argument("--no-serve-leg", action="store_true", help="skip the short serving leg of the default line")
+    ap.add_argument("--serve-requests", type=int, default=128, help="requests of the serving leg")
     ap.add_argument("--tol", type=float, default=1e-5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-split-bf16", action="store_true",
@@ -647,7 +712,8 @@ def main():
         print(json.dumps({"metric": "K-L solves/s + p99 latency (serving)", "n_gpus": 1, "data": "synthetic",
                           "dtype": "f32", **res}), flush=True)
         return
-    res = measure(K, torch, args.precision, args.steps, args.warmup, args.tol)
+    name = args.workload
+    res = measure(K, torch, name, args.precision, args.steps, args.warmup, args.tol)
     probs = res["probs"]
     line = {
         "metric": METRIC,
@@ -662,35 +728,33 @@ def main():
         "vs_baseline": None,
         "dtype": "f32" if args.precision == "fp32" else "bf16x3",
         "data": "synthetic",
-        "config": {"workload": "unit cube p=3 20^3 (N=12167), M=50, b=16: Galerkin-IBQ + collocation x "
-                               "Gaussian(l=0.5) + exponential-L1(l=1), one full K-L solve each",
-                   "solves_per_step": len(probs), "tol": args.tol, "precision": args.precision},
+        "config": {"workload": WORKLOADS[name], "solves_per_step": len(probs), "tol": args.tol,
+                   "precision": args.precision},
         "solves_per_s": res["nsolves"] / res["elapsed"],
         "latency_ms": latency(res["lat"]),
-        "eig_err": {"max_floored_rel_err": res["worst"], "per_problem": res["eig"]},
-        "roofline": {"bound": "alu", "achieved": res["achieved"], "peak": res["peak"], "unit": "pairs/s",
-                     "frac": res["achieved"] / res["peak"],
-                     "traffic": measured_traffic() if args.precision == "fp32" else None,
-                     "traffic_unit": "HBM bytes per launch",
-                     "algorithmic_bytes_per_launch": TRAFFIC["algorithmic_bytes"],
-                     "serial_valu_mfma_peak": res["speak"] if args.precision == "fp32" else None,
-                     "frac_of_serial_peak": res["achieved"] / res["speak"] if args.precision == "fp32" else None,
-                     "kernel": "gamma_f32_kernel" if args.precision == "fp32" else "gamma_bf16x3_kernel",
-                     "launches": res["launches"], "kernel_ms": res["gl_ms"],
-                     "kernel_share_of_step": res["gl_ms"] / 1e3 / res["elapsed"]},
+        "eig_err": {"max_floored_rel_err": res["worst"], "bar": 1e-6 if args.precision == "fp32" else 1e-5,
+                    "per_problem": res["eig"]},
+        "roofline": roofline(res, name, args.precision),
     }
     if args.precision == "fp32" and not args.no_split_bf16:
         # the same workload with the contraction in split hi/lo BF16 (its bar: 1e-5)
         nb = max(1, min(args.steps, 3))
-        rb = measure(K, torch, "bf16x3", nb, 1, args.tol)
+        rb = measure(K, torch, name, "bf16x3", nb, 1, args.tol)
         line["split_bf16"] = {
             "value": rb["pairs"] / rb["elapsed"], "unit": "pairs/s", "steps": nb,
             "solves_per_s": rb["nsolves"] / rb["elapsed"], "latency_ms": latency(rb["lat"]),
-            "eig_err": {"max_floored_rel_err": rb["worst"],
+            "eig_err": {"max_floored_rel_err": rb["worst"], "bar": 1e-5,
                         "per_problem": {k: v["max_floored_rel_err"] for k, v in rb["eig"].items()}},
-            "roofline": {"bound": "alu", "achieved": rb["achieved"], "peak": rb["peak"], "unit": "pairs/s",
-                         "frac": rb["achieved"] / rb["peak"], "kernel": "gamma_bf16x3_kernel",
-                         "launches": rb["launches"], "kernel_ms": rb["gl_ms"]}}
+            "roofline": roofline(rb, name, "bf16x3")}
+    if not args.no_serve_leg:
+        sv = serve_benchmark(args.serve_requests, [1.5], args.pair_cap, args.tol)
+        r = sv["rho_1.5"]
+        line["serving"] = {
+            "requests": sv["requests"], "rho": 1.5, "pair_cap_per_block_product": args.pair_cap,
+            "server": {k: r["server"][k] for k in ("solves_per_s", "p50_ms", "p99_ms", "completed", "max_active")},
+            "sequential": {k: r["sequential"][k] for k in ("solves_per_s", "p50_ms", "p99_ms")},
+            "max_eig_diff_vs_alone_rel_lambda1": r["max_eig_diff_vs_alone_rel_lambda1"],
+            "nonzero_status": len(r["server_nonzero_status"]) + len(sv["sequential_nonzero_status"])}
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(probs)
     print(json.dumps(line), flush=True)

@@ -108,6 +108,18 @@ def test_stored_cube_reference_matches_the_oracle():
     assert np.abs(got - ref).max() <= 1e-14 * ref[0]
 
 
+def test_stored_cube_p2_64_reference_matches_the_oracle():
+    import json
+    import numpy as np
+    import sys
+    sys.path.insert(0, ROOT)
+    from oracle import product1d
+    rec = json.load(open(os.path.join(ROOT, "tests", "golden", "cube_p2_64_reference_spectra.json")))
+    got = np.array(rec["spectra"]["galerkin-gaussian"]["lambda"])
+    ref = product1d.galerkin_box_spectrum(2, (64, 64, 64), "gaussian", 0.2, M=len(got))
+    assert np.abs(got - ref).max() <= 1e-14 * ref[0]
+
+
 def test_nurbs_descriptor_validation():
     """KA_NURBS control nets are checked on the host (no device work)."""
     import paper_2101_00629_amd as K
