@@ -284,6 +284,7 @@ static int setup_impl(const ka_desc* d, hipStream_t stream, Problem** out, const
       P->Linv[k] = upload(P, to_vec(Li), ok);
       P->LinvT[k] = upload(P, to_vec(LiT), ok);
       P->Zinv[k] = upload(P, to_vec(matmul(LiT, Li)), ok);
+      P->ZinvT[k] = P->Zinv[k];   // the mass matrix is symmetric
       P->Zk[k] = upload(P, to_vec(Zk), ok);   // mass matrix: exact L2 norms of eigenfunctions
       Vec xq, wq;
       element_gauss(t, d->nq > 0 ? d->nq : p + 1, xq, wq);
@@ -303,6 +304,7 @@ static int setup_impl(const ka_desc* d, hipStream_t stream, Problem** out, const
       P->Linv[k] = upload(P, to_vec(Li), ok);
       P->LinvT[k] = upload(P, to_vec(LiT), ok);
       P->Zinv[k] = upload(P, to_vec(matmul(LiT, Li)), ok);
+      P->ZinvT[k] = P->Zinv[k];   // the mass matrix is symmetric
       P->Zk[k] = upload(P, to_vec(Zk), ok);   // mass matrix: exact L2 norms of eigenfunctions
       const Vec& ti = z.tint[k];
       const Vec g = greville(ti, p);
@@ -334,6 +336,7 @@ static int setup_impl(const ka_desc* d, hipStream_t stream, Problem** out, const
         return fail(KA_ERR_SINGULAR, "collocation matrix Z_k is singular");
       }
       P->Zinv[k] = upload(P, to_vec(Zci), ok);
+      P->ZinvT[k] = upload(P, to_vec(transpose(Zci)), ok);
       P->T[k] = upload(P, to_vec32(Rq), ok);
       P->TT[k] = upload(P, to_vec32(transpose(Rq)), ok);
       pts1d[k] = g;
@@ -447,7 +450,8 @@ static int setup_impl(const ka_desc* d, hipStream_t stream, Problem** out, const
 // operator pieces
 // ---------------------------------------------------------------------------
 static ModeArgs mode_args(const void* in, int in_layout, int64_t in_ld, void* out, int out_layout, int64_t out_ld,
-                          const int dims[3], int mode, int m, const void* mat, int nv, const float* scale) {
+                          const int dims[3], int mode, int m, const void* mat, const void* matT, int nv,
+                          const float* scale) {
   ModeArgs a;
   a.in = in;
   a.in_layout = in_layout;
@@ -459,6 +463,7 @@ static ModeArgs mode_args(const void* in, int in_layout, int64_t in_ld, void* ou
   a.mode = mode;
   a.m = m;
   a.mat = mat;
+  a.matT = matT;
   a.nv = nv;
   a.out_scale = scale;
   return a;
@@ -507,30 +512,31 @@ int gamma_step(Problem* P, const float* Y, float* Z, hipStream_t s) {
   return KA_OK;
 }
 
-// Three FP64 mode products with per-direction matrices mats[k] (n_k x n_k),
-// in-place on a column block through the two FP64 workspaces.
-static int kron64(Problem* P, double* const mats[3], const double* X, int64_t ldx, double* Y, int64_t ldy, int nv,
-                  hipStream_t s) {
+// Three FP64 mode products with per-direction matrices mats[k] (n_k x n_k) on
+// a point-major block (point stride b) in `src`, through `other`; the result
+// is left in `other`.
+static int kron64_pt(Problem* P, double* const mats[3], double* const matsT[3], double* src, double* other, int nv,
+                     hipStream_t s) {
   const int* n = P->n;
-  const int64_t N = P->N;
-  HIP_TRY(launch_mode_f64(mode_args(X, LAYOUT_COL, ldx, P->w64a, LAYOUT_COL, N, n, 0, n[0], mats[0], nv, nullptr), s));
-  HIP_TRY(launch_mode_f64(mode_args(P->w64a, LAYOUT_COL, N, P->w64b, LAYOUT_COL, N, n, 1, n[1], mats[1], nv, nullptr), s));
-  HIP_TRY(launch_mode_f64(mode_args(P->w64b, LAYOUT_COL, N, Y, LAYOUT_COL, ldy, n, 2, n[2], mats[2], nv, nullptr), s));
+  const int b = P->b;
+  HIP_TRY(launch_mode_f64(mode_args(src, LAYOUT_PT, b, other, LAYOUT_PT, b, n, 0, n[0], mats[0], matsT[0], nv, nullptr), s));
+  HIP_TRY(launch_mode_f64(mode_args(other, LAYOUT_PT, b, src, LAYOUT_PT, b, n, 1, n[1], mats[1], matsT[1], nv, nullptr), s));
+  HIP_TRY(launch_mode_f64(mode_args(src, LAYOUT_PT, b, other, LAYOUT_PT, b, n, 2, n[2], mats[2], matsT[2], nv, nullptr), s));
   return KA_OK;
 }
 
-// X (FP64, column layout) -> Galerkin: J B~^-T M X ; collocation: JW R_q X.
-// Output: point-major FP32 in w32a with point stride b.
-static int forward_transfer(Problem* P, const double* X, int64_t ldx, int nv, hipStream_t s) {
+// Point-major FP64 block `src` (point stride b) -> Galerkin: J B~^-T M X ;
+// collocation: JW R_q X.  Output: point-major FP32 in w32b (point stride b).
+static int forward_transfer(Problem* P, const double* src, int nv, hipStream_t s) {
   const int b = P->b;
   const int* n = P->n;
   const int* m = P->d.method == KA_GALERKIN_IBQ ? P->nt : P->nq;
   int d0[3] = {n[0], n[1], n[2]};
-  HIP_TRY(launch_mode_f64_to_f32(mode_args(X, LAYOUT_COL, ldx, P->w32b, LAYOUT_PT, b, d0, 0, m[0], P->T[0], nv, nullptr), s));
+  HIP_TRY(launch_mode_f64_to_f32(mode_args(src, LAYOUT_PT, b, P->w32b, LAYOUT_PT, b, d0, 0, m[0], P->T[0], P->TT[0], nv, nullptr), s));
   int d1[3] = {m[0], n[1], n[2]};
-  HIP_TRY(launch_mode_f32(mode_args(P->w32b, LAYOUT_PT, b, P->w32a, LAYOUT_PT, b, d1, 1, m[1], P->T[1], nv, nullptr), s));
+  HIP_TRY(launch_mode_f32(mode_args(P->w32b, LAYOUT_PT, b, P->w32a, LAYOUT_PT, b, d1, 1, m[1], P->T[1], P->TT[1], nv, nullptr), s));
   int d2[3] = {m[0], m[1], n[2]};
-  HIP_TRY(launch_mode_f32(mode_args(P->w32a, LAYOUT_PT, b, P->w32b, LAYOUT_PT, b, d2, 2, m[2], P->T[2], nv, P->cscale), s));
+  HIP_TRY(launch_mode_f32(mode_args(P->w32a, LAYOUT_PT, b, P->w32b, LAYOUT_PT, b, d2, 2, m[2], P->T[2], P->TT[2], nv, P->cscale), s));
   return KA_OK;   // result in w32b
 }
 
@@ -540,16 +546,14 @@ static int forward_transfer(Problem* P, const double* X, int64_t ldx, int nv, hi
 //   (nine-step algorithm, steps 1-4).  Collocation: R_q per direction with
 //   J W on the last store (Algorithm 1, steps 1-2).
 int apply_pre(Problem* P, int form, const double* X, int64_t ldx, int nv, hipStream_t s) {
-  const int64_t N = P->N;
-  int rc;
-  const double* src = X;
-  int64_t lds = ldx;
+  const int b = P->b;
+  HIP_TRY(col64_to_pt64(X, ldx, P->w64a, b, P->N, nv, s));
+  double* src = P->w64a;
   if (P->d.method != KA_COLLOCATION && form == KA_APRIME) {
-    if ((rc = kron64(P, P->LinvT, X, ldx, P->w64a, N, nv, s))) return rc;
-    src = P->w64a;
-    lds = N;
+    if (int rc = kron64_pt(P, P->LinvT, P->Linv, P->w64a, P->w64b, nv, s)) return rc;
+    src = P->w64b;
   }
-  return forward_transfer(P, src, lds, nv, s);
+  return forward_transfer(P, src, nv, s);
 }
 
 // Operator steps after the kernel product: w32a (point-major FP32) -> Y.
@@ -563,24 +567,24 @@ int apply_post(Problem* P, int form, double* Y, int64_t ldy, int nv, hipStream_t
   if (P->d.method != KA_COLLOCATION) {
     const int* m = P->d.method == KA_GALERKIN_IBQ ? P->nt : P->nq;
     int d0[3] = {m[0], m[1], m[2]};
-    HIP_TRY(launch_mode_f32(mode_args(P->w32a, LAYOUT_PT, b, P->w32b, LAYOUT_PT, b, d0, 0, n[0], P->TT[0], nv, nullptr), s));
+    HIP_TRY(launch_mode_f32(mode_args(P->w32a, LAYOUT_PT, b, P->w32b, LAYOUT_PT, b, d0, 0, n[0], P->TT[0], P->T[0], nv, nullptr), s));
     int d1[3] = {n[0], m[1], m[2]};
-    HIP_TRY(launch_mode_f32(mode_args(P->w32b, LAYOUT_PT, b, P->w32a, LAYOUT_PT, b, d1, 1, n[1], P->TT[1], nv, nullptr), s));
+    HIP_TRY(launch_mode_f32(mode_args(P->w32b, LAYOUT_PT, b, P->w32a, LAYOUT_PT, b, d1, 1, n[1], P->TT[1], P->T[1], nv, nullptr), s));
     int d2[3] = {n[0], n[1], m[2]};
+    HIP_TRY(launch_mode_f32_to_f64(mode_args(P->w32a, LAYOUT_PT, b, P->w64b, LAYOUT_PT, b, d2, 2, n[2], P->TT[2], P->T[2], nv, nullptr), s));
+    double* res = P->w64b;
     if (form == KA_APRIME) {
-      HIP_TRY(launch_mode_f32_to_f64(mode_args(P->w32a, LAYOUT_PT, b, P->w64b, LAYOUT_COL, N, d2, 2, n[2], P->TT[2], nv, nullptr), s));
-      HIP_TRY(launch_mode_f64(mode_args(P->w64b, LAYOUT_COL, N, P->w64a, LAYOUT_COL, N, nn, 0, n[0], P->Linv[0], nv, nullptr), s));
-      HIP_TRY(launch_mode_f64(mode_args(P->w64a, LAYOUT_COL, N, P->w64b, LAYOUT_COL, N, nn, 1, n[1], P->Linv[1], nv, nullptr), s));
-      HIP_TRY(launch_mode_f64(mode_args(P->w64b, LAYOUT_COL, N, Y, LAYOUT_COL, ldy, nn, 2, n[2], P->Linv[2], nv, nullptr), s));
-    } else {
-      HIP_TRY(launch_mode_f32_to_f64(mode_args(P->w32a, LAYOUT_PT, b, Y, LAYOUT_COL, ldy, d2, 2, n[2], P->TT[2], nv, nullptr), s));
+      if (int rc = kron64_pt(P, P->Linv, P->LinvT, P->w64b, P->w64a, nv, s)) return rc;
+      res = P->w64a;
     }
+    HIP_TRY(pt64_to_col64(res, b, Y, ldy, N, nv, s));
     return KA_OK;
   }
   if (form == KA_APRIME) {
-    HIP_TRY(launch_mode_f32in_f64(mode_args(P->w32a, LAYOUT_PT, b, P->w64a, LAYOUT_COL, N, nn, 0, n[0], P->Zinv[0], nv, nullptr), s));
-    HIP_TRY(launch_mode_f64(mode_args(P->w64a, LAYOUT_COL, N, P->w64b, LAYOUT_COL, N, nn, 1, n[1], P->Zinv[1], nv, nullptr), s));
-    HIP_TRY(launch_mode_f64(mode_args(P->w64b, LAYOUT_COL, N, Y, LAYOUT_COL, ldy, nn, 2, n[2], P->Zinv[2], nv, nullptr), s));
+    HIP_TRY(launch_mode_f32in_f64(mode_args(P->w32a, LAYOUT_PT, b, P->w64a, LAYOUT_PT, b, nn, 0, n[0], P->Zinv[0], P->ZinvT[0], nv, nullptr), s));
+    HIP_TRY(launch_mode_f64(mode_args(P->w64a, LAYOUT_PT, b, P->w64b, LAYOUT_PT, b, nn, 1, n[1], P->Zinv[1], P->ZinvT[1], nv, nullptr), s));
+    HIP_TRY(launch_mode_f64(mode_args(P->w64b, LAYOUT_PT, b, P->w64a, LAYOUT_PT, b, nn, 2, n[2], P->Zinv[2], P->ZinvT[2], nv, nullptr), s));
+    HIP_TRY(pt64_to_col64(P->w64a, b, Y, ldy, N, nv, s));
   } else {
     HIP_TRY(cast_pt32_to_col64(P->w32a, b, Y, ldy, N, nv, P->wrow64, s));   // A itself: W(g) divided out
   }
@@ -620,14 +624,27 @@ int apply_block(Problem* P, int form, const double* X, int64_t ldx, double* Y, i
 }
 
 int solve_block(Problem* P, int op, double* X, int64_t ld, int nv, hipStream_t s) {
+  double* const* mats = nullptr;
+  double* const* matsT = nullptr;
   if (op == KA_ZINV) {
     if (P->wrow64) HIP_TRY(scale_rows(X, P->N, nv, ld, P->wrow64, s));   // general NURBS: diag(W(g)) first
-    return kron64(P, P->Zinv, X, ld, X, ld, nv, s);
+    mats = P->Zinv;
+    matsT = P->ZinvT;
+  } else if (P->d.method == KA_COLLOCATION) {
+    return fail(KA_ERR_STATE, "L solves exist for the Galerkin methods only");
+  } else if (op == KA_LINV) {
+    mats = P->Linv;
+    matsT = P->LinvT;
+  } else if (op == KA_LTINV) {
+    mats = P->LinvT;
+    matsT = P->Linv;
+  } else {
+    return fail(KA_ERR_ARG, "bad solve op");
   }
-  if (P->d.method == KA_COLLOCATION) return fail(KA_ERR_STATE, "L solves exist for the Galerkin methods only");
-  if (op == KA_LINV) return kron64(P, P->Linv, X, ld, X, ld, nv, s);
-  if (op == KA_LTINV) return kron64(P, P->LinvT, X, ld, X, ld, nv, s);
-  return fail(KA_ERR_ARG, "bad solve op");
+  HIP_TRY(col64_to_pt64(X, ld, P->w64a, P->b, P->N, nv, s));
+  if (int rc = kron64_pt(P, mats, matsT, P->w64a, P->w64b, nv, s)) return rc;
+  HIP_TRY(pt64_to_col64(P->w64b, P->b, X, ld, P->N, nv, s));
+  return KA_OK;
 }
 
 }  // namespace ka

@@ -84,6 +84,7 @@ struct ModeArgs {
   int mode;               // 0, 1, 2
   int m;                  // output size along `mode`
   const void* mat;        // m x n_in[mode], row-major
+  const void* matT;       // its transpose, n_in[mode] x m row-major (point-major layouts need it)
   int nv;                 // vectors
   const float* out_scale; // optional per-point scale of the output (output dims)
 };
@@ -97,6 +98,11 @@ hipError_t launch_mode_f32in_f64(const ModeArgs& a, hipStream_t s);            /
 // point-major FP32 (point stride ld_in) -> column-major FP64, divided by div[i] if div is not NULL
 hipError_t cast_pt32_to_col64(const float* in, int64_t ld_in, double* out, int64_t ld_out, int64_t npts, int nv,
                               const double* div, hipStream_t s);
+// FP64 layout changes: point-major (point stride ld) <-> column-major (column stride ld)
+hipError_t pt64_to_col64(const double* in, int64_t ld_in, double* out, int64_t ld_out, int64_t npts, int nv,
+                         hipStream_t s);
+hipError_t col64_to_pt64(const double* in, int64_t ld_in, double* out, int64_t ld_out, int64_t npts, int nv,
+                         hipStream_t s);
 
 // ---- FP64 dense helpers (eigensolver) ----------------------------------
 // C(m x n) = alpha * A^T B + beta * C, A: K x m (lda), B: K x n (ldb); split-K
@@ -174,6 +180,7 @@ struct Problem {
   double* LinvT[3] = {nullptr, nullptr, nullptr};   // (L_k^-T) n x n  (Galerkin)
   double* Linv[3] = {nullptr, nullptr, nullptr};    // (L_k^-1)
   double* Zinv[3] = {nullptr, nullptr, nullptr};    // (Z_k^-1) (collocation LU inverse / Galerkin mass inverse)
+  double* ZinvT[3] = {nullptr, nullptr, nullptr};   // (Z_k^-1)^T (the same array as Zinv where Z_k is symmetric)
   double* Zk[3] = {nullptr, nullptr, nullptr};      // Galerkin: mass matrices Z_k (n x n)
   float* T[3] = {nullptr, nullptr, nullptr};        // Galerkin: B~_k^-T M_k (nt x n); collocation: R_q,k (nq x n)
   float* TT[3] = {nullptr, nullptr, nullptr};       // transposes (n x nt)

@@ -177,6 +177,7 @@ ModeArgs col_mode(const double* in, int64_t in_ld, double* out, int64_t out_ld, 
   a.mode = mode;
   a.m = m;
   a.mat = mat;
+  a.matT = nullptr;   // column-major layouts read mat
   a.nv = nv;
   a.out_scale = nullptr;
   return a;

@@ -5,14 +5,119 @@
 // on a block as three mode products, each contracting one tensor index with
 // a small dense univariate matrix.
 //
-// One thread per output element; threads are ordered like the output's
-// memory so the stores coalesce.  The univariate matrix (at most a few
-// hundred rows) is read through the cache.
+// The operator keeps its blocks point-major (the nv values of a point
+// contiguous) between the two ends of a block application, which convert
+// from and to the column-major API layout with LDS-tiled transposes.  In the
+// point-major layout every mode product reads and writes whole point rows:
+// lanes run over the block's vectors, each thread accumulates R outputs
+// along the mode from one pass over its input fiber (R-fold reuse of every
+// load), and the matrix entries are the same for the whole wave (scalar
+// loads).  A general per-output kernel covers the column-major cases.
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
 
 #include "ka_internal.hpp"
 
 namespace ka {
+
+// Point-major mode product: out[(p_out) * out_ld + j] = scale[p_out] *
+// sum_c mat[m * nk + c] * in[(p_in(c)) * in_ld + j], with the matrix given
+// transposed (matT[c * m_out + m]) so that the R entries a thread needs per
+// input value are contiguous.  Threads: x over (rest position, j) with j
+// fastest, y over groups of R-output chunks of the mode (chunk mc =
+// blockIdx.y + k gridDim.y), so the matrix entries are uniform across the
+// workgroup and come through the scalar cache.
+template <typename TIn, typename TAcc, typename TOut, int R>
+__global__ __launch_bounds__(256) void mode_pt_kernel(const TIn* __restrict__ in, int64_t in_ld, TOut* __restrict__ out,
+                                                      int64_t out_ld, const TAcc* __restrict__ matT,
+                                                      const float* __restrict__ scale, int n0, int n1, int n2,
+                                                      int mode, int m, int nv, int64_t nthreads) {
+  constexpr int U = 4;   // input values in flight per thread
+  const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= nthreads) return;
+  const int j = (int)(id % nv);
+  const int64_t r = id / nv;
+  // the two indices other than `mode`, the first of them fastest
+  const int nin[3] = {n0, n1, n2};
+  const int da = mode == 0 ? n1 : n0;
+  const int ia = (int)(r % da), ib = (int)(r / da);
+  int oi[3];
+  oi[mode] = 0;
+  oi[mode == 0 ? 1 : 0] = ia;
+  oi[mode == 2 ? 1 : 2] = ib;
+  int no[3] = {n0, n1, n2};
+  no[mode] = m;
+  const int64_t pin = oi[0] + (int64_t)n0 * (oi[1] + (int64_t)n1 * oi[2]);
+  const int64_t pout = oi[0] + (int64_t)no[0] * (oi[1] + (int64_t)no[1] * oi[2]);
+  const int64_t sin = mode == 0 ? 1 : (mode == 1 ? (int64_t)n0 : (int64_t)n0 * n1);
+  const int64_t sout = mode == 0 ? 1 : (mode == 1 ? (int64_t)no[0] : (int64_t)no[0] * no[1]);
+  const int nk = nin[mode];
+  const TIn* src = in + pin * in_ld + j;
+  const int64_t step = sin * in_ld;
+  for (int mc = blockIdx.y; mc * R < m; mc += gridDim.y) {
+    const int m0 = mc * R;
+    const int rows = m - m0 < R ? m - m0 : R;
+    TAcc acc[R];
+#pragma unroll
+    for (int q = 0; q < R; ++q) acc[q] = (TAcc)0;
+    if (rows == R) {
+      int c = 0;
+      for (; c + U <= nk; c += U) {
+        TAcc x[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) x[u] = (TAcc)src[(int64_t)(c + u) * step];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const TAcc* a = matT + (int64_t)(c + u) * m + m0;
+#pragma unroll
+          for (int q = 0; q < R; ++q) acc[q] += a[q] * x[u];
+        }
+      }
+      for (; c < nk; ++c) {
+        const TAcc x = (TAcc)src[(int64_t)c * step];
+        const TAcc* a = matT + (int64_t)c * m + m0;
+#pragma unroll
+        for (int q = 0; q < R; ++q) acc[q] += a[q] * x;
+      }
+    } else {
+      for (int c = 0; c < nk; ++c) {
+        const TAcc x = (TAcc)src[(int64_t)c * step];
+        const TAcc* a = matT + (int64_t)c * m + m0;
+#pragma unroll
+        for (int q = 0; q < R; ++q)
+          if (q < rows) acc[q] += a[q] * x;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      if (q < rows) {
+        const int64_t po = pout + (int64_t)(m0 + q) * sout;
+        TAcc v = acc[q];
+        if (scale) v *= (TAcc)scale[po];
+        out[po * out_ld + j] = (TOut)v;
+      }
+    }
+  }
+}
+
+template <typename TIn, typename TAcc, typename TOut>
+static hipError_t launch_mode_pt(const ModeArgs& a, hipStream_t s) {
+  constexpr int R = 16;
+  const int nk = a.n_in[a.mode];
+  const int64_t nrest = (int64_t)a.n_in[0] * a.n_in[1] * a.n_in[2] / nk;
+  const int64_t nthreads = nrest * a.nv;
+  if (nthreads == 0 || a.m == 0) return hipSuccess;
+  if (!a.matT) return hipErrorInvalidValue;
+  const int chunks = (a.m + R - 1) / R;
+  // enough workgroups for small tensors: spread the output chunks over y
+  const int gy = (int)std::min<int64_t>(chunks, std::max<int64_t>(1, (65536 + nthreads - 1) / nthreads));
+  const dim3 grid((unsigned)((nthreads + 255) / 256), (unsigned)gy);
+  hipLaunchKernelGGL((mode_pt_kernel<TIn, TAcc, TOut, R>), grid, dim3(256), 0, s, (const TIn*)a.in, a.in_ld,
+                     (TOut*)a.out, a.out_ld, (const TAcc*)a.matT, a.out_scale, a.n_in[0], a.n_in[1], a.n_in[2],
+                     a.mode, a.m, a.nv, nthreads);
+  return hipGetLastError();
+}
 
 template <typename TIn, typename TAcc, typename TOut>
 __global__ void mode_product_kernel(ModeArgs a, int64_t total) {
@@ -59,6 +164,7 @@ __global__ void mode_product_kernel(ModeArgs a, int64_t total) {
 
 template <typename TIn, typename TAcc, typename TOut>
 static hipError_t launch_mode(const ModeArgs& a, hipStream_t s) {
+  if (a.in_layout == LAYOUT_PT && a.out_layout == LAYOUT_PT) return launch_mode_pt<TIn, TAcc, TOut>(a, s);
   int no[3] = {a.n_in[0], a.n_in[1], a.n_in[2]};
   no[a.mode] = a.m;
   const int64_t total = (int64_t)no[0] * no[1] * no[2] * a.nv;
@@ -75,21 +181,83 @@ hipError_t launch_mode_f32(const ModeArgs& a, hipStream_t s) { return launch_mod
 hipError_t launch_mode_f32_to_f64(const ModeArgs& a, hipStream_t s) { return launch_mode<float, float, double>(a, s); }
 hipError_t launch_mode_f32in_f64(const ModeArgs& a, hipStream_t s) { return launch_mode<float, double, double>(a, s); }
 
-__global__ void cast_pt32_col64_kernel(const float* __restrict__ in, int64_t ld_in, double* __restrict__ out,
-                                       int64_t ld_out, int64_t npts, int nv, const double* __restrict__ div) {
-  const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (id >= npts * nv) return;
-  const int64_t i = id % npts, j = id / npts;
-  const double v = (double)in[i * ld_in + j];
-  out[i + j * ld_out] = div ? v / div[i] : v;
+// Layout changes between the column-major API blocks (element (i, j) at
+// i + j ld) and the point-major operator blocks (at i ld + j), through LDS
+// tiles of 64 points x 64 vectors so that both sides are read and written in
+// memory order.  kPad keeps the transposed LDS reads free of bank conflicts.
+constexpr int kTP = 64;
+constexpr int kPad = 1;
+
+// point-major TIn (ld_in) -> column-major TOut (ld_out), divided by div[i] if given
+template <typename TIn, typename TOut>
+__global__ __launch_bounds__(256) void pt_to_col_kernel(const TIn* __restrict__ in, int64_t ld_in,
+                                                        TOut* __restrict__ out, int64_t ld_out, int64_t npts, int nv,
+                                                        const double* __restrict__ div) {
+  __shared__ double t[kTP][kTP + kPad];
+  const int64_t p0 = (int64_t)blockIdx.x * kTP;
+  const int j0 = blockIdx.y * kTP;
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  for (int pp = ty; pp < kTP; pp += 4) {          // read point rows: lanes over vectors
+    const int64_t p = p0 + pp;
+    const int j = j0 + tx;
+    if (p < npts && j < nv) t[pp][tx] = (double)in[p * ld_in + j];
+  }
+  __syncthreads();
+  for (int jj = ty; jj < kTP; jj += 4) {          // write columns: lanes over points
+    const int64_t p = p0 + tx;
+    const int j = j0 + jj;
+    if (p < npts && j < nv) {
+      const double v = t[tx][jj];
+      out[p + (int64_t)j * ld_out] = (TOut)(div ? v / div[p] : v);
+    }
+  }
+}
+
+// column-major double (ld_in) -> point-major double (ld_out)
+__global__ __launch_bounds__(256) void col_to_pt_kernel(const double* __restrict__ in, int64_t ld_in,
+                                                        double* __restrict__ out, int64_t ld_out, int64_t npts,
+                                                        int nv) {
+  __shared__ double t[kTP][kTP + kPad];
+  const int64_t p0 = (int64_t)blockIdx.x * kTP;
+  const int j0 = blockIdx.y * kTP;
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  for (int jj = ty; jj < kTP; jj += 4) {          // read columns: lanes over points
+    const int64_t p = p0 + tx;
+    const int j = j0 + jj;
+    if (p < npts && j < nv) t[jj][tx] = in[p + (int64_t)j * ld_in];
+  }
+  __syncthreads();
+  for (int pp = ty; pp < kTP; pp += 4) {          // write point rows: lanes over vectors
+    const int64_t p = p0 + pp;
+    const int j = j0 + tx;
+    if (p < npts && j < nv) out[p * ld_out + j] = t[tx][pp];
+  }
+}
+
+static dim3 tile_grid(int64_t npts, int nv) {
+  return dim3((unsigned)((npts + kTP - 1) / kTP), (unsigned)((nv + kTP - 1) / kTP));
 }
 
 hipError_t cast_pt32_to_col64(const float* in, int64_t ld_in, double* out, int64_t ld_out, int64_t npts, int nv,
                               const double* div, hipStream_t s) {
-  const int64_t tot = npts * nv;
-  if (tot == 0) return hipSuccess;
-  hipLaunchKernelGGL(cast_pt32_col64_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, in, ld_in, out,
-                     ld_out, npts, nv, div);
+  if (npts * nv == 0) return hipSuccess;
+  hipLaunchKernelGGL((pt_to_col_kernel<float, double>), tile_grid(npts, nv), dim3(256), 0, s, in, ld_in, out, ld_out,
+                     npts, nv, div);
+  return hipGetLastError();
+}
+
+hipError_t pt64_to_col64(const double* in, int64_t ld_in, double* out, int64_t ld_out, int64_t npts, int nv,
+                         hipStream_t s) {
+  if (npts * nv == 0) return hipSuccess;
+  hipLaunchKernelGGL((pt_to_col_kernel<double, double>), tile_grid(npts, nv), dim3(256), 0, s, in, ld_in, out,
+                     ld_out, npts, nv, nullptr);
+  return hipGetLastError();
+}
+
+hipError_t col64_to_pt64(const double* in, int64_t ld_in, double* out, int64_t ld_out, int64_t npts, int nv,
+                         hipStream_t s) {
+  if (npts * nv == 0) return hipSuccess;
+  hipLaunchKernelGGL(col_to_pt_kernel, tile_grid(npts, nv), dim3(256), 0, s, in, ld_in, out, ld_out, npts, nv);
   return hipGetLastError();
 }
 
