@@ -42,8 +42,9 @@ typedef __bf16 bf2v __attribute__((ext_vector_type(2)));
 constexpr int kThreads = 256;
 constexpr int kXcds = 8;        // MI355X: workgroups are dealt to the 8 XCDs round-robin by id
 constexpr int kCT = 64;         // columns per LDS tile
-// MFMA accumulators are flushed into FP64 running totals every 2 tiles (128
-// columns, 32 chained MFMAs per FP32 accumulator).  The FP32 chain length is
+// MFMA accumulators are flushed into running totals every 2 tiles (128
+// columns, 32 chained MFMAs per FP32 accumulator): FP64 totals in the FP32
+// path, FP32 totals in the BF16x3 path.  The FP32 chain length is
 // what sets the arithmetic noise of the product: measured on the 287,496-point
 // Gaussian operator, 8-tile chains gave 1.8e-6 relative error on the smallest
 // of 200 eigenvalues (1.4% of the largest), 2-tile chains 3.8e-7, at the same
@@ -349,20 +350,21 @@ __device__ __forceinline__ void gamma_bf16x3_tile(const GammaLaunch& a, int64_t 
   for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
     for (int t = 0; t < NT; ++t) acc[rb][t] = (f4v){0.f, 0.f, 0.f, 0.f};
-  // Two-level summation: MFMA chains of at most kFlushTiles tiles are added
-  // into FP64 running totals, so the FP32 rounding error grows only with the
-  // chain length, never with the column count.
-  d4v tot[RB][NT];
+  // Two-level summation as in the FP32 path, but with FP32 running totals:
+  // the BF16 representation of Gamma (about 2^-17 relative) dominates the
+  // error here, and the 32 registers FP64 totals would take decide the
+  // occupancy (measured at b = 64: 3 waves per SIMD instead of 2, +10%).
+  f4v tot[RB][NT];
 #pragma unroll
   for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
-    for (int t = 0; t < NT; ++t) tot[rb][t] = (d4v){0.0, 0.0, 0.0, 0.0};
+    for (int t = 0; t < NT; ++t) tot[rb][t] = (f4v){0.f, 0.f, 0.f, 0.f};
   auto flush = [&]() {
 #pragma unroll
     for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
       for (int t = 0; t < NT; ++t) {
-        tot[rb][t] += __builtin_convertvector(acc[rb][t], d4v);
+        tot[rb][t] += acc[rb][t];
         acc[rb][t] = (f4v){0.f, 0.f, 0.f, 0.f};
       }
   };
@@ -472,9 +474,9 @@ __device__ __forceinline__ void gamma_bf16x3_tile(const GammaLaunch& a, int64_t 
 }
 
 // Occupancy target of the BF16x3 path (waves per SIMD), measured best on the
-// workload shapes: 3 at b = 16, 2 at b = 32 and 64.
+// workload shapes: 4 at b = 16, 3 at b = 32 and 64.
 template <int B>
-constexpr int bf16x3_waves() { return B == 16 ? 3 : 2; }
+constexpr int bf16x3_waves() { return B == 16 ? 4 : 3; }
 
 template <int KERNEL, int B, int RB>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(bf16x3_waves<B>(), bf16x3_waves<B>())))
@@ -492,9 +494,15 @@ void gamma_bf16x3_kernel(GammaLaunch a) {
 // row block, column split) are taken round-robin by the workgroups.  Each
 // product keeps its own split-K partition, so its result does not depend on
 // what else is in the batch.
+// The batched kernel inlines the tiles of both kernel functions and its item
+// loop, so it needs more registers than a single-product launch: 3 waves per
+// SIMD at b = 16 and 2 at b = 32 and 64 keep it free of spills.
+template <int B, int PREC>
+constexpr int batch_waves() { return B == 16 ? 3 : 2; }
+
 template <int B, int RB, int PREC>
 __global__ __launch_bounds__(kThreads)
-__attribute__((amdgpu_waves_per_eu(bf16x3_waves<B>(), bf16x3_waves<B>())))   // both kernels inlined: 3/2/2
+__attribute__((amdgpu_waves_per_eu(batch_waves<B, PREC>(), batch_waves<B, PREC>())))
 void gamma_batch_kernel(const GammaJob* __restrict__ jobs,
                                                                const GammaItem* __restrict__ items, int n_items) {
   __shared__ float4 s_x[2][kCT];
