@@ -155,12 +155,12 @@ __device__ __forceinline__ void gamma_f32_tile(const GammaLaunch& a, int64_t rbl
       ybuf[v] = (c < c_end) ? *reinterpret_cast<const float4*>(a.Y + c * B + (e % B))
                             : make_float4(0.f, 0.f, 0.f, 0.f);
     }
+    // raw coordinates: the scale is applied in stash(), after the tile's work,
+    // so no wait for these loads (which would also wait for Y) lands here
     if (threadIdx.x < kCT) {
       const int64_t c = ct + threadIdx.x;
       if (c < c_end)
-        xbuf = make_float4(load_coord(a.xc, c, a.xc_stride, 0, a.coord_scale),
-                           load_coord(a.xc, c, a.xc_stride, 1, a.coord_scale),
-                           load_coord(a.xc, c, a.xc_stride, 2, a.coord_scale), 0.f);
+        xbuf = make_float4(a.xc[c * a.xc_stride], a.xc[c * a.xc_stride + 1], a.xc[c * a.xc_stride + 2], 0.f);
       else
         xbuf = make_float4(0.f, 0.f, 0.f, 0.f);
     }
@@ -172,7 +172,8 @@ __device__ __forceinline__ void gamma_f32_tile(const GammaLaunch& a, int64_t rbl
       float* dst = &s_y[buf][(e / B) * YS + (e % B)];
       dst[0] = ybuf[v].x; dst[1] = ybuf[v].y; dst[2] = ybuf[v].z; dst[3] = ybuf[v].w;
     }
-    if (threadIdx.x < kCT) s_x[buf][threadIdx.x] = xbuf;
+    if (threadIdx.x < kCT)
+      s_x[buf][threadIdx.x] = make_float4(xbuf.x * a.coord_scale, xbuf.y * a.coord_scale, xbuf.z * a.coord_scale, 0.f);
   };
 
   int buf = 0;
@@ -387,12 +388,12 @@ __device__ __forceinline__ void gamma_bf16x3_tile(const GammaLaunch& a, int64_t 
         lbuf[v] = in ? src[E + e] : make_uint4(0u, 0u, 0u, 0u);
       }
     }
+    // raw coordinates: the scale is applied in stash(), after the tile's work,
+    // so no wait for these loads (which would also wait for Y) lands here
     if (threadIdx.x < kCT) {
       const int64_t c = ct + threadIdx.x;
       if (c < c_end)
-        xbuf = make_float4(load_coord(a.xc, c, a.xc_stride, 0, a.coord_scale),
-                           load_coord(a.xc, c, a.xc_stride, 1, a.coord_scale),
-                           load_coord(a.xc, c, a.xc_stride, 2, a.coord_scale), 0.f);
+        xbuf = make_float4(a.xc[c * a.xc_stride], a.xc[c * a.xc_stride + 1], a.xc[c * a.xc_stride + 2], 0.f);
       else
         xbuf = make_float4(0.f, 0.f, 0.f, 0.f);
     }
@@ -406,7 +407,8 @@ __device__ __forceinline__ void gamma_bf16x3_tile(const GammaLaunch& a, int64_t 
         s_yl[buf][e] = lbuf[v];
       }
     }
-    if (threadIdx.x < kCT) s_x[buf][threadIdx.x] = xbuf;
+    if (threadIdx.x < kCT)
+      s_x[buf][threadIdx.x] = make_float4(xbuf.x * a.coord_scale, xbuf.y * a.coord_scale, xbuf.z * a.coord_scale, 0.f);
   };
 
   int buf = 0;
