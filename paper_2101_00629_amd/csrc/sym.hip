@@ -77,18 +77,14 @@ __global__ __launch_bounds__(64) void sym_section_kernel(double* __restrict__ wo
 }
 
 // one thread per cluster that meets the wanted range [n - nvec, n).  Up to
-// order kInvLds a workgroup of kInvThreads threads keeps each thread's LU
-// fields and iterated vector in LDS ([field][i][thread]); above it they live
-// in the interleaved global arrays F and Xw.
-constexpr int kInvThreads = 16;
-constexpr int kInvLds = 200;
-
-template <bool LDS>
-__global__ __launch_bounds__(LDS ? kInvThreads : 64) void sym_invit_kernel(double* __restrict__ work, int n,
-                                                                           int nvec) {
-  constexpr int NT = LDS ? kInvThreads : 64;
-  __shared__ double sd[LDS ? kInvLds : kSymTriMax], se[LDS ? kInvLds : kSymTriMax];
-  __shared__ double fx[LDS ? 6 * kInvLds * kInvThreads : 1];
+// order MAXN a workgroup of NT threads keeps each thread's LU fields and
+// iterated vector in LDS ([field][i][thread]; 6 MAXN NT doubles): 16 threads
+// up to order 200, 2 up to 512, 1 up to 960.  Above that they live in the
+// interleaved global arrays F and Xw (64 threads per workgroup).
+template <bool LDS, int NT, int MAXN>
+__global__ __launch_bounds__(NT) void sym_invit_kernel(double* __restrict__ work, int n, int nvec) {
+  __shared__ double sd[LDS ? MAXN : kSymTriMax], se[LDS ? MAXN : kSymTriMax];
+  __shared__ double fx[LDS ? 6 * MAXN * NT : 1];
   const SymWork sw = sym_work_split(work, n);
   for (int i = threadIdx.x; i < n; i += NT) {
     sd[i] = sw.d[i];
@@ -134,6 +130,51 @@ __global__ __launch_bounds__(64) void sym_back_kernel(double* __restrict__ work,
     for (int i = 0; i < n; ++i) sw.V[(int64_t)i * n + k] = xs[i * 64 + t];
 }
 
+// Above order kBackLds: one wave per 4 vectors, 16 lanes per vector.  Lane r
+// of a vector holds its elements r, r + 16, ... (NS of them) in registers;
+// for each reflector the 16 lanes form the dot product with a fixed
+// butterfly, then update their own elements.  No barriers: every wave walks
+// the reflectors (read through the cache) on its own.
+template <int NS>
+__global__ __launch_bounds__(64) void sym_back_wave_kernel(double* __restrict__ work, int n, int nvec) {
+  const SymWork sw = sym_work_split(work, n);
+  const int lane = threadIdx.x & 63, r = lane & 15;
+  const int k = n - nvec + blockIdx.x * 4 + (lane >> 4);
+  const bool act = k < n;
+  const int kk = act ? k : n - 1;
+  double x[NS];
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    const int i = r + 16 * s;
+    x[s] = (i < n) ? sw.V[(int64_t)i * n + kk] : 0.0;
+  }
+  for (int j = n - 3; j >= 0; --j) {
+    const double b = sw.beta[j];
+    if (b == 0.0) continue;                      // uniform over the grid
+    const double* v = sw.A + (int64_t)j * n;     // reflector: rows j + 1 .. n - 1 of column j
+    double dot = 0.0;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      const int i = r + 16 * s;
+      if (i > j && i < n) dot += v[i] * x[s];
+    }
+#pragma unroll
+    for (int off = 8; off > 0; off >>= 1) dot += __shfl_xor(dot, off, 16);
+    const double sc = b * dot;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {          // v again, now from the cache
+      const int i = r + 16 * s;
+      if (i > j && i < n) x[s] -= sc * v[i];
+    }
+  }
+  if (act)
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      const int i = r + 16 * s;
+      if (i < n) sw.V[(int64_t)i * n + k] = x[s];
+    }
+}
+
 // theta descending (all n); S column k (k < nvec) = vector n-1-k
 __global__ __launch_bounds__(256) void sym_out_kernel(const double* __restrict__ work, int n, int nvec,
                                                       double* __restrict__ theta, double* __restrict__ S, int lds) {
@@ -156,15 +197,21 @@ hipError_t sym_eig_tri(const double* H, int n, int ldh, int nvec, double* theta,
   hipLaunchKernelGGL(sym_section_kernel, dim3(n), dim3(64), 0, s, work, n);
   if (nvec > 0) {
     const int g64 = (nvec + 63) / 64;
-    if (n <= kInvLds)
-      hipLaunchKernelGGL(sym_invit_kernel<true>, dim3((nvec + kInvThreads - 1) / kInvThreads), dim3(kInvThreads), 0,
-                         s, work, n, nvec);
+    if (n <= 200)
+      hipLaunchKernelGGL((sym_invit_kernel<true, 16, 200>), dim3((nvec + 15) / 16), dim3(16), 0, s, work, n, nvec);
+    else if (n <= 512)
+      hipLaunchKernelGGL((sym_invit_kernel<true, 2, 512>), dim3((nvec + 1) / 2), dim3(2), 0, s, work, n, nvec);
+    else if (n <= 960)
+      hipLaunchKernelGGL((sym_invit_kernel<true, 1, 960>), dim3(nvec), dim3(1), 0, s, work, n, nvec);
     else
-      hipLaunchKernelGGL(sym_invit_kernel<false>, dim3(g64), dim3(64), 0, s, work, n, nvec);
+      hipLaunchKernelGGL((sym_invit_kernel<false, 64, 1>), dim3(g64), dim3(64), 0, s, work, n, nvec);
+    const int g4 = (nvec + 3) / 4;
     if (n <= kBackLds)
       hipLaunchKernelGGL(sym_back_kernel<true>, dim3(g64), dim3(64), 0, s, work, n, nvec);
+    else if (n <= 512)
+      hipLaunchKernelGGL(sym_back_wave_kernel<32>, dim3(g4), dim3(64), 0, s, work, n, nvec);
     else
-      hipLaunchKernelGGL(sym_back_kernel<false>, dim3(g64), dim3(64), 0, s, work, n, nvec);
+      hipLaunchKernelGGL(sym_back_wave_kernel<64>, dim3(g4), dim3(64), 0, s, work, n, nvec);
   }
   const int64_t nq = std::max<int64_t>((int64_t)n * nvec, n);
   hipLaunchKernelGGL(sym_out_kernel, dim3((unsigned)((nq + 255) / 256)), dim3(256), 0, s, work, n, nvec, theta, S,
