@@ -42,6 +42,28 @@ struct NsTeam {
     __syncthreads();
     return s;
   }
+  // groups of the multishift sweep: the waves, ordered among their own
+  // threads by a wavefront-scope fence (one wave's LDS operations complete in
+  // issue order)
+  __device__ int gsize() const { return 64; }
+  __device__ int group() const { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
+  __device__ void gsync() const { __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront"); }
+  __device__ double gpick(double v, int src) const {      // v of lane src (src uniform in the wave)
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), src);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), src);
+    return __hiloint2double(hi, lo);
+  }
+  __device__ int imax(int x) const {
+    for (int off = 32; off > 0; off >>= 1) x = max(x, __shfl_xor(x, off));
+    if (NT == 64) return x;
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = (double)x;
+    __syncthreads();
+    int s = x;
+#pragma unroll
+    for (int w = 0; w < NT / 64; ++w) s = max(s, (int)red[w]);
+    __syncthreads();
+    return s;
+  }
 };
 
 template <bool LDS>
@@ -64,8 +86,9 @@ __global__ __launch_bounds__(kNsThreads) void ns_hess_kernel(const double* __res
 }
 
 // ---- eigenvalue QR by one wave, matrix in LDS --------------------------------------------
-// The Francis double-shift iteration of ns_qr_values (nonsym_core.hpp) with
-// the same arithmetic, arranged for the 64 lanes of one wave:
+// The Francis double-shift iteration of ns_qr_values (nonsym_core.hpp),
+// arranged for the 64 lanes of one wave (the reflector's reciprocals by
+// ns_recip, the rest the same arithmetic):
 //  - the two searches of each iteration (the negligible sub-diagonal that
 //    splits the active window, and the start m of the double step) test 64
 //    positions at once and take the first hit with a ballot, instead of a
@@ -97,7 +120,9 @@ __device__ inline double ns_lane_value(double c0, double c1, double c2, int idx)
   return ns_readlane(v, idx & 63);
 }
 
-__device__ int ns_qr_values_wave(double* hb, int n, double* wr, double* wi, double* anorm_out) {
+// Inlined, so that each call site reads its band with LDS instructions.
+__device__ KA_FORCEINLINE int ns_qr_values_wave(double* hb, int n, double* wr, double* wi, double* anorm_out,
+                                                double tol = kNsEps) {
   const int t = threadIdx.x;
 #define HB(i, j) hb[(j) * ((j) + 7) / 2 + (i)]
   double anorm = 0.0;
@@ -120,7 +145,7 @@ __device__ int ns_qr_values_wave(double* hb, int n, double* wr, double* wi, doub
         if (l0 >= 1) {
           double s = fabs(HB(l0 - 1, l0 - 1)) + fabs(HB(l0, l0));
           if (s == 0.0) s = anorm;
-          hit = fabs(HB(l0, l0 - 1)) <= kNsEps * s;
+          hit = fabs(HB(l0, l0 - 1)) <= tol * s;
         }
         const unsigned long long mask = __ballot(hit);
         if (mask) {
@@ -233,7 +258,7 @@ __device__ int ns_qr_values_wave(double* hb, int n, double* wr, double* wi, doub
           r = notlast ? NS_LANE(k + 2 - l) : 0.0;
           xx = fabs(p) + fabs(q) + fabs(r);
           if (xx != 0.0) {
-            const double ixx = 1.0 / xx;
+            const double ixx = ns_recip(xx);
             p *= ixx;
             q *= ixx;
             r *= ixx;
@@ -258,7 +283,7 @@ __device__ int ns_qr_values_wave(double* hb, int n, double* wr, double* wi, doub
           }
         }
         const double pp = p + s;
-        const double is = 1.0 / s, ipp = 1.0 / pp;
+        const double is = ns_recip(s), ipp = ns_recip(pp);
         const double x1 = pp * is, y1 = q * is, z1 = r * is;
         const double q1 = q * ipp, r1 = r * ipp;
         // rows k..k+2, columns k..nn.  Loads are unconditional at clamped,
@@ -316,16 +341,69 @@ __device__ int ns_qr_values_wave(double* hb, int n, double* wr, double* wi, doub
   return fail;
 }
 
-template <bool LDS>
+constexpr int kNsMsFrom = 64;     // orders from which the multishift kernel below takes over
+
 __global__ __launch_bounds__(64) void ns_qr_kernel(double* __restrict__ work, int n, int nv) {
-  __shared__ double hb_lds[LDS ? (size_t)kNsBandLds * (kNsBandLds + 7) / 2 + 8 : 1];
+  __shared__ double hb[ns_band_doubles(kNsMsFrom)];
   const NsWork ws = ns_work_split(work, n, nv);
-  double* hb = LDS ? hb_lds : ws.HB;
   NsTeam<64> tm{nullptr};
   ns_band_fill(tm, ws.A, n, ws.hsub, n, hb, ws.HT);
   __syncthreads();
-  const int fail = LDS ? ns_qr_values_wave(hb, n, ws.wr0, ws.wi0, ws.misc)
-                       : ns_qr_values(tm, hb, n, ws.wr0, ws.wi0, ws.misc);
+  const int fail = ns_qr_values_wave(hb, n, ws.wr0, ws.wi0, ws.misc);
+  if (threadIdx.x == 0) ws.misc[1] = fail;
+}
+
+// ---- eigenvalue QR from order kNsMsFrom: multishift sweeps by one workgroup ----------------
+// ns_ms_run (nonsym_core.hpp) with a team of one wave per bulge.  The band
+// lives in LDS up to order kNsMsLds (with the sweep scratch, 162.1 KB of the
+// 160 KiB); above that it starts in the work buffer and moves to LDS once the
+// deflations have shrunk the leading block to that order.  Wave 0 computes
+// each sweep's shifts with the one-wave loop above on the trailing block.
+constexpr int kNsMsThreads = 64 * kNsMsBulges;
+constexpr int kNsMsLds = 196;
+
+struct NsWaveSmallEig {
+  int* flag;
+  __device__ int operator()(double* sb, int ns, double* sr, double* si, double tol) const {
+    if (threadIdx.x < 64) {
+      const int f = ns_qr_values_wave(sb, ns, sr, si, nullptr, tol);
+      if (threadIdx.x == 0) *flag = f;
+    }
+    __syncthreads();
+    return *flag;
+  }
+};
+
+template <bool LDS>
+__global__ __launch_bounds__(kNsMsThreads) void ns_qr_ms_kernel(double* __restrict__ work, int n, int nv) {
+  __shared__ double band[ns_band_doubles(kNsMsLds)];
+  __shared__ double scr[ns_ms_scratch_doubles()];
+  __shared__ double red[kNsMsThreads / 64];
+  __shared__ int flag;
+  const NsWork ws = ns_work_split(work, n, nv);
+  NsTeam<kNsMsThreads> tm{red};
+  const NsWaveSmallEig small{&flag};
+  int nn = n - 1, fail = 0;
+  double shift = 0.0;
+  if (LDS) {
+    ns_band_fill(tm, ws.A, n, ws.hsub, n, band, ws.HT);
+    __syncthreads();
+    const double anorm = ns_band_norm(tm, band, n);
+    fail = ns_ms_run(tm, band, nn, shift, anorm, -1, ws.wr0, ws.wi0, scr, small);
+    if (threadIdx.x == 0) ws.misc[0] = anorm;
+  } else {
+    // in the work buffer until the leading block fits the LDS band, then there
+    ns_band_fill(tm, ws.A, n, ws.hsub, n, ws.HB, ws.HT);
+    __syncthreads();
+    const double anorm = ns_band_norm(tm, ws.HB, n);
+    fail = ns_ms_run(tm, ws.HB, nn, shift, anorm, kNsMsLds - 1, ws.wr0, ws.wi0, scr, small);
+    if (!fail) {
+      const int cnt = (nn + 1) * (nn + 8) / 2;
+      for (int e = threadIdx.x; e < cnt; e += kNsMsThreads) band[e] = ws.HB[e];
+      fail = ns_ms_run(tm, band, nn, shift, anorm, -1, ws.wr0, ws.wi0, scr, small);
+    }
+    if (threadIdx.x == 0) ws.misc[0] = anorm;
+  }
   if (threadIdx.x == 0) ws.misc[1] = fail;
 }
 
@@ -420,10 +498,12 @@ hipError_t nonsym_eig(const double* H, int n, int ldh, int nvec, double* wr, dou
     hipLaunchKernelGGL(ns_hess_kernel<true>, dim3(1), dim3(kNsThreads), 0, s, H, n, ldh, work, nv);
   else
     hipLaunchKernelGGL(ns_hess_kernel<false>, dim3(1), dim3(kNsThreads), 0, s, H, n, ldh, work, nv);
-  if (n <= kNsBandLds)
-    hipLaunchKernelGGL(ns_qr_kernel<true>, dim3(1), dim3(64), 0, s, work, n, nv);
+  if (n < kNsMsFrom)
+    hipLaunchKernelGGL(ns_qr_kernel, dim3(1), dim3(64), 0, s, work, n, nv);
+  else if (n <= kNsMsLds)
+    hipLaunchKernelGGL(ns_qr_ms_kernel<true>, dim3(1), dim3(kNsMsThreads), 0, s, work, n, nv);
   else
-    hipLaunchKernelGGL(ns_qr_kernel<false>, dim3(1), dim3(64), 0, s, work, n, nv);
+    hipLaunchKernelGGL(ns_qr_ms_kernel<false>, dim3(1), dim3(kNsMsThreads), 0, s, work, n, nv);
   hipLaunchKernelGGL(ns_rank_kernel, dim3((n + 255) / 256), dim3(256), 0, s, work, n, nv);
   const int g64 = (nv + 63) / 64;
   if (nvec > 0) {

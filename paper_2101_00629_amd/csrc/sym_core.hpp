@@ -34,6 +34,9 @@
 #define KA_HD
 #endif
 #endif
+#ifndef KA_FORCEINLINE
+#define KA_FORCEINLINE __attribute__((always_inline)) inline
+#endif
 
 namespace ka {
 
