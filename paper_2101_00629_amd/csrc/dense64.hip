@@ -35,92 +35,127 @@ __global__ void split_reduce_kernel(const double* __restrict__ part, int nsplit,
 
 // ---------------------------------------------------------------------------
 // C = alpha A^T B + beta C for tall A (K x m) and B (K x n): the projections
-// and Gram matrices of the block eigensolver (K = N up to ~10^6, m and n up to
-// a few hundred).  The product is bound by reading A and B once, so the aim is
-// many loads in flight, with the arithmetic on the FP64 matrix cores.
+// and Gram matrices of the block eigensolver (K = N up to ~10^6, m up to a
+// few hundred, n the block width).  The product reads A and B once from HBM
+// and does 2 K m n flops on the FP64 matrix cores; a workgroup therefore takes
+// a 128 x 64 block of C, so that A is read once and B once per 128 rows of C.
 //
-// v_mfma_f64_16x16x4f64, one wave per 16 x 16 output tile and 16-row group:
-// A lane l holds (i = l % 16, k = l / 16), B lane l holds (k = l / 16,
-// j = l % 16), accumulator register r of lane l holds (i = l / 16 + 4 r,
-// j = l % 16).  The four MFMAs of a group may take its 16 rows in any
-// partition, so lane l reads the four consecutive rows 4 (l / 16) .. + 3 of its
-// column of A and of B (MFMA s takes row 4 (l / 16) + s).  The 4 waves of a
-// workgroup take interleaved groups of its row range and are summed through LDS
-// in wave order; row ranges (splits) go to a partial array that
-// split_reduce_kernel sums in split order, or straight to C with one split.
+// v_mfma_f64_16x16x4f64 layout: A lane l holds (i = l % 16, k = l / 16), B
+// lane l holds (k = l / 16, j = l % 16), accumulator register r of lane l
+// holds (i = l / 16 + 4 r, j = l % 16).  The four MFMAs of a 16-row step may
+// take its rows in any partition, so lane l reads the four consecutive rows
+// 4 (l / 16) .. + 3 of its columns of A and B (MFMA s takes row 4 (l / 16) + s).
+// Each of the 4 waves holds two 16-row tiles of C across the block's four
+// 16-column tiles (8 accumulators) and runs over the split's rows with the
+// next step's loads issued before the current step's MFMAs.  Row ranges
+// (splits) go to a partial array that split_reduce_kernel sums in split order,
+// or straight to C with one split.
 // ---------------------------------------------------------------------------
 typedef double tn_d4 __attribute__((ext_vector_type(4)));
-constexpr int kTnU = 2;                 // groups per wave per iteration (8 + 8 loads per lane in flight)
-constexpr int kTnRows = 64 * kTnU;      // rows per workgroup iteration; splits are multiples of it
+constexpr int kTnI = 2;                     // 16-row tiles of C per wave
+constexpr int kTnRowsC = 4 * 16 * kTnI;     // rows of C (columns of A) per workgroup
+constexpr int kTnStep = 32;                 // rows of A and B per loop iteration (two 16-row steps)
 
 __global__ __launch_bounds__(256) void dgemm_tn_mfma_kernel(int m, int n, int64_t K, const double* __restrict__ A,
                                                             int64_t lda, const double* __restrict__ B, int64_t ldb,
                                                             int64_t k_per_split, double* __restrict__ part,
                                                             double alpha, double beta, double* __restrict__ C,
                                                             int64_t ldc) {
-  __shared__ double red[3][4][64];
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, q = lane >> 4;
-  const int i = blockIdx.x * 16 + (lane & 15), j = blockIdx.y * 16 + (lane & 15);
-  const bool iok = i < m, jok = j < n;
-  const double* __restrict__ Ai = A + (int64_t)(iok ? i : 0) * lda;
-  const double* __restrict__ Bj = B + (int64_t)(jok ? j : 0) * ldb;
-  const int64_t kb = (int64_t)blockIdx.z * k_per_split;
-  const int64_t ke = (kb + k_per_split < K) ? kb + k_per_split : K;
-  tn_d4 acc = {0.0, 0.0, 0.0, 0.0};
-  // the loop bound is uniform over the wave (the matrix cores need all lanes)
-  for (int64_t g0 = kb + 16 * w; g0 < ke; g0 += kTnRows) {
-    // loads at clamped addresses (rows past the range are read at row ke - 1
-    // and weighted by zero), all issued before the first MFMA
-    double a[kTnU][4], bv[kTnU][4];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, q = lane >> 4, c16 = lane & 15;
+  const int i0 = blockIdx.x * kTnRowsC + w * 16 * kTnI;   // this wave's first row of C
+  if (i0 >= m) return;                                     // (no barriers in this kernel)
+  const int j0 = blockIdx.y * 64;
+  const double* Ap[kTnI];
+  bool aok[kTnI];
 #pragma unroll
-    for (int u = 0; u < kTnU; ++u)
-#pragma unroll
-      for (int s = 0; s < 4; ++s) {
-        const int64_t r = g0 + 64 * u + 4 * q + s;
-        const int64_t rc = r < ke ? r : ke - 1;
-        a[u][s] = Ai[rc];
-        bv[u][s] = Bj[rc];
-      }
-#pragma unroll
-    for (int u = 0; u < kTnU; ++u)
-#pragma unroll
-      for (int s = 0; s < 4; ++s) {
-        const bool ok = g0 + 64 * u + 4 * q + s < ke;
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(ok && iok ? a[u][s] : 0.0, ok && jok ? bv[u][s] : 0.0, acc,
-                                                   0, 0, 0);
-      }
+  for (int u = 0; u < kTnI; ++u) {
+    const int i = i0 + 16 * u + c16;
+    aok[u] = i < m;
+    Ap[u] = A + (int64_t)(aok[u] ? i : 0) * lda;
   }
-  if (w > 0)
+  const double* Bp[4];
+  bool bok[4];
 #pragma unroll
-    for (int r = 0; r < 4; ++r) red[w - 1][r][lane] = acc[r];
-  __syncthreads();
-  if (w > 0) return;
-  const int jo = blockIdx.y * 16 + (lane & 15);
+  for (int t = 0; t < 4; ++t) {
+    const int j = j0 + 16 * t + c16;
+    bok[t] = j < n;
+    Bp[t] = B + (int64_t)(bok[t] ? j : 0) * ldb;
+  }
+  const int64_t kb = (int64_t)blockIdx.z * k_per_split;
+  const int64_t ke = kb + k_per_split < K ? kb + k_per_split : K;
+  tn_d4 acc[kTnI][4];
 #pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const double v = ((acc[r] + red[0][r][lane]) + red[1][r][lane]) + red[2][r][lane];
-    const int io = blockIdx.x * 16 + q + 4 * r;
-    if (io >= m || jo >= n) continue;
-    if (part) {
-      part[((size_t)blockIdx.z * n + jo) * m + io] = v;   // partial[z][j][i]
-    } else {
-      double* c = C + io + (int64_t)jo * ldc;
-      *c = (beta == 0.0) ? alpha * v : alpha * v + beta * *c;
+  for (int u = 0; u < kTnI; ++u)
+#pragma unroll
+    for (int t = 0; t < 4; ++t) acc[u][t] = (tn_d4){0.0, 0.0, 0.0, 0.0};
+  // one 16-row step; rows past the range are read at row ke - 1 (a valid
+  // address) and weighted by zero
+  auto load = [&](int64_t g, double (&a)[kTnI][4], double (&b)[4][4]) {
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int64_t r = g + 4 * q + s;
+      const int64_t rc = r < ke ? r : ke - 1;
+#pragma unroll
+      for (int u = 0; u < kTnI; ++u) a[u][s] = Ap[u][rc];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) b[t][s] = Bp[t][rc];
+    }
+  };
+  auto step = [&](int64_t g, const double (&a)[kTnI][4], const double (&b)[4][4]) {
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const bool ok = g + 4 * q + s < ke;
+#pragma unroll
+      for (int u = 0; u < kTnI; ++u) {
+        const double av = ok && aok[u] ? a[u][s] : 0.0;
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+          acc[u][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bok[t] ? b[t][s] : 0.0, acc[u][t], 0, 0, 0);
+      }
+    }
+  };
+  if (kb < ke) {
+    double a0[kTnI][4], b0[4][4], a1[kTnI][4], b1[4][4];
+    load(kb, a0, b0);
+    for (int64_t g = kb; g < ke; g += kTnStep) {   // uniform over the wave (the matrix cores need all lanes)
+      load(g + 16, a1, b1);
+      step(g, a0, b0);
+      load(g + kTnStep, a0, b0);
+      step(g + 16, a1, b1);
     }
   }
+#pragma unroll
+  for (int u = 0; u < kTnI; ++u)
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int jo = j0 + 16 * t + c16;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int io = i0 + 16 * u + q + 4 * r;
+        if (io >= m || jo >= n) continue;
+        const double v = acc[u][t][r];
+        if (part) {
+          part[((size_t)blockIdx.z * n + jo) * m + io] = v;   // partial[z][j][i]
+        } else {
+          double* c = C + io + (int64_t)jo * ldc;
+          *c = (beta == 0.0) ? alpha * v : alpha * v + beta * *c;
+        }
+      }
+    }
 }
 
-// Row splits: about 1024 workgroups, at least 256 rows each, whole multiples
-// of kTnRows, at most 256 splits; products with K < 1024 take one split.
+// Row splits: about 512 workgroups (two per CU), at least 256 rows each,
+// whole multiples of kTnStep, at most 256 splits; products with K < 1024
+// take one split.
 static int64_t tn_rows_per_split(int m, int n, int64_t K) {
   if (K < 1024) return K > 0 ? K : 1;
-  const int64_t tiles = (int64_t)((m + 15) / 16) * ((n + 15) / 16);
-  int64_t ns = (1024 + tiles - 1) / tiles;
+  const int64_t tiles = (int64_t)((m + kTnRowsC - 1) / kTnRowsC) * ((n + 63) / 64);
+  int64_t ns = (512 + tiles - 1) / tiles;
   if (ns > K / 256) ns = K / 256;
   if (ns > 256) ns = 256;
   if (ns < 1) ns = 1;
-  int64_t kps = (K + ns - 1) / ns;
-  return (kps + kTnRows - 1) / kTnRows * kTnRows;
+  const int64_t kps = (K + ns - 1) / ns;
+  return (kps + kTnStep - 1) / kTnStep * kTnStep;
 }
 
 static int tn_splits(int m, int n, int64_t K) {
@@ -138,7 +173,7 @@ hipError_t dgemm_tn(int m, int n, int64_t K, double alpha, const double* A, int6
   if (m <= 0 || n <= 0) return hipSuccess;
   const int64_t kps = tn_rows_per_split(m, n, K);
   const int ns = tn_splits(m, n, K);
-  const dim3 grid((m + 15) / 16, (n + 15) / 16, ns);
+  const dim3 grid((m + kTnRowsC - 1) / kTnRowsC, (n + 63) / 64, ns);
   hipLaunchKernelGGL(dgemm_tn_mfma_kernel, grid, dim3(256), 0, s, m, n, K, A, lda, B, ldb, kps,
                      ns > 1 ? work : nullptr, alpha, beta, C, ldc);
   hipError_t e = hipGetLastError();
@@ -233,7 +268,8 @@ hipError_t dgemm_nn(int64_t M, int n, int k, double alpha, const double* A, int6
 // status: 0 ok, 1 a pivot was not positive or lost (rank-deficient block).
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(64) void chol_upper_inv_kernel(const double* __restrict__ G, int n, int ldg,
-                                                            double* __restrict__ Rinv, int ldr, int* status) {
+                                                            double* __restrict__ Rinv, int ldr, int* status,
+                                                            const double* __restrict__ ref) {
   __shared__ double R[64][65];
   __shared__ double X[64][65];
   __shared__ int bad;
@@ -248,7 +284,8 @@ __global__ __launch_bounds__(64) void chol_upper_inv_kernel(const double* __rest
       double d = R[j][j];
       for (int k = 0; k < j; ++k) d -= R[k][j] * R[k][j];
       const double orig = G[j + j * ldg];
-      if (!(d > 1e-26 * orig) || !(orig > 1e-300)) {
+      const double floor = ref ? kOrthKeep * kOrthKeep * ref[j] * ref[j] : 0.0;
+      if (!(d > 1e-26 * orig) || !(orig > 1e-300) || !(d > floor)) {
         bad = 1;
         d = 1.0;
       }
@@ -282,9 +319,10 @@ __global__ __launch_bounds__(64) void chol_upper_inv_kernel(const double* __rest
   if (t == 0) *status = bad;
 }
 
-hipError_t chol_upper_inv(const double* G, int n, int ldg, double* Rinv, int ldr, int* status, hipStream_t s) {
+hipError_t chol_upper_inv(const double* G, int n, int ldg, double* Rinv, int ldr, int* status, hipStream_t s,
+                          const double* ref) {
   if (n > 64) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(chol_upper_inv_kernel, dim3(1), dim3(64), 0, s, G, n, ldg, Rinv, ldr, status);
+  hipLaunchKernelGGL(chol_upper_inv_kernel, dim3(1), dim3(64), 0, s, G, n, ldg, Rinv, ldr, status, ref);
   return hipGetLastError();
 }
 

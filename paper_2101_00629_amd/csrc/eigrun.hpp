@@ -12,7 +12,7 @@ struct EigWork {
   double *X = nullptr, *AX = nullptr, *P = nullptr, *XS = nullptr, *AXS = nullptr, *R = nullptr, *T = nullptr;
   double *H = nullptr, *Hc = nullptr, *C = nullptr, *G = nullptr, *Rinv = nullptr, *theta = nullptr,
          *thetai = nullptr, *S = nullptr, *norms = nullptr, *ework = nullptr, *tnwork = nullptr,
-         *nwork = nullptr, *Wm = nullptr, *Gm = nullptr;
+         *nwork = nullptr, *Wm = nullptr, *Gm = nullptr, *pnorm = nullptr;
   int* status = nullptr;
 };
 

@@ -117,7 +117,7 @@ size_t eig_workspace_bytes(int64_t N, int M, int b) {
   s += al((size_t)m_max * b * 8) + 2 * al((size_t)b * b * 8) + 3 * al((size_t)m_max * 8);
   s += al(std::max({sym_eig_work(m_max), sym_tri_work(m_max), nonsym_eig_work(m_max, std::min(nev + 1, m_max))}) * 8);
   s += al(tn_work_doubles(m_max, b, N) * 8);
-  s += al(column_norms_work(N, ncol) * 8) + al(256);
+  s += al(column_norms_work(N, std::max(ncol, b)) * 8) + al((size_t)b * 8) + al(256);
   return s;
 }
 
@@ -170,11 +170,17 @@ int EigRun::alloc(size_t bytes, double** out) {
 int64_t lambda_doubles(const ka_desc& d, int M) { return d.method == KA_COLLOCATION ? 2 * (int64_t)M : M; }
 
 // Orthonormalise P (N x pw) against X[:, :k] (block CGS twice) and within
-// itself (Cholesky-QR twice).  Rank-deficient blocks are redrawn at random.
+// itself (Cholesky-QR twice).  Rank-deficient blocks are redrawn at random:
+// a column is rank-deficient when what is left of it after the projections
+// is below kOrthKeep of its norm before them (the Krylov space is exhausted
+// along it, and the rest is rounding, which normalisation would blow up into
+// directions not orthogonal to X), or when the Cholesky factorisation of the
+// block's Gram matrix loses a pivot.
 int EigRun::orth_block(int k, int pw) {
   const int64_t N = P_->N;
   for (int attempt = 0; attempt < 4; ++attempt) {
     if (k > 0) {
+      HIP_TRY(column_norms(w_.P, N, pw, N, w_.pnorm, w_.nwork, s_));
       for (int pass = 0; pass < 2; ++pass) {
         HIP_TRY(dgemm_tn(k, pw, N, 1.0, w_.X, N, w_.P, N, 0.0, w_.C, k, w_.tnwork, s_));
         HIP_TRY(dgemm_nn(N, pw, k, -1.0, w_.X, N, w_.C, k, 1.0, w_.P, N, s_));
@@ -184,7 +190,8 @@ int EigRun::orth_block(int k, int pw) {
     // block that fails the first pass is redrawn all the same)
     for (int pass = 0; pass < 2; ++pass) {
       HIP_TRY(dgemm_tn(pw, pw, N, 1.0, w_.P, N, w_.P, N, 0.0, w_.G, pw, w_.tnwork, s_));
-      HIP_TRY(chol_upper_inv(w_.G, pw, pw, w_.Rinv, pw, w_.status + pass, s_));
+      HIP_TRY(chol_upper_inv(w_.G, pw, pw, w_.Rinv, pw, w_.status + pass, s_,
+                             pass == 0 && k > 0 ? w_.pnorm : nullptr));
       HIP_TRY(dgemm_nn(N, pw, pw, 1.0, w_.P, N, w_.Rinv, pw, 0.0, w_.T, N, s_));
       HIP_TRY(copy_cols(w_.T, N, w_.P, N, N, pw, s_));
     }
@@ -241,7 +248,8 @@ int EigRun::start() {
   KA_TRY(alloc((size_t)m * 8, &w_.norms));
   KA_TRY(alloc(std::max({sym_eig_work(m), sym_tri_work(m), nonsym_eig_work(m, std::min(nev_ + 1, m))}) * 8, &w_.ework));
   KA_TRY(alloc(tn_work_doubles(m, b, N) * 8, &w_.tnwork));
-  KA_TRY(alloc(column_norms_work(N, ncol) * 8, &w_.nwork));
+  KA_TRY(alloc(column_norms_work(N, std::max(ncol, b)) * 8, &w_.nwork));
+  KA_TRY(alloc((size_t)b * 8, &w_.pnorm));
   {
     double* st = nullptr;
     KA_TRY(alloc(256, &st));

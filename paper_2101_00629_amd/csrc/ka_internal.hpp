@@ -115,8 +115,10 @@ hipError_t dgemm_tn(int m, int n, int64_t K, double alpha, const double* A, int6
 hipError_t dgemm_nn(int64_t M, int n, int k, double alpha, const double* A, int64_t lda,
                     const double* B, int64_t ldb, double beta, double* C, int64_t ldc, hipStream_t s);
 // Small dense kernels, one workgroup each.
+// ref (optional, n norms): a pivot below (kOrthKeep ref_j)^2 also counts as lost.
+constexpr double kOrthKeep = 1e-9;
 hipError_t chol_upper_inv(const double* G, int n, int ldg, double* Rinv, int ldr, int* status,
-                          hipStream_t s);
+                          hipStream_t s, const double* ref = nullptr);
 hipError_t sym_eig(const double* H, int n, int ldh, double* theta, double* S, int lds, double* work,
                    hipStream_t s);
 size_t sym_eig_work(int n);
