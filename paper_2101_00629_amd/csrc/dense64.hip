@@ -186,71 +186,99 @@ hipError_t dgemm_tn(int m, int n, int64_t K, double alpha, const double* A, int6
 
 // ---------------------------------------------------------------------------
 // C = alpha A B + beta C for tall A (M x k) and small B (k x n): basis
-// updates X C and restarts X S of the block eigensolver.  One workgroup per
-// 16-row tile of C and up to 64 columns (four 16-column MFMA tiles), its 4
-// waves taking interleaved 4-column steps of A (the same fragment layout as
-// the A^T B kernel above; lane l reads A at row l % 16, column 4 s + l / 16, so
-// 16 lanes read 128 contiguous bytes) and summed through LDS in wave order.
+// updates X C, restarts X S and the Cholesky-QR step of the block
+// eigensolver (M = N, k and n up to a few hundred).
+//
+// A workgroup computes 64 rows x 128 columns of C: wave w holds rows
+// 16 w .. 16 w + 15 across eight 16-column MFMA tiles (the MFMA layout of the
+// A^T B kernel above: lane l of the A operand reads A at row l % 16 and
+// column 4 s + l / 16, so 16 lanes read 128 contiguous bytes).  B goes through
+// LDS in chunks of 32 rows, stored row-major with a padded row so that a
+// fragment read (4 rows x 16 columns) touches every bank twice, the least a
+// 64-lane FP64 read can.  While a chunk's MFMAs run, the next chunk of B and
+// the next 8 A values per lane are already loading.
 // ---------------------------------------------------------------------------
-constexpr int kNnU = 4;   // 4-column steps per wave per iteration
+constexpr int kNnJ = 8;                      // 16-column tiles per workgroup
+constexpr int kNnKC = 32;                    // rows of B per LDS chunk
+constexpr int kNnBW = 16 * kNnJ + 16;        // padded LDS row of B (doubles)
+constexpr int kNnSE = kNnKC * 16 * kNnJ / 256;   // staged B elements per thread
 
 __global__ __launch_bounds__(256) void dgemm_nn_mfma_kernel(int64_t M, int n, int k, const double* __restrict__ A,
                                                             int64_t lda, const double* __restrict__ B, int64_t ldb,
                                                             double alpha, double beta, double* __restrict__ C,
                                                             int64_t ldc) {
-  __shared__ double red[3][4][4][64];
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, q = lane >> 4;
-  const int64_t i = (int64_t)blockIdx.x * 16 + (lane & 15);
+  __shared__ double Bs[2][kNnKC][kNnBW];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, q = lane >> 4, c16 = lane & 15;
+  const int64_t r0 = (int64_t)blockIdx.x * 64 + 16 * w;
+  const int64_t i = r0 + c16;
   const bool iok = i < M;
   const double* __restrict__ Ai = A + (iok ? i : M - 1);
-  const int j0 = blockIdx.y * 64;
-  const int jt = (n - j0 + 15) / 16 < 4 ? (n - j0 + 15) / 16 : 4;   // column tiles of this workgroup
-  tn_d4 acc[4];
+  const int j0 = blockIdx.y * 16 * kNnJ;
+  const int jt = (n - j0 + 15) / 16 < kNnJ ? (n - j0 + 15) / 16 : kNnJ;   // column tiles of this workgroup
+  const int nch = (k + kNnKC - 1) / kNnKC;
+  tn_d4 acc[kNnJ];
 #pragma unroll
-  for (int t = 0; t < 4; ++t) acc[t] = (tn_d4){0.0, 0.0, 0.0, 0.0};
-  for (int base = 4 * w; base < k; base += 16 * kNnU) {   // uniform over the wave
-    double a[kNnU], bv[kNnU][4];
+  for (int t = 0; t < kNnJ; ++t) acc[t] = (tn_d4){0.0, 0.0, 0.0, 0.0};
+  double st[kNnSE];
+  auto fetch_b = [&](int c) {                // chunk c of B (zeros past k and n), consecutive threads down a column
 #pragma unroll
-    for (int u = 0; u < kNnU; ++u) {
-      const int kr = base + 16 * u + q;
-      const int kc = kr < k ? kr : k - 1;
-      a[u] = Ai[(int64_t)kc * lda];
-#pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        const int j = j0 + 16 * t + (lane & 15);
-        bv[u][t] = (t < jt) ? B[kc + (int64_t)(j < n ? j : n - 1) * ldb] : 0.0;
-      }
+    for (int v = 0; v < kNnSE; ++v) {
+      const int e = threadIdx.x + 256 * v;
+      const int kk = c * kNnKC + e % kNnKC, j = j0 + e / kNnKC;
+      st[v] = (kk < k && j < n) ? B[kk + (int64_t)j * ldb] : 0.0;
     }
+  };
+  auto put_b = [&](int buf) {
 #pragma unroll
-    for (int u = 0; u < kNnU; ++u) {
-      const int kr = base + 16 * u + q;
-      const double av = (kr < k && iok) ? a[u] : 0.0;
-#pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        if (t >= jt) break;
-        const int j = j0 + 16 * t + (lane & 15);
-        acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, j < n ? bv[u][t] : 0.0, acc[t], 0, 0, 0);
-      }
+    for (int v = 0; v < kNnSE; ++v) {
+      const int e = threadIdx.x + 256 * v;
+      Bs[buf][e % kNnKC][e / kNnKC] = st[v];
     }
-  }
-  if (w > 0)
+  };
+  double a[kNnKC / 4], an[kNnKC / 4];
+  auto fetch_a = [&](int c, double (&x)[kNnKC / 4]) {   // rows past k are read at row k - 1 and weighted by zero
 #pragma unroll
-    for (int t = 0; t < 4; ++t)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) red[w - 1][t][r][lane] = acc[t][r];
+    for (int s = 0; s < kNnKC / 4; ++s) {
+      const int kk = c * kNnKC + 4 * s + q;
+      x[s] = k > 0 ? Ai[(int64_t)(kk < k ? kk : k - 1) * lda] : 0.0;
+    }
+  };
+  fetch_b(0);
+  put_b(0);
+  fetch_a(0, a);
   __syncthreads();
-  if (w > 0) return;
+  for (int c = 0; c < nch; ++c) {            // uniform over the workgroup
+    const int buf = c & 1;
+    if (c + 1 < nch) {
+      fetch_b(c + 1);
+      fetch_a(c + 1, an);
+    }
 #pragma unroll
-  for (int t = 0; t < 4; ++t) {
-    const int jo = j0 + 16 * t + (lane & 15);
+    for (int s = 0; s < kNnKC / 4; ++s) {
+      const int kk = c * kNnKC + 4 * s + q;
+      const double av = (kk < k && iok) ? a[s] : 0.0;
+#pragma unroll
+      for (int t = 0; t < kNnJ; ++t)
+        if (t < jt)
+          acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, Bs[buf][4 * s + q][16 * t + c16], acc[t], 0, 0, 0);
+    }
+    if (c + 1 < nch) {
+      put_b(buf ^ 1);                        // the other buffer: its last readers finished before the barrier
+#pragma unroll
+      for (int s = 0; s < kNnKC / 4; ++s) a[s] = an[s];
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int t = 0; t < kNnJ; ++t) {
+    const int jo = j0 + 16 * t + c16;
     if (t >= jt || jo >= n) continue;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int64_t io = (int64_t)blockIdx.x * 16 + q + 4 * r;
+      const int64_t io = r0 + q + 4 * r;
       if (io >= M) continue;
-      const double v = ((acc[t][r] + red[0][t][r][lane]) + red[1][t][r][lane]) + red[2][t][r][lane];
-      double* c = C + io + (int64_t)jo * ldc;
-      *c = (beta == 0.0) ? alpha * v : alpha * v + beta * *c;
+      double* cp = C + io + (int64_t)jo * ldc;
+      *cp = (beta == 0.0) ? alpha * acc[t][r] : alpha * acc[t][r] + beta * *cp;
     }
   }
 }
@@ -258,7 +286,7 @@ __global__ __launch_bounds__(256) void dgemm_nn_mfma_kernel(int64_t M, int n, in
 hipError_t dgemm_nn(int64_t M, int n, int k, double alpha, const double* A, int64_t lda, const double* B,
                     int64_t ldb, double beta, double* C, int64_t ldc, hipStream_t s) {
   if (M <= 0 || n <= 0) return hipSuccess;
-  const dim3 grid((unsigned)((M + 15) / 16), (n + 63) / 64, 1);
+  const dim3 grid((unsigned)((M + 63) / 64), (n + 16 * kNnJ - 1) / (16 * kNnJ), 1);
   hipLaunchKernelGGL(dgemm_nn_mfma_kernel, grid, dim3(256), 0, s, M, n, k, A, lda, B, ldb, alpha, beta, C, ldc);
   return hipGetLastError();
 }
