@@ -71,6 +71,10 @@ KA_HD inline double sym_copysign(double a, double b) { return b >= 0.0 ? fabs(a)
 // Team interface: tid(), size(), sync(), sum(x) (total over the team, returned to
 // every thread).  v: team-shared scratch of >= n doubles.  A: n x n column-major
 // (may live in fast memory); w: a free column of >= n doubles for the product.
+// elements per thread whose loads the tridiagonalisation issues together
+// (enough in flight to cover the latency of a matrix held in device memory)
+constexpr int kSymBatch = 8;
+
 template <class Team>
 KA_HD void sym_tridiagonalize(Team& tm, double* A, int n, double* d, double* e, double* beta, double* v,
                               double* w) {
@@ -96,16 +100,21 @@ KA_HD void sym_tridiagonalize(Team& tm, double* A, int n, double* d, double* e, 
     tm.sync();
     if (!skip) {
       double* A22 = A + (j + 1) + (size_t)(j + 1) * n;
-      // w = b A22 v  (two partial sums shorten the dependent FMA chain)
+      // w = b A22 v: a thread per row, kSymBatch columns at a time with their
+      // loads issued together (eight partial sums, added in a fixed tree)
       for (int r = t; r < m; r += NT) {
-        double acc0 = 0.0, acc1 = 0.0;
+        const double* row = A22 + r;
+        double acc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
         int c = 0;
-        for (; c + 1 < m; c += 2) {
-          acc0 += A22[r + (size_t)c * n] * v[c];
-          acc1 += A22[r + (size_t)(c + 1) * n] * v[c + 1];
+        for (; c + kSymBatch - 1 < m; c += kSymBatch) {
+          double a[kSymBatch];
+#pragma unroll
+          for (int u = 0; u < kSymBatch; ++u) a[u] = row[(size_t)(c + u) * n];
+#pragma unroll
+          for (int u = 0; u < kSymBatch; ++u) acc[u % 8] += a[u] * v[c + u];
         }
-        if (c < m) acc0 += A22[r + (size_t)c * n] * v[c];
-        w[r] = b * (acc0 + acc1);
+        for (; c < m; ++c) acc[0] += row[(size_t)c * n] * v[c];
+        w[r] = b * (((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7])));
       }
       tm.sync();
       double wv = 0.0;
@@ -114,11 +123,28 @@ KA_HD void sym_tridiagonalize(Team& tm, double* A, int n, double* d, double* e, 
       const double K = 0.5 * b * wv;
       for (int r = t; r < m; r += NT) w[r] -= K * v[r];
       tm.sync();
-      // A22 <- A22 - v w^T - w v^T  (= H A22 H), spread over the whole team,
-      // one element per thread and pass in memory order
-      for (int q = t; q < m * m; q += NT) {
-        const int r = q % m, c = q / m;
-        A22[r + (size_t)c * n] -= v[r] * w[c] + w[r] * v[c];
+      // A22 <- A22 - v w^T - w v^T  (= H A22 H): thread t takes row t % m in
+      // the columns of its group t / m (groups of m threads; the columns of a
+      // row are shared out among the groups), kSymBatch columns at a time with
+      // the loads first, so that consecutive threads touch consecutive rows
+      const int groups = NT >= m ? NT / m : 1;
+      for (int r0 = t; r0 < groups * m; r0 += NT) {   // one pass when NT >= m, else rows r0, r0 + NT, ...
+        const int r = NT >= m ? r0 % m : r0, g = NT >= m ? r0 / m : 0;
+        if (r >= m) continue;
+        double* row = A22 + r;
+        const double vr = v[r], wr = w[r];
+        int c = g;
+        for (; c + (kSymBatch - 1) * groups < m; c += kSymBatch * groups) {
+          double a[kSymBatch];
+#pragma unroll
+          for (int u = 0; u < kSymBatch; ++u) a[u] = row[(size_t)(c + u * groups) * n];
+#pragma unroll
+          for (int u = 0; u < kSymBatch; ++u) {
+            const int cc = c + u * groups;
+            row[(size_t)cc * n] = a[u] - (vr * w[cc] + wr * v[cc]);
+          }
+        }
+        for (; c < m; c += groups) row[(size_t)c * n] -= vr * w[c] + wr * v[c];
       }
     }
     tm.sync();
