@@ -79,7 +79,7 @@ __global__ __launch_bounds__(kNsThreads) void ns_hess_kernel(const double* __res
     for (int i = threadIdx.x; i < n; i += kNsThreads) A[i + (size_t)j * ld] = H[i + (int64_t)j * ldh];
   __syncthreads();
   NsTeam<kNsThreads> tm{red};
-  ns_hessenberg(tm, A, ld, n, ws.hsub, ws.beta, v, w);
+  ns_hessenberg<LDS ? 2 : 8>(tm, A, ld, n, ws.hsub, ws.beta, v, w);
   if (LDS)
     for (int j = 0; j < n; ++j)
       for (int i = threadIdx.x; i < n; i += kNsThreads) ws.A[i + (size_t)j * n] = A[i + (size_t)j * ld];

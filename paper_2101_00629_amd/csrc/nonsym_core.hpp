@@ -78,7 +78,10 @@ KA_HD inline double ns_cabs(double a, double b) { return sqrt(a * a + b * b); }
 // ---- stage 1: Hessenberg reduction by a team ---------------------------------------------
 // A: n x n with leading dimension ld (fast memory if available).  v, w: team
 // scratch of >= n doubles each.  Team interface as in sym_core.hpp.
-template <class Team>
+// loads per thread that the Hessenberg reduction issues together: 8 where A
+// lives in device memory, 2 where it is in LDS (there more only costs
+// registers)
+template <int kNsBatch = 8, class Team>
 KA_HD void ns_hessenberg(Team& tm, double* A, int ld, int n, double* hsub, double* beta, double* v, double* w) {
   const int t = tm.tid(), NT = tm.size();
 #define AH(i, j) A[(i) + (size_t)(j) * ld]
@@ -99,42 +102,78 @@ KA_HD void ns_hessenberg(Team& tm, double* A, int ld, int n, double* hsub, doubl
     }
     tm.sync();
     if (!skip) {
-      // left: A[j+1:, c] -= b v (v^T A[j+1:, c]) for c > j
+      // Each loop below issues kNsBatch loads per thread together, so that
+      // enough are in flight when A lives in device memory; the dot products
+      // keep eight partial sums added in a fixed tree.
+      // left: A[j+1:, c] -= b v (v^T A[j+1:, c]) for c > j (a thread per column)
       for (int c = j + 1 + t; c < n; c += NT) {
-        double s0 = 0.0, s1 = 0.0;
+        const double* col = &AH(j + 1, c);
+        double acc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
         int i = 0;
-        for (; i + 1 < m; i += 2) {
-          s0 += v[i] * AH(j + 1 + i, c);
-          s1 += v[i + 1] * AH(j + 2 + i, c);
+        for (; i + kNsBatch - 1 < m; i += kNsBatch) {
+          double a[kNsBatch];
+#pragma unroll
+          for (int u = 0; u < kNsBatch; ++u) a[u] = col[i + u];
+#pragma unroll
+          for (int u = 0; u < kNsBatch; ++u) acc[u % 8] += v[i + u] * a[u];
         }
-        if (i < m) s0 += v[i] * AH(j + 1 + i, c);
-        w[c] = b * (s0 + s1);
+        for (; i < m; ++i) acc[0] += v[i] * col[i];
+        w[c] = b * (((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7])));
       }
       tm.sync();
-      // the rank-one updates are spread over the whole team, one element per
-      // thread and pass, in memory order (each element takes the same single
-      // update as in a row-by-row loop)
-      const int nc = n - j - 1;
-      for (int e = t; e < m * nc; e += NT) {
-        const int i = e % m, c = j + 1 + e / m;
-        AH(j + 1 + i, c) -= w[c] * v[i];
+      // the rank-one updates: thread t takes row t % (rows) in the columns of
+      // its group t / (rows), so that consecutive threads touch consecutive
+      // rows (each element takes the same single update as in a row-by-row loop)
+      {
+        const int nc = n - j - 1, groups = NT >= m ? NT / m : 1;
+        for (int r0 = t; r0 < (NT >= m ? groups * m : m); r0 += NT) {
+          const int i = NT >= m ? r0 % m : r0, g = NT >= m ? r0 / m : 0;
+          double* row = &AH(j + 1 + i, j + 1);
+          const double vi = v[i];
+          int c = g;
+          for (; c + (kNsBatch - 1) * groups < nc; c += kNsBatch * groups) {
+            double a[kNsBatch];
+#pragma unroll
+            for (int u = 0; u < kNsBatch; ++u) a[u] = row[(size_t)(c + u * groups) * ld];
+#pragma unroll
+            for (int u = 0; u < kNsBatch; ++u) row[(size_t)(c + u * groups) * ld] = a[u] - w[j + 1 + c + u * groups] * vi;
+          }
+          for (; c < nc; c += groups) row[(size_t)c * ld] -= w[j + 1 + c] * vi;
+        }
       }
       tm.sync();
-      // right: A[r, j+1:] -= b (A[r, j+1:] v) v^T for every row
+      // right: A[r, j+1:] -= b (A[r, j+1:] v) v^T for every row (a thread per row)
       for (int r = t; r < n; r += NT) {
-        double s0 = 0.0, s1 = 0.0;
+        const double* row = &AH(r, j + 1);
+        double acc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
         int i = 0;
-        for (; i + 1 < m; i += 2) {
-          s0 += AH(r, j + 1 + i) * v[i];
-          s1 += AH(r, j + 2 + i) * v[i + 1];
+        for (; i + kNsBatch - 1 < m; i += kNsBatch) {
+          double a[kNsBatch];
+#pragma unroll
+          for (int u = 0; u < kNsBatch; ++u) a[u] = row[(size_t)(i + u) * ld];
+#pragma unroll
+          for (int u = 0; u < kNsBatch; ++u) acc[u % 8] += a[u] * v[i + u];
         }
-        if (i < m) s0 += AH(r, j + 1 + i) * v[i];
-        w[r] = b * (s0 + s1);
+        for (; i < m; ++i) acc[0] += row[(size_t)i * ld] * v[i];
+        w[r] = b * (((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7])));
       }
       tm.sync();
-      for (int e = t; e < n * m; e += NT) {
-        const int r = e % n, i = e / n;
-        AH(r, j + 1 + i) -= w[r] * v[i];
+      {
+        const int groups = NT >= n ? NT / n : 1;
+        for (int r0 = t; r0 < (NT >= n ? groups * n : n); r0 += NT) {
+          const int r = NT >= n ? r0 % n : r0, g = NT >= n ? r0 / n : 0;
+          double* row = &AH(r, j + 1);
+          const double wr = w[r];
+          int i = g;
+          for (; i + (kNsBatch - 1) * groups < m; i += kNsBatch * groups) {
+            double a[kNsBatch];
+#pragma unroll
+            for (int u = 0; u < kNsBatch; ++u) a[u] = row[(size_t)(i + u * groups) * ld];
+#pragma unroll
+            for (int u = 0; u < kNsBatch; ++u) row[(size_t)(i + u * groups) * ld] = a[u] - wr * v[i + u * groups];
+          }
+          for (; i < m; i += groups) row[(size_t)i * ld] -= wr * v[i];
+        }
       }
     }
     tm.sync();
