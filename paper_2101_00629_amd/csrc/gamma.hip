@@ -556,6 +556,8 @@ static int rows_per_block(int b, int precision) {
   return 4 * 16 * (b == 64 ? 2 : 4);
 }
 
+constexpr int64_t kMinSplitCols = 512;
+
 GammaPlan gamma_plan(int64_t nr, int64_t nc, int b, int precision) {
   GammaPlan p;
   p.rows_per_block = rows_per_block(b, precision);
@@ -569,11 +571,13 @@ GammaPlan gamma_plan(int64_t nr, int64_t nc, int b, int precision) {
     p.work_bytes = 0;
     return p;
   }
-  // Fill the chip: aim for >= 2048 workgroups, but keep >= 2048 columns per
-  // split so the partial-sum traffic stays small next to the pair work.
+  // Fill the chip: aim for >= 2048 workgroups, but keep >= kMinSplitCols
+  // columns per split so the partial-sum traffic stays small next to the pair
+  // work (a split's partial sums are b floats per row; its pairs are
+  // kMinSplitCols per row at least).
   const int64_t target = 2048;
   int64_t ns = (target + p.row_blocks - 1) / p.row_blocks;
-  const int64_t max_by_cols = nc / 2048;
+  const int64_t max_by_cols = nc / kMinSplitCols;
   if (ns > max_by_cols) ns = max_by_cols;
   if (ns > 64) ns = 64;
   if (ns < 1) ns = 1;
