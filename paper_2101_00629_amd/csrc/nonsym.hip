@@ -86,9 +86,8 @@ __global__ __launch_bounds__(kNsThreads) void ns_hess_kernel(const double* __res
 }
 
 // ---- eigenvalue QR by one wave, matrix in LDS --------------------------------------------
-// The Francis double-shift iteration of ns_qr_values (nonsym_core.hpp),
-// arranged for the 64 lanes of one wave (the reflector's reciprocals by
-// ns_recip, the rest the same arithmetic):
+// The Francis double-shift iteration of ns_qr_values (nonsym_core.hpp, the
+// same arithmetic), arranged for the 64 lanes of one wave:
 //  - the two searches of each iteration (the negligible sub-diagonal that
 //    splits the active window, and the start m of the double step) test 64
 //    positions at once and take the first hit with a ballot, instead of a
@@ -101,6 +100,10 @@ __global__ __launch_bounds__(kNsThreads) void ns_hess_kernel(const double* __res
 // LDS operations of one wave complete in issue order, so ordering between
 // the phases needs only a compiler fence at wavefront scope (no wait).
 constexpr int kNsQrIt = (kNsBandLds + 63) / 64;   // lane iterations over a window of <= kNsBandLds
+
+// s_waitcnt operand with lgkmcnt = 0 and the other counters at their
+// maximum (no wait): all LDS operations of the wave have completed
+constexpr int kNsWaitLds = 0xC07F;
 
 __device__ inline void ns_wave_fence() { __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront"); }
 
@@ -251,35 +254,34 @@ __device__ KA_FORCEINLINE int ns_qr_values_wave(double* hb, int n, double* wr, d
 #define NS_LANE(idx) ns_lane_value(c[0], c[1], c[2], (idx))
       for (int k = m; k <= nn - 1; ++k) {
         const bool notlast = (k != nn - 1);
-        double xx = 0.0;
         if (k != m) {
           p = NS_LANE(k - l);
           q = NS_LANE(k + 1 - l);
           r = notlast ? NS_LANE(k + 2 - l) : 0.0;
-          xx = fabs(p) + fabs(q) + fabs(r);
-          if (xx != 0.0) {
-            const double ixx = ns_recip(xx);
-            p *= ixx;
-            q *= ixx;
-            r *= ixx;
-          }
         }
-        const double s = ns_sgn(sqrt(p * p + q * q + r * r), p);
+        const NsHouse h = ns_house3(p, q, r);
+        p = h.p;
+        q = h.q;
+        r = h.r;
+        const double s = h.s;
         const int imax = (nn < k + 3) ? nn : k + 3;
         if (s == 0.0) {
-          // no reflection at this step: the next one reads column k from memory
+          // no reflection at this step: the next one reads column k from
+          // memory.  The loads are waited for here, on this rare path, so
+          // that the loop head does not wait for all LDS operations.
 #pragma unroll
           for (int it = 0; it < kNsQrIt; ++it) {
             const int i = l + t + 64 * it;
             if (i <= imax) c[it] = HB(i, k);
           }
+          __builtin_amdgcn_s_waitcnt(kNsWaitLds);
           continue;
         }
         if (t == 0) {
           if (k == m) {
             if (l != m) HB(k, k - 1) = -HB(k, k - 1);
           } else {
-            HB(k, k - 1) = -s * xx;
+            HB(k, k - 1) = ldexp(-s, h.e);
           }
         }
         const double pp = p + s;
@@ -355,10 +357,12 @@ __global__ __launch_bounds__(64) void ns_qr_kernel(double* __restrict__ work, in
 
 // ---- eigenvalue QR from order kNsMsFrom: multishift sweeps by one workgroup ----------------
 // ns_ms_run (nonsym_core.hpp) with a team of one wave per bulge.  The band
-// lives in LDS up to order kNsMsLds (with the sweep scratch, 162.1 KB of the
-// 160 KiB); above that it starts in the work buffer and moves to LDS once the
-// deflations have shrunk the leading block to that order.  Wave 0 computes
-// each sweep's shifts with the one-wave loop above on the trailing block.
+// lives in LDS up to order kNsMsLds (with the sweep scratch, 162.2 KB of the
+// 160 KiB).  Above that its columns below kNsMsLds are in LDS and the rest in
+// the work buffer (NsSplitBand: accesses through generic pointers) until the
+// deflations have shrunk the leading block to that order; from then on it is
+// all in LDS.  Wave 0 computes each sweep's shifts with the one-wave loop
+// above on the trailing block.
 constexpr int kNsMsThreads = 64 * kNsMsBulges;
 constexpr int kNsMsLds = 196;
 
@@ -388,20 +392,21 @@ __global__ __launch_bounds__(kNsMsThreads) void ns_qr_ms_kernel(double* __restri
   if (LDS) {
     ns_band_fill(tm, ws.A, n, ws.hsub, n, band, ws.HT);
     __syncthreads();
-    const double anorm = ns_band_norm(tm, band, n);
-    fail = ns_ms_run(tm, band, nn, shift, anorm, -1, ws.wr0, ws.wi0, scr, small);
+    const double anorm = ns_band_norm(tm, NsBand{band}, n);
+    fail = ns_ms_run(tm, NsBand{band}, nn, shift, anorm, -1, ws.wr0, ws.wi0, scr, small);
     if (threadIdx.x == 0) ws.misc[0] = anorm;
   } else {
-    // in the work buffer until the leading block fits the LDS band, then there
+    // columns below kNsMsLds in LDS, the rest in the work buffer, until the
+    // deflations have shrunk the leading block to fit the LDS band
     ns_band_fill(tm, ws.A, n, ws.hsub, n, ws.HB, ws.HT);
     __syncthreads();
-    const double anorm = ns_band_norm(tm, ws.HB, n);
-    fail = ns_ms_run(tm, ws.HB, nn, shift, anorm, kNsMsLds - 1, ws.wr0, ws.wi0, scr, small);
-    if (!fail) {
-      const int cnt = (nn + 1) * (nn + 8) / 2;
-      for (int e = threadIdx.x; e < cnt; e += kNsMsThreads) band[e] = ws.HB[e];
-      fail = ns_ms_run(tm, band, nn, shift, anorm, -1, ws.wr0, ws.wi0, scr, small);
-    }
+    const double anorm = ns_band_norm(tm, NsBand{ws.HB}, n);
+    const int cnt = kNsMsLds * (kNsMsLds + 7) / 2;
+    for (int e = threadIdx.x; e < cnt; e += kNsMsThreads) band[e] = ws.HB[e];
+    __syncthreads();
+    fail = ns_ms_run(tm, NsSplitBand{band, ws.HB, kNsMsLds}, nn, shift, anorm, kNsMsLds - 1, ws.wr0, ws.wi0, scr,
+                     small);
+    if (!fail) fail = ns_ms_run(tm, NsBand{band}, nn, shift, anorm, -1, ws.wr0, ws.wi0, scr, small);
     if (threadIdx.x == 0) ws.misc[0] = anorm;
   }
   if (threadIdx.x == 0) ws.misc[1] = fail;

@@ -75,6 +75,61 @@ KA_HD inline NsWork ns_work_split(double* w, int n, int nv) {
 KA_HD inline double ns_sgn(double a, double b) { return b >= 0.0 ? fabs(a) : -fabs(a); }
 KA_HD inline double ns_cabs(double a, double b) { return sqrt(a * a + b * b); }
 
+// reciprocal for the reflector coefficients: two Newton steps on the
+// hardware estimate on the device, a division on the host
+KA_HD inline double ns_recip(double x) {
+#ifdef __HIP_DEVICE_COMPILE__
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(fma(-x, r, 1.0), r, r);
+  return fma(fma(-x, r, 1.0), r, r);
+#else
+  return 1.0 / x;
+#endif
+}
+
+// square root of x in [1/16, 4] (no scaling or special cases needed there):
+// on the device the hardware reciprocal square root estimate refined by the
+// coupled Newton iteration for sqrt(x) and 1/(2 sqrt(x)) (Markstein), one
+// step for both and two more for the root; a library call on the host
+KA_HD inline double ns_sqrt_mid(double x) {
+#ifdef __HIP_DEVICE_COMPILE__
+  const double y = __builtin_amdgcn_rsq(x);
+  double g = x * y, h = 0.5 * y;
+  const double e = fma(-h, g, 0.5);
+  g = fma(g, e, g);
+  h = fma(h, e, h);
+  g = fma(fma(-g, g, x), h, g);
+  return fma(fma(-g, g, x), h, g);
+#else
+  return sqrt(x);
+#endif
+}
+
+// The 3 x 3 Householder data of a double-shift step from the vector
+// (v0, v1, v2): the vector scaled by the power of two 2^-e that brings its
+// largest magnitude into [1/2, 1) (exact; the reflection does not depend on
+// the scale), s = +-||(p, q, r)|| with the sign of p (0 if the vector is
+// zero), and e, so that the reflection leaves -s 2^e in the first entry.
+struct NsHouse {
+  double p, q, r, s;
+  int e;
+};
+KA_HD inline NsHouse ns_house3(double v0, double v1, double v2) {
+  const double m = fmax(fmax(fabs(v0), fabs(v1)), fabs(v2));
+  NsHouse h{0.0, 0.0, 0.0, 0.0, 0};
+  if (m == 0.0) return h;
+#ifdef __HIP_DEVICE_COMPILE__
+  h.e = __builtin_amdgcn_frexp_exp(m);
+#else
+  frexp(m, &h.e);
+#endif
+  h.p = ldexp(v0, -h.e);
+  h.q = ldexp(v1, -h.e);
+  h.r = ldexp(v2, -h.e);
+  h.s = ns_sgn(ns_sqrt_mid(h.p * h.p + h.q * h.q + h.r * h.r), h.p);
+  return h;
+}
+
 // ---- stage 1: Hessenberg reduction by a team ---------------------------------------------
 // A: n x n with leading dimension ld (fast memory if available).  v, w: team
 // scratch of >= n doubles each.  Team interface as in sym_core.hpp.
@@ -190,6 +245,37 @@ KA_HD void ns_hessenberg(Team& tm, double* A, int ld, int n, double* hsub, doubl
 // (the sub-diagonal, the two bulge diagonals and the upper triangle).
 KA_HD inline size_t ns_band_index(int i, int j) { return (size_t)j * (j + 7) / 2 + i; }
 
+// Band storage as the QR stages see it: entry (i, j) at col(j)[i].  NsBand is
+// one array; NsSplitBand keeps the columns below `cut` in one array (LDS on
+// the device) and the rest in another (device memory), both at the packed
+// index above, so the columns below `cut` need no copy when the band moves
+// wholly into the first array.  base(): the first array; contig(): the order
+// of the leading block it holds in plain band layout.
+// Columns below contig() are in the first array, the others in the second;
+// first_col(j) and second_col(j) give a column's storage as a pointer derived
+// from that array alone, so that code using only such pointers is compiled for
+// that array's address space.
+struct NsBand {
+  static constexpr bool kSplit = false;
+  double* p;
+  KA_HD double* col(int j) const { return p + ns_band_index(0, j); }
+  KA_HD double* base() const { return p; }
+  KA_HD int contig() const { return 1 << 30; }
+  KA_HD double* first_col(int j) const { return p + ns_band_index(0, j); }
+  KA_HD double* second_col(int j) const { return p + ns_band_index(0, j); }
+};
+struct NsSplitBand {
+  static constexpr bool kSplit = true;
+  double* lo;
+  double* hi;
+  int cut;
+  KA_HD double* col(int j) const { return (j < cut ? lo : hi) + ns_band_index(0, j); }
+  KA_HD double* base() const { return lo; }
+  KA_HD int contig() const { return cut; }
+  KA_HD double* first_col(int j) const { return lo + ns_band_index(0, j); }
+  KA_HD double* second_col(int j) const { return hi + ns_band_index(0, j); }
+};
+
 // Fill the banded copy (and, if given, the row-major copy HT) from stage 1's
 // output (team, then sync by the caller).
 template <class Team>
@@ -225,10 +311,10 @@ KA_HD inline bool ns_exceptional_top(int its) { return its >= 30 && (its / 10) %
 // pair, or the exceptional values.  The step starts at the largest m in
 // [l, nn-2] below which two consecutive sub-diagonal entries are small
 // enough, else at l, and chases one 3x3 bulge to the bottom.
-template <class Team>
-KA_HD void ns_ds_iteration(Team& tm, double* hb, int l, int nn, double x, double y, double w) {
+template <class Team, class Band>
+KA_HD void ns_ds_iteration(Team& tm, const Band& B, int l, int nn, double x, double y, double w) {
   const int t = tm.tid(), NT = tm.size();
-#define HB(i, j) hb[ns_band_index((i), (j))]
+#define HB(i, j) (B.col(j)[i])
   int m;
   double p = 0.0, q = 0.0, r = 0.0, z = 0.0;
   for (m = nn - 2; m >= l; --m) {
@@ -256,31 +342,27 @@ KA_HD void ns_ds_iteration(Team& tm, double* hb, int l, int nn, double x, double
   // bulge chase over the active window [l, nn]
   for (int k = m; k <= nn - 1; ++k) {
     const bool notlast = (k != nn - 1);
-    double xx = 0.0;
     if (k != m) {
       p = HB(k, k - 1);
       q = HB(k + 1, k - 1);
       r = notlast ? HB(k + 2, k - 1) : 0.0;
-      xx = fabs(p) + fabs(q) + fabs(r);
-      if (xx != 0.0) {
-        const double ixx = 1.0 / xx;
-        p *= ixx;
-        q *= ixx;
-        r *= ixx;
-      }
     }
-    const double s = ns_sgn(sqrt(p * p + q * q + r * r), p);
+    const NsHouse h = ns_house3(p, q, r);
+    p = h.p;
+    q = h.q;
+    r = h.r;
+    const double s = h.s;
     tm.sync();
     if (s == 0.0) continue;
     if (t == 0) {
       if (k == m) {
         if (l != m) HB(k, k - 1) = -HB(k, k - 1);
       } else {
-        HB(k, k - 1) = -s * xx;
+        HB(k, k - 1) = ldexp(-s, h.e);
       }
     }
     const double pp = p + s;
-    const double is = 1.0 / s, ipp = 1.0 / pp;
+    const double is = ns_recip(s), ipp = ns_recip(pp);
     const double x1 = pp * is, y1 = q * is, z1 = r * is;
     const double q1 = q * ipp, r1 = r * ipp;
     for (int j = k + t; j <= nn; j += NT) {
@@ -383,7 +465,7 @@ KA_HD int ns_qr_values(Team& tm, double* hb, int n, double* wr, double* wi, doub
         w = -0.4375 * s * s;
       }
       ++its;
-      ns_ds_iteration(tm, hb, l, nn, x, y, w);
+      ns_ds_iteration(tm, NsBand{hb}, l, nn, x, y, w);
     }
   }
   tm.sync();
@@ -425,28 +507,16 @@ KA_HD constexpr size_t ns_ms_scratch_doubles() {
   return ns_band_doubles(kNsMsMax) + 2 * kNsMsMax + 2 * 8 * kNsMsBulges + 8;
 }
 
-// reciprocal for the reflector coefficients: two Newton steps on the
-// hardware estimate on the device, a division on the host
-KA_HD inline double ns_recip(double x) {
-#ifdef __HIP_DEVICE_COMPILE__
-  double r = __builtin_amdgcn_rcp(x);
-  r = fma(fma(-x, r, 1.0), r, r);
-  return fma(fma(-x, r, 1.0), r, r);
-#else
-  return 1.0 / x;
-#endif
-}
-
 // largest l in [1, nn] with a negligible sub-diagonal H(l, l-1), else 0
 // (each thread scans its own positions from the top, then a team maximum)
-template <class Team>
-KA_HD int ns_find_split(Team& tm, const double* hb, int nn, double anorm) {
+template <class Team, class Band>
+KA_HD int ns_find_split(Team& tm, const Band& B, int nn, double anorm) {
   const int t = tm.tid(), NT = tm.size();
   int best = 0;
   for (int l0 = nn - t; l0 >= 1; l0 -= NT) {
-    double s = fabs(hb[ns_band_index(l0 - 1, l0 - 1)]) + fabs(hb[ns_band_index(l0, l0)]);
+    double s = fabs(B.col(l0 - 1)[l0 - 1]) + fabs(B.col(l0)[l0]);
     if (s == 0.0) s = anorm;
-    if (fabs(hb[ns_band_index(l0, l0 - 1)]) <= kNsEps * s) {
+    if (fabs(B.col(l0 - 1)[l0]) <= kNsEps * s) {
       best = l0;
       break;
     }
@@ -483,11 +553,12 @@ KA_HD inline void ns_pair_shifts(double* sr, double* si, int ns) {
 // First column of (H - s1 I)(H - s2 I) at the top of the window, rows l..l+2,
 // up to a positive factor (divided by |h00 - s2| + |Im s2| + |h10| against
 // overflow); s1, s2 both real or a conjugate pair.
-KA_HD inline void ns_ms_first_column(const double* hb, int l, double sr1, double si1, double sr2, double si2,
+template <class Band>
+KA_HD inline void ns_ms_first_column(const Band& B, int l, double sr1, double si1, double sr2, double si2,
                                      double* v) {
-  const double h00 = hb[ns_band_index(l, l)], h10 = hb[ns_band_index(l + 1, l)];
-  const double h01 = hb[ns_band_index(l, l + 1)], h11 = hb[ns_band_index(l + 1, l + 1)];
-  const double h21 = hb[ns_band_index(l + 2, l + 1)];
+  const double h00 = B.col(l)[l], h10 = B.col(l)[l + 1];
+  const double h01 = B.col(l + 1)[l], h11 = B.col(l + 1)[l + 1];
+  const double h21 = B.col(l + 1)[l + 2];
   const double s = fabs(h00 - sr2) + fabs(si2) + fabs(h10);
   if (s == 0.0) {
     v[0] = v[1] = v[2] = 0.0;
@@ -502,33 +573,32 @@ KA_HD inline void ns_ms_first_column(const double* hb, int l, double sr1, double
 // Reflector of a bulge at step k from v = the entries (k..k+2, k-1), or at
 // k = l from the shift polynomial's first column: R[0] = 1 if there is a
 // reflection, R[1..5] = the coefficients of the row and column updates.  For
-// k > l the column k-1 is set to what the reflection leaves (-s xx, 0, 0).
+// k > l the column k-1 is set to what the reflection leaves (-s 2^e, 0, 0).
 // (computed by every thread of a group from the same values; only the one
 // with store set writes the matrix and the table entry R)
 struct NsRefl {
   double f, x1, y1, z1, q1, r1;   // f = 1 if there is a reflection
 };
-KA_HD inline NsRefl ns_ms_reflector_g(double* hb, int l, int nn, int k, double v0, double v1, double v2, double* R,
+template <class Band>
+KA_HD inline NsRefl ns_ms_reflector_g(const Band& B, int l, int nn, int k, double v0, double v1, double v2, double* R,
                                       bool store) {
   const bool notlast = k != nn - 1;
   if (!notlast) v2 = 0.0;
   NsRefl c{0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-  const double xx = fabs(v0) + fabs(v1) + fabs(v2);
-  if (xx == 0.0) {
+  const NsHouse h = ns_house3(v0, v1, v2);
+  if (h.s == 0.0) {
     if (store) R[0] = 0.0;
     return c;
   }
-  const double ixx = ns_recip(xx);
-  const double p = v0 * ixx, q = v1 * ixx, r = v2 * ixx;
-  const double s = ns_sgn(sqrt(p * p + q * q + r * r), p);
-  const double pp = p + s;
-  const double is = ns_recip(s), ipp = ns_recip(pp);
-  c = NsRefl{1.0, pp * is, q * is, r * is, q * ipp, r * ipp};
+  const double pp = h.p + h.s;
+  const double is = ns_recip(h.s), ipp = ns_recip(pp);
+  c = NsRefl{1.0, pp * is, h.q * is, h.r * is, h.q * ipp, h.r * ipp};
   if (store) {
     if (k > l) {
-      hb[ns_band_index(k, k - 1)] = -s * xx;
-      hb[ns_band_index(k + 1, k - 1)] = 0.0;
-      if (notlast) hb[ns_band_index(k + 2, k - 1)] = 0.0;
+      double* c = B.col(k - 1);
+      c[k] = ldexp(-h.s, h.e);
+      c[k + 1] = 0.0;
+      if (notlast) c[k + 2] = 0.0;
     }
     R[0] = c.f;
     R[1] = c.x1;
@@ -553,15 +623,18 @@ KA_HD inline NsRefl ns_ms_reflector_g(double* hb, int l, int nn, int k, double v
 //    (k+1..k+3, k) it has just computed, picked from the threads that hold
 //    them (every thread of the group computes it, the first one stores it).
 // A group's threads run over consecutive columns (rows phase) or rows
-// (columns phase), four at a time with the loads first.  A group with a
+// (columns phase), four at a time with the loads first.  On the last step
+// (k = nn-1) the third row or column is a copy of the second with weight 0
+// (the reflector has r = 0), so that the arithmetic has no branch and every
+// load is issued with the others; only its store is skipped.  A group with a
 // single bulge (every group on the device) keeps its coefficients in
 // registers; otherwise they come from the table.
-template <class Team>
-KA_HD void ns_ms_sweep(Team& tm, double* hb, int l, int nn, const double* sr, const double* si, int nb, double* rt) {
+template <class Team, class Band>
+KA_HD void ns_ms_sweep(Team& tm, const Band& B, int l, int nn, const double* sr, const double* si, int nb, double* rt) {
   const int t = tm.tid(), NT = tm.size(), G = tm.gsize();
   const int grp = tm.group(), lane = t - grp * G, ngrp = NT / G;
   const bool own = ngrp >= nb;
-#define HB(i, j) hb[ns_band_index((i), (j))]
+#define HB(i, j) (B.col(j)[i])
   for (int i = l + 2 + t; i <= nn; i += NT) {
     HB(i, i - 2) = 0.0;
     if (i >= l + 3) HB(i, i - 3) = 0.0;
@@ -570,9 +643,9 @@ KA_HD void ns_ms_sweep(Team& tm, double* hb, int l, int nn, const double* sr, co
   NsRefl mine{0.0, 0.0, 0.0, 0.0, 0.0, 0.0};           // this round's reflector of the group's bulge (own)
   if (grp == 0) {
     double v[3];
-    ns_ms_first_column(hb, l, sr[0], si[0], sr[1], si[1], v);
+    ns_ms_first_column(B, l, sr[0], si[0], sr[1], si[1], v);
     tm.gsync();
-    mine = ns_ms_reflector_g(hb, l, nn, l, v[0], v[1], v[2], rt, lane == 0);
+    mine = ns_ms_reflector_g(B, l, nn, l, v[0], v[1], v[2], rt, lane == 0);
   }
   const int rounds = 3 * (nb - 1) + (nn - l);
   for (int rd = 0; rd < rounds; ++rd) {
@@ -586,29 +659,54 @@ KA_HD void ns_ms_sweep(Team& tm, double* hb, int l, int nn, const double* sr, co
       if (c.f == 0.0) continue;
       const bool notlast = k != nn - 1;
       const int k2 = notlast ? k + 2 : k + 1;
-      for (int j0 = k + lane; j0 <= nn; j0 += 4 * G) {
-        double a0[4], a1[4], a2[4];
-        double* col[4];
+      auto rowupd = [&](int ja, int jb, auto colf) {   // columns ja..jb, all in one array
+        for (int j0 = ja + lane; j0 <= jb; j0 += 4 * G) {
+          double a0[4], a1[4], a2[4];
+          double* col[4];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int j = j0 + u * G <= nn ? j0 + u * G : nn;
-          col[u] = hb + ns_band_index(0, j);
-          a0[u] = col[u][k];
-          a1[u] = col[u][k + 1];
-          a2[u] = col[u][k2];
-        }
+          for (int u = 0; u < 4; ++u) {
+            const int j = j0 + u * G <= jb ? j0 + u * G : jb;
+            col[u] = colf(j);
+            a0[u] = col[u][k];
+            a1[u] = col[u][k + 1];
+            a2[u] = col[u][k2];
+          }
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          if (j0 + u * G <= nn) {
-            double pv = a0[u] + c.q1 * a1[u];
-            if (notlast) {
-              pv += c.r1 * a2[u];
-              col[u][k + 2] = a2[u] - pv * c.z1;
+          for (int u = 0; u < 4; ++u) {
+            const double pv = a0[u] + c.q1 * a1[u] + c.r1 * a2[u];   // r1 = 0 on the last step
+            if (j0 + u * G <= jb) {
+              if (notlast) col[u][k + 2] = a2[u] - pv * c.z1;
+              col[u][k + 1] = a1[u] - pv * c.y1;
+              col[u][k] = a0[u] - pv * c.x1;
             }
-            col[u][k + 1] = a1[u] - pv * c.y1;
-            col[u][k] = a0[u] - pv * c.x1;
           }
         }
+      };
+      if constexpr (Band::kSplit) {
+        // the first G columns in the second array are loaded before the
+        // columns in the first, so that their (longer) latency overlaps
+        const int cut = B.contig(), ga = k > cut ? k : cut;
+        const bool hasg = nn >= ga;
+        double g0 = 0.0, g1 = 0.0, g2 = 0.0;
+        double* gc = nullptr;
+        if (hasg) {
+          gc = B.second_col(ga + lane <= nn ? ga + lane : nn);
+          g0 = gc[k];
+          g1 = gc[k + 1];
+          g2 = gc[k2];
+        }
+        if (k < cut) rowupd(k, nn < cut ? nn : cut - 1, [&](int j) { return B.first_col(j); });
+        if (hasg) {
+          if (ga + lane <= nn) {
+            const double pv = g0 + c.q1 * g1 + c.r1 * g2;
+            if (notlast) gc[k + 2] = g2 - pv * c.z1;
+            gc[k + 1] = g1 - pv * c.y1;
+            gc[k] = g0 - pv * c.x1;
+          }
+          if (nn >= ga + G) rowupd(ga + G, nn, [&](int j) { return B.second_col(j); });
+        }
+      } else {
+        rowupd(k, nn, [&](int j) { return B.col(j); });
       }
     }
     tm.sync();
@@ -620,53 +718,59 @@ KA_HD void ns_ms_sweep(Team& tm, double* hb, int l, int nn, const double* sr, co
       if (upd) {
         const bool notlast = k != nn - 1;
         const int imax = nn < k + 3 ? nn : k + 3;
-        double* c0 = hb + ns_band_index(0, k);          // the three columns (uniform in a group)
-        double* c1 = hb + ns_band_index(0, k + 1);
-        double* c2 = hb + ns_band_index(0, notlast ? k + 2 : k + 1);
-        for (int i0 = l + lane; i0 <= imax; i0 += 4 * G) {
-          double a0[4], a1[4], a2[4];
+        const int k2 = notlast ? k + 2 : k + 1;
+        auto colupd = [&](double* c0, double* c1, double* c2) {   // the three columns (uniform in a group)
+          for (int i0 = l + lane; i0 <= imax; i0 += 4 * G) {
+            double a0[4], a1[4], a2[4];
 #pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            const int i = i0 + u * G <= imax ? i0 + u * G : imax;
-            a0[u] = c0[i];
-            a1[u] = c1[i];
-            a2[u] = c2[i];
-          }
+            for (int u = 0; u < 4; ++u) {
+              const int i = i0 + u * G <= imax ? i0 + u * G : imax;
+              a0[u] = c0[i];
+              a1[u] = c1[i];
+              a2[u] = c2[i];
+            }
 #pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            const int i = i0 + u * G;
-            if (i <= imax) {
-              double pv = c.x1 * a0[u] + c.y1 * a1[u];
-              if (notlast) {
-                pv += c.z1 * a2[u];
-                c2[i] = a2[u] - pv * c.r1;
+            for (int u = 0; u < 4; ++u) {
+              const int i = i0 + u * G;
+              const double pv = c.x1 * a0[u] + c.y1 * a1[u] + c.z1 * a2[u];   // z1 = 0 on the last step
+              if (i <= imax) {
+                if (notlast) c2[i] = a2[u] - pv * c.r1;
+                c1[i] = a1[u] - pv * c.q1;
+                const double h = a0[u] - pv;
+                c0[i] = h;
+                keep0 = i == k + 1 ? h : keep0;
+                keep1 = i == k + 2 ? h : keep1;
+                keep2 = i == k + 3 ? h : keep2;
               }
-              c1[i] = a1[u] - pv * c.q1;
-              const double h = a0[u] - pv;
-              c0[i] = h;
-              keep0 = i == k + 1 ? h : keep0;
-              keep1 = i == k + 2 ? h : keep1;
-              keep2 = i == k + 3 ? h : keep2;
             }
           }
-        }
+        };
+        if (!Band::kSplit || k2 < B.contig())
+          colupd(B.first_col(k), B.first_col(k + 1), B.first_col(k2));
+        else if (k >= B.contig())
+          colupd(B.second_col(k), B.second_col(k + 1), B.second_col(k2));
+        else
+          colupd(B.col(k), B.col(k + 1), B.col(k2));
       }
       NsRefl next{0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
       if (kn >= l && kn <= nn - 1) {
-        double v[3];
-        if (kn == l) {
-          ns_ms_first_column(hb, l, sr[2 * b], si[2 * b], sr[2 * b + 1], si[2 * b + 1], v);
-        } else if (upd) {
-          v[0] = tm.gpick(keep0, (k + 1 - l) % G);
-          v[1] = tm.gpick(keep1, (k + 2 - l) % G);
-          v[2] = k + 3 <= nn ? tm.gpick(keep2, (k + 3 - l) % G) : 0.0;
-        } else {                                       // no reflection this round: as the matrix holds them
-          v[0] = HB(kn, kn - 1);
-          v[1] = HB(kn + 1, kn - 1);
-          v[2] = kn + 2 <= nn ? HB(kn + 2, kn - 1) : 0.0;
+        if (upd) {                                     // (kn > l) from registers: no wait for the stores above
+          const double v0 = tm.gpick(keep0, (k + 1 - l) % G);
+          const double v1 = tm.gpick(keep1, (k + 2 - l) % G);
+          const double v2 = k + 3 <= nn ? tm.gpick(keep2, (k + 3 - l) % G) : 0.0;
+          next = ns_ms_reflector_g(B, l, nn, kn, v0, v1, v2, Rn + 8 * b, lane == 0);
+        } else {
+          double v[3];
+          if (kn == l) {
+            ns_ms_first_column(B, l, sr[2 * b], si[2 * b], sr[2 * b + 1], si[2 * b + 1], v);
+          } else {                                     // no reflection this round: as the matrix holds them
+            v[0] = HB(kn, kn - 1);
+            v[1] = HB(kn + 1, kn - 1);
+            v[2] = kn + 2 <= nn ? HB(kn + 2, kn - 1) : 0.0;
+          }
+          tm.gsync();                                  // every thread has read before the first one stores
+          next = ns_ms_reflector_g(B, l, nn, kn, v[0], v[1], v[2], Rn + 8 * b, lane == 0);
         }
-        tm.gsync();                                    // every thread has read before the first one stores
-        next = ns_ms_reflector_g(hb, l, nn, kn, v[0], v[1], v[2], Rn + 8 * b, lane == 0);
       } else if (lane == 0) {
         Rn[8 * b] = 0.0;
       }
@@ -678,7 +782,7 @@ KA_HD void ns_ms_sweep(Team& tm, double* hb, int l, int nn, const double* sr, co
 }
 
 // All eigenvalues by multishift sweeps on large windows and double steps on
-// small ones, for the leading block [0, nn] of the band hb, until that block
+// small ones, for the leading block [0, nn] of the band B, until that block
 // is below order stop + 1 (stop = -1: to the end).  nn and shift (the
 // accumulated exceptional shift) carry the state between calls, so that a
 // caller can move the band to faster storage between two calls.  anorm: the
@@ -690,8 +794,8 @@ KA_HD void ns_ms_sweep(Team& tm, double* hb, int l, int nn, const double* sr, co
 // returning the same status to all.  Returns 0, or 1 when an
 // eigenvalue needed more than kNsQrMaxIts iterations.  Inlined, so that each
 // call site accesses its storage with the instructions of its address space.
-template <class Team, class SmallEig>
-KA_HD KA_FORCEINLINE int ns_ms_run(Team& tm, double* hb, int& nn, double& shift, double anorm, int stop, double* wr,
+template <class Team, class Band, class SmallEig>
+KA_HD KA_FORCEINLINE int ns_ms_run(Team& tm, const Band& B, int& nn, double& shift, double anorm, int stop, double* wr,
                                    double* wi, double* scr, const SmallEig& small_eig) {
   const int t = tm.tid(), NT = tm.size();
   double* sb = scr;
@@ -699,19 +803,19 @@ KA_HD KA_FORCEINLINE int ns_ms_run(Team& tm, double* hb, int& nn, double& shift,
   double* si = sr + kNsMsMax;
   double* rt = si + kNsMsMax;
   int fail = 0;
-#define HB(i, j) hb[ns_band_index((i), (j))]
+#define HB(i, j) (B.col(j)[i])
   while (nn > stop && !fail) {
     int its = 0;
     while (true) {
       tm.sync();
-      if (nn + 1 < kNsMsMinWindow) {                            // the rest: one call of the small solver
-        fail = small_eig(hb, nn + 1, wr, wi, kNsEps);
+      if (nn + 1 < kNsMsMinWindow && nn < B.contig()) {         // the rest: one call of the small solver
+        fail = small_eig(B.base(), nn + 1, wr, wi, kNsEps);
         if (t == 0)
           for (int i = 0; i <= nn; ++i) wr[i] += shift;
         nn = -1;
         break;
       }
-      const int l = ns_find_split(tm, hb, nn, anorm);
+      const int l = ns_find_split(tm, B, nn, anorm);
       double x = HB(nn, nn);
       if (l == nn) {
         if (t == 0) {
@@ -746,7 +850,7 @@ KA_HD KA_FORCEINLINE int ns_ms_run(Team& tm, double* hb, int& nn, double& shift,
       ++its;
       const int win = nn - l + 1;
       if (ex || win < kNsMsMinWindow) {
-        ns_ds_iteration(tm, hb, l, nn, x, y, w);
+        ns_ds_iteration(tm, B, l, nn, x, y, w);
         continue;
       }
       const int ns = ns_ms_shifts(win), o = nn - ns + 1;
@@ -754,12 +858,12 @@ KA_HD KA_FORCEINLINE int ns_ms_run(Team& tm, double* hb, int& nn, double& shift,
         for (int i = t; i <= j + 3; i += NT) sb[ns_band_index(i, j)] = (i <= j + 1 && i < ns) ? HB(o + i, o + j) : 0.0;
       tm.sync();
       if (small_eig(sb, ns, sr, si, kNsShiftTol)) {
-        ns_ds_iteration(tm, hb, l, nn, x, y, w);
+        ns_ds_iteration(tm, B, l, nn, x, y, w);
         continue;
       }
       if (t == 0) ns_pair_shifts(sr, si, ns);
       tm.sync();
-      ns_ms_sweep(tm, hb, l, nn, sr, si, ns / 2, rt);
+      ns_ms_sweep(tm, B, l, nn, sr, si, ns / 2, rt);
     }
   }
 #undef HB
@@ -769,31 +873,34 @@ KA_HD KA_FORCEINLINE int ns_ms_run(Team& tm, double* hb, int& nn, double& shift,
 
 // norm of the upper Hessenberg band (sum of absolute entries), the scale of
 // the deflation test where two diagonal entries are both zero
-template <class Team>
-KA_HD double ns_band_norm(Team& tm, const double* hb, int n) {
+template <class Team, class Band>
+KA_HD double ns_band_norm(Team& tm, const Band& B, int n) {
   const int t = tm.tid(), NT = tm.size();
   double anorm = 0.0;
-  for (int j = t; j < n; j += NT)
-    for (int i = 0; i <= j + 1 && i < n; ++i) anorm += fabs(hb[ns_band_index(i, j)]);
+  for (int j = t; j < n; j += NT) {
+    const double* c = B.col(j);
+    for (int i = 0; i <= j + 1 && i < n; ++i) anorm += fabs(c[i]);
+  }
   return tm.sum(anorm);
 }
 
-// The whole eigenvalue stage by ns_ms_run; with fast != nullptr the band
-// moves to fast (a band of order fast_n) once the leading block fits there.
+// The whole eigenvalue stage by ns_ms_run on the band hb.  With fast !=
+// nullptr (a band of order fast_n) and n > fast_n, the columns below fast_n
+// move to fast first and the band is split there until the leading block fits
+// in fast; the device does the same with LDS.
 template <class Team, class SmallEig>
 KA_HD int ns_qr_values_ms(Team& tm, double* hb, int n, double* wr, double* wi, double* anorm_out, double* scr,
                           const SmallEig& small_eig, double* fast, int fast_n) {
-  const double anorm = ns_band_norm(tm, hb, n);
+  const double anorm = ns_band_norm(tm, NsBand{hb}, n);
   if (anorm_out && tm.tid() == 0) *anorm_out = anorm;
   int nn = n - 1;
   double shift = 0.0;
-  if (fast && nn + 1 > fast_n) {
-    if (ns_ms_run(tm, hb, nn, shift, anorm, fast_n - 1, wr, wi, scr, small_eig)) return 1;
-    const size_t cnt = (size_t)(nn + 1) * (nn + 8) / 2;        // columns 0..nn of the band
-    for (size_t e = tm.tid(); e < cnt; e += tm.size()) fast[e] = hb[e];
-    hb = fast;
-  }
-  return ns_ms_run(tm, hb, nn, shift, anorm, -1, wr, wi, scr, small_eig);
+  if (!fast || n <= fast_n) return ns_ms_run(tm, NsBand{hb}, nn, shift, anorm, -1, wr, wi, scr, small_eig);
+  const size_t cnt = (size_t)fast_n * (fast_n + 7) / 2;          // columns 0 .. fast_n - 1 of the band
+  for (size_t e = tm.tid(); e < cnt; e += tm.size()) fast[e] = hb[e];
+  tm.sync();
+  if (ns_ms_run(tm, NsSplitBand{fast, hb, fast_n}, nn, shift, anorm, fast_n - 1, wr, wi, scr, small_eig)) return 1;
+  return ns_ms_run(tm, NsBand{fast}, nn, shift, anorm, -1, wr, wi, scr, small_eig);
 }
 
 // ---- stage 3: rank of eigenvalue c by descending real part (ties by index) ---------------

@@ -113,7 +113,7 @@ extern "C" void ka_host_ms_first_column(const double* H, int n, double sr1, doub
   std::vector<double> hb(ka::ns_band_doubles(n), 0.0);
   for (int j = 0; j < n; ++j)
     for (int i = 0; i <= j + 1 && i < n; ++i) hb[ka::ns_band_index(i, j)] = H[i + (size_t)j * n];
-  ka::ns_ms_first_column(hb.data(), 0, sr1, si1, sr2, si2, v);
+  ka::ns_ms_first_column(ka::NsBand{hb.data()}, 0, sr1, si1, sr2, si2, v);
 }
 
 // the multishift sweep's pairing of shifts, in place
