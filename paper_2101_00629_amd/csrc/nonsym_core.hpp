@@ -249,9 +249,8 @@ KA_HD inline size_t ns_band_index(int i, int j) { return (size_t)j * (j + 7) / 2
 // one array; NsSplitBand keeps the columns below `cut` in one array (LDS on
 // the device) and the rest in another (device memory), both at the packed
 // index above, so the columns below `cut` need no copy when the band moves
-// wholly into the first array.  base(): the first array; contig(): the order
-// of the leading block it holds in plain band layout.
-// Columns below contig() are in the first array, the others in the second;
+// wholly into the first array.  Columns below contig() are in the first
+// array, the others in the second (kSplit: whether there is a second);
 // first_col(j) and second_col(j) give a column's storage as a pointer derived
 // from that array alone, so that code using only such pointers is compiled for
 // that array's address space.
@@ -259,7 +258,6 @@ struct NsBand {
   static constexpr bool kSplit = false;
   double* p;
   KA_HD double* col(int j) const { return p + ns_band_index(0, j); }
-  KA_HD double* base() const { return p; }
   KA_HD int contig() const { return 1 << 30; }
   KA_HD double* first_col(int j) const { return p + ns_band_index(0, j); }
   KA_HD double* second_col(int j) const { return p + ns_band_index(0, j); }
@@ -270,7 +268,6 @@ struct NsSplitBand {
   double* hi;
   int cut;
   KA_HD double* col(int j) const { return (j < cut ? lo : hi) + ns_band_index(0, j); }
-  KA_HD double* base() const { return lo; }
   KA_HD int contig() const { return cut; }
   KA_HD double* first_col(int j) const { return lo + ns_band_index(0, j); }
   KA_HD double* second_col(int j) const { return hi + ns_band_index(0, j); }
@@ -487,14 +484,15 @@ KA_HD int ns_qr_values(Team& tm, double* hb, int n, double* wr, double* wi, doub
 // round is a reordering of applying the bulges one at a time, bottom first,
 // and the team applies each phase in parallel.  The entries a reflector
 // annihilates are stored as zeros, because the bulge behind passes over them.
-// Deflation, exceptional shifts and small windows are handled as in
-// ns_qr_values (same checks, double steps).
+// Deflation and exceptional shifts are handled as in ns_qr_values (same
+// checks, double steps); a window below kNsMsMinWindow goes to the small
+// solver whole.
 constexpr int kNsMsMax = 16;          // most shifts per sweep
 // The trailing block's eigenvalues only steer a sweep, so its QR stops at
 // this relative sub-diagonal size; with the test blocks of the host suite
 // that takes 40% fewer bulge steps and no more sweeps than machine precision.
 constexpr double kNsShiftTol = 1e-8;
-constexpr int kNsMsMinWindow = 24;    // smaller windows take double steps
+constexpr int kNsMsMinWindow = 24;    // smaller windows go to the small solver
 KA_HD inline int ns_ms_shifts(int win) {
   const int s = win >= 96 ? kNsMsMax : (win / 6) & ~1;
   return s < 4 ? 4 : s;
@@ -503,9 +501,15 @@ constexpr int kNsMsBulges = kNsMsMax / 2;
 // team-shared scratch of the multishift driver: the trailing block (band
 // layout), the shifts, and two reflector tables (this round's and the next
 // round's) of 8 doubles per bulge
-KA_HD constexpr size_t ns_ms_scratch_doubles() {
+// sweep scratch: the small solver's band, the shifts, the reflector tables,
+// and the eigenvalues of a small window (at the end, past the band of a
+// window below kNsMsMinWindow, which overlays the shifts and tables)
+KA_HD constexpr size_t ns_ms_window_values() {
   return ns_band_doubles(kNsMsMax) + 2 * kNsMsMax + 2 * 8 * kNsMsBulges + 8;
 }
+KA_HD constexpr size_t ns_ms_scratch_doubles() { return ns_ms_window_values() + 2 * kNsMsMinWindow; }
+static_assert(ns_band_doubles(kNsMsMinWindow - 1) <= ns_ms_window_values(),
+              "the band of a small window fits before its eigenvalues");
 
 // largest l in [1, nn] with a negligible sub-diagonal H(l, l-1), else 0
 // (each thread scans its own positions from the top, then a team maximum)
@@ -781,16 +785,17 @@ KA_HD void ns_ms_sweep(Team& tm, const Band& B, int l, int nn, const double* sr,
 #undef HB
 }
 
-// All eigenvalues by multishift sweeps on large windows and double steps on
-// small ones, for the leading block [0, nn] of the band B, until that block
-// is below order stop + 1 (stop = -1: to the end).  nn and shift (the
+// All eigenvalues by multishift sweeps on large windows and the small solver
+// on small ones (on a copy; a window [l, nn] split off by a negligible
+// H(l, l-1) has eigenvalues of its own), for the leading block [0, nn] of the
+// band B, until that block is below order stop + 1 (stop = -1: to the end).  nn and shift (the
 // accumulated exceptional shift) carry the state between calls, so that a
 // caller can move the band to faster storage between two calls.  anorm: the
 // norm of the whole matrix.  scr: team-shared scratch of
 // ns_ms_scratch_doubles().  small_eig(sb, ns, sr, si, tol): all eigenvalues
-// of a band of order ns (the trailing block copied to sb for a sweep's shifts,
-// with tol = kNsShiftTol, and at the end the leading block below order
-// kNsMsMinWindow in place, with tol = kNsEps), called by every thread,
+// of a band of order ns (copied to sb = scr: a window's trailing block for a
+// sweep's shifts, with tol = kNsShiftTol, or a whole window below order
+// kNsMsMinWindow, with tol = kNsEps), called by every thread,
 // returning the same status to all.  Returns 0, or 1 when an
 // eigenvalue needed more than kNsQrMaxIts iterations.  Inlined, so that each
 // call site accesses its storage with the instructions of its address space.
@@ -802,19 +807,13 @@ KA_HD KA_FORCEINLINE int ns_ms_run(Team& tm, const Band& B, int& nn, double& shi
   double* sr = sb + ns_band_doubles(kNsMsMax);
   double* si = sr + kNsMsMax;
   double* rt = si + kNsMsMax;
+  double* wv = scr + ns_ms_window_values();
   int fail = 0;
 #define HB(i, j) (B.col(j)[i])
   while (nn > stop && !fail) {
     int its = 0;
     while (true) {
       tm.sync();
-      if (nn + 1 < kNsMsMinWindow && nn < B.contig()) {         // the rest: one call of the small solver
-        fail = small_eig(B.base(), nn + 1, wr, wi, kNsEps);
-        if (t == 0)
-          for (int i = 0; i <= nn; ++i) wr[i] += shift;
-        nn = -1;
-        break;
-      }
       const int l = ns_find_split(tm, B, nn, anorm);
       double x = HB(nn, nn);
       if (l == nn) {
@@ -849,15 +848,30 @@ KA_HD KA_FORCEINLINE int ns_ms_run(Team& tm, const Band& B, int& nn, double& shi
       }
       ++its;
       const int win = nn - l + 1;
-      if (ex || win < kNsMsMinWindow) {
+      if (ex) {
         ns_ds_iteration(tm, B, l, nn, x, y, w);
         continue;
       }
-      const int ns = ns_ms_shifts(win), o = nn - ns + 1;
+      // one call of the small solver on a copy: a small window whole (its
+      // eigenvalues are final), else the window's trailing block for the
+      // sweep's shifts
+      const bool whole = win < kNsMsMinWindow;
+      const int ns = whole ? win : ns_ms_shifts(win), o = nn - ns + 1;
       for (int j = 0; j < ns; ++j)
         for (int i = t; i <= j + 3; i += NT) sb[ns_band_index(i, j)] = (i <= j + 1 && i < ns) ? HB(o + i, o + j) : 0.0;
       tm.sync();
-      if (small_eig(sb, ns, sr, si, kNsShiftTol)) {
+      const int sf = small_eig(sb, ns, whole ? wv : sr, whole ? wv + kNsMsMinWindow : si, whole ? kNsEps : kNsShiftTol);
+      if (whole) {
+        fail = sf;
+        if (t == 0)
+          for (int i = 0; i < win; ++i) {
+            wr[l + i] = wv[i] + shift;
+            wi[l + i] = wv[kNsMsMinWindow + i];
+          }
+        nn = l - 1;
+        break;
+      }
+      if (sf) {
         ns_ds_iteration(tm, B, l, nn, x, y, w);
         continue;
       }
