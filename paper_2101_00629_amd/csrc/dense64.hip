@@ -359,13 +359,17 @@ hipError_t chol_upper_inv(const double* G, int n, int ldg, double* Rinv, int ldr
 // runs ne-1 rounds of ne/2 disjoint rotations in round-robin order (circle
 // method: index ne-1 meets r, and (r+i) meets (r-i) mod ne-1).  A round
 // updates A <- J^T A J one 2x2 block (pair k1, pair k2) per work item, so a
-// round costs two barriers.  A lives in LDS for ne <= 128, else in `work`;
+// round costs two barriers.  A lives in LDS for ne <= 136 (the Gram matrix of
+// a restart with up to M + b = 135 kept vectors), else in `work`;
 // eigenvectors accumulate in `work`.  Output: theta descending, S columns in
 // the same order.
 // ---------------------------------------------------------------------------
 constexpr int kEigThreads = 1024;
 constexpr int kEigMax = 1024;
-constexpr int kEigLds = 128;
+constexpr int kEigLds = 136;
+// A, the pair and rotation tables and the reduction slots in one workgroup's LDS
+static_assert(kEigLds * kEigLds * 8 + (kEigMax / 2) * (4 + 4 + 8 + 8) + 2 * (kEigThreads / 64) * 8 <= 160 * 1024,
+              "the LDS variant of the Jacobi kernel fits in 160 KiB");
 
 size_t sym_eig_work(int n) {
   const int ne = n + (n & 1);

@@ -599,10 +599,16 @@ KA_HD inline NsRefl ns_ms_reflector_g(const Band& B, int l, int nn, int k, doubl
   c = NsRefl{1.0, pp * is, h.q * is, h.r * is, h.q * ipp, h.r * ipp};
   if (store) {
     if (k > l) {
-      double* c = B.col(k - 1);
-      c[k] = ldexp(-h.s, h.e);
-      c[k + 1] = 0.0;
-      if (notlast) c[k + 2] = 0.0;
+      const double sub = ldexp(-h.s, h.e);
+      auto put = [&](double* c) {
+        c[k] = sub;
+        c[k + 1] = 0.0;
+        if (notlast) c[k + 2] = 0.0;
+      };
+      if (!Band::kSplit || k - 1 < B.contig())
+        put(B.first_col(k - 1));
+      else
+        put(B.second_col(k - 1));
     }
     R[0] = c.f;
     R[1] = c.x1;
