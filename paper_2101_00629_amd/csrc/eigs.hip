@@ -10,9 +10,11 @@
 //   vectors), and when X is full: Rayleigh-Ritz (small dense eigensolve of H),
 //   residuals |A'y - theta y|, convergence test, thick restart keeping the
 //   leading nev Ritz vectors.
-// Galerkin (symmetric A'): parallel Jacobi on H, X <- X S, H <- diag(theta).
+// Galerkin (symmetric A'): tridiagonal route on H (Householder, multisection,
+// inverse iteration), X <- X S, H <- diag(theta).
 // Collocation (A' = Z^-1 A, non-symmetric): Hessenberg QR on H, restart onto
-// an orthonormal basis of the wanted Ritz vectors, H <- W^T S^T H S W.
+// an orthonormal basis of the wanted Ritz vectors (W from a Jacobi eigensolve
+// of their Gram matrix), H <- W^T S^T H S W.
 //
 // The solve is a resumable state machine (EigRun): pre_apply() issues the
 // operator steps up to the kernel product, the caller runs the product
