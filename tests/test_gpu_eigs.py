@@ -404,12 +404,12 @@ def test_gauss_galerkin_full_size_cube(precision, bar):
 
 @pytest.mark.parametrize("M", [60, 80, 140])
 def test_collocation_rayleigh_ritz_orders_above_128(M):
-    """Rayleigh-Ritz orders 124, 144 and 204 (M + b kept plus 3 blocks of 16):
-    the eigenvalue QR runs as multishift sweeps by one workgroup, with the
-    band in LDS (124, 144) or first in device memory and then moved into LDS
-    once the deflations have shrunk it to order 196 (204).  Cube p = 2, 8^3,
-    exponential l = 1, against the exact product-of-1D collocation spectrum
-    at the floored FP32 bar."""
+    """Rayleigh-Ritz orders 124, 144 and 236 (M + b kept plus 3, 3 and 5
+    blocks of 16): the eigenvalue QR runs as multishift sweeps by one
+    workgroup, with the band in LDS (124, 144) or split between LDS and
+    device memory until the deflations have shrunk the leading block to order
+    196 (236).  Cube p = 2, 8^3, exponential l = 1, against the exact
+    product-of-1D collocation spectrum at the floored FP32 bar."""
     desc = K.make_desc("collocation", "cube", 2, (8, 8, 8), "exponential", 1.0, block=16, seed=4)
     prob = K.Problem(desc)
     rc, lam, info = K.ka_eigs(prob.h, M, tol=1e-6, maxit=80)
