@@ -1,12 +1,14 @@
 // FP64 dense kernels of the block eigensolver: tall-skinny products for the
 // block orthogonalisation and Rayleigh-Ritz projection, Cholesky-QR of a
-// block, the small dense symmetric eigensolve (parallel cyclic Jacobi), column
-// norms, residual assembly, sign normalisation and a counter-based normal
+// block, the orthonormal basis of a set of vectors from their Gram matrix
+// (pivoted Cholesky, for the collocation restart), column norms, residual
+// assembly, sign normalisation and a counter-based normal
 // generator for start blocks.  All reductions use a fixed partition and a
 // fixed summation order, so results depend only on the shapes.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "basis_core.hpp"
 #include "ka_internal.hpp"
 
 namespace ka {
@@ -355,160 +357,79 @@ hipError_t chol_upper_inv(const double* G, int n, int ldg, double* Rinv, int ldr
 }
 
 // ---------------------------------------------------------------------------
-// Symmetric eigensolve by parallel cyclic Jacobi, one workgroup.  Each sweep
-// runs ne-1 rounds of ne/2 disjoint rotations in round-robin order (circle
-// method: index ne-1 meets r, and (r+i) meets (r-i) mod ne-1).  A round
-// updates A <- J^T A J one 2x2 block (pair k1, pair k2) per work item, so a
-// round costs two barriers.  A lives in LDS for ne <= 136 (the Gram matrix of
-// a restart with up to M + b = 135 kept vectors), else in `work`;
-// eigenvectors accumulate in `work`.  Output: theta descending, S columns in
-// the same order.
+// Orthonormal basis of span(S) from its Gram matrix G = S^T S (n x n, n at
+// most the Rayleigh-Ritz order): diagonal-pivoted Cholesky with a rank cut and
+// the inverse of its factor (basis_core.hpp), one workgroup, working copy in
+// LDS up to order kBasisLds.  W (n x rank, leading dimension ldw) = P R^-1;
+// rank goes to a device int.
 // ---------------------------------------------------------------------------
-constexpr int kEigThreads = 1024;
-constexpr int kEigMax = 1024;
-constexpr int kEigLds = 136;
-// A, the pair and rotation tables and the reduction slots in one workgroup's LDS
-static_assert(kEigLds * kEigLds * 8 + (kEigMax / 2) * (4 + 4 + 8 + 8) + 2 * (kEigThreads / 64) * 8 <= 160 * 1024,
-              "the LDS variant of the Jacobi kernel fits in 160 KiB");
+constexpr int kBasisThreads = 1024;
 
-size_t sym_eig_work(int n) {
-  const int ne = n + (n & 1);
-  return (size_t)ne * ne * 2 + 4 * (size_t)ne;
-}
-
-__device__ __forceinline__ void rr_pair(int r, int k, int ne, int& p, int& q) {
-  const int m = ne - 1;
-  int a, b;
-  if (k == 0) {
-    a = m;
-    b = r;
-  } else {
-    a = (r + k) % m;
-    b = (r - k + m) % m;
+struct BasisTeam {
+  double* rv;   // one slot per wave
+  int* ri;
+  __device__ int tid() const { return threadIdx.x; }
+  __device__ int size() const { return kBasisThreads; }
+  __device__ void sync() const { __syncthreads(); }
+  // index of the largest v (smallest index among equals; -1 if none has one)
+  __device__ static bool better(double v, int i, double bv, int bi) {
+    return i >= 0 && (bi < 0 || v > bv || (v == bv && i < bi));
   }
-  p = a < b ? a : b;
-  q = a < b ? b : a;
-}
+  __device__ int argmax(double v, int i) const {
+    for (int off = 32; off > 0; off >>= 1) {
+      const double ov = __shfl_xor(v, off);
+      const int oi = __shfl_xor(i, off);
+      if (better(ov, oi, v, i)) {
+        v = ov;
+        i = oi;
+      }
+    }
+    if ((threadIdx.x & 63) == 0) {
+      rv[threadIdx.x >> 6] = v;
+      ri[threadIdx.x >> 6] = i;
+    }
+    __syncthreads();
+    double bv = rv[0];
+    int bi = ri[0];
+    for (int w = 1; w < kBasisThreads / 64; ++w)
+      if (better(rv[w], ri[w], bv, bi)) {
+        bv = rv[w];
+        bi = ri[w];
+      }
+    __syncthreads();
+    return bi;
+  }
+};
+
+// the working copy in LDS up to order kBasisLds, else in `work`
+constexpr int kBasisLds = 136;
+static_assert((kBasisLds * kBasisLds + 2 * kBasisLds) * 8 + (kBasisThreads / 64) * 12 <= 160 * 1024,
+              "the LDS variant of the basis kernel fits in 160 KiB");
 
 template <bool LDS>
-__global__ __launch_bounds__(kEigThreads) void jacobi_kernel(const double* __restrict__ H, int n, int ldh,
-                                                              double* __restrict__ theta, double* __restrict__ S,
-                                                              int lds, double* __restrict__ work) {
-  const int ne = n + (n & 1);       // even size (a dummy index when n is odd)
-  __shared__ double A_lds[LDS ? kEigLds * kEigLds : 1];
-  double* A = LDS ? A_lds : work;   // ne x ne, column-major
-  double* V = work + (size_t)ne * ne;
-  double* tmpv = work + (size_t)2 * ne * ne;
-  __shared__ int pp[kEigMax / 2], qq[kEigMax / 2];
-  __shared__ double cs[kEigMax / 2], sn[kEigMax / 2];
-  __shared__ double red[2][kEigThreads / 64];
-  const int t = threadIdx.x, nt = blockDim.x;
-  const int half = ne / 2;
-  for (int64_t e = t; e < (int64_t)ne * ne; e += nt) {
-    const int i = (int)(e % ne), j = (int)(e / ne);
-    A[e] = (i < n && j < n) ? 0.5 * (H[i + (int64_t)j * ldh] + H[j + (int64_t)i * ldh]) : 0.0;
-    V[e] = (i == j) ? 1.0 : 0.0;
-  }
-  __syncthreads();
-  for (int sweep = 0; sweep < 40; ++sweep) {
-    // convergence test: off-diagonal vs total Frobenius norm
-    double off = 0.0, tot = 0.0;
-    for (int64_t e = t; e < (int64_t)ne * ne; e += nt) {
-      const int i = (int)(e % ne), j = (int)(e / ne);
-      const double a2 = A[e] * A[e];
-      tot += a2;
-      if (i != j) off += a2;
-    }
-    for (int o = 32; o > 0; o >>= 1) {
-      off += __shfl_xor(off, o);
-      tot += __shfl_xor(tot, o);
-    }
-    if ((t & 63) == 0) {
-      red[0][t >> 6] = off;
-      red[1][t >> 6] = tot;
-    }
-    __syncthreads();
-    double offs = 0.0, tots = 0.0;
-    for (int w = 0; w < nt / 64; ++w) {
-      offs += red[0][w];
-      tots += red[1][w];
-    }
-    __syncthreads();
-    if (offs <= 1e-30 * tots || tots == 0.0) break;
-    for (int round = 0; round < ne - 1; ++round) {
-      for (int k = t; k < half; k += nt) {
-        int p, q;
-        rr_pair(round, k, ne, p, q);
-        pp[k] = p;
-        qq[k] = q;
-        const double apq = A[p + (int64_t)q * ne];
-        const double app = A[p + (int64_t)p * ne], aqq = A[q + (int64_t)q * ne];
-        double c = 1.0, s = 0.0;
-        if (fabs(apq) > 1e-300) {
-          const double tau = (aqq - app) / (2.0 * apq);
-          const double tt = (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-          c = 1.0 / sqrt(1.0 + tt * tt);
-          s = tt * c;
-        }
-        cs[k] = c;
-        sn[k] = s;
-      }
-      __syncthreads();
-      // A <- J^T A J, one 2 x 2 block per item (rows of pair k1, columns of pair k2)
-      for (int64_t e = t; e < (int64_t)half * half; e += nt) {
-        const int k1 = (int)(e % half), k2 = (int)(e / half);
-        const double c1 = cs[k1], s1 = sn[k1], c2 = cs[k2], s2 = sn[k2];
-        if (s1 == 0.0 && s2 == 0.0) continue;
-        const int p1 = pp[k1], q1 = qq[k1], p2 = pp[k2], q2 = qq[k2];
-        double* a00 = A + p1 + (int64_t)p2 * ne;
-        double* a01 = A + p1 + (int64_t)q2 * ne;
-        double* a10 = A + q1 + (int64_t)p2 * ne;
-        double* a11 = A + q1 + (int64_t)q2 * ne;
-        const double b00 = *a00, b01 = *a01, b10 = *a10, b11 = *a11;
-        const double rpp = c1 * b00 - s1 * b10, rpq = c1 * b01 - s1 * b11;
-        const double rqp = s1 * b00 + c1 * b10, rqq = s1 * b01 + c1 * b11;
-        *a00 = c2 * rpp - s2 * rpq;
-        *a01 = s2 * rpp + c2 * rpq;
-        *a10 = c2 * rqp - s2 * rqq;
-        *a11 = s2 * rqp + c2 * rqq;
-      }
-      // V <- V J
-      for (int64_t e = t; e < (int64_t)half * ne; e += nt) {
-        const int l = (int)(e % ne), k = (int)(e / ne);
-        const double c = cs[k], s = sn[k];
-        if (s == 0.0) continue;
-        const int p = pp[k], q = qq[k];
-        const double vp = V[l + (int64_t)p * ne], vq = V[l + (int64_t)q * ne];
-        V[l + (int64_t)p * ne] = c * vp - s * vq;
-        V[l + (int64_t)q * ne] = s * vp + c * vq;
-      }
-      __syncthreads();
-    }
-  }
-  // sort descending (ties by index) over the first n
-  for (int i = t; i < n; i += nt) tmpv[i] = A[i + (int64_t)i * ne];
-  __syncthreads();
-  for (int i = t; i < n; i += nt) {
-    const double di = tmpv[i];
-    int rank = 0;
-    for (int j = 0; j < n; ++j) {
-      const double dj = tmpv[j];
-      if (dj > di || (dj == di && j < i)) ++rank;
-    }
-    theta[rank] = di;
-    for (int l = 0; l < n; ++l) S[l + (int64_t)rank * lds] = V[l + (int64_t)i * ne];
-  }
+__global__ __launch_bounds__(kBasisThreads) void pchol_basis_kernel(const double* __restrict__ G, int n, int ldg,
+                                                                    double cut, double* __restrict__ work,
+                                                                    double* __restrict__ W, int ldw,
+                                                                    int* __restrict__ rank) {
+  __shared__ double rv[kBasisThreads / 64];
+  __shared__ int ri[kBasisThreads / 64];
+  __shared__ double w_lds[LDS ? kBasisLds * kBasisLds + 2 * kBasisLds : 1];
+  BasisTeam tm{rv, ri};
+  const int r = pchol_basis(tm, G, ldg, n, cut, LDS ? w_lds : work, W, ldw);
+  if (threadIdx.x == 0) *rank = r;
 }
 
-hipError_t sym_eig(const double* H, int n, int ldh, double* theta, double* S, int lds, double* work,
-                   hipStream_t s) {
-  if (n <= 0) return hipSuccess;
-  if (n > kEigMax - 1) return hipErrorInvalidValue;
-  const int ne = n + (n & 1);
-  if (ne <= kEigLds)
-    hipLaunchKernelGGL(jacobi_kernel<true>, dim3(1), dim3(kEigThreads), 0, s, H, n, ldh, theta, S, lds, work);
+size_t basis_work(int n) { return pchol_basis_work(n); }
+
+hipError_t orthonormal_basis(const double* G, int n, int ldg, double cut, double* W, int ldw, double* work,
+                             int* rank, hipStream_t s) {
+  if (n < 0 || ldg < n || ldw < n) return hipErrorInvalidValue;
+  if (n <= kBasisLds)
+    hipLaunchKernelGGL(pchol_basis_kernel<true>, dim3(1), dim3(kBasisThreads), 0, s, G, n, ldg, cut, work, W, ldw,
+                       rank);
   else
-    hipLaunchKernelGGL(jacobi_kernel<false>, dim3(1), dim3(kEigThreads), 0, s, H, n, ldh, theta, S, lds, work);
+    hipLaunchKernelGGL(pchol_basis_kernel<false>, dim3(1), dim3(kBasisThreads), 0, s, G, n, ldg, cut, work, W, ldw,
+                       rank);
   return hipGetLastError();
 }
 

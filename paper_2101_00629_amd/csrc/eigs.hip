@@ -13,8 +13,8 @@
 // Galerkin (symmetric A'): tridiagonal route on H (Householder, multisection,
 // inverse iteration), X <- X S, H <- diag(theta).
 // Collocation (A' = Z^-1 A, non-symmetric): Hessenberg QR on H, restart onto
-// an orthonormal basis of the wanted Ritz vectors (W from a Jacobi eigensolve
-// of their Gram matrix), H <- W^T S^T H S W.
+// an orthonormal basis of the wanted Ritz vectors (W from a pivoted Cholesky of
+// their Gram matrix, twice), H <- W^T S^T H S W.
 //
 // The solve is a resumable state machine (EigRun): pre_apply() issues the
 // operator steps up to the kernel product, the caller runs the product
@@ -76,12 +76,12 @@ __global__ void symmetrize_block_kernel(double* H, int ld, int k, int pw) {
   *b = v;
 }
 
-__global__ void inv_sqrt_kernel(const double* g, int n, double* out) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) out[i] = g[i] > 0.0 ? 1.0 / sqrt(g[i]) : 0.0;
-}
-
 }  // namespace
+
+// Rank cut of the restart basis: a kept Ritz vector whose squared distance
+// from the span of the ones chosen before it is at or below this fraction of
+// the largest squared norm is dropped (the vectors are normalised).
+constexpr double kBasisCut = 1e-12;
 
 // ---- sizes ----------------------------------------------------------------
 static void basis_sizes(int64_t N, int M, int b, int& nev, int& m_max, bool& full) {
@@ -117,7 +117,7 @@ size_t eig_workspace_bytes(int64_t N, int M, int b) {
   s += 3 * al((size_t)N * ncol * 8);
   s += 5 * al((size_t)m_max * m_max * 8);
   s += al((size_t)m_max * b * 8) + 2 * al((size_t)b * b * 8) + 3 * al((size_t)m_max * 8);
-  s += al(std::max({sym_eig_work(m_max), sym_tri_work(m_max), nonsym_eig_work(m_max, std::min(nev + 1, m_max))}) * 8);
+  s += al(std::max({basis_work(m_max), sym_tri_work(m_max), nonsym_eig_work(m_max, std::min(nev + 1, m_max))}) * 8);
   s += al(tn_work_doubles(m_max, b, N) * 8);
   s += al(column_norms_work(N, std::max(ncol, b)) * 8) + al((size_t)b * 8) + al(256);
   return s;
@@ -248,7 +248,7 @@ int EigRun::start() {
   KA_TRY(alloc((size_t)m * 8, &w_.theta));
   KA_TRY(alloc((size_t)m * 8, &w_.thetai));
   KA_TRY(alloc((size_t)m * 8, &w_.norms));
-  KA_TRY(alloc(std::max({sym_eig_work(m), sym_tri_work(m), nonsym_eig_work(m, std::min(nev_ + 1, m))}) * 8, &w_.ework));
+  KA_TRY(alloc(std::max({basis_work(m), sym_tri_work(m), nonsym_eig_work(m, std::min(nev_ + 1, m))}) * 8, &w_.ework));
   KA_TRY(alloc(tn_work_doubles(m, b, N) * 8, &w_.tnwork));
   KA_TRY(alloc(column_norms_work(N, std::max(ncol, b)) * 8, &w_.nwork));
   KA_TRY(alloc((size_t)b * 8, &w_.pnorm));
@@ -394,17 +394,24 @@ int EigRun::rayleigh_ritz(bool& stop) {
   } else {
     int nkeep = std::min(nev_, k);
     if (nkeep < nk && thi_[nkeep - 1] > 0.0) ++nkeep;
-    // orthonormal basis of the kept Ritz vectors: W = V Lambda^-1/2 from S^T S = V Lambda V^T
+    // orthonormal basis of the kept Ritz vectors: W with S W orthonormal, by
+    // pivoted Cholesky of G = S^T S (vectors dependent on the chosen ones to
+    // kBasisCut are dropped), then once more on W1^T G W1, which restores the
+    // orthonormality that the first pass loses to the conditioning of S
     HIP_TRY(dgemm_tn(nkeep, nkeep, k, 1.0, w_.S, m, w_.S, m, 0.0, w_.Gm, m, w_.tnwork, s_));
-    HIP_TRY(sym_eig(w_.Gm, nkeep, m, w_.norms, w_.Wm, m, w_.ework, s_));
-    std::vector<double> gl(nkeep);
-    HIP_TRY(hipMemcpyAsync(gl.data(), w_.norms, sizeof(double) * nkeep, hipMemcpyDeviceToHost, s_));
+    HIP_TRY(orthonormal_basis(w_.Gm, nkeep, m, kBasisCut, w_.Wm, m, w_.ework, w_.status + 1, s_));
+    int r1 = 0, good = 0;
+    HIP_TRY(hipMemcpyAsync(&r1, w_.status + 1, sizeof(int), hipMemcpyDeviceToHost, s_));
     HIP_TRY(hipStreamSynchronize(s_));
-    int good = 0;
-    while (good < nkeep && gl[good] > 1e-12 * gl[0]) ++good;
-    hipLaunchKernelGGL(inv_sqrt_kernel, dim3((good + 63) / 64), dim3(64), 0, s_, w_.norms, good, w_.norms);
-    HIP_TRY(hipGetLastError());
-    HIP_TRY(scale_cols(w_.Wm, nkeep, good, m, w_.norms, s_));
+    if (r1 < 1) return fail(KA_ERR_SINGULAR, "restart: the kept Ritz vectors span nothing");
+    HIP_TRY(dgemm_nn(nkeep, r1, nkeep, 1.0, w_.Gm, m, w_.Wm, m, 0.0, w_.Hc, m, s_));                 // G W1
+    HIP_TRY(dgemm_tn(r1, r1, nkeep, 1.0, w_.Wm, m, w_.Hc, m, 0.0, w_.Gm, m, w_.tnwork, s_));        // W1^T G W1
+    HIP_TRY(orthonormal_basis(w_.Gm, r1, m, kBasisCut, w_.Hc, m, w_.ework, w_.status + 1, s_));     // W2
+    HIP_TRY(hipMemcpyAsync(&good, w_.status + 1, sizeof(int), hipMemcpyDeviceToHost, s_));
+    HIP_TRY(hipStreamSynchronize(s_));
+    if (good < 1) return fail(KA_ERR_SINGULAR, "restart: the kept Ritz vectors span nothing");
+    HIP_TRY(dgemm_nn(nkeep, good, r1, 1.0, w_.Wm, m, w_.Hc, m, 0.0, w_.Gm, m, s_));                  // W = W1 W2
+    HIP_TRY(copy_cols(w_.Gm, m, w_.Wm, m, nkeep, good, s_));
     // X <- XS W, AX <- AXS W
     HIP_TRY(dgemm_nn(N, good, nkeep, 1.0, w_.XS, N, w_.Wm, m, 0.0, w_.T, N, s_));
     HIP_TRY(copy_cols(w_.T, N, w_.X, N, N, good, s_));

@@ -119,11 +119,15 @@ hipError_t dgemm_nn(int64_t M, int n, int k, double alpha, const double* A, int6
 constexpr double kOrthKeep = 1e-9;
 hipError_t chol_upper_inv(const double* G, int n, int ldg, double* Rinv, int ldr, int* status,
                           hipStream_t s, const double* ref = nullptr);
-hipError_t sym_eig(const double* H, int n, int ldh, double* theta, double* S, int lds, double* work,
-                   hipStream_t s);
-size_t sym_eig_work(int n);
+// Orthonormal basis of the span of vectors S from G = S^T S (n x n): W (n x
+// rank, leading dimension ldw) with S W orthonormal, by diagonal-pivoted
+// Cholesky stopped at the first pivot at or below cut * max G(i, i); rank to a
+// device int.  work: basis_work(n) doubles.  The collocation thick restart.
+hipError_t orthonormal_basis(const double* G, int n, int ldg, double cut, double* W, int ldw, double* work,
+                             int* rank, hipStream_t s);
+size_t basis_work(int n);
 // Tridiagonal route (Householder, multisection, inverse iteration): the Galerkin
-// Rayleigh-Ritz step.  The Jacobi solver above stays for near-identity Gram matrices.
+// Rayleigh-Ritz step.
 // All n eigenvalues (theta, descending) and the eigenvectors of the nvec largest
 // (S columns 0 .. nvec-1).
 hipError_t sym_eig_tri(const double* H, int n, int ldh, int nvec, double* theta, double* S, int lds, double* work,
