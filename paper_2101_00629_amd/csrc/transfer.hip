@@ -101,9 +101,12 @@ __global__ __launch_bounds__(256) void mode_pt_kernel(const TIn* __restrict__ in
   }
 }
 
-template <typename TIn, typename TAcc, typename TOut>
-static hipError_t launch_mode_pt(const ModeArgs& a, hipStream_t s) {
-  constexpr int R = 16;
+// R outputs per thread and pass over the input fiber: 33 for modes longer than
+// 16, so that a mode of 66 (the 64^3 cube at p = 2) takes two passes instead
+// of five.  Every pass re-reads the fiber, and at that size the re-reads
+// come from HBM: 4.8 times the input bytes with R = 16.
+template <typename TIn, typename TAcc, typename TOut, int R>
+static hipError_t launch_mode_pt_r(const ModeArgs& a, hipStream_t s) {
   const int nk = a.n_in[a.mode];
   const int64_t nrest = (int64_t)a.n_in[0] * a.n_in[1] * a.n_in[2] / nk;
   const int64_t nthreads = nrest * a.nv;
@@ -117,6 +120,11 @@ static hipError_t launch_mode_pt(const ModeArgs& a, hipStream_t s) {
                      (TOut*)a.out, a.out_ld, (const TAcc*)a.matT, a.out_scale, a.n_in[0], a.n_in[1], a.n_in[2],
                      a.mode, a.m, a.nv, nthreads);
   return hipGetLastError();
+}
+
+template <typename TIn, typename TAcc, typename TOut>
+static hipError_t launch_mode_pt(const ModeArgs& a, hipStream_t s) {
+  return a.m > 16 ? launch_mode_pt_r<TIn, TAcc, TOut, 33>(a, s) : launch_mode_pt_r<TIn, TAcc, TOut, 16>(a, s);
 }
 
 template <typename TIn, typename TAcc, typename TOut>
