@@ -46,42 +46,38 @@ __global__ void split_reduce_kernel(const double* __restrict__ part, int nsplit,
 // lane l holds (k = l / 16, j = l % 16), accumulator register r of lane l
 // holds (i = l / 16 + 4 r, j = l % 16).  The four MFMAs of a 16-row step may
 // take its rows in any partition, so lane l reads the four consecutive rows
-// 4 (l / 16) .. + 3 of its columns of A and B (MFMA s takes row 4 (l / 16) + s).
+// 4 (l / 16) .. + 3 of its columns of A (MFMA s takes row 4 (l / 16) + s).
 // Each of the 4 waves holds two 16-row tiles of C across the block's four
-// 16-column tiles (8 accumulators) and runs over the split's rows with the
-// next step's loads issued before the current step's MFMAs.  Row ranges
-// (splits) go to a partial array that split_reduce_kernel sums in split order,
-// or straight to C with one split.
+// 16-column tiles (8 accumulators) and reads A straight from memory, the
+// next step's rows issued before the current step's MFMAs.  B, the same for
+// the 4 waves, goes through LDS in chunks of kTnStep rows (zero past the
+// row range and past n, so the clamped rows of A beyond the range add
+// nothing), double buffered with one barrier per chunk.  Row ranges (splits)
+// go to a partial array that split_reduce_kernel sums in split order, or
+// straight to C with one split.
 // ---------------------------------------------------------------------------
 typedef double tn_d4 __attribute__((ext_vector_type(4)));
 constexpr int kTnI = 2;                     // 16-row tiles of C per wave
 constexpr int kTnRowsC = 4 * 16 * kTnI;     // rows of C (columns of A) per workgroup
-constexpr int kTnStep = 32;                 // rows of A and B per loop iteration (two 16-row steps)
+constexpr int kTnStep = 32;                 // rows of A and B per chunk (two 16-row steps)
+constexpr int kTnBW = 64 + 8;               // padded LDS row of a B chunk (doubles)
+constexpr int kTnSE = kTnStep * 64 / 256;   // staged B elements per thread
 
 __global__ __launch_bounds__(256) void dgemm_tn_mfma_kernel(int m, int n, int64_t K, const double* __restrict__ A,
                                                             int64_t lda, const double* __restrict__ B, int64_t ldb,
                                                             int64_t k_per_split, double* __restrict__ part,
                                                             double alpha, double beta, double* __restrict__ C,
                                                             int64_t ldc) {
+  __shared__ double Bs[2][kTnStep][kTnBW];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, q = lane >> 4, c16 = lane & 15;
   const int i0 = blockIdx.x * kTnRowsC + w * 16 * kTnI;   // this wave's first row of C
-  if (i0 >= m) return;                                     // (no barriers in this kernel)
+  const bool on = i0 < m;                                  // (a wave past m only stages B)
   const int j0 = blockIdx.y * 64;
   const double* Ap[kTnI];
-  bool aok[kTnI];
 #pragma unroll
   for (int u = 0; u < kTnI; ++u) {
     const int i = i0 + 16 * u + c16;
-    aok[u] = i < m;
-    Ap[u] = A + (int64_t)(aok[u] ? i : 0) * lda;
-  }
-  const double* Bp[4];
-  bool bok[4];
-#pragma unroll
-  for (int t = 0; t < 4; ++t) {
-    const int j = j0 + 16 * t + c16;
-    bok[t] = j < n;
-    Bp[t] = B + (int64_t)(bok[t] ? j : 0) * ldb;
+    Ap[u] = A + (int64_t)(i < m ? i : 0) * lda;
   }
   const int64_t kb = (int64_t)blockIdx.z * k_per_split;
   const int64_t ke = kb + k_per_split < K ? kb + k_per_split : K;
@@ -90,42 +86,66 @@ __global__ __launch_bounds__(256) void dgemm_tn_mfma_kernel(int m, int n, int64_
   for (int u = 0; u < kTnI; ++u)
 #pragma unroll
     for (int t = 0; t < 4; ++t) acc[u][t] = (tn_d4){0.0, 0.0, 0.0, 0.0};
-  // one 16-row step; rows past the range are read at row ke - 1 (a valid
-  // address) and weighted by zero
-  auto load = [&](int64_t g, double (&a)[kTnI][4], double (&b)[4][4]) {
+  double st[kTnSE];
+  auto fetch_b = [&](int64_t g) {            // consecutive threads down a column of B
+#pragma unroll
+    for (int v = 0; v < kTnSE; ++v) {
+      const int e = threadIdx.x + 256 * v;
+      const int64_t r = g + e % kTnStep;
+      const int j = j0 + e / kTnStep;
+      st[v] = (r < ke && j < n) ? B[r + (int64_t)j * ldb] : 0.0;
+    }
+  };
+  auto put_b = [&](int buf) {
+#pragma unroll
+    for (int v = 0; v < kTnSE; ++v) {
+      const int e = threadIdx.x + 256 * v;
+      Bs[buf][e % kTnStep][e / kTnStep] = st[v];
+    }
+  };
+  // one 16-row step of A; rows past the range are read at row ke - 1 (a
+  // valid address) and meet zeros of B
+  auto load_a = [&](int64_t g, double (&a)[kTnI][4]) {
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
       const int64_t r = g + 4 * q + s;
       const int64_t rc = r < ke ? r : ke - 1;
 #pragma unroll
       for (int u = 0; u < kTnI; ++u) a[u][s] = Ap[u][rc];
-#pragma unroll
-      for (int t = 0; t < 4; ++t) b[t][s] = Bp[t][rc];
     }
   };
-  auto step = [&](int64_t g, const double (&a)[kTnI][4], const double (&b)[4][4]) {
+  auto step = [&](int buf, int h, const double (&a)[kTnI][4]) {
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
-      const bool ok = g + 4 * q + s < ke;
+      double bv[4];
 #pragma unroll
-      for (int u = 0; u < kTnI; ++u) {
-        const double av = ok && aok[u] ? a[u][s] : 0.0;
+      for (int t = 0; t < 4; ++t) bv[t] = Bs[buf][16 * h + 4 * q + s][16 * t + c16];
 #pragma unroll
-        for (int t = 0; t < 4; ++t)
-          acc[u][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bok[t] ? b[t][s] : 0.0, acc[u][t], 0, 0, 0);
-      }
+      for (int u = 0; u < kTnI; ++u)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) acc[u][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u][s], bv[t], acc[u][t], 0, 0, 0);
     }
   };
-  if (kb < ke) {
-    double a0[kTnI][4], b0[4][4], a1[kTnI][4], b1[4][4];
-    load(kb, a0, b0);
-    for (int64_t g = kb; g < ke; g += kTnStep) {   // uniform over the wave (the matrix cores need all lanes)
-      load(g + 16, a1, b1);
-      step(g, a0, b0);
-      load(g + kTnStep, a0, b0);
-      step(g + 16, a1, b1);
+  if (kb < ke) {                             // uniform over the workgroup, like every branch below
+    double a0[kTnI][4], a1[kTnI][4];
+    fetch_b(kb);
+    put_b(0);
+    load_a(kb, a0);
+    __syncthreads();
+    int buf = 0;
+    for (int64_t g = kb; g < ke; g += kTnStep) {
+      const bool more = g + kTnStep < ke;
+      if (more) fetch_b(g + kTnStep);
+      load_a(g + 16, a1);
+      if (on) step(buf, 0, a0);
+      if (more) load_a(g + kTnStep, a0);
+      if (on) step(buf, 1, a1);
+      if (more) put_b(buf ^ 1);              // its last readers finished before the previous barrier
+      __syncthreads();
+      buf ^= 1;
     }
   }
+  if (!on) return;
 #pragma unroll
   for (int u = 0; u < kTnI; ++u)
 #pragma unroll
