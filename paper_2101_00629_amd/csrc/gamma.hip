@@ -147,20 +147,28 @@ __device__ __forceinline__ void gamma_f32_tile(const GammaLaunch& a, int64_t rbl
   float4 ybuf[YV];
   float4 xbuf;
 
+  // A tile's addresses are a base common to the workgroup plus a 32-bit
+  // offset per thread that does not change from tile to tile, and the range
+  // test compares the tile row with the rows left, so no 64-bit address
+  // arithmetic or compare runs per load.
   auto fetch = [&](int64_t ct) {
+    const float* yt = a.Y + ct * B;
+    const int64_t left = c_end - ct;
+    const int rem = left < kCT ? (int)left : kCT;   // rows of this tile in range
 #pragma unroll
     for (int v = 0; v < YV; ++v) {
       const int e = (threadIdx.x + v * kThreads) * 4;   // element in tile (b fastest)
-      const int64_t c = ct + e / B;
-      ybuf[v] = (c < c_end) ? *reinterpret_cast<const float4*>(a.Y + c * B + (e % B))
-                            : make_float4(0.f, 0.f, 0.f, 0.f);
+      const int row = e / B;
+      ybuf[v] = row < rem ? *reinterpret_cast<const float4*>(yt + (row * B + e % B))
+                          : make_float4(0.f, 0.f, 0.f, 0.f);
     }
     // raw coordinates: the scale is applied in stash(), after the tile's work,
     // so no wait for these loads (which would also wait for Y) lands here
     if (threadIdx.x < kCT) {
-      const int64_t c = ct + threadIdx.x;
-      if (c < c_end)
-        xbuf = make_float4(a.xc[c * a.xc_stride], a.xc[c * a.xc_stride + 1], a.xc[c * a.xc_stride + 2], 0.f);
+      const float* xt = a.xc + ct * a.xc_stride;
+      const int o = (int)threadIdx.x * a.xc_stride;
+      if ((int)threadIdx.x < rem)
+        xbuf = make_float4(xt[o], xt[o + 1], xt[o + 2], 0.f);
       else
         xbuf = make_float4(0.f, 0.f, 0.f, 0.f);
     }
