@@ -68,7 +68,7 @@ def peak_pairs(kernel):
 TRAFFIC = {
     "cube20": {"gamma_src_sha256_16": "81efab07a96bcf05", "fetch_bytes": 37.5e6, "write_bytes": 52.4e6,
                "algorithmic_bytes": 33.2e6},
-    "cube64": {"gamma_src_sha256_16": "3efcc44a654b53e3", "fetch_bytes": 5.933e9, "write_bytes": 7.360e7,
+    "cube64": {"gamma_src_sha256_16": "13652e004824aa0f", "fetch_bytes": 5.861e9, "write_bytes": 7.360e7,
                "algorithmic_bytes": 287496 * (2 * 16 + 8 * 64 + 4)},
 }
 

@@ -397,11 +397,13 @@ __device__ __forceinline__ void gamma_bf16x3_tile(const GammaLaunch& a, int64_t 
       }
     }
     // raw coordinates: the scale is applied in stash(), after the tile's work,
-    // so no wait for these loads (which would also wait for Y) lands here
+    // so no wait for these loads (which would also wait for Y) lands here;
+    // a shared base plus a 32-bit offset per thread, as in the FP32 path
     if (threadIdx.x < kCT) {
-      const int64_t c = ct + threadIdx.x;
-      if (c < c_end)
-        xbuf = make_float4(a.xc[c * a.xc_stride], a.xc[c * a.xc_stride + 1], a.xc[c * a.xc_stride + 2], 0.f);
+      const float* xt = a.xc + ct * a.xc_stride;
+      const int o = (int)threadIdx.x * a.xc_stride;
+      if ((int64_t)threadIdx.x < c_end - ct)
+        xbuf = make_float4(xt[o], xt[o + 1], xt[o + 2], 0.f);
       else
         xbuf = make_float4(0.f, 0.f, 0.f, 0.f);
     }
