@@ -268,25 +268,29 @@ def kernel_rates(warm=3, reps=10):
     """Raw fused kernel product (ka_gamma_apply) at the workload shapes, both
     precisions: median per-launch device time over `reps` launches after
     `warm` warm-up launches, HIP events on the launch stream.  Points are
-    uniform in the unit cube (the kernel's cost does not depend on where the
-    points are); Y is N(0,1)."""
+    tensor grids of the workloads' point counts in the problems' order (first
+    direction fastest) on the workloads' domains: the FP32 Gaussian path takes
+    its centred Gram form for row blocks of small extent, so the cost depends
+    on how the points are ordered.  Y is N(0,1)."""
     import torch
     import paper_2101_00629_amd as K
-    from workloads import normal_block, uniform_points
+    from workloads import normal_block, tensor_grid_points
 
-    shapes = [  # (name, kernel, ell, rows, cols, b)
-        ("cube p3 20^3 Galerkin Gaussian", "gaussian", 0.5, 12167, 12167, 16),
-        ("cube p3 20^3 Galerkin exponential (C0)", "exponential", 1.0, 226981, 226981, 16),
-        ("cube p3 20^3 collocation", "gaussian", 0.5, 12167, 512000, 16),
-        ("annulus p4 32x32x16 Galerkin Gaussian", "gaussian", 0.5, 25920, 25920, 32),
-        ("annulus p4 32x32x16 Galerkin exponential (C0)", "exponential", 0.25, 1081665, 1081665, 32),
-        ("annulus p4 32x32x16 collocation", "gaussian", 0.5, 25920, 2048000, 32),
-        ("cube p2 64^3 Galerkin Gaussian", "gaussian", 0.2, 287496, 287496, 64),
+    shapes = [  # (name, kernel, ell, domain, row grid, column grid, b)
+        ("cube p3 20^3 Galerkin Gaussian", "gaussian", 0.5, "cube", (23, 23, 23), (23, 23, 23), 16),
+        ("cube p3 20^3 Galerkin exponential (C0)", "exponential", 1.0, "cube", (61, 61, 61), (61, 61, 61), 16),
+        ("cube p3 20^3 collocation", "gaussian", 0.5, "cube", (23, 23, 23), (80, 80, 80), 16),
+        ("annulus p4 32x32x16 Galerkin Gaussian", "gaussian", 0.5, "quarter_annulus", (36, 36, 20), (36, 36, 20), 32),
+        ("annulus p4 32x32x16 Galerkin exponential (C0)", "exponential", 0.25, "quarter_annulus", (129, 129, 65),
+         (129, 129, 65), 32),
+        ("annulus p4 32x32x16 collocation", "gaussian", 0.5, "quarter_annulus", (36, 36, 20), (160, 160, 80), 32),
+        ("cube p2 64^3 Galerkin Gaussian", "gaussian", 0.2, "cube", (66, 66, 66), (66, 66, 66), 64),
     ]
     out = []
-    for name, kern, ell, nr, nc, b in shapes:
-        xc = torch.tensor(uniform_points(7, nc), dtype=torch.float32, device="cuda")
-        xr = xc[:nr] if nr <= nc else torch.tensor(uniform_points(8, nr), dtype=torch.float32, device="cuda")
+    for name, kern, ell, dom, gr, gc, b in shapes:
+        xc = torch.tensor(tensor_grid_points(gc, dom), dtype=torch.float32, device="cuda")
+        xr = xc if gr == gc else torch.tensor(tensor_grid_points(gr, dom), dtype=torch.float32, device="cuda")
+        nr, nc = xr.shape[0], xc.shape[0]
         y = torch.tensor(normal_block(9, nc, b, dtype=np.float32), device="cuda")
         z = torch.empty((nr, b), dtype=torch.float32, device="cuda")
         for prec, pname in ((K.KA_FP32, "fp32"), (K.KA_BF16X3, "bf16x3")):

@@ -29,6 +29,7 @@
 #include <stdint.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "ka_internal.hpp"
 
@@ -94,6 +95,28 @@ __device__ __forceinline__ float load_coord(const float* p, int64_t i, int strid
 template <int B>
 constexpr int y_stride() { return (B == 16) ? 16 : B + 16; }
 
+// Centred Gram form of the Gaussian exponent (FP32 path).  With c the centre
+// of the bounding box of a workgroup's rows, xt = x - c and yt = y - c (scaled
+// coordinates),
+//     2^-|x - y|^2 = 2^-|xt|^2 * 2^((2 yt) . xt - |yt|^2),
+// so the exponents of 16 x 16 pairs, less the row term, are one
+// v_mfma_f32_16x16x4_f32: A holds (2 yt, -|yt|^2) of 16 columns and B holds
+// (xt, 1) of 16 rows; the row factor 2^-|xt|^2 multiplies the finished row of
+// the product.  Lane l of the result holds row l % 16 against four columns,
+// which is where the kernel product's A operand expects Gamma when column
+// 4 * (m % 4) + m / 4 of the group is put in A row m: result entry r of lane l
+// is then column 4 r + l / 16, the column of k-slot l / 16 in product step
+// 4 r.  This replaces three differences and three multiply-adds per pair by
+// 1/64 of an MFMA.  Rounding: the terms are of size R^2 (R the half-diagonal
+// of the rows' box) where the difference form's are of size |x - y|^2, so the
+// form is taken only for boxes with R^2 <= kGramR2 in scaled units (the
+// exponent is then off by a few units of 2^-24 R^2 at most, Gamma by ln 2
+// times that relative, and the factored terms stay below 2^(R^2)); wider row
+// blocks keep the difference form.  Row blocks of tensor-grid points in their
+// natural order qualify at the workload sizes: R^2 = 9.0 on the 66^3 cube at
+// ell = 0.2, at most 11.5 on the quarter annulus r in [1, 2] at ell = 0.5.
+constexpr float kGramR2 = 16.f;
+
 // One work item: rows [rblk * ROWS, +ROWS) against the column range of split
 // `split` of one kernel product.  LDS buffers are provided by the caller.
 template <int KERNEL, int B, int RB>
@@ -102,6 +125,8 @@ __device__ __forceinline__ void gamma_f32_tile(const GammaLaunch& a, int64_t rbl
   constexpr int NT = B / 16;
   constexpr int YS = y_stride<B>();
   constexpr int ROWS = 4 * 16 * RB;
+  constexpr bool kGauss = KERNEL == KA_GAUSSIAN;
+  __shared__ float s_box[4][8];   // per-wave bounding boxes of the rows (Gaussian)
 
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
@@ -117,6 +142,27 @@ __device__ __forceinline__ void gamma_f32_tile(const GammaLaunch& a, int64_t rbl
     rx[rb] = load_coord(a.xr, r, a.xr_stride, 0, a.coord_scale);
     ry[rb] = load_coord(a.xr, r, a.xr_stride, 1, a.coord_scale);
     rz[rb] = load_coord(a.xr, r, a.xr_stride, 2, a.coord_scale);
+  }
+  if constexpr (kGauss) {
+    // the wave's box (lanes l and l + 16 hold the same rows), to LDS
+    float lo[3] = {rx[0], ry[0], rz[0]}, hi[3] = {rx[0], ry[0], rz[0]};
+#pragma unroll
+    for (int rb = 1; rb < RB; ++rb) {
+      lo[0] = fminf(lo[0], rx[rb]); hi[0] = fmaxf(hi[0], rx[rb]);
+      lo[1] = fminf(lo[1], ry[rb]); hi[1] = fmaxf(hi[1], ry[rb]);
+      lo[2] = fminf(lo[2], rz[rb]); hi[2] = fmaxf(hi[2], rz[rb]);
+    }
+#pragma unroll
+    for (int o = 1; o < 16; o <<= 1)
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        lo[k] = fminf(lo[k], __shfl_xor(lo[k], o));
+        hi[k] = fmaxf(hi[k], __shfl_xor(hi[k], o));
+      }
+    if (lane < 3) {
+      s_box[wave][lane] = lane == 0 ? lo[0] : (lane == 1 ? lo[1] : lo[2]);
+      s_box[wave][4 + lane] = lane == 0 ? hi[0] : (lane == 1 ? hi[1] : hi[2]);
+    }
   }
 
   f4v acc[RB][NT];
@@ -173,67 +219,144 @@ __device__ __forceinline__ void gamma_f32_tile(const GammaLaunch& a, int64_t rbl
         xbuf = make_float4(0.f, 0.f, 0.f, 0.f);
     }
   };
-  auto stash = [&](int buf) {
-#pragma unroll
-    for (int v = 0; v < YV; ++v) {
-      const int e = (threadIdx.x + v * kThreads) * 4;
-      float* dst = &s_y[buf][(e / B) * YS + (e % B)];
-      dst[0] = ybuf[v].x; dst[1] = ybuf[v].y; dst[2] = ybuf[v].z; dst[3] = ybuf[v].w;
-    }
-    if (threadIdx.x < kCT)
-      s_x[buf][threadIdx.x] = make_float4(xbuf.x * a.coord_scale, xbuf.y * a.coord_scale, xbuf.z * a.coord_scale, 0.f);
-  };
 
-  int buf = 0;
   fetch(c_begin);
-  stash(0);
-  __syncthreads();
-  // Tiles go in groups of kFlushTiles with an unconditional flush after each
-  // group, so the MFMA accumulators enter every group at zero and are never
-  // carried around the loop.  The next tile is always fetched: beyond c_end
-  // it is zero-filled (Y = 0), so a padding tile in the last group adds
-  // exactly zero.
-  for (int64_t cg = c_begin; cg < c_end; cg += kFlushTiles * kCT) {
+  // centre and extent of the workgroup's rows; uniform over the workgroup
+  float cx = 0.f, cy = 0.f, cz = 0.f;
+  bool gram = false;
+  if constexpr (kGauss) {
+    __syncthreads();
+    float lo[3], hi[3];
 #pragma unroll
-  for (int f = 0; f < kFlushTiles; ++f) {
-    const int64_t ct = cg + f * kCT;
-    fetch(ct + kCT);
-    // Fully unrolled: with a rolled loop the register allocator rotates the
-    // accumulators through AGPR copies every step (measured at b = 64: 40
-    // extra VALU instructions per 16 MFMAs).  The LDS operands of step k + 1
-    // are read before step k is computed, and a scheduling barrier keeps the
-    // compiler from sinking those reads back to their use, so every LDS read
-    // has one whole step of work to complete in (measured: +4-5% at b = 16).
-    float4 pc = s_x[buf][lane >> 4];
-    float yc[NT];
-#pragma unroll
-    for (int t = 0; t < NT; ++t) yc[t] = s_y[buf][(lane >> 4) * YS + 16 * t + (lane & 15)];
-#pragma unroll
-    for (int k = 0; k < kCT; k += 4) {
-      const float4 p = pc;
-      float yv[NT];
-#pragma unroll
-      for (int t = 0; t < NT; ++t) yv[t] = yc[t];
-      if (k + 4 < kCT) {
-        const int cn = k + 4 + (lane >> 4);
-        pc = s_x[buf][cn];
-#pragma unroll
-        for (int t = 0; t < NT; ++t) yc[t] = s_y[buf][cn * YS + 16 * t + (lane & 15)];
-      }
-      __builtin_amdgcn_sched_barrier(0);
+    for (int k = 0; k < 3; ++k) {
+      lo[k] = fminf(fminf(s_box[0][k], s_box[1][k]), fminf(s_box[2][k], s_box[3][k]));
+      hi[k] = fmaxf(fmaxf(s_box[0][4 + k], s_box[1][4 + k]), fmaxf(s_box[2][4 + k], s_box[3][4 + k]));
+    }
+    cx = 0.5f * (lo[0] + hi[0]);
+    cy = 0.5f * (lo[1] + hi[1]);
+    cz = 0.5f * (lo[2] + hi[2]);
+    const float ex = 0.5f * (hi[0] - lo[0]), ey = 0.5f * (hi[1] - lo[1]), ez = 0.5f * (hi[2] - lo[2]);
+    gram = __builtin_amdgcn_readfirstlane((int)(ex * ex + ey * ey + ez * ez <= kGramR2)) != 0;
+  }
+
+  // the tile loop, for the difference form (G false) or the Gram form
+  auto run = [&](auto gram_tag) {
+    constexpr bool G = decltype(gram_tag)::value;
+    // Gram form: B operand (xt, 1) of each row sub-block
+    float bx[RB];
+    if constexpr (G) {
+      const int q = lane >> 4;
 #pragma unroll
       for (int rb = 0; rb < RB; ++rb) {
-        const float g = __builtin_amdgcn_exp2f(-pair_exponent<KERNEL>(rx[rb] - p.x, ry[rb] - p.y, rz[rb] - p.z));
-#pragma unroll
-        for (int t = 0; t < NT; ++t)
-          acc[rb][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(g, yv[t], acc[rb][t], 0, 0, 0);
+        const float tx = rx[rb] - cx, ty = ry[rb] - cy, tz = rz[rb] - cz;
+        bx[rb] = q == 0 ? tx : (q == 1 ? ty : (q == 2 ? tz : 1.f));
       }
     }
-    stash(buf ^ 1);
+    const f4v zero4 = {0.f, 0.f, 0.f, 0.f};
+    auto stash = [&](int buf) {
+#pragma unroll
+      for (int v = 0; v < YV; ++v) {
+        const int e = (threadIdx.x + v * kThreads) * 4;
+        float* dst = &s_y[buf][(e / B) * YS + (e % B)];
+        dst[0] = ybuf[v].x; dst[1] = ybuf[v].y; dst[2] = ybuf[v].z; dst[3] = ybuf[v].w;
+      }
+      if (threadIdx.x < kCT) {
+        if constexpr (G) {
+          const float tx = xbuf.x * a.coord_scale - cx, ty = xbuf.y * a.coord_scale - cy,
+                      tz = xbuf.z * a.coord_scale - cz;
+          s_x[buf][threadIdx.x] = make_float4(2.f * tx, 2.f * ty, 2.f * tz,
+                                              -__builtin_fmaf(tz, tz, __builtin_fmaf(ty, ty, tx * tx)));
+        } else {
+          s_x[buf][threadIdx.x] =
+              make_float4(xbuf.x * a.coord_scale, xbuf.y * a.coord_scale, xbuf.z * a.coord_scale, 0.f);
+        }
+      }
+    };
+
+    int buf = 0;
+    stash(0);
     __syncthreads();
-    buf ^= 1;
-  }
-    flush();
+    // Tiles go in groups of kFlushTiles with an unconditional flush after each
+    // group, so the MFMA accumulators enter every group at zero and are never
+    // carried around the loop.  The next tile is always fetched: beyond c_end
+    // it is zero-filled (Y = 0), so a padding tile in the last group adds
+    // exactly zero.
+    for (int64_t cg = c_begin; cg < c_end; cg += kFlushTiles * kCT) {
+#pragma unroll
+      for (int f = 0; f < kFlushTiles; ++f) {
+        const int64_t ct = cg + f * kCT;
+        fetch(ct + kCT);
+        // Fully unrolled: with a rolled loop the register allocator rotates the
+        // accumulators through AGPR copies every step (measured at b = 64: 40
+        // extra VALU instructions per 16 MFMAs).  The LDS operands of step k + 1
+        // are read before step k is computed, and a scheduling barrier keeps the
+        // compiler from sinking those reads back to their use, so every LDS read
+        // has one whole step of work to complete in (measured: +4-5% at b = 16).
+        float4 pc = s_x[buf][lane >> 4];
+        float yc[NT];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) yc[t] = s_y[buf][(lane >> 4) * YS + 16 * t + (lane & 15)];
+        // Gram form: the exponents of each group of 16 columns, one group ahead
+        const float* sxf = reinterpret_cast<const float*>(&s_x[buf][0]);
+        const int aoff = 4 * (4 * (lane & 3) + ((lane >> 2) & 3)) + (lane >> 4);
+        f4v dcur[RB], dnext[RB];
+        if constexpr (G) {
+          const float ad = sxf[aoff];
+#pragma unroll
+          for (int rb = 0; rb < RB; ++rb) dcur[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(ad, bx[rb], zero4, 0, 0, 0);
+        }
+#pragma unroll
+        for (int k = 0; k < kCT; k += 4) {
+          const float4 p = pc;
+          float yv[NT];
+#pragma unroll
+          for (int t = 0; t < NT; ++t) yv[t] = yc[t];
+          float adn = 0.f;
+          if (k + 4 < kCT) {
+            const int cn = k + 4 + (lane >> 4);
+            if constexpr (!G) pc = s_x[buf][cn];
+#pragma unroll
+            for (int t = 0; t < NT; ++t) yc[t] = s_y[buf][cn * YS + 16 * t + (lane & 15)];
+          }
+          if constexpr (G) {
+            if (k % 16 == 0 && k + 16 < kCT) adn = sxf[4 * (k + 16) + aoff];
+          }
+          __builtin_amdgcn_sched_barrier(0);
+          if constexpr (G) {
+            if (k % 16 == 0 && k + 16 < kCT) {
+#pragma unroll
+              for (int rb = 0; rb < RB; ++rb)
+                dnext[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(adn, bx[rb], zero4, 0, 0, 0);
+            }
+          }
+#pragma unroll
+          for (int rb = 0; rb < RB; ++rb) {
+            float g;
+            if constexpr (G) g = __builtin_amdgcn_exp2f(dcur[rb][(k / 4) % 4]);
+            else g = __builtin_amdgcn_exp2f(-pair_exponent<KERNEL>(rx[rb] - p.x, ry[rb] - p.y, rz[rb] - p.z));
+#pragma unroll
+            for (int t = 0; t < NT; ++t)
+              acc[rb][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(g, yv[t], acc[rb][t], 0, 0, 0);
+          }
+          if constexpr (G) {
+            if (k % 16 == 12 && k + 4 < kCT) {
+#pragma unroll
+              for (int rb = 0; rb < RB; ++rb) dcur[rb] = dnext[rb];
+            }
+          }
+        }
+        stash(buf ^ 1);
+        __syncthreads();
+        buf ^= 1;
+      }
+      flush();
+    }
+  };
+  if constexpr (kGauss) {
+    if (gram) run(std::true_type{});
+    else run(std::false_type{});
+  } else {
+    run(std::false_type{});
   }
 
   float* out = a.nsplit > 1 ? a.partial + (size_t)split * a.nr * B : a.Z;
@@ -244,8 +367,15 @@ __device__ __forceinline__ void gamma_f32_tile(const GammaLaunch& a, int64_t rbl
       const int64_t row = row0 + 16 * rb + 4 * (lane >> 4) + r;
       if (row < a.nr) {
         const float sc = a.out_scale * (a.rs ? a.rs[row] : 1.0f);
+        double f = sc;
+        if (gram) {   // the row factor 2^-|xt|^2 of the Gram form
+          const float tx = load_coord(a.xr, row, a.xr_stride, 0, a.coord_scale) - cx;
+          const float ty = load_coord(a.xr, row, a.xr_stride, 1, a.coord_scale) - cy;
+          const float tz = load_coord(a.xr, row, a.xr_stride, 2, a.coord_scale) - cz;
+          f *= exp2(-(double)__builtin_fmaf(tz, tz, __builtin_fmaf(ty, ty, tx * tx)));
+        }
 #pragma unroll
-        for (int t = 0; t < NT; ++t) out[row * B + 16 * t + (lane & 15)] = (float)((double)sc * tot[rb][t][r]);
+        for (int t = 0; t < NT; ++t) out[row * B + 16 * t + (lane & 15)] = (float)(f * tot[rb][t][r]);
       }
     }
   }

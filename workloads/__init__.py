@@ -143,6 +143,23 @@ def uniform_points(seed, n, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0)):
     return lo + (hi - lo) * rng.random((n, 3))
 
 
+def tensor_grid_points(counts, domain="cube"):
+    """Tensor grid of counts[0] x counts[1] x counts[2] points with the first
+    direction fastest (the order of the problems' point sets), evenly spaced in
+    the parameters, shape (n, 3), FP64.  domain "cube": the unit cube.
+    "quarter_annulus": angle 0..pi/2 (first direction), radius 1..2, height
+    0..1."""
+    u = [np.linspace(0.0, 1.0, int(c)) for c in counts]
+    w, v, t = np.meshgrid(u[2], u[1], u[0], indexing="ij")
+    t, v, w = t.ravel(), v.ravel(), w.ravel()
+    if domain == "cube":
+        return np.stack([t, v, w], axis=1)
+    if domain == "quarter_annulus":
+        r, th = 1.0 + v, 0.5 * math.pi * t
+        return np.stack([r * np.cos(th), r * np.sin(th), w], axis=1)
+    raise ValueError(domain)
+
+
 SERVING_SEED = 210100629
 
 
