@@ -29,7 +29,6 @@
 #include <stdint.h>
 
 #include <algorithm>
-#include <type_traits>
 
 #include "ka_internal.hpp"
 
@@ -117,6 +116,86 @@ constexpr int y_stride() { return (B == 16) ? 16 : B + 16; }
 // ell = 0.2, at most 11.5 on the quarter annulus r in [1, 2] at ell = 0.5.
 constexpr float kGramR2 = 16.f;
 
+// Bounding box of a wave's rows (lanes l and l + 16 hold the same rows) into
+// the wave's entry of s_box: lo in [0..2], hi in [4..6].
+template <int RB>
+__device__ __forceinline__ void gram_box_put(const float* rx, const float* ry, const float* rz, int lane, int wave,
+                                             float (*s_box)[8]) {
+  float lo[3] = {rx[0], ry[0], rz[0]}, hi[3] = {rx[0], ry[0], rz[0]};
+#pragma unroll
+  for (int rb = 1; rb < RB; ++rb) {
+    lo[0] = fminf(lo[0], rx[rb]); hi[0] = fmaxf(hi[0], rx[rb]);
+    lo[1] = fminf(lo[1], ry[rb]); hi[1] = fmaxf(hi[1], ry[rb]);
+    lo[2] = fminf(lo[2], rz[rb]); hi[2] = fmaxf(hi[2], rz[rb]);
+  }
+#pragma unroll
+  for (int o = 1; o < 16; o <<= 1)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      lo[k] = fminf(lo[k], __shfl_xor(lo[k], o));
+      hi[k] = fmaxf(hi[k], __shfl_xor(hi[k], o));
+    }
+  if (lane < 3) {
+    s_box[wave][lane] = lane == 0 ? lo[0] : (lane == 1 ? lo[1] : lo[2]);
+    s_box[wave][4 + lane] = lane == 0 ? hi[0] : (lane == 1 ? hi[1] : hi[2]);
+  }
+}
+
+// After gram_box_put on every wave: a barrier, then the centre of the
+// workgroup's box and whether the Gram form applies (uniform over the
+// workgroup).  The barrier also orders this read before any later rewrite of
+// s_box: every wave passes at least one more barrier before its next item.
+__device__ __forceinline__ bool gram_box_take(float (*s_box)[8], float& cx, float& cy, float& cz) {
+  __syncthreads();
+  float lo[3], hi[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    lo[k] = fminf(fminf(s_box[0][k], s_box[1][k]), fminf(s_box[2][k], s_box[3][k]));
+    hi[k] = fmaxf(fmaxf(s_box[0][4 + k], s_box[1][4 + k]), fmaxf(s_box[2][4 + k], s_box[3][4 + k]));
+  }
+  cx = 0.5f * (lo[0] + hi[0]);
+  cy = 0.5f * (lo[1] + hi[1]);
+  cz = 0.5f * (lo[2] + hi[2]);
+  const float ex = 0.5f * (hi[0] - lo[0]), ey = 0.5f * (hi[1] - lo[1]), ez = 0.5f * (hi[2] - lo[2]);
+  return __builtin_amdgcn_readfirstlane((int)(ex * ex + ey * ey + ez * ez <= kGramR2)) != 0;
+}
+
+// A-operand data of one column in the Gram form: (2 yt, -|yt|^2) from the raw
+// coordinates.
+__device__ __forceinline__ float4 gram_column(float4 raw, float scale, float cx, float cy, float cz) {
+  const float tx = raw.x * scale - cx, ty = raw.y * scale - cy, tz = raw.z * scale - cz;
+  return make_float4(2.f * tx, 2.f * ty, 2.f * tz, -__builtin_fmaf(tz, tz, __builtin_fmaf(ty, ty, tx * tx)));
+}
+
+// The row factor 2^-|xt|^2 of the Gram form.
+__device__ __forceinline__ double gram_row_factor(const GammaLaunch& a, int64_t row, float cx, float cy, float cz) {
+  const float tx = load_coord(a.xr, row, a.xr_stride, 0, a.coord_scale) - cx;
+  const float ty = load_coord(a.xr, row, a.xr_stride, 1, a.coord_scale) - cy;
+  const float tz = load_coord(a.xr, row, a.xr_stride, 2, a.coord_scale) - cz;
+  return exp2(-(double)__builtin_fmaf(tz, tz, __builtin_fmaf(ty, ty, tx * tx)));
+}
+
+// Row box of a work item and whether the centred Gram form applies to it
+// (Gaussian kernel only); contains a workgroup barrier.
+template <int RB>
+__device__ __forceinline__ bool gram_rows(const GammaLaunch& a, int64_t rblk, float (*s_box)[8], float& cx,
+                                          float& cy, float& cz) {
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int64_t row0 = rblk * (4 * 16 * RB) + wave * 16 * RB;
+  float rx[RB], ry[RB], rz[RB];
+#pragma unroll
+  for (int rb = 0; rb < RB; ++rb) {
+    int64_t r = row0 + 16 * rb + (lane & 15);
+    if (r >= a.nr) r = a.nr - 1;
+    rx[rb] = load_coord(a.xr, r, a.xr_stride, 0, a.coord_scale);
+    ry[rb] = load_coord(a.xr, r, a.xr_stride, 1, a.coord_scale);
+    rz[rb] = load_coord(a.xr, r, a.xr_stride, 2, a.coord_scale);
+  }
+  gram_box_put<RB>(rx, ry, rz, lane, wave, s_box);
+  return gram_box_take(s_box, cx, cy, cz);
+}
+
 // One work item: rows [rblk * ROWS, +ROWS) against the column range of split
 // `split` of one kernel product.  LDS buffers are provided by the caller.
 template <int KERNEL, int B, int RB>
@@ -125,8 +204,6 @@ __device__ __forceinline__ void gamma_f32_tile(const GammaLaunch& a, int64_t rbl
   constexpr int NT = B / 16;
   constexpr int YS = y_stride<B>();
   constexpr int ROWS = 4 * 16 * RB;
-  constexpr bool kGauss = KERNEL == KA_GAUSSIAN;
-  __shared__ float s_box[4][8];   // per-wave bounding boxes of the rows (Gaussian)
 
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
@@ -142,27 +219,6 @@ __device__ __forceinline__ void gamma_f32_tile(const GammaLaunch& a, int64_t rbl
     rx[rb] = load_coord(a.xr, r, a.xr_stride, 0, a.coord_scale);
     ry[rb] = load_coord(a.xr, r, a.xr_stride, 1, a.coord_scale);
     rz[rb] = load_coord(a.xr, r, a.xr_stride, 2, a.coord_scale);
-  }
-  if constexpr (kGauss) {
-    // the wave's box (lanes l and l + 16 hold the same rows), to LDS
-    float lo[3] = {rx[0], ry[0], rz[0]}, hi[3] = {rx[0], ry[0], rz[0]};
-#pragma unroll
-    for (int rb = 1; rb < RB; ++rb) {
-      lo[0] = fminf(lo[0], rx[rb]); hi[0] = fmaxf(hi[0], rx[rb]);
-      lo[1] = fminf(lo[1], ry[rb]); hi[1] = fmaxf(hi[1], ry[rb]);
-      lo[2] = fminf(lo[2], rz[rb]); hi[2] = fmaxf(hi[2], rz[rb]);
-    }
-#pragma unroll
-    for (int o = 1; o < 16; o <<= 1)
-#pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        lo[k] = fminf(lo[k], __shfl_xor(lo[k], o));
-        hi[k] = fmaxf(hi[k], __shfl_xor(hi[k], o));
-      }
-    if (lane < 3) {
-      s_box[wave][lane] = lane == 0 ? lo[0] : (lane == 1 ? lo[1] : lo[2]);
-      s_box[wave][4 + lane] = lane == 0 ? hi[0] : (lane == 1 ? hi[1] : hi[2]);
-    }
   }
 
   f4v acc[RB][NT];
@@ -219,144 +275,67 @@ __device__ __forceinline__ void gamma_f32_tile(const GammaLaunch& a, int64_t rbl
         xbuf = make_float4(0.f, 0.f, 0.f, 0.f);
     }
   };
-
-  fetch(c_begin);
-  // centre and extent of the workgroup's rows; uniform over the workgroup
-  float cx = 0.f, cy = 0.f, cz = 0.f;
-  bool gram = false;
-  if constexpr (kGauss) {
-    __syncthreads();
-    float lo[3], hi[3];
+  auto stash = [&](int buf) {
 #pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      lo[k] = fminf(fminf(s_box[0][k], s_box[1][k]), fminf(s_box[2][k], s_box[3][k]));
-      hi[k] = fmaxf(fmaxf(s_box[0][4 + k], s_box[1][4 + k]), fmaxf(s_box[2][4 + k], s_box[3][4 + k]));
+    for (int v = 0; v < YV; ++v) {
+      const int e = (threadIdx.x + v * kThreads) * 4;
+      float* dst = &s_y[buf][(e / B) * YS + (e % B)];
+      dst[0] = ybuf[v].x; dst[1] = ybuf[v].y; dst[2] = ybuf[v].z; dst[3] = ybuf[v].w;
     }
-    cx = 0.5f * (lo[0] + hi[0]);
-    cy = 0.5f * (lo[1] + hi[1]);
-    cz = 0.5f * (lo[2] + hi[2]);
-    const float ex = 0.5f * (hi[0] - lo[0]), ey = 0.5f * (hi[1] - lo[1]), ez = 0.5f * (hi[2] - lo[2]);
-    gram = __builtin_amdgcn_readfirstlane((int)(ex * ex + ey * ey + ez * ez <= kGramR2)) != 0;
-  }
+    if (threadIdx.x < kCT)
+      s_x[buf][threadIdx.x] = make_float4(xbuf.x * a.coord_scale, xbuf.y * a.coord_scale, xbuf.z * a.coord_scale, 0.f);
+  };
 
-  // the tile loop, for the difference form (G false) or the Gram form
-  auto run = [&](auto gram_tag) {
-    constexpr bool G = decltype(gram_tag)::value;
-    // Gram form: B operand (xt, 1) of each row sub-block
-    float bx[RB];
-    if constexpr (G) {
-      const int q = lane >> 4;
+  int buf = 0;
+  fetch(c_begin);
+  stash(0);
+  __syncthreads();
+  // Tiles go in groups of kFlushTiles with an unconditional flush after each
+  // group, so the MFMA accumulators enter every group at zero and are never
+  // carried around the loop.  The next tile is always fetched: beyond c_end
+  // it is zero-filled (Y = 0), so a padding tile in the last group adds
+  // exactly zero.
+  for (int64_t cg = c_begin; cg < c_end; cg += kFlushTiles * kCT) {
+#pragma unroll
+  for (int f = 0; f < kFlushTiles; ++f) {
+    const int64_t ct = cg + f * kCT;
+    fetch(ct + kCT);
+    // Fully unrolled: with a rolled loop the register allocator rotates the
+    // accumulators through AGPR copies every step (measured at b = 64: 40
+    // extra VALU instructions per 16 MFMAs).  The LDS operands of step k + 1
+    // are read before step k is computed, and a scheduling barrier keeps the
+    // compiler from sinking those reads back to their use, so every LDS read
+    // has one whole step of work to complete in (measured: +4-5% at b = 16).
+    float4 pc = s_x[buf][lane >> 4];
+    float yc[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) yc[t] = s_y[buf][(lane >> 4) * YS + 16 * t + (lane & 15)];
+#pragma unroll
+    for (int k = 0; k < kCT; k += 4) {
+      const float4 p = pc;
+      float yv[NT];
+#pragma unroll
+      for (int t = 0; t < NT; ++t) yv[t] = yc[t];
+      if (k + 4 < kCT) {
+        const int cn = k + 4 + (lane >> 4);
+        pc = s_x[buf][cn];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) yc[t] = s_y[buf][cn * YS + 16 * t + (lane & 15)];
+      }
+      __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
       for (int rb = 0; rb < RB; ++rb) {
-        const float tx = rx[rb] - cx, ty = ry[rb] - cy, tz = rz[rb] - cz;
-        bx[rb] = q == 0 ? tx : (q == 1 ? ty : (q == 2 ? tz : 1.f));
+        const float g = __builtin_amdgcn_exp2f(-pair_exponent<KERNEL>(rx[rb] - p.x, ry[rb] - p.y, rz[rb] - p.z));
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+          acc[rb][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(g, yv[t], acc[rb][t], 0, 0, 0);
       }
     }
-    const f4v zero4 = {0.f, 0.f, 0.f, 0.f};
-    auto stash = [&](int buf) {
-#pragma unroll
-      for (int v = 0; v < YV; ++v) {
-        const int e = (threadIdx.x + v * kThreads) * 4;
-        float* dst = &s_y[buf][(e / B) * YS + (e % B)];
-        dst[0] = ybuf[v].x; dst[1] = ybuf[v].y; dst[2] = ybuf[v].z; dst[3] = ybuf[v].w;
-      }
-      if (threadIdx.x < kCT) {
-        if constexpr (G) {
-          const float tx = xbuf.x * a.coord_scale - cx, ty = xbuf.y * a.coord_scale - cy,
-                      tz = xbuf.z * a.coord_scale - cz;
-          s_x[buf][threadIdx.x] = make_float4(2.f * tx, 2.f * ty, 2.f * tz,
-                                              -__builtin_fmaf(tz, tz, __builtin_fmaf(ty, ty, tx * tx)));
-        } else {
-          s_x[buf][threadIdx.x] =
-              make_float4(xbuf.x * a.coord_scale, xbuf.y * a.coord_scale, xbuf.z * a.coord_scale, 0.f);
-        }
-      }
-    };
-
-    int buf = 0;
-    stash(0);
+    stash(buf ^ 1);
     __syncthreads();
-    // Tiles go in groups of kFlushTiles with an unconditional flush after each
-    // group, so the MFMA accumulators enter every group at zero and are never
-    // carried around the loop.  The next tile is always fetched: beyond c_end
-    // it is zero-filled (Y = 0), so a padding tile in the last group adds
-    // exactly zero.
-    for (int64_t cg = c_begin; cg < c_end; cg += kFlushTiles * kCT) {
-#pragma unroll
-      for (int f = 0; f < kFlushTiles; ++f) {
-        const int64_t ct = cg + f * kCT;
-        fetch(ct + kCT);
-        // Fully unrolled: with a rolled loop the register allocator rotates the
-        // accumulators through AGPR copies every step (measured at b = 64: 40
-        // extra VALU instructions per 16 MFMAs).  The LDS operands of step k + 1
-        // are read before step k is computed, and a scheduling barrier keeps the
-        // compiler from sinking those reads back to their use, so every LDS read
-        // has one whole step of work to complete in (measured: +4-5% at b = 16).
-        float4 pc = s_x[buf][lane >> 4];
-        float yc[NT];
-#pragma unroll
-        for (int t = 0; t < NT; ++t) yc[t] = s_y[buf][(lane >> 4) * YS + 16 * t + (lane & 15)];
-        // Gram form: the exponents of each group of 16 columns, one group ahead
-        const float* sxf = reinterpret_cast<const float*>(&s_x[buf][0]);
-        const int aoff = 4 * (4 * (lane & 3) + ((lane >> 2) & 3)) + (lane >> 4);
-        f4v dcur[RB], dnext[RB];
-        if constexpr (G) {
-          const float ad = sxf[aoff];
-#pragma unroll
-          for (int rb = 0; rb < RB; ++rb) dcur[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(ad, bx[rb], zero4, 0, 0, 0);
-        }
-#pragma unroll
-        for (int k = 0; k < kCT; k += 4) {
-          const float4 p = pc;
-          float yv[NT];
-#pragma unroll
-          for (int t = 0; t < NT; ++t) yv[t] = yc[t];
-          float adn = 0.f;
-          if (k + 4 < kCT) {
-            const int cn = k + 4 + (lane >> 4);
-            if constexpr (!G) pc = s_x[buf][cn];
-#pragma unroll
-            for (int t = 0; t < NT; ++t) yc[t] = s_y[buf][cn * YS + 16 * t + (lane & 15)];
-          }
-          if constexpr (G) {
-            if (k % 16 == 0 && k + 16 < kCT) adn = sxf[4 * (k + 16) + aoff];
-          }
-          __builtin_amdgcn_sched_barrier(0);
-          if constexpr (G) {
-            if (k % 16 == 0 && k + 16 < kCT) {
-#pragma unroll
-              for (int rb = 0; rb < RB; ++rb)
-                dnext[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(adn, bx[rb], zero4, 0, 0, 0);
-            }
-          }
-#pragma unroll
-          for (int rb = 0; rb < RB; ++rb) {
-            float g;
-            if constexpr (G) g = __builtin_amdgcn_exp2f(dcur[rb][(k / 4) % 4]);
-            else g = __builtin_amdgcn_exp2f(-pair_exponent<KERNEL>(rx[rb] - p.x, ry[rb] - p.y, rz[rb] - p.z));
-#pragma unroll
-            for (int t = 0; t < NT; ++t)
-              acc[rb][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(g, yv[t], acc[rb][t], 0, 0, 0);
-          }
-          if constexpr (G) {
-            if (k % 16 == 12 && k + 4 < kCT) {
-#pragma unroll
-              for (int rb = 0; rb < RB; ++rb) dcur[rb] = dnext[rb];
-            }
-          }
-        }
-        stash(buf ^ 1);
-        __syncthreads();
-        buf ^= 1;
-      }
-      flush();
-    }
-  };
-  if constexpr (kGauss) {
-    if (gram) run(std::true_type{});
-    else run(std::false_type{});
-  } else {
-    run(std::false_type{});
+    buf ^= 1;
+  }
+    flush();
   }
 
   float* out = a.nsplit > 1 ? a.partial + (size_t)split * a.nr * B : a.Z;
@@ -367,18 +346,185 @@ __device__ __forceinline__ void gamma_f32_tile(const GammaLaunch& a, int64_t rbl
       const int64_t row = row0 + 16 * rb + 4 * (lane >> 4) + r;
       if (row < a.nr) {
         const float sc = a.out_scale * (a.rs ? a.rs[row] : 1.0f);
-        double f = sc;
-        if (gram) {   // the row factor 2^-|xt|^2 of the Gram form
-          const float tx = load_coord(a.xr, row, a.xr_stride, 0, a.coord_scale) - cx;
-          const float ty = load_coord(a.xr, row, a.xr_stride, 1, a.coord_scale) - cy;
-          const float tz = load_coord(a.xr, row, a.xr_stride, 2, a.coord_scale) - cz;
-          f *= exp2(-(double)__builtin_fmaf(tz, tz, __builtin_fmaf(ty, ty, tx * tx)));
+#pragma unroll
+        for (int t = 0; t < NT; ++t) out[row * B + 16 * t + (lane & 15)] = (float)((double)sc * tot[rb][t][r]);
+      }
+    }
+  }
+}
+
+// The FP32 tile in the centred Gram form (Gaussian kernel, centre c of the
+// rows' box): per group of 16 columns and row sub-block one Gram MFMA gives
+// the exponents, computed one group ahead of the product steps that use them.
+template <int B, int RB>
+__device__ __forceinline__ void gamma_f32_gram_tile(const GammaLaunch& a, int64_t rblk, int split,
+                                                    float4 (*s_x)[kCT], float (*s_y)[kCT * y_stride<B>()],
+                                                    float cx, float cy, float cz) {
+  constexpr int NT = B / 16;
+  constexpr int YS = y_stride<B>();
+  constexpr int ROWS = 4 * 16 * RB;
+
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int64_t row0 = rblk * ROWS + wave * 16 * RB;
+  const int64_t c_begin = (int64_t)split * a.cols_per_split;
+  const int64_t c_end = (c_begin + a.cols_per_split < a.nc) ? c_begin + a.cols_per_split : a.nc;
+
+  // B operand (xt, 1) of each row sub-block
+  float bx[RB];
+#pragma unroll
+  for (int rb = 0; rb < RB; ++rb) {
+    int64_t r = row0 + 16 * rb + (lane & 15);
+    if (r >= a.nr) r = a.nr - 1;
+    const int q = lane >> 4;
+    const float v = q < 3 ? load_coord(a.xr, r, a.xr_stride, q, a.coord_scale) : 0.f;
+    bx[rb] = q == 0 ? v - cx : (q == 1 ? v - cy : (q == 2 ? v - cz : 1.f));
+  }
+  const f4v zero4 = {0.f, 0.f, 0.f, 0.f};
+
+  f4v acc[RB][NT];
+#pragma unroll
+  for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[rb][t] = (f4v){0.f, 0.f, 0.f, 0.f};
+  d4v tot[RB][NT];   // FP64 running totals, as in the difference form
+#pragma unroll
+  for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+    for (int t = 0; t < NT; ++t) tot[rb][t] = (d4v){0.0, 0.0, 0.0, 0.0};
+  auto flush = [&]() {
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        tot[rb][t] += __builtin_convertvector(acc[rb][t], d4v);
+        acc[rb][t] = (f4v){0.f, 0.f, 0.f, 0.f};
+      }
+  };
+
+  constexpr int YV = kCT * B / 4 / kThreads;
+  float4 ybuf[YV];
+  float4 xbuf;
+  auto fetch = [&](int64_t ct) {
+    const float* yt = a.Y + ct * B;
+    const int64_t left = c_end - ct;
+    const int rem = left < kCT ? (int)left : kCT;
+#pragma unroll
+    for (int v = 0; v < YV; ++v) {
+      const int e = (threadIdx.x + v * kThreads) * 4;
+      const int row = e / B;
+      ybuf[v] = row < rem ? *reinterpret_cast<const float4*>(yt + (row * B + e % B))
+                          : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+    if (threadIdx.x < kCT) {
+      const float* xt = a.xc + ct * a.xc_stride;
+      const int o = (int)threadIdx.x * a.xc_stride;
+      if ((int)threadIdx.x < rem)
+        xbuf = make_float4(xt[o], xt[o + 1], xt[o + 2], 0.f);
+      else
+        xbuf = make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+  };
+  auto stash = [&](int buf) {
+#pragma unroll
+    for (int v = 0; v < YV; ++v) {
+      const int e = (threadIdx.x + v * kThreads) * 4;
+      float* dst = &s_y[buf][(e / B) * YS + (e % B)];
+      dst[0] = ybuf[v].x; dst[1] = ybuf[v].y; dst[2] = ybuf[v].z; dst[3] = ybuf[v].w;
+    }
+    if (threadIdx.x < kCT) s_x[buf][threadIdx.x] = gram_column(xbuf, a.coord_scale, cx, cy, cz);
+  };
+
+  int buf = 0;
+  fetch(c_begin);
+  stash(0);
+  __syncthreads();
+  // A operand of the Gram MFMA: component l / 16 of column 4 (m % 4) + m / 4
+  // of the group, m = l % 16
+  const int aoff = 4 * (4 * (lane & 3) + ((lane >> 2) & 3)) + (lane >> 4);
+  for (int64_t cg = c_begin; cg < c_end; cg += kFlushTiles * kCT) {
+#pragma unroll
+    for (int f = 0; f < kFlushTiles; ++f) {
+      const int64_t ct = cg + f * kCT;
+      fetch(ct + kCT);
+      // LDS operands one step ahead, held there by a scheduling barrier, as
+      // in the difference form
+      float yc[NT];
+#pragma unroll
+      for (int t = 0; t < NT; ++t) yc[t] = s_y[buf][(lane >> 4) * YS + 16 * t + (lane & 15)];
+      const float* sxf = reinterpret_cast<const float*>(&s_x[buf][0]);
+      f4v dcur[RB], dnext[RB];
+      {
+        const float ad = sxf[aoff];
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb) dcur[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(ad, bx[rb], zero4, 0, 0, 0);
+      }
+#pragma unroll
+      for (int k = 0; k < kCT; k += 4) {
+        float yv[NT];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) yv[t] = yc[t];
+        float adn = 0.f;
+        if (k + 4 < kCT) {
+          const int cn = k + 4 + (lane >> 4);
+#pragma unroll
+          for (int t = 0; t < NT; ++t) yc[t] = s_y[buf][cn * YS + 16 * t + (lane & 15)];
         }
+        if (k % 16 == 0 && k + 16 < kCT) adn = sxf[4 * (k + 16) + aoff];
+        __builtin_amdgcn_sched_barrier(0);
+        if (k % 16 == 0 && k + 16 < kCT) {
+#pragma unroll
+          for (int rb = 0; rb < RB; ++rb)
+            dnext[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(adn, bx[rb], zero4, 0, 0, 0);
+        }
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb) {
+          const float g = __builtin_amdgcn_exp2f(dcur[rb][(k / 4) % 4]);
+#pragma unroll
+          for (int t = 0; t < NT; ++t)
+            acc[rb][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(g, yv[t], acc[rb][t], 0, 0, 0);
+        }
+        if (k % 16 == 12 && k + 4 < kCT) {
+#pragma unroll
+          for (int rb = 0; rb < RB; ++rb) dcur[rb] = dnext[rb];
+        }
+      }
+      stash(buf ^ 1);
+      __syncthreads();
+      buf ^= 1;
+    }
+    flush();
+  }
+
+  float* out = a.nsplit > 1 ? a.partial + (size_t)split * a.nr * B : a.Z;
+#pragma unroll
+  for (int rb = 0; rb < RB; ++rb) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int64_t row = row0 + 16 * rb + 4 * (lane >> 4) + r;
+      if (row < a.nr) {
+        const float sc = a.out_scale * (a.rs ? a.rs[row] : 1.0f);
+        const double f = sc * gram_row_factor(a, row, cx, cy, cz);
 #pragma unroll
         for (int t = 0; t < NT; ++t) out[row * B + 16 * t + (lane & 15)] = (float)(f * tot[rb][t][r]);
       }
     }
   }
+}
+
+// One FP32 work item: the Gram form where it applies, else the difference
+// form.
+template <int KERNEL, int B, int RB>
+__device__ __forceinline__ void gamma_f32_item(const GammaLaunch& a, int64_t rblk, int split, float4 (*s_x)[kCT],
+                                               float (*s_y)[kCT * y_stride<B>()], float (*s_box)[8]) {
+  if constexpr (KERNEL == KA_GAUSSIAN) {
+    float cx, cy, cz;
+    if (gram_rows<RB>(a, rblk, s_box, cx, cy, cz)) {
+      gamma_f32_gram_tile<B, RB>(a, rblk, split, s_x, s_y, cx, cy, cz);
+      return;
+    }
+  }
+  gamma_f32_tile<KERNEL, B, RB>(a, rblk, split, s_x, s_y);
 }
 
 // Occupancy target of the FP32 path (waves per SIMD).  FP32 MFMA and VALU
@@ -393,10 +539,11 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(f32_wa
 void gamma_f32_kernel(GammaLaunch a) {
   __shared__ float4 s_x[2][kCT];
   __shared__ float s_y[2][kCT * y_stride<B>()];
+  __shared__ float s_box[4][8];
   int64_t rblk;
   int split;
   if (!gamma_item(a, rblk, split)) return;
-  gamma_f32_tile<KERNEL, B, RB>(a, rblk, split, s_x, s_y);
+  gamma_f32_item<KERNEL, B, RB>(a, rblk, split, s_x, s_y, s_box);
 }
 
 // ---------------------------------------------------------------------------
@@ -615,21 +762,200 @@ __device__ __forceinline__ void gamma_bf16x3_tile(const GammaLaunch& a, int64_t 
   }
 }
 
+// The BF16x3 tile in the centred Gram form of the FP32 path (Gaussian kernel,
+// centre c of the rows' box).  The 8 columns 32 ks + 8 (l / 16) + u of lane
+// l's A operand come from two Gram MFMAs, the first over columns
+// 32 ks + 8 (m / 4) + m % 4 in A row m (u = 0..3 in result entries 0..3), the
+// second over the same columns + 4 (u = 4..7), so the pre-split Y keeps its
+// layout.  Per pair this leaves the exp2 and the hi/lo split on the VALU.
+template <int B, int RB>
+__device__ __forceinline__ void gamma_bf16x3_gram_tile(const GammaLaunch& a, int64_t rblk, int split,
+                                                       float4 (*s_x)[kCT], uint4 (*s_yh)[kKS * (B / 16) * 64],
+                                                       uint4 (*s_yl)[kKS * (B / 16) * 64], float cx, float cy,
+                                                       float cz) {
+  constexpr int NT = B / 16;
+  constexpr int KS = kKS;
+  constexpr int ROWS = 4 * 16 * RB;
+
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int64_t row0 = rblk * ROWS + wave * 16 * RB;
+  const int64_t c_begin = (int64_t)split * a.cols_per_split;
+  const int64_t c_end = (c_begin + a.cols_per_split < a.nc) ? c_begin + a.cols_per_split : a.nc;
+
+  // B operand (xt, 1) of each row sub-block
+  float bx[RB];
+#pragma unroll
+  for (int rb = 0; rb < RB; ++rb) {
+    int64_t r = row0 + 16 * rb + (lane & 15);
+    if (r >= a.nr) r = a.nr - 1;
+    const int q = lane >> 4;
+    const float v = q < 3 ? load_coord(a.xr, r, a.xr_stride, q, a.coord_scale) : 0.f;
+    bx[rb] = q == 0 ? v - cx : (q == 1 ? v - cy : (q == 2 ? v - cz : 1.f));
+  }
+  const f4v zero4 = {0.f, 0.f, 0.f, 0.f};
+
+  f4v acc[RB][NT];
+#pragma unroll
+  for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[rb][t] = (f4v){0.f, 0.f, 0.f, 0.f};
+  f4v tot[RB][NT];   // FP32 running totals, as in the difference form
+#pragma unroll
+  for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+    for (int t = 0; t < NT; ++t) tot[rb][t] = (f4v){0.f, 0.f, 0.f, 0.f};
+  auto flush = [&]() {
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        tot[rb][t] += acc[rb][t];
+        acc[rb][t] = (f4v){0.f, 0.f, 0.f, 0.f};
+      }
+  };
+
+  constexpr int E = KS * NT * 64;
+  constexpr int FPT = (E + kThreads - 1) / kThreads;
+  uint4 hbuf[FPT], lbuf[FPT];
+  float4 xbuf;
+
+  auto fetch = [&](int64_t ct) {
+    const uint4* src = a.ys + (ct / kCT) * (2 * E);
+    const bool in = ct < c_end;
+#pragma unroll
+    for (int v = 0; v < FPT; ++v) {
+      const int e = threadIdx.x + v * kThreads;
+      if (e < E) {
+        hbuf[v] = in ? src[e] : make_uint4(0u, 0u, 0u, 0u);
+        lbuf[v] = in ? src[E + e] : make_uint4(0u, 0u, 0u, 0u);
+      }
+    }
+    if (threadIdx.x < kCT) {
+      const float* xt = a.xc + ct * a.xc_stride;
+      const int o = (int)threadIdx.x * a.xc_stride;
+      if ((int64_t)threadIdx.x < c_end - ct)
+        xbuf = make_float4(xt[o], xt[o + 1], xt[o + 2], 0.f);
+      else
+        xbuf = make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+  };
+  auto stash = [&](int buf) {
+#pragma unroll
+    for (int v = 0; v < FPT; ++v) {
+      const int e = threadIdx.x + v * kThreads;
+      if (e < E) {
+        s_yh[buf][e] = hbuf[v];
+        s_yl[buf][e] = lbuf[v];
+      }
+    }
+    if (threadIdx.x < kCT) s_x[buf][threadIdx.x] = gram_column(xbuf, a.coord_scale, cx, cy, cz);
+  };
+
+  int buf = 0;
+  fetch(c_begin);
+  stash(0);
+  __syncthreads();
+  for (int64_t cg = c_begin; cg < c_end; cg += kFlushTiles * kCT) {
+#pragma unroll
+    for (int f = 0; f < kFlushTiles; ++f) {
+      const int64_t ct = cg + f * kCT;
+      fetch(ct + kCT);
+      const float* sxf = reinterpret_cast<const float*>(&s_x[buf][0]);
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks) {
+        const int m = lane & 15;
+        const int col = ks * 32 + 8 * (m >> 2) + (m & 3);
+        const float ad0 = sxf[4 * col + (lane >> 4)];
+        const float ad1 = sxf[4 * (col + 4) + (lane >> 4)];
+        bf8v yh[NT], yl[NT];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+          yh[t] = __builtin_bit_cast(bf8v, s_yh[buf][(ks * NT + t) * 64 + lane]);
+          yl[t] = __builtin_bit_cast(bf8v, s_yl[buf][(ks * NT + t) * 64 + lane]);
+        }
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb) {
+          const f4v d0 = __builtin_amdgcn_mfma_f32_16x16x4f32(ad0, bx[rb], zero4, 0, 0, 0);
+          const f4v d1 = __builtin_amdgcn_mfma_f32_16x16x4f32(ad1, bx[rb], zero4, 0, 0, 0);
+          float g[8];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            g[u] = __builtin_amdgcn_exp2f(d0[u]);
+            g[4 + u] = __builtin_amdgcn_exp2f(d1[u]);
+          }
+          uint4 gh, gl;
+          split2(g[0], g[1], gh.x, gl.x);
+          split2(g[2], g[3], gh.y, gl.y);
+          split2(g[4], g[5], gh.z, gl.z);
+          split2(g[6], g[7], gh.w, gl.w);
+          const bf8v ah = __builtin_bit_cast(bf8v, gh);
+          const bf8v al = __builtin_bit_cast(bf8v, gl);
+#pragma unroll
+          for (int t = 0; t < NT; ++t) {
+            acc[rb][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, yh[t], acc[rb][t], 0, 0, 0);
+            acc[rb][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, yl[t], acc[rb][t], 0, 0, 0);
+            acc[rb][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, yh[t], acc[rb][t], 0, 0, 0);
+          }
+        }
+      }
+      stash(buf ^ 1);
+      __syncthreads();
+      buf ^= 1;
+    }
+    flush();
+  }
+
+  float* out = a.nsplit > 1 ? a.partial + (size_t)split * a.nr * B : a.Z;
+#pragma unroll
+  for (int rb = 0; rb < RB; ++rb) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int64_t row = row0 + 16 * rb + 4 * (lane >> 4) + r;
+      if (row < a.nr) {
+        const float sc = a.out_scale * (a.rs ? a.rs[row] : 1.0f);
+        const double f = sc * gram_row_factor(a, row, cx, cy, cz);
+#pragma unroll
+        for (int t = 0; t < NT; ++t) out[row * B + 16 * t + (lane & 15)] = (float)(f * tot[rb][t][r]);
+      }
+    }
+  }
+}
+
+// One BF16x3 work item: the Gram form where it applies, else the difference
+// form.
+template <int KERNEL, int B, int RB>
+__device__ __forceinline__ void gamma_bf16x3_item(const GammaLaunch& a, int64_t rblk, int split, float4 (*s_x)[kCT],
+                                                  uint4 (*s_yh)[kKS * (B / 16) * 64],
+                                                  uint4 (*s_yl)[kKS * (B / 16) * 64], float (*s_box)[8]) {
+  if constexpr (KERNEL == KA_GAUSSIAN) {
+    float cx, cy, cz;
+    if (gram_rows<RB>(a, rblk, s_box, cx, cy, cz)) {
+      gamma_bf16x3_gram_tile<B, RB>(a, rblk, split, s_x, s_yh, s_yl, cx, cy, cz);
+      return;
+    }
+  }
+  gamma_bf16x3_tile<KERNEL, B, RB>(a, rblk, split, s_x, s_yh, s_yl);
+}
+
 // Occupancy target of the BF16x3 path (waves per SIMD), measured best on the
-// workload shapes: 4 at b = 16, 3 at b = 32 and 64.
-template <int B>
-constexpr int bf16x3_waves() { return B == 16 ? 4 : 3; }
+// workload shapes: 4 at b = 16, 3 at b = 32 and 64; 2 for the Gaussian kernel
+// at b = 64, whose Gram-form loop would spill at 3.
+template <int KERNEL, int B>
+constexpr int bf16x3_waves() { return B == 16 ? 4 : (B == 64 && KERNEL == KA_GAUSSIAN ? 2 : 3); }
 
 template <int KERNEL, int B, int RB>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(bf16x3_waves<B>(), bf16x3_waves<B>())))
+__global__ __launch_bounds__(kThreads)
+__attribute__((amdgpu_waves_per_eu(bf16x3_waves<KERNEL, B>(), bf16x3_waves<KERNEL, B>())))
 void gamma_bf16x3_kernel(GammaLaunch a) {
   __shared__ float4 s_x[2][kCT];
   __shared__ uint4 s_yh[2][kKS * (B / 16) * 64];
   __shared__ uint4 s_yl[2][kKS * (B / 16) * 64];
+  __shared__ float s_box[4][8];
   int64_t rblk;
   int split;
   if (!gamma_item(a, rblk, split)) return;
-  gamma_bf16x3_tile<KERNEL, B, RB>(a, rblk, split, s_x, s_yh, s_yl);
+  gamma_bf16x3_item<KERNEL, B, RB>(a, rblk, split, s_x, s_yh, s_yl, s_box);
 }
 
 // Several kernel products in one persistent launch: work items (product,
@@ -651,18 +977,19 @@ void gamma_batch_kernel(const GammaJob* __restrict__ jobs,
   __shared__ float s_y[PREC == KA_FP32 ? 2 : 1][PREC == KA_FP32 ? kCT * y_stride<B>() : 1];
   __shared__ uint4 s_yh[PREC == KA_FP32 ? 1 : 2][PREC == KA_FP32 ? 1 : kKS * (B / 16) * 64];
   __shared__ uint4 s_yl[PREC == KA_FP32 ? 1 : 2][PREC == KA_FP32 ? 1 : kKS * (B / 16) * 64];
+  __shared__ float s_box[4][8];
   for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
     const GammaItem item = items[it];
     const GammaLaunch a = jobs[item.job].a;
     const int kernel = jobs[item.job].kernel;
     if constexpr (PREC == KA_FP32) {
       auto sy = reinterpret_cast<float(*)[kCT * y_stride<B>()]>(&s_y[0][0]);
-      if (kernel == KA_GAUSSIAN) gamma_f32_tile<KA_GAUSSIAN, B, RB>(a, item.rblk, item.split, s_x, sy);
+      if (kernel == KA_GAUSSIAN) gamma_f32_item<KA_GAUSSIAN, B, RB>(a, item.rblk, item.split, s_x, sy, s_box);
       else gamma_f32_tile<KA_EXP_L1, B, RB>(a, item.rblk, item.split, s_x, sy);
     } else {
       auto yh = reinterpret_cast<uint4(*)[kKS * (B / 16) * 64]>(&s_yh[0][0]);
       auto yl = reinterpret_cast<uint4(*)[kKS * (B / 16) * 64]>(&s_yl[0][0]);
-      if (kernel == KA_GAUSSIAN) gamma_bf16x3_tile<KA_GAUSSIAN, B, RB>(a, item.rblk, item.split, s_x, yh, yl);
+      if (kernel == KA_GAUSSIAN) gamma_bf16x3_item<KA_GAUSSIAN, B, RB>(a, item.rblk, item.split, s_x, yh, yl, s_box);
       else gamma_bf16x3_tile<KA_EXP_L1, B, RB>(a, item.rblk, item.split, s_x, yh, yl);
     }
     __syncthreads();
