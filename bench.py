@@ -66,9 +66,9 @@ def peak_pairs(kernel):
 # Algorithmic bytes per launch: every point's coordinates (16 B), Y row
 # (4 b B) and Z row (4 b B) once, plus the row and column scales.
 TRAFFIC = {
-    "cube20": {"gamma_src_sha256_16": "81efab07a96bcf05", "fetch_bytes": 37.5e6, "write_bytes": 52.4e6,
+    "cube20": {"gamma_src_sha256_16": "eda120bfe777898e", "fetch_bytes": 36.85e6, "write_bytes": 54.48e6,
                "algorithmic_bytes": 33.2e6},
-    "cube64": {"gamma_src_sha256_16": "13652e004824aa0f", "fetch_bytes": 5.861e9, "write_bytes": 7.360e7,
+    "cube64": {"gamma_src_sha256_16": "eda120bfe777898e", "fetch_bytes": 5.919e9, "write_bytes": 7.360e7,
                "algorithmic_bytes": 287496 * (2 * 16 + 8 * 64 + 4)},
 }
 

@@ -113,8 +113,13 @@ constexpr int y_stride() { return (B == 16) ? 16 : B + 16; }
 // times that relative, and the factored terms stay below 2^(R^2)); wider row
 // blocks keep the difference form.  Row blocks of tensor-grid points in their
 // natural order qualify at the workload sizes: R^2 = 9.0 on the 66^3 cube at
-// ell = 0.2, at most 11.5 on the quarter annulus r in [1, 2] at ell = 0.5.
-constexpr float kGramR2 = 16.f;
+// ell = 0.2 (18.0 for the blocks that straddle two z-layers), at most 11.5 on
+// the quarter annulus r in [1, 2] at ell = 0.5.  The cut takes in the
+// straddling blocks on purpose: workgroups of one launch that run the two
+// forms at different speeds drift apart in their column streams and stop
+// sharing the XCD's L2 (measured on the 66^3 launch with a cut of 16: 5x the
+// HBM fetch, 29.7 GB against 5.9 GB per launch).
+constexpr float kGramR2 = 20.f;
 
 // Bounding box of a wave's rows (lanes l and l + 16 hold the same rows) into
 // the wave's entry of s_box: lo in [0..2], hi in [4..6].

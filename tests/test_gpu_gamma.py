@@ -6,7 +6,10 @@ difference give ~4e-7 relative error in Gamma, exp2 ~1e-7, and FP32
 accumulation over ~400 MFMA steps ~sqrt(400) u = 1.2e-6 typical, so
 tol = 1e-5 (~170 u) leaves headroom for the worst case.  Split BF16x3: the
 dropped lo*lo product and the BF16 rounding of the lo parts cost up to
-2^-16 = 1.5e-5 per product on top, so tol = 6e-5.
+2^-16 = 1.5e-5 per product on top, so tol = 6e-5.  Row blocks of small
+extent take the centred Gram form of the Gaussian exponent, whose terms are
+of size R^2 <= 20 (scaled units) instead of |x - y|^2: a few units of 2^-24
+R^2 in the exponent, at most ~4e-6 relative in Gamma, inside the same bars.
 """
 import numpy as np
 import pytest
@@ -14,7 +17,7 @@ import torch
 
 import paper_2101_00629_amd as K
 from oracle import kernels
-from workloads import normal_block, uniform_points
+from workloads import normal_block, tensor_grid_points, uniform_points
 
 pytestmark = pytest.mark.gpu
 
@@ -71,6 +74,55 @@ def test_gamma_split_k_path(precision, nr, nc):
     Y = normal_block(6, nc, b)
     Z = _run(K.KA_GAUSSIAN, 1.0, 0.5, Xr, Xc, Y, precision)
     ref, scale = _reference(K.KA_GAUSSIAN, 1.0, 0.5, Xr, Xc, Y)
+    assert (np.abs(Z - ref) / scale).max() < TOL[precision]
+
+
+def _block_r2(X, ell, rows):
+    """Half-diagonal^2 of each row block's box in the kernel's scaled
+    coordinates (sqrt(log2 e) / ell): blocks at or below 20 take the centred
+    Gram form of the Gaussian product, wider ones the difference form."""
+    Xs = X.astype(np.float32).astype(np.float64) * (np.sqrt(np.log2(np.e)) / ell)
+    out = []
+    for i in range(0, len(Xs), rows):
+        B = Xs[i:i + rows]
+        out.append((((B.max(0) - B.min(0)) / 2) ** 2).sum())
+    return np.array(out)
+
+
+@pytest.mark.parametrize("precision", [K.KA_FP32, K.KA_BF16X3])
+@pytest.mark.parametrize("b", [16, 32, 64])
+def test_gamma_gram_and_difference_forms_in_one_launch(precision, b):
+    # rows: a 13 x 11 x 9 tensor grid in its natural order (compact row
+    # blocks: centred Gram form), then a random cloud in [-1, 2]^3 (wide
+    # blocks: difference form); ragged row and column counts
+    ell = 0.3
+    grid = tensor_grid_points((13, 11, 9))
+    Xr = np.concatenate([grid, uniform_points(21, 700, lo=(-1, -1, -1), hi=(2, 2, 2))])
+    Xc = np.concatenate([tensor_grid_points((17, 13, 7), "quarter_annulus") * 0.6, uniform_points(22, 300)])
+    rows = 128 if b == 64 else 256            # rows per workgroup of the kernel product
+    r2 = _block_r2(Xr, ell, rows)
+    ngrid = len(grid) // rows                  # blocks made of grid rows only
+    assert (r2[:ngrid] <= 20).all() and (r2[ngrid + 1:] > 20).all()
+    Y = normal_block(23, len(Xc), b)
+    Z = _run(K.KA_GAUSSIAN, 1.1, ell, Xr, Xc, Y, precision)
+    ref, scale = _reference(K.KA_GAUSSIAN, 1.1, ell, Xr, Xc, Y)
+    assert np.isfinite(Z).all()
+    err = np.abs(Z - ref) / scale
+    assert err.max() < TOL[precision], err.max()
+
+
+@pytest.mark.parametrize("precision", [K.KA_FP32, K.KA_BF16X3])
+def test_gamma_gram_form_split_k(precision):
+    # grid rows (Gram form) against many columns: split-K partial sums of the
+    # Gram form, each scaled by the rows' factor before the reduction
+    nr_grid, nc, b, ell = (10, 10, 2), 20011, 16, 0.4
+    Xr = tensor_grid_points(nr_grid)
+    assert (_block_r2(Xr, ell, 256) <= 20).all()
+    Xc = uniform_points(24, nc)
+    Y = normal_block(25, nc, b)
+    assert K.ka_gamma_workspace(len(Xr), nc, b, precision) > 0
+    Z = _run(K.KA_GAUSSIAN, 1.0, ell, Xr, Xc, Y, precision)
+    ref, scale = _reference(K.KA_GAUSSIAN, 1.0, ell, Xr, Xc, Y)
     assert (np.abs(Z - ref) / scale).max() < TOL[precision]
 
 
