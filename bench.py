@@ -33,15 +33,23 @@ METRIC = "Γ-pair evals/s vs roofline; K-L solves/s + p99 latency @1e-6 eig err"
 
 # MI355X unit counts: 256 CUs x 4 SIMDs x 16 lanes at 2.4 GHz issue 39.32e12
 # lane-instructions/s of non-packed FP32 VALU work; v_exp_f32 issues at half
-# rate (two issue slots).  Gaussian pair: 3 sub + mul + 2 fma + exp = 8 slots;
-# exponential pair: 3 sub + 2 add (abs as operand modifiers) + exp = 7 slots.
+# rate (two issue slots).  Gaussian pair in the centred Gram form, which the
+# kernel takes for row blocks of small extent (every workload here): the
+# distance comes from the matrix cores, the VALU keeps the exp = 2 slots (the
+# difference form, for wide row blocks, takes 3 sub + mul + 2 fma + exp = 8).
+# Exponential pair: 3 sub + 2 add (abs as operand modifiers) + exp = 7 slots.
 VALU_SLOTS_PER_S = 256 * 4 * 16 * 2.4e9
-SLOTS = {"gaussian": 8, "exponential": 7}
+SLOTS = {"gaussian": 2, "exponential": 7}
 # The contraction: b/16 v_mfma_f32_16x16x4_f32 (2048 flops each) per 64 pairs,
-# published dense FP32 matrix peak 157.3 TFLOP/s.  On gfx950 FP32 MFMA and VALU
-# work do not overlap (measured: mixed waves take the sum of the two times), so
-# the attainable rate of the FP32 path is the serial combination of both.
+# published dense FP32 matrix peak 157.3 TFLOP/s; the Gram form adds one more
+# per 256 pairs for the distances.  On gfx950 FP32 MFMA and VALU work do not
+# overlap (measured: mixed waves take the sum of the two times), so the
+# attainable rate of the FP32 path is the serial combination of both.
 MFMA_F32_FLOPS = 157.3e12
+
+
+def mfma_per_64_pairs(kernel, b):
+    return b / 16.0 + (0.25 if kernel == "gaussian" else 0.0)
 
 
 def mfma_pairs(b):
@@ -50,8 +58,8 @@ def mfma_pairs(b):
 
 
 def serial_peak_pairs(kernel, b):
-    mfma_pairs = MFMA_F32_FLOPS / 2048.0 * 64.0 * 16.0 / b
-    return 1.0 / (1.0 / peak_pairs(kernel) + 1.0 / mfma_pairs)
+    mfma_issue_pairs = MFMA_F32_FLOPS / 2048.0 * 64.0 / mfma_per_64_pairs(kernel, b)
+    return 1.0 / (1.0 / peak_pairs(kernel) + 1.0 / mfma_issue_pairs)
 
 
 def peak_pairs(kernel):
@@ -67,7 +75,7 @@ def peak_pairs(kernel):
 # (4 b B) and Z row (4 b B) once, plus the row and column scales.
 TRAFFIC = {
     "cube20": {"gamma_src_sha256_16": "eda120bfe777898e", "fetch_bytes": 36.85e6, "write_bytes": 54.48e6,
-               "algorithmic_bytes": 33.2e6},
+               "algorithmic_bytes": 33.9e6},
     "cube64": {"gamma_src_sha256_16": "eda120bfe777898e", "fetch_bytes": 5.919e9, "write_bytes": 7.360e7,
                "algorithmic_bytes": 287496 * (2 * 16 + 8 * 64 + 4)},
 }
@@ -695,7 +703,7 @@ def main():
         return
     if args.kernel_rates:
         print(json.dumps({"metric": "fused kernel product pairs/s at the workload shapes", "n_gpus": 1,
-                          "data": "synthetic (uniform points, N(0,1) blocks)", "unit": "pairs/s",
+                          "data": "synthetic (tensor-grid points in the problems' order, N(0,1) blocks)", "unit": "pairs/s",
                           "rates": kernel_rates()}), flush=True)
         return
     if args.kl_sample:
