@@ -16,6 +16,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "ka_internal.hpp"
 
@@ -61,7 +62,10 @@ __global__ __launch_bounds__(256) void mode_pt_kernel(const TIn* __restrict__ in
     TAcc acc[R];
 #pragma unroll
     for (int q = 0; q < R; ++q) acc[q] = (TAcc)0;
-    if (rows == R) {
+    // U input values in flight per thread, in full chunks and in the last,
+    // partial one alike (there only the chunk's rows are read and summed)
+    auto sweep = [&](auto full_tag) {
+      constexpr bool FULL = decltype(full_tag)::value;
       int c = 0;
       for (; c + U <= nk; c += U) {
         TAcc x[U];
@@ -71,24 +75,20 @@ __global__ __launch_bounds__(256) void mode_pt_kernel(const TIn* __restrict__ in
         for (int u = 0; u < U; ++u) {
           const TAcc* a = matT + (int64_t)(c + u) * m + m0;
 #pragma unroll
-          for (int q = 0; q < R; ++q) acc[q] += a[q] * x[u];
+          for (int q = 0; q < R; ++q)
+            if (FULL || q < rows) acc[q] += a[q] * x[u];
         }
       }
       for (; c < nk; ++c) {
         const TAcc x = (TAcc)src[(int64_t)c * step];
         const TAcc* a = matT + (int64_t)c * m + m0;
 #pragma unroll
-        for (int q = 0; q < R; ++q) acc[q] += a[q] * x;
-      }
-    } else {
-      for (int c = 0; c < nk; ++c) {
-        const TAcc x = (TAcc)src[(int64_t)c * step];
-        const TAcc* a = matT + (int64_t)c * m + m0;
-#pragma unroll
         for (int q = 0; q < R; ++q)
-          if (q < rows) acc[q] += a[q] * x;
+          if (FULL || q < rows) acc[q] += a[q] * x;
       }
-    }
+    };
+    if (rows == R) sweep(std::true_type{});
+    else sweep(std::false_type{});
 #pragma unroll
     for (int q = 0; q < R; ++q) {
       if (q < rows) {
@@ -102,9 +102,11 @@ __global__ __launch_bounds__(256) void mode_pt_kernel(const TIn* __restrict__ in
 }
 
 // R outputs per thread and pass over the input fiber: 33 for modes longer than
-// 16, so that a mode of 66 (the 64^3 cube at p = 2) takes two passes instead
+// 32, so that a mode of 66 (the 64^3 cube at p = 2) takes two passes instead
 // of five.  Every pass re-reads the fiber, and at that size the re-reads
-// come from HBM: 4.8 times the input bytes with R = 16.
+// come from HBM: 4.8 times the input bytes with R = 16.  Modes of 17 to 32
+// keep R = 16: two passes, the first one full, where 33 would make one pass
+// with up to half of its accumulators idle.
 template <typename TIn, typename TAcc, typename TOut, int R>
 static hipError_t launch_mode_pt_r(const ModeArgs& a, hipStream_t s) {
   const int nk = a.n_in[a.mode];
@@ -124,7 +126,7 @@ static hipError_t launch_mode_pt_r(const ModeArgs& a, hipStream_t s) {
 
 template <typename TIn, typename TAcc, typename TOut>
 static hipError_t launch_mode_pt(const ModeArgs& a, hipStream_t s) {
-  return a.m > 16 ? launch_mode_pt_r<TIn, TAcc, TOut, 33>(a, s) : launch_mode_pt_r<TIn, TAcc, TOut, 16>(a, s);
+  return a.m > 32 ? launch_mode_pt_r<TIn, TAcc, TOut, 33>(a, s) : launch_mode_pt_r<TIn, TAcc, TOut, 16>(a, s);
 }
 
 template <typename TIn, typename TAcc, typename TOut>
