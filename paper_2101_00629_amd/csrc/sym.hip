@@ -15,12 +15,15 @@ namespace ka {
 constexpr int kTriThreads = 512;
 constexpr int kTriLds = 128;
 constexpr int kSymTriMax = 1024;
+constexpr int kTriNb = kSymNbMax;   // panel width of the blocked reduction
 constexpr int kBackLds = 240;
 
 size_t sym_tri_work(int n) { return sym_tri_work_doubles(n); }
 
 struct BlockTeam {
-  double* red;   // one slot per wave
+  double* red;    // one slot per wave
+  double* redv;   // kVecMax slots per wave (sumv)
+  static constexpr int kVecMax = 2 * kSymNbMax;
   __device__ int tid() const { return threadIdx.x; }
   __device__ int size() const { return kTriThreads; }
   __device__ void sync() const { __syncthreads(); }
@@ -34,6 +37,25 @@ struct BlockTeam {
     __syncthreads();
     return s;
   }
+  // out[i] = sum over the workgroup of x[i], i < k <= kVecMax (out: shared)
+  __device__ void sumv(const double* x, int k, double* out) const {
+#pragma unroll
+    for (int i = 0; i < kVecMax; ++i) {
+      if (i < k) {
+        double y = x[i];
+        for (int off = 32; off > 0; off >>= 1) y += __shfl_xor(y, off);
+        if ((threadIdx.x & 63) == 0) redv[(threadIdx.x >> 6) * kVecMax + i] = y;
+      }
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < k) {
+      double s = 0.0;
+#pragma unroll
+      for (int w = 0; w < kTriThreads / 64; ++w) s += redv[w * kVecMax + threadIdx.x];
+      out[threadIdx.x] = s;
+    }
+    __syncthreads();
+  }
 };
 
 template <bool LDS>
@@ -42,14 +64,20 @@ __global__ __launch_bounds__(kTriThreads) void sym_tridiag_kernel(const double* 
   __shared__ double A_lds[LDS ? kTriLds * kTriLds : 1];
   __shared__ double v[kSymTriMax], w[kSymTriMax];
   __shared__ double red[kTriThreads / 64];
+  // blocked reduction (matrix in device memory): the panel's V and W columns
+  __shared__ double VW[LDS ? 1 : 2 * kSymTriMax * kSymNbMax];
+  __shared__ double yz[BlockTeam::kVecMax], redv[(kTriThreads / 64) * BlockTeam::kVecMax];
   const SymWork sw = sym_work_split(work, n);
   double* A = LDS ? A_lds : sw.A;
   for (int j = 0; j < n; ++j)
     for (int i = threadIdx.x; i < n; i += kTriThreads)
       A[i + (int64_t)j * n] = 0.5 * (H[i + (int64_t)j * ldh] + H[j + (int64_t)i * ldh]);
   __syncthreads();
-  BlockTeam tm{red};
-  sym_tridiagonalize(tm, A, n, sw.d, sw.e, sw.beta, v, w);
+  BlockTeam tm{red, redv};
+  if constexpr (LDS)
+    sym_tridiagonalize(tm, A, n, sw.d, sw.e, sw.beta, v, w);
+  else
+    sym_tridiagonalize_blocked(tm, A, n, sw.d, sw.e, sw.beta, v, w, VW, VW + (size_t)n * kSymNbMax, yz, kTriNb);
   if (LDS)
     for (int64_t q = threadIdx.x; q < (int64_t)n * n; q += kTriThreads) sw.A[q] = A[q];
   if (threadIdx.x == 0) sym_bounds(sw.d, sw.e, n, sw.bnd);

@@ -161,6 +161,168 @@ KA_HD void sym_tridiagonalize(Team& tm, double* A, int n, double* d, double* e, 
   tm.sync();
 }
 
+// Blocked form of the same reduction (the split of LAPACK's latrd and syr2k):
+// within a panel of nb columns the two-sided updates are deferred.  Column j
+// of the panel first takes the updates of the panel's earlier columns, the
+// product A22 v is corrected for them (A22 is read as stored, without them),
+// and the trailing matrix takes all of the panel's updates at the panel's
+// end, as one rank-2nb update.  The passes over the matrix per nb columns go
+// from 3 nb to nb + 2, for a matrix held in device memory; the arithmetic is
+// the same up to the order of the sums.  Team: as above, plus
+// sumv(x, k, out): out[i] = sum over the team of x[i], i < k, into
+// team-shared out, returned to every thread.  V, W: team-shared, nb columns of
+// n doubles each (panel column s at V[s * n + r], rows r in the matrix's
+// numbering, zero at and above the column's diagonal); yz: team-shared,
+// >= 2 kSymNbMax doubles.
+constexpr int kSymNbMax = 8;
+
+template <class Team>
+KA_HD KA_FORCEINLINE void sym_tridiagonalize_blocked(Team& tm, double* A, int n, double* d, double* e, double* beta,
+                                                     double* v, double* w, double* V, double* W, double* yz, int nb) {
+  const int t = tm.tid(), NT = tm.size();
+  if (nb > kSymNbMax) nb = kSymNbMax;
+  if (nb < 1) nb = 1;
+  for (int p0 = 0; p0 + 2 < n; p0 += nb) {
+    const int pend = p0 + nb < n - 2 ? p0 + nb : n - 2;   // panel columns p0 .. pend - 1
+    for (int j = p0; j < pend; ++j) {
+      const int sn = j - p0;                 // earlier columns of this panel
+      const int m = n - j - 1;
+      double* colj = A + (size_t)j * n;
+      // column j, rows j .. n-1: the panel's deferred updates
+      if (sn > 0) {
+        for (int r = j + t; r < n; r += NT) {
+          double c = colj[r];
+          for (int q = 0; q < sn; ++q) c -= V[(size_t)q * n + r] * W[(size_t)q * n + j] + W[(size_t)q * n + r] * V[(size_t)q * n + j];
+          colj[r] = c;
+        }
+        tm.sync();
+      }
+      double* col = colj + j + 1;             // column j below the diagonal
+      double ss = 0.0;
+      for (int i = t; i < m; i += NT) ss += col[i] * col[i];
+      ss = tm.sum(ss);
+      const double x0 = col[0];
+      const double alpha = -sym_copysign(sqrt(ss), x0);
+      const double v0 = x0 - alpha;
+      const bool skip = !(ss > 1e-300);
+      const double vtv = ss - x0 * x0 + v0 * v0;
+      const double b = skip ? 0.0 : 2.0 / vtv;
+      for (int i = t; i < m; i += NT) v[i] = (i == 0) ? v0 : col[i];
+      if (t == 0) {
+        d[j] = colj[j];
+        e[j] = skip ? x0 : alpha;
+        beta[j] = b;
+      }
+      tm.sync();
+      if (!skip) {
+        const double* A22 = A + (j + 1) + (size_t)(j + 1) * n;
+        // p = A22 v as stored: a thread per row, kSymBatch loads in flight
+        for (int r = t; r < m; r += NT) {
+          const double* row = A22 + r;
+          double acc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+          int c = 0;
+          for (; c + kSymBatch - 1 < m; c += kSymBatch) {
+            double a[kSymBatch];
+#pragma unroll
+            for (int u = 0; u < kSymBatch; ++u) a[u] = row[(size_t)(c + u) * n];
+#pragma unroll
+            for (int u = 0; u < kSymBatch; ++u) acc[u % 8] += a[u] * v[c + u];
+          }
+          for (; c < m; ++c) acc[0] += row[(size_t)c * n] * v[c];
+          w[r] = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
+        }
+        // the panel's deferred part: p -= V (W^T v) + W (V^T v)
+        if (sn > 0) {
+          double part[2 * kSymNbMax];
+#pragma unroll
+          for (int q = 0; q < 2 * kSymNbMax; ++q) part[q] = 0.0;
+          for (int c = t; c < m; c += NT) {
+            const double vc = v[c];
+            const size_t rc = (size_t)(j + 1 + c);
+#pragma unroll
+            for (int q = 0; q < kSymNbMax; ++q)
+              if (q < sn) {
+                part[q] += W[(size_t)q * n + rc] * vc;
+                part[kSymNbMax + q] += V[(size_t)q * n + rc] * vc;
+              }
+          }
+          tm.sumv(part, 2 * kSymNbMax, yz);
+          for (int r = t; r < m; r += NT) {
+            const size_t rr = (size_t)(j + 1 + r);
+            double c = w[r];
+            for (int q = 0; q < sn; ++q) c -= V[(size_t)q * n + rr] * yz[q] + W[(size_t)q * n + rr] * yz[kSymNbMax + q];
+            w[r] = c;
+          }
+        }
+        double wv = 0.0;
+        for (int r = t; r < m; r += NT) {
+          w[r] *= b;
+          wv += w[r] * v[r];
+        }
+        wv = tm.sum(wv);
+        const double K = 0.5 * b * wv;
+        for (int r = t; r < m; r += NT) w[r] -= K * v[r];
+      } else {
+        for (int r = t; r < m; r += NT) w[r] = 0.0;
+      }
+      tm.sync();
+      // panel column sn, and the reflector for the back-transformation
+      for (int r = t; r < n; r += NT) {
+        V[(size_t)sn * n + r] = r > j ? v[r - j - 1] : 0.0;
+        W[(size_t)sn * n + r] = r > j ? w[r - j - 1] : 0.0;
+      }
+      for (int i = t; i < m; i += NT) col[i] = v[i];
+      tm.sync();
+    }
+    // the trailing matrix, rows and columns pend .. n-1, takes the panel's
+    // updates: A <- A - V W^T - W V^T; thread t takes row t % mt in the
+    // columns of its group t / mt, kSymBatch columns at a time
+    const int ns = pend - p0, mt = n - pend;
+    const int groups = NT >= mt ? NT / mt : 1;
+    for (int r0 = t; r0 < groups * mt; r0 += NT) {
+      const int r = NT >= mt ? r0 % mt : r0, g = NT >= mt ? r0 / mt : 0;
+      const size_t rr = (size_t)(pend + r);
+      double vr[kSymNbMax], wr[kSymNbMax];
+#pragma unroll
+      for (int q = 0; q < kSymNbMax; ++q) {
+        vr[q] = q < ns ? V[(size_t)q * n + rr] : 0.0;
+        wr[q] = q < ns ? W[(size_t)q * n + rr] : 0.0;
+      }
+      double* row = A + rr + (size_t)pend * n;
+      int c = g;
+      for (; c + (kSymBatch - 1) * groups < mt; c += kSymBatch * groups) {
+        double a[kSymBatch];
+#pragma unroll
+        for (int u = 0; u < kSymBatch; ++u) a[u] = row[(size_t)(c + u * groups) * n];
+#pragma unroll
+        for (int u = 0; u < kSymBatch; ++u) {
+          const size_t cc = (size_t)(pend + c + u * groups);
+          double x = a[u];
+#pragma unroll
+          for (int q = 0; q < kSymNbMax; ++q)
+            if (q < ns) x -= vr[q] * W[(size_t)q * n + cc] + wr[q] * V[(size_t)q * n + cc];
+          row[(size_t)(c + u * groups) * n] = x;
+        }
+      }
+      for (; c < mt; c += groups) {
+        const size_t cc = (size_t)(pend + c);
+        double x = row[(size_t)c * n];
+        for (int q = 0; q < ns; ++q) x -= vr[q] * W[(size_t)q * n + cc] + wr[q] * V[(size_t)q * n + cc];
+        row[(size_t)c * n] = x;
+      }
+    }
+    tm.sync();
+  }
+  if (t == 0) {
+    if (n >= 2) {
+      d[n - 2] = A[(n - 2) + (size_t)(n - 2) * n];
+      e[n - 2] = A[(n - 1) + (size_t)(n - 2) * n];
+    }
+    d[n - 1] = A[(n - 1) + (size_t)(n - 1) * n];
+  }
+  tm.sync();
+}
+
 // Gershgorin interval and norm estimate of T (d, e)
 KA_HD inline void sym_bounds(const double* d, const double* e, int n, double* bnd) {
   double lo = 1e300, hi = -1e300, tn = 0.0;

@@ -10,18 +10,28 @@ struct HostTeam {
   int size() const { return 1; }
   void sync() const {}
   double sum(double x) const { return x; }
+  void sumv(const double* x, int k, double* out) const {
+    for (int i = 0; i < k; ++i) out[i] = x[i];
+  }
 };
 }  // namespace
 
 // theta descending (all n), S (n x nvec column-major) the unit eigenvectors of
-// the nvec largest; returns the number of clusters met among them
-extern "C" int ka_host_sym_eig(const double* H, int n, int nvec, double* theta, double* S) {
+// the nvec largest; returns the number of clusters met among them.  nb > 0
+// takes the blocked tridiagonalisation with panels of nb columns.
+extern "C" int ka_host_sym_eig_nb(const double* H, int n, int nvec, double* theta, double* S, int nb) {
   std::vector<double> work(ka::sym_tri_work_doubles(n)), v(n), w(n);
   ka::SymWork sw = ka::sym_work_split(work.data(), n);
   for (int j = 0; j < n; ++j)
     for (int i = 0; i < n; ++i) sw.A[i + (size_t)j * n] = 0.5 * (H[i + (size_t)j * n] + H[j + (size_t)i * n]);
   HostTeam tm;
-  ka::sym_tridiagonalize(tm, sw.A, n, sw.d, sw.e, sw.beta, v.data(), w.data());
+  if (nb > 0) {
+    std::vector<double> V((size_t)n * ka::kSymNbMax), W((size_t)n * ka::kSymNbMax), yz(2 * ka::kSymNbMax);
+    ka::sym_tridiagonalize_blocked(tm, sw.A, n, sw.d, sw.e, sw.beta, v.data(), w.data(), V.data(), W.data(),
+                                   yz.data(), nb);
+  } else {
+    ka::sym_tridiagonalize(tm, sw.A, n, sw.d, sw.e, sw.beta, v.data(), w.data());
+  }
   ka::sym_bounds(sw.d, sw.e, n, sw.bnd);
   const double pivmin = ka::sym_pivmin(sw.bnd);
   for (int k = 0; k < n; ++k) {
@@ -51,4 +61,8 @@ extern "C" int ka_host_sym_eig(const double* H, int n, int nvec, double* theta, 
     for (int i = 0; i < n; ++i) S[i + (size_t)k * n] = sw.V[(size_t)i * n + src];
   }
   return clusters;
+}
+
+extern "C" int ka_host_sym_eig(const double* H, int n, int nvec, double* theta, double* S) {
+  return ka_host_sym_eig_nb(H, n, nvec, theta, S, 0);
 }

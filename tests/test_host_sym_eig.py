@@ -22,6 +22,8 @@ def lib(tmp_path_factory):
     dp = ctypes.POINTER(ctypes.c_double)
     L.ka_host_sym_eig.argtypes = [dp, ctypes.c_int, ctypes.c_int, dp, dp]
     L.ka_host_sym_eig.restype = ctypes.c_int
+    L.ka_host_sym_eig_nb.argtypes = [dp, ctypes.c_int, ctypes.c_int, dp, dp, ctypes.c_int]
+    L.ka_host_sym_eig_nb.restype = ctypes.c_int
     return L
 
 
@@ -120,3 +122,44 @@ def test_leading_vectors_only(lib, nvec):
     H = (Q * lam) @ Q.T
     nc, th, S = _eig(lib, H, nvec=nvec)
     _check(H, th, S)
+
+
+def _eig_nb(lib, H, nb, nvec=None):
+    n = H.shape[0]
+    nvec = n if nvec is None else nvec
+    Hc = np.asfortranarray(H, dtype=np.float64)
+    th, S = np.zeros(n), np.zeros((n, nvec), order="F")
+    p = lambda a: a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    nc = lib.ka_host_sym_eig_nb(p(Hc), n, nvec, p(th), p(S), nb)
+    return nc, th, S
+
+
+@pytest.mark.parametrize("nb", [1, 3, 8])
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 9, 10, 11, 37, 130, 229])
+def test_blocked_tridiagonalisation(lib, n, nb):
+    """The blocked reduction (deferred panel updates) against LAPACK, on panel
+    counts that divide n - 2 and ones that leave a ragged last panel; its
+    eigenvalues also match the unblocked reduction's to rounding."""
+    rng = np.random.default_rng(1000 + n)
+    A = rng.standard_normal((n, n))
+    H = A + A.T
+    nc, th, S = _eig_nb(lib, H, nb)
+    _check(H, th, S)
+    _, th0, _ = _eig(lib, H)
+    assert np.abs(th - th0).max() <= 1e-12 * max(np.abs(th0).max(), 1e-300) * max(1, n / 10)
+
+
+@pytest.mark.parametrize("nb", [3, 8])
+def test_blocked_multiplicities_and_zero_columns(lib, nb):
+    # exact multiplicities (zero reflectors: columns already reduced) and a
+    # matrix with an exactly zero off-diagonal block
+    Q, _ = np.linalg.qr(np.random.default_rng(5).standard_normal((40, 40)))
+    lam = np.repeat([3.0, 1.0, -2.0, 0.5], 10)
+    H = (Q * lam) @ Q.T
+    nc, th, S = _eig_nb(lib, H, nb)
+    _check(H, th, S)
+    B = np.zeros((24, 24))
+    B[:12, :12] = np.diag(np.arange(12.0))
+    B[12:, 12:] = np.eye(12) * 2.0 + 0.1
+    nc, th, S = _eig_nb(lib, B, nb)
+    _check(B, th, S)
