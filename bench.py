@@ -46,6 +46,7 @@ SLOTS = {"gaussian": 2, "exponential": 7}
 # overlap (measured: mixed waves take the sum of the two times), so the
 # attainable rate of the FP32 path is the serial combination of both.
 MFMA_F32_FLOPS = 157.3e12
+MFMA_BF16_FLOPS = 2.5e15   # published dense BF16 matrix peak
 
 
 def mfma_per_64_pairs(kernel, b):
@@ -517,8 +518,11 @@ def roofline(res, name, precision):
     """Roofline record of the fused kernel product.  FP32: the contraction's
     2 b flops per pair on the FP32 matrix cores (157.3 TFLOP/s) and the tile
     evaluation's VALU slots do not overlap on gfx950; whichever takes longer
-    per pair is the bound ("mfma" for b = 64).  BF16x3: VALU bound (the BF16
-    contraction is 16x faster), peak from the unit counts."""
+    per pair is the bound ("mfma" for b = 64).  BF16x3: against the dense
+    BF16 matrix peak (2.5 PFLOP/s) with the three products' 6 b flops per
+    pair; with the Gram form its VALU work per pair is the exp and the hi/lo
+    split, and the matrix cores are the busiest unit (about 0.4 of the cycles
+    at b = 64, VALU issue about 0.33)."""
     a = res["achieved"]
     rec = {"kernel": "gamma_f32_kernel" if precision == "fp32" else "gamma_bf16x3_kernel",
            "launches": res["launches"], "kernel_ms": res["gl_ms"],
@@ -536,7 +540,9 @@ def roofline(res, name, precision):
         rec.update(traffic=measured_traffic(name), traffic_unit="HBM bytes per launch",
                    algorithmic_bytes_per_launch=TRAFFIC[name]["algorithmic_bytes"])
     else:
-        rec.update(bound="alu", achieved=a, peak=res["valu_peak"], unit="pairs/s", frac=a / res["valu_peak"])
+        flops = a * 3.0 * res["flops_per_pair"]
+        rec.update(bound="mfma", achieved=flops / 1e12, peak=MFMA_BF16_FLOPS / 1e12, unit="TFLOP/s",
+                   frac=flops / MFMA_BF16_FLOPS)
     return rec
 
 
