@@ -230,17 +230,27 @@ constexpr int kNnKC = 32;                    // rows of B per LDS chunk
 constexpr int kNnBW = 16 * kNnJ + 16;        // padded LDS row of B (doubles)
 constexpr int kNnSE = kNnKC * 16 * kNnJ / 256;   // staged B elements per thread
 
+// Grid: 1-D, the row blocks rounded up to a multiple of 8 times the column
+// blocks.  Workgroup L runs on XCD L % 8; on each XCD the column blocks of a
+// row block follow one another, so the block's 64 rows of A are read from HBM
+// about once and then from that XCD's L2 (with the column blocks outermost,
+// A was read from HBM once per column block).
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4)))
 void dgemm_nn_mfma_kernel(int64_t M, int n, int k, const double* __restrict__ A, int64_t lda,
                           const double* __restrict__ B, int64_t ldb, double alpha, double beta,
                           double* __restrict__ C, int64_t ldc) {
   __shared__ double Bs[2][kNnKC][kNnBW];
+  const int ncb = (n + 16 * kNnJ - 1) / (16 * kNnJ);
+  const int64_t L = blockIdx.x, seq = L / 8;
+  const int64_t rb = (seq / ncb) * 8 + L % 8;   // row block
+  const int cb = (int)(seq % ncb);              // column block
+  if (rb * 64 >= M) return;                     // padding workgroup (whole workgroup)
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, q = lane >> 4, c16 = lane & 15;
-  const int64_t r0 = (int64_t)blockIdx.x * 64 + 16 * w;
+  const int64_t r0 = rb * 64 + 16 * w;
   const int64_t i = r0 + c16;
   const bool iok = i < M;
   const double* __restrict__ Ai = A + (iok ? i : M - 1);
-  const int j0 = blockIdx.y * 16 * kNnJ;
+  const int j0 = cb * 16 * kNnJ;
   const int jt = (n - j0 + 15) / 16 < kNnJ ? (n - j0 + 15) / 16 : kNnJ;   // column tiles of this workgroup
   const int nch = (k + kNnKC - 1) / kNnKC;
   tn_d4 acc[kNnJ];
@@ -313,7 +323,10 @@ void dgemm_nn_mfma_kernel(int64_t M, int n, int k, const double* __restrict__ A,
 hipError_t dgemm_nn(int64_t M, int n, int k, double alpha, const double* A, int64_t lda, const double* B,
                     int64_t ldb, double beta, double* C, int64_t ldc, hipStream_t s) {
   if (M <= 0 || n <= 0) return hipSuccess;
-  const dim3 grid((unsigned)((M + 63) / 64), (n + 16 * kNnJ - 1) / (16 * kNnJ), 1);
+  const int64_t nrb8 = ((M + 63) / 64 + 7) / 8 * 8;
+  const int64_t ncb = (n + 16 * kNnJ - 1) / (16 * kNnJ);
+  if (nrb8 * ncb > 0x7fffffff) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)(nrb8 * ncb), 1, 1);
   hipLaunchKernelGGL(dgemm_nn_mfma_kernel, grid, dim3(256), 0, s, M, n, k, A, lda, B, ldb, alpha, beta, C, ldc);
   return hipGetLastError();
 }
