@@ -689,8 +689,8 @@ def main():
                     help="first run one plain device copy of MIB MiB (reference for HBM traffic counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: the kernel product of one GPU's share; "
-              "multi-GPU runs are not part of this build (see DESIGN.md, sharding)", file=sys.stderr)
+        print("bench.py measures one GPU (--gpus 1): multi-GPU execution is not implemented; the path would shard "
+              "the kernel product by rows, one all-gather of Z per block product", file=sys.stderr)
         sys.exit(2)
 
     import torch
