@@ -275,9 +275,68 @@ KA_HD KA_FORCEINLINE void sym_tridiagonalize_blocked(Team& tm, double* A, int n,
       tm.sync();
     }
     // the trailing matrix, rows and columns pend .. n-1, takes the panel's
-    // updates: A <- A - V W^T - W V^T; thread t takes row t % mt in the
-    // columns of its group t / mt, kSymBatch columns at a time
+    // updates: A <- A - V W^T - W V^T
     const int ns = pend - p0, mt = n - pend;
+#if defined(__HIP_DEVICE_COMPILE__)
+    {
+      // On the FP64 matrix cores: a 16 x 16 tile takes tile - L R^T with
+      // L = [V W] (its rows) and R = [W V] (its columns), K = 2 kSymNbMax in
+      // four v_mfma_f64_16x16x4f64 (A lane l: row l % 16, k l / 16; B lane l:
+      // k l / 16, column l % 16; accumulator entry e of lane l: row
+      // l / 16 + 4 e, column l % 16).  Each wave takes four tiles at a time,
+      // their loads issued together; parts of tiles past the matrix are
+      // neither read nor written, and panel columns past ns weigh zero.
+      typedef double sym_d4 __attribute__((ext_vector_type(4)));
+      constexpr int kTiles = 4;
+      const int lane = t & 63, wv = t >> 6, nwv = NT >> 6;
+      const int li = lane & 15, lk = lane >> 4;
+      const int n16 = (mt + 15) / 16, ntl = n16 * n16;
+      for (int base = wv * kTiles; base < ntl; base += nwv * kTiles) {
+        sym_d4 acc[kTiles];
+#pragma unroll
+        for (int u = 0; u < kTiles; ++u) {
+          const int tile = base + u;
+          const int ti = tile % n16, tj = tile / n16;
+          const int cj = tj * 16 + li;
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const int ri = ti * 16 + lk + 4 * e;
+            acc[u][e] = (tile < ntl && ri < mt && cj < mt) ? A[(size_t)(pend + ri) + (size_t)(pend + cj) * n] : 0.0;
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < kTiles; ++u) {
+          const int tile = base + u;
+          const int ti = tile % n16, tj = tile / n16;
+          const int ra = ti * 16 + li, cb = tj * 16 + li;
+#pragma unroll
+          for (int h = 0; h < 2 * kSymNbMax / 4; ++h) {
+            const int k = 4 * h + lk, q = k % kSymNbMax;
+            const bool first = k < kSymNbMax;
+            double av = 0.0, bv = 0.0;
+            if (tile < ntl && q < ns) {
+              if (ra < mt) av = -(first ? V : W)[(size_t)q * n + pend + ra];
+              if (cb < mt) bv = (first ? W : V)[(size_t)q * n + pend + cb];
+            }
+            acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[u], 0, 0, 0);
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < kTiles; ++u) {
+          const int tile = base + u;
+          const int ti = tile % n16, tj = tile / n16;
+          const int cj = tj * 16 + li;
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const int ri = ti * 16 + lk + 4 * e;
+            if (tile < ntl && ri < mt && cj < mt) A[(size_t)(pend + ri) + (size_t)(pend + cj) * n] = acc[u][e];
+          }
+        }
+      }
+    }
+#else
+    // thread t takes row t % mt in the columns of its group t / mt,
+    // kSymBatch columns at a time
     const int groups = NT >= mt ? NT / mt : 1;
     for (int r0 = t; r0 < groups * mt; r0 += NT) {
       const int r = NT >= mt ? r0 % mt : r0, g = NT >= mt ? r0 / mt : 0;
@@ -311,6 +370,7 @@ KA_HD KA_FORCEINLINE void sym_tridiagonalize_blocked(Team& tm, double* A, int n,
         row[(size_t)c * n] = x;
       }
     }
+#endif
     tm.sync();
   }
   if (t == 0) {
